@@ -1,0 +1,604 @@
+/*
+ * FP64 reference ("oracle") for the Cyrus+ real-time O-DU puncturing-codebook
+ * builder (arXiv 2506.00167).
+ *
+ * TEST INFRASTRUCTURE. Only the test suite, the smoke check and the CPU
+ * baseline of the benchmark load this file. The product path never calls it and
+ * shares no code with it: the HIP library has its own kernels, headers and
+ * helpers. The oracle is plain, slow and written to be checked against the
+ * paper by eye: every loop follows the definition it cites, in float64.
+ *
+ * What it computes (the O-DU side of Sec. IV-C, Sec. V-B and Alg. 2, extended
+ * from one mini-slot to the tree of all arrival sequences over a slot):
+ *
+ *   For every prefix (k_1..k_tau) of URLLC arrival counts, tau = 1..M,
+ *   k_t in {0..K} with K = floor(N/L) (Sec. III-A, Sec. IV-A):
+ *     c_in   = sum of the puncturing vectors chosen on the path so far
+ *     if k_tau == 0: no URLLC packet, nothing is punctured (the no-arrival
+ *                    branch is not considered by the O-DU, Sec. IV-C footnote)
+ *     else:          x = features(s(t), c_in, tau, k_tau)
+ *                    z = f_a(x)                      actor forward, Sec. VI-B
+ *                    p = softmax(z)                  policy split
+ *                    xq = KL projection of T*p onto {0 <= m_e <= R_e,
+ *                         sum m_e = T}               Eqs. (6)-(7)
+ *                    a = integer rounding of xq keeping sum = T
+ *     node state passed to the children = c_in + a
+ *
+ * Readings of points the paper leaves open (each is listed with its reason in
+ * the design notes of the repository):
+ *   - f_a outputs E logits; the split is softmax(z) instead of a Gaussian
+ *     sample passed through tanh. The KL projection of Eq. (7) only rescales
+ *     its input, so any positive vector proportional to the policy output
+ *     gives the same projection.
+ *   - softmax arguments z_e - max(z) are clamped below at -80, so every p_e is
+ *     positive and the capped split stays well defined.
+ *   - T = min(U*k, sum_e R_e): demand is capped by the RBs scheduled in the
+ *     TTI (Eq. (7) has no solution above that). Caps are per mini-slot.
+ *   - The integer step is largest remainder (Hamilton) rounding with ties
+ *     broken towards the lower UE index; the paper names Huntington-Hill,
+ *     which cannot place fewer units than there are positive quotas.
+ *   - Features (dim 4E+2, blocks of E): R_e/32, MCS_e/32, SINR_e/32, c_e/64,
+ *     then tau/8 and k/8. All scales are powers of two.
+ *   - BFS node order, level by level; within a level k_1 is the most
+ *     significant digit, so the children of node i of level tau-1 are nodes
+ *     (K+1)i + k of level tau.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORACLE_OK 0
+#define ORACLE_EINVAL (-1)
+#define ORACLE_ENOMEM (-2)
+
+#define ORACLE_EXACT 0
+#define ORACLE_BF16 1
+#define ORACLE_FP8_E4M3 2
+
+#define SOFTMAX_FLOOR (-80.0)
+#define MAX_UE 64
+#define MAX_WIDTH 4096
+
+typedef struct {
+    int32_t num_ue;        /* E */
+    int32_t max_arrival;   /* K */
+    int32_t num_minislots; /* M */
+    int32_t rb_per_unit;   /* U */
+} oracle_tree;
+
+typedef struct {
+    int32_t num_layers;      /* weight layers: hidden layers + output layer */
+    const int32_t* dims;     /* num_layers + 1 widths: d_in, hidden..., E */
+    const float* const* w;   /* w[l]: row-major [dims[l+1]][dims[l]] */
+    const float* const* b;   /* b[l]: [dims[l+1]] */
+    int32_t precision;       /* ORACLE_EXACT, ORACLE_BF16, ORACLE_FP8_E4M3 */
+    const double* act_scale; /* FP8: scale of each layer input (num_layers) */
+    const double* const* wq; /* optional: w[l] already rounded to `precision`
+                                (oracle_quantize_weights); NULL rounds on use */
+} oracle_actor;
+
+/* ---------------------------------------------------------------- tree size */
+
+static int64_t ipow64(int64_t base, int32_t e)
+{
+    int64_t r = 1;
+    for (int32_t i = 0; i < e; ++i)
+        r *= base;
+    return r;
+}
+
+/* First node index of level tau in BFS order: ((K+1)^tau - 1) / K. */
+int64_t oracle_level_offset(int32_t K, int32_t tau)
+{
+    return (ipow64(K + 1, tau) - 1) / K;
+}
+
+/* Nodes in levels 0..M, the root included. */
+int64_t oracle_num_nodes(int32_t K, int32_t M)
+{
+    return oracle_level_offset(K, M + 1);
+}
+
+/* ------------------------------------------------------- number formats */
+
+/* Round v to the nearest value with `bits` significant bits (ties to even),
+ * with the exponent of the quantum floored at min_exp (gradual underflow). */
+static double round_sig(double v, int bits, int min_exp)
+{
+    if (v == 0.0 || !isfinite(v))
+        return v;
+    int e;
+    frexp(fabs(v), &e);              /* |v| = f * 2^e, f in [0.5, 1) */
+    int q_exp = (e - 1) - (bits - 1); /* exponent of one unit in the last place */
+    if (q_exp < min_exp)
+        q_exp = min_exp;
+    double q = ldexp(1.0, q_exp);
+    return nearbyint(v / q) * q; /* default rounding mode: nearest, ties even */
+}
+
+/* bfloat16: 8 significant bits, exponent range of float32. */
+double oracle_round_bf16(double v)
+{
+    return round_sig(v, 8, -126 - 7);
+}
+
+/* OCP FP8 E4M3 (no infinities): 4 significant bits, smallest normal 2^-6,
+ * subnormal quantum 2^-9, largest finite 448. Out-of-range values saturate. */
+double oracle_round_e4m3(double v)
+{
+    double r = round_sig(v, 4, -9);
+    if (r > 448.0)
+        r = 448.0;
+    if (r < -448.0)
+        r = -448.0;
+    return r;
+}
+
+/* ------------------------------------------------------------- features */
+
+/* State vector of one node: s(t) per UE (RBs, MCS, SINR), the RBs punctured
+ * so far on this path, the mini-slot index and the arrival count. The paper
+ * feeds [s(t), j] (Sec. VI-B); the extra per-UE channel features and the
+ * carried state follow the tree extension. */
+void oracle_features(int32_t E, const int32_t* rb, const int32_t* mcs, const float* sinr_db,
+                     const int32_t* c, int32_t tau, int32_t k, double* x)
+{
+    for (int32_t e = 0; e < E; ++e) {
+        x[e] = rb[e] / 32.0;
+        x[E + e] = mcs[e] / 32.0;
+        x[2 * E + e] = (double)sinr_db[e] / 32.0;
+        x[3 * E + e] = c[e] / 64.0;
+    }
+    x[4 * E] = tau / 8.0;
+    x[4 * E + 1] = k / 8.0;
+}
+
+/* -------------------------------------------------------------- actor */
+
+static double quantize(double v, int32_t precision, double scale)
+{
+    if (precision == ORACLE_BF16)
+        return oracle_round_bf16(v);
+    if (precision == ORACLE_FP8_E4M3)
+        return oracle_round_e4m3(v / scale) * scale;
+    return v;
+}
+
+/* Power-of-two per-tensor scale for E4M3 weights: the smallest 2^n with
+ * max|w| / 2^n <= 448. */
+double oracle_e4m3_weight_scale(const float* w, int64_t n)
+{
+    double amax = 0.0;
+    for (int64_t i = 0; i < n; ++i)
+        if (fabs((double)w[i]) > amax)
+            amax = fabs((double)w[i]);
+    if (amax == 0.0)
+        return 1.0;
+    double s = 1.0;
+    while (amax / s > 448.0)
+        s *= 2.0;
+    while (amax / (s * 0.5) <= 448.0)
+        s *= 0.5;
+    return s;
+}
+
+/* Round a whole weight tensor to `precision`, scale included, into doubles
+ * (the values the reduced-precision forward pass multiplies with). */
+void oracle_quantize_weights(const float* w, int64_t n, int32_t precision, double* out)
+{
+    double s = (precision == ORACLE_FP8_E4M3) ? oracle_e4m3_weight_scale(w, n) : 1.0;
+    for (int64_t i = 0; i < n; ++i)
+        out[i] = quantize((double)w[i], precision, s);
+}
+
+/* Forward pass of the actor f_a: h_{l+1} = ReLU(W_l h_l + b_l) for the hidden
+ * layers and z = W_L h_L + b_L for the output (Sec. VI-B: each layer is the
+ * product with the weight matrix plus the bias, then the activation, layer
+ * after layer). The three-layer actor of the case study is num_layers = 2.
+ *
+ * With a reduced precision the layer inputs and weights are first rounded to
+ * that format (per-tensor power-of-two scales for E4M3), the products and
+ * sums stay exact in float64, and the bias is added unrounded. amax, if not
+ * NULL, receives the running maximum |input| of every layer. */
+int oracle_mlp(const oracle_actor* f, const double* x, double* z, double* amax)
+{
+    if (!f || f->num_layers < 1)
+        return ORACLE_EINVAL;
+    double* h = (double*)malloc(sizeof(double) * MAX_WIDTH);
+    double* g = (double*)malloc(sizeof(double) * MAX_WIDTH);
+    if (!h || !g) {
+        free(h);
+        free(g);
+        return ORACLE_ENOMEM;
+    }
+    int32_t n_in = f->dims[0];
+    for (int32_t i = 0; i < n_in; ++i)
+        h[i] = x[i];
+    for (int32_t l = 0; l < f->num_layers; ++l) {
+        int32_t in = f->dims[l], out = f->dims[l + 1];
+        if (in > MAX_WIDTH || out > MAX_WIDTH) {
+            free(h);
+            free(g);
+            return ORACLE_EINVAL;
+        }
+        double s_act = (f->act_scale ? f->act_scale[l] : 1.0);
+        double s_w = 1.0;
+        if (f->precision == ORACLE_FP8_E4M3 && !f->wq)
+            s_w = oracle_e4m3_weight_scale(f->w[l], (int64_t)in * out);
+        if (amax)
+            for (int32_t i = 0; i < in; ++i)
+                if (fabs(h[i]) > amax[l])
+                    amax[l] = fabs(h[i]);
+        for (int32_t i = 0; i < in; ++i)
+            h[i] = quantize(h[i], f->precision, s_act);
+        for (int32_t o = 0; o < out; ++o) {
+            double acc = 0.0;
+            if (f->wq) {
+                const double* wrow = f->wq[l] + (int64_t)o * in;
+                for (int32_t i = 0; i < in; ++i)
+                    acc += wrow[i] * h[i];
+            } else {
+                const float* wrow = f->w[l] + (int64_t)o * in;
+                for (int32_t i = 0; i < in; ++i)
+                    acc += quantize((double)wrow[i], f->precision, s_w) * h[i];
+            }
+            acc += (double)f->b[l][o];
+            g[o] = (l + 1 < f->num_layers && acc < 0.0) ? 0.0 : acc;
+        }
+        memcpy(h, g, sizeof(double) * out);
+    }
+    memcpy(z, h, sizeof(double) * f->dims[f->num_layers]);
+    free(h);
+    free(g);
+    return ORACLE_OK;
+}
+
+/* ------------------------------------------- feasibility enforcer, Sec. V-B */
+
+/* p_e = exp(z_e - max z) / sum_j exp(z_j - max z), arguments clamped at -80. */
+void oracle_softmax(int32_t E, const double* z, double* p)
+{
+    double zmax = z[0];
+    for (int32_t e = 1; e < E; ++e)
+        if (z[e] > zmax)
+            zmax = z[e];
+    double sum = 0.0;
+    for (int32_t e = 0; e < E; ++e) {
+        double d = z[e] - zmax;
+        if (d < SOFTMAX_FLOOR)
+            d = SOFTMAX_FLOOR;
+        p[e] = exp(d);
+        sum += p[e];
+    }
+    for (int32_t e = 0; e < E; ++e)
+        p[e] /= sum;
+}
+
+/* Infeasibility (i): the nearest vector in KL divergence, Eqs. (6)-(7),
+ *     min  sum_e b_e log(b_e / bhat_e)   s.t.  0 <= bhat_e <= R_e,
+ *                                              sum_e bhat_e = T,
+ * for b proportional to p. Stationarity of the Lagrangian gives
+ * bhat_e = min(R_e, s * p_e) with one multiplier s fixed by the sum: UEs whose
+ * proportional share reaches their cap are pinned to it and the rest of the
+ * demand is split in proportion to p among the others ("water-filling").
+ * The capped set only grows and s only increases, so at most E passes.
+ * Returns the final s; x receives bhat. */
+double oracle_capped_scale(int32_t E, const double* p, const int32_t* R, int64_t T, double* x)
+{
+    int capped[MAX_UE];
+    int64_t rsum = 0;
+    for (int32_t e = 0; e < E; ++e) {
+        capped[e] = 0;
+        rsum += R[e];
+    }
+    if (T <= 0) {
+        for (int32_t e = 0; e < E; ++e)
+            x[e] = 0.0;
+        return 0.0;
+    }
+    if (T >= rsum) { /* all capacity is used: bhat = R */
+        for (int32_t e = 0; e < E; ++e)
+            x[e] = R[e];
+        return INFINITY;
+    }
+    double s = 0.0;
+    for (;;) {
+        double rem = (double)T, psum = 0.0;
+        for (int32_t e = 0; e < E; ++e) {
+            if (capped[e])
+                rem -= R[e];
+            else
+                psum += p[e];
+        }
+        s = rem / psum;
+        int added = 0;
+        for (int32_t e = 0; e < E; ++e)
+            if (!capped[e] && s * p[e] >= (double)R[e]) {
+                capped[e] = 1;
+                added = 1;
+            }
+        if (!added)
+            break;
+    }
+    for (int32_t e = 0; e < E; ++e)
+        x[e] = capped[e] ? (double)R[e] : s * p[e];
+    return s;
+}
+
+/* Infeasibility (ii): integer rounding that keeps sum = T. Largest remainder:
+ * floor every share, then give one more unit to each of the r = T - sum floor
+ * UEs with the largest fractional parts among those still below their cap,
+ * ties to the lower UE index. Among integer vectors with the same sum and
+ * bounds this minimises sum (a_e - x_e)^2. */
+void oracle_largest_remainder(int32_t E, const double* x, const int32_t* R, int64_t T, int32_t* a)
+{
+    int64_t fsum = 0;
+    for (int32_t e = 0; e < E; ++e) {
+        a[e] = (int32_t)floor(x[e]);
+        fsum += a[e];
+    }
+    int64_t r = T - fsum;
+    int picked[MAX_UE];
+    for (int32_t e = 0; e < E; ++e)
+        picked[e] = 0;
+    for (int64_t n = 0; n < r; ++n) {
+        int32_t best = -1;
+        double best_frac = -1.0;
+        for (int32_t e = 0; e < E; ++e) {
+            if (picked[e] || a[e] >= R[e])
+                continue;
+            double frac = x[e] - floor(x[e]);
+            if (frac > best_frac) { /* strict: equal fractions keep the lower index */
+                best = e;
+                best_frac = frac;
+            }
+        }
+        if (best < 0)
+            break;
+        picked[best] = 1;
+        a[best] += 1;
+    }
+}
+
+/* Distance in float64 from the nearest input change that would flip a
+ * decision of the integer step: a share crossing an integer (floor), or the
+ * r-th and (r+1)-th largest eligible remainders swapping order, or a share
+ * crossing its cap. INFINITY when nothing can flip. */
+double oracle_margin(int32_t E, const double* x, const double* p, double s, const int32_t* R, int64_t T)
+{
+    int64_t rsum = 0;
+    for (int32_t e = 0; e < E; ++e)
+        rsum += R[e];
+    if (T <= 0 || T >= rsum)
+        return INFINITY;
+    double m = INFINITY;
+    double fr[MAX_UE];
+    int elig[MAX_UE];
+    int64_t fsum = 0;
+    int32_t n_elig = 0;
+    for (int32_t e = 0; e < E; ++e) {
+        double f = floor(x[e]);
+        fsum += (int64_t)f;
+        fr[e] = x[e] - f;
+        elig[e] = (f < R[e]);
+        n_elig += elig[e];
+        if (R[e] > 0) { /* cap switch */
+            double d = fabs(s * p[e] - (double)R[e]);
+            if (d < m)
+                m = d;
+        }
+        if (x[e] < (double)R[e]) { /* floor ambiguity of an uncapped share */
+            if (f >= 1.0 && fr[e] < m)
+                m = fr[e];
+            if (f + 1.0 <= (double)R[e] && 1.0 - fr[e] < m)
+                m = 1.0 - fr[e];
+        }
+    }
+    int64_t r = T - fsum;
+    if (r > 0 && r < n_elig) {
+        /* r-th and (r+1)-th largest remainders among eligible UEs */
+        double sorted[MAX_UE];
+        int32_t n = 0;
+        for (int32_t e = 0; e < E; ++e)
+            if (elig[e])
+                sorted[n++] = fr[e];
+        for (int32_t i = 1; i < n; ++i) { /* insertion sort, descending */
+            double v = sorted[i];
+            int32_t j = i - 1;
+            while (j >= 0 && sorted[j] < v) {
+                sorted[j + 1] = sorted[j];
+                --j;
+            }
+            sorted[j + 1] = v;
+        }
+        double gap = sorted[r - 1] - sorted[r];
+        if (gap < m)
+            m = gap;
+    }
+    return m;
+}
+
+/* From logits to the integer puncturing vector of one node: softmax, capped
+ * split of T = min(U*k, sum R) and largest remainder. Returns the margin. */
+double oracle_allocate(int32_t E, const double* z, const int32_t* R, int32_t U, int32_t k, int32_t* a,
+                       double* x_out)
+{
+    double p[MAX_UE], x[MAX_UE];
+    int64_t rsum = 0;
+    for (int32_t e = 0; e < E; ++e)
+        rsum += R[e];
+    int64_t demand = (int64_t)U * k;
+    int64_t T = demand < rsum ? demand : rsum;
+    oracle_softmax(E, z, p);
+    double s = oracle_capped_scale(E, p, R, T, x);
+    oracle_largest_remainder(E, x, R, T, a);
+    if (x_out)
+        for (int32_t e = 0; e < E; ++e)
+            x_out[e] = x[e];
+    return oracle_margin(E, x, p, s, R, T);
+}
+
+/* ----------------------------------------------------------- tree / Alg. 2 */
+
+static int check_inputs(const oracle_tree* t, const oracle_actor* f)
+{
+    if (!t || !f)
+        return ORACLE_EINVAL;
+    if (t->num_ue < 1 || t->num_ue > MAX_UE || t->max_arrival < 1 || t->num_minislots < 1 ||
+        t->rb_per_unit < 0)
+        return ORACLE_EINVAL;
+    if (f->dims[0] != 4 * t->num_ue + 2 || f->dims[f->num_layers] != t->num_ue)
+        return ORACLE_EINVAL;
+    return ORACLE_OK;
+}
+
+/* One evaluated node: features, actor, enforcer. */
+static int eval_node(const oracle_tree* t, const oracle_actor* f, const int32_t* rb, const int32_t* mcs,
+                     const float* sinr, const int32_t* c_in, int32_t tau, int32_t k, int32_t* a,
+                     double* z, double* margin)
+{
+    double x[4 * MAX_UE + 2];
+    oracle_features(t->num_ue, rb, mcs, sinr, c_in, tau, k, x);
+    int rc = oracle_mlp(f, x, z, NULL);
+    if (rc)
+        return rc;
+    double m = oracle_allocate(t->num_ue, z, rb, t->rb_per_unit, k, a, NULL);
+    if (margin)
+        *margin = m;
+    return ORACLE_OK;
+}
+
+/* Free-running build of the whole codebook tree (Alg. 2 for every arrival
+ * prefix). alloc: [nodes][E] bytes. logits: [nodes][E] or NULL. margin:
+ * [nodes] or NULL. The root and k = 0 nodes hold a zero allocation, zero
+ * logits and an infinite margin. */
+int oracle_build_tree(const oracle_tree* t, const oracle_actor* f, const int32_t* rb, const int32_t* mcs,
+                      const float* sinr, uint8_t* alloc, double* logits, double* margin)
+{
+    int rc = check_inputs(t, f);
+    if (rc)
+        return rc;
+    const int32_t E = t->num_ue, K = t->max_arrival;
+    const int64_t nodes = oracle_num_nodes(K, t->num_minislots);
+    int32_t* state = (int32_t*)calloc((size_t)nodes * E, sizeof(int32_t)); /* c_in + a per node */
+    if (!state)
+        return ORACLE_ENOMEM;
+    memset(alloc, 0, (size_t)nodes * E);
+    if (logits)
+        memset(logits, 0, sizeof(double) * (size_t)nodes * E);
+    if (margin)
+        margin[0] = INFINITY;
+    for (int32_t tau = 1; tau <= t->num_minislots && rc == ORACLE_OK; ++tau) {
+        const int64_t off = oracle_level_offset(K, tau), poff = oracle_level_offset(K, tau - 1);
+        const int64_t width = ipow64(K + 1, tau);
+        for (int64_t i = 0; i < width; ++i) {
+            const int64_t node = off + i, parent = poff + i / (K + 1);
+            const int32_t k = (int32_t)(i % (K + 1));
+            const int32_t* c_in = state + parent * E;
+            int32_t a[MAX_UE] = {0};
+            double z[MAX_UE] = {0}, m = INFINITY;
+            if (k > 0) {
+                rc = eval_node(t, f, rb, mcs, sinr, c_in, tau, k, a, z, &m);
+                if (rc)
+                    break;
+            }
+            for (int32_t e = 0; e < E; ++e) {
+                alloc[node * E + e] = (uint8_t)a[e];
+                state[node * E + e] = c_in[e] + a[e];
+                if (logits)
+                    logits[node * E + e] = z[e];
+            }
+            if (margin)
+                margin[node] = m;
+        }
+    }
+    free(state);
+    return rc;
+}
+
+/* Conditioned evaluation: each listed node is recomputed from the state its
+ * ancestors reach under a GIVEN codebook (for instance one produced
+ * elsewhere), so a disagreement in a parent cannot spread to its children.
+ * given: [nodes][E]. out_alloc: [n][E]. out_logits: [n][E] or NULL.
+ * out_margin: [n] or NULL. */
+int oracle_eval_conditioned(const oracle_tree* t, const oracle_actor* f, const int32_t* rb,
+                            const int32_t* mcs, const float* sinr, const uint8_t* given,
+                            const int64_t* node_ids, int64_t n, int32_t* out_alloc, double* out_logits,
+                            double* out_margin)
+{
+    int rc = check_inputs(t, f);
+    if (rc)
+        return rc;
+    const int32_t E = t->num_ue, K = t->max_arrival;
+    const int64_t nodes = oracle_num_nodes(K, t->num_minislots);
+    for (int64_t j = 0; j < n; ++j) {
+        int64_t node = node_ids[j];
+        if (node < 0 || node >= nodes)
+            return ORACLE_EINVAL;
+        int32_t tau = 0;
+        while (oracle_level_offset(K, tau + 1) <= node)
+            ++tau;
+        int32_t a[MAX_UE] = {0}, c_in[MAX_UE] = {0};
+        double z[MAX_UE] = {0}, m = INFINITY;
+        if (tau > 0) {
+            int64_t i = node - oracle_level_offset(K, tau);
+            int32_t k = (int32_t)(i % (K + 1));
+            /* walk up: c_in is the sum of the given allocations of the
+             * strict ancestors */
+            int64_t anc_i = i / (K + 1);
+            for (int32_t lev = tau - 1; lev >= 1; --lev) {
+                const uint8_t* g = given + (oracle_level_offset(K, lev) + anc_i) * E;
+                for (int32_t e = 0; e < E; ++e)
+                    c_in[e] += g[e];
+                anc_i /= (K + 1);
+            }
+            if (k > 0) {
+                rc = eval_node(t, f, rb, mcs, sinr, c_in, tau, k, a, z, &m);
+                if (rc)
+                    return rc;
+            }
+        }
+        for (int32_t e = 0; e < E; ++e) {
+            out_alloc[j * E + e] = a[e];
+            if (out_logits)
+                out_logits[j * E + e] = z[e];
+        }
+        if (out_margin)
+            out_margin[j] = m;
+    }
+    return ORACLE_OK;
+}
+
+/* Sequential roll-out of one arrival sequence k_1..k_len, as the O-RU would
+ * experience it mini-slot by mini-slot (Alg. 3): the state starts at zero and
+ * accumulates the chosen vector after every mini-slot. out: [len][E]. amax, if
+ * not NULL, collects the largest |input| seen by each actor layer. */
+int oracle_rollout(const oracle_tree* t, const oracle_actor* f, const int32_t* rb, const int32_t* mcs,
+                   const float* sinr, const int32_t* seq, int32_t len, int32_t* out, double* amax)
+{
+    int rc = check_inputs(t, f);
+    if (rc)
+        return rc;
+    const int32_t E = t->num_ue;
+    int32_t c[MAX_UE] = {0};
+    for (int32_t tau = 1; tau <= len; ++tau) {
+        int32_t k = seq[tau - 1];
+        if (k < 0 || k > t->max_arrival)
+            return ORACLE_EINVAL;
+        int32_t a[MAX_UE] = {0};
+        if (k > 0) {
+            double x[4 * MAX_UE + 2], z[MAX_UE];
+            oracle_features(E, rb, mcs, sinr, c, tau, k, x);
+            rc = oracle_mlp(f, x, z, amax);
+            if (rc)
+                return rc;
+            oracle_allocate(E, z, rb, t->rb_per_unit, k, a, NULL);
+        }
+        for (int32_t e = 0; e < E; ++e) {
+            out[(tau - 1) * E + e] = a[e];
+            c[e] += a[e];
+        }
+    }
+    return ORACLE_OK;
+}

@@ -1,0 +1,175 @@
+"""Seeded synthetic inputs for the puncturing-codebook builder.
+
+This module only draws numbers: actor weights, per-UE scheduling state and the
+named tree shapes. It holds none of the method's arithmetic, so both the HIP
+path and the FP64 oracle can consume what it produces without sharing code.
+
+Input recipe (the paper's simulator and trained actor are not available, so
+seeded draws stand in for them):
+
+* eMBB scheduling vector s(t) (Sec. III-A): per UE an RB count R_e ~ U{8..32};
+  the per-UE channel features are MCS_e ~ U{0..27} and SINR_e ~ N(15, 5) dB,
+  drawn in float64 and rounded to float32 (the value both paths consume).
+* Actor weights f_a (Sec. V-B): a ReLU MLP, Xavier-uniform weights
+  U(+-sqrt(6/(fan_in+fan_out))) and biases U(+-1/sqrt(fan_in)), drawn in
+  float64 and rounded to float32. Row-major [out][in].
+* URLLC arrival alphabet {0..K} per mini-slot, K = floor(N/L) (Sec. IV-A).
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import List, Tuple
+
+import numpy as np
+
+PRECISIONS = ("fp32", "bf16", "fp8")
+
+
+@dataclasses.dataclass(frozen=True)
+class TreeConfig:
+    """Shape of one codebook tree and its actor network.
+
+    num_ue        E, eMBB UEs per cell.
+    max_arrival   K = floor(N/L), largest URLLC arrival count per mini-slot.
+    num_minislots M, mini-slots per slot (7 in NR).
+    rb_per_unit   U, RBs one URLLC arrival punctures.
+    hidden        hidden widths of the actor MLP.
+    precision     arithmetic of the layer GEMMs: fp32, bf16 or fp8 (e4m3).
+    """
+
+    num_ue: int
+    max_arrival: int
+    num_minislots: int = 7
+    rb_per_unit: int = 2
+    hidden: Tuple[int, ...] = (256, 256)
+    precision: str = "fp32"
+
+    @property
+    def d_in(self) -> int:
+        return 4 * self.num_ue + 2
+
+    @property
+    def dims(self) -> Tuple[int, ...]:
+        return (self.d_in,) + tuple(self.hidden) + (self.num_ue,)
+
+    @property
+    def num_nodes(self) -> int:
+        k1 = self.max_arrival + 1
+        return (k1 ** (self.num_minislots + 1) - 1) // self.max_arrival
+
+    @property
+    def num_evals(self) -> int:
+        return (self.max_arrival + 1) ** self.num_minislots - 1
+
+    @property
+    def macs_per_eval(self) -> int:
+        d = self.dims
+        return sum(d[i] * d[i + 1] for i in range(len(d) - 1))
+
+    @property
+    def flops_per_codebook(self) -> int:
+        return 2 * self.macs_per_eval * self.num_evals
+
+    def with_precision(self, precision: str) -> "TreeConfig":
+        return dataclasses.replace(self, precision=precision)
+
+
+# Named workloads. The first is small enough for the oracle to finish in well
+# under a second; the second is the single-codebook latency workload.
+TINY = TreeConfig(num_ue=4, max_arrival=2, hidden=(256, 256))
+TREE_E8K3 = TreeConfig(num_ue=8, max_arrival=3, hidden=(256, 256))
+STRESS_E16K4 = TreeConfig(num_ue=16, max_arrival=4, hidden=(512, 512, 512), precision="fp8")
+# The paper's own codebook shape: depth 1, E = 10, K = floor(780/300) = 2,
+# one hidden layer of 128 neurons (Sec. VI, case-study parameters).
+PAPER_DEPTH1 = TreeConfig(num_ue=10, max_arrival=2, num_minislots=1, hidden=(128,))
+
+WORKLOADS = {
+    "tiny-e4k2": TINY,
+    "tree-e8k3": TREE_E8K3,
+    "stress-e16k4": STRESS_E16K4,
+    "paper-depth1": PAPER_DEPTH1,
+}
+
+WEIGHT_SEEDS = {"tiny-e4k2": 1, "tree-e8k3": 2, "stress-e16k4": 200000, "paper-depth1": 4}
+CALIBRATION_SEED = 3
+UE_SEED_BASE = 1_000_000
+
+
+def make_weights(cfg: TreeConfig, seed: int) -> List[Tuple[np.ndarray, np.ndarray]]:
+    """Xavier-uniform float32 weights [out][in] and uniform biases per layer."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    layers = []
+    d = cfg.dims
+    for i in range(len(d) - 1):
+        fan_in, fan_out = d[i], d[i + 1]
+        lim_w = np.sqrt(6.0 / (fan_in + fan_out))
+        lim_b = 1.0 / np.sqrt(fan_in)
+        w = rng.uniform(-lim_w, lim_w, size=(fan_out, fan_in)).astype(np.float32)
+        b = rng.uniform(-lim_b, lim_b, size=(fan_out,)).astype(np.float32)
+        layers.append((np.ascontiguousarray(w), np.ascontiguousarray(b)))
+    return layers
+
+
+@dataclasses.dataclass
+class UEState:
+    """Per-UE scheduling state of one TTI: RBs, MCS index and SINR (dB)."""
+
+    rb: np.ndarray  # int32 [E]
+    mcs: np.ndarray  # int32 [E]
+    sinr_db: np.ndarray  # float32 [E]
+
+    @property
+    def num_ue(self) -> int:
+        return int(self.rb.shape[0])
+
+
+def make_ue_state(num_ue: int, seed: int) -> UEState:
+    rng = np.random.Generator(np.random.PCG64(seed))
+    rb = rng.integers(8, 33, size=num_ue).astype(np.int32)
+    mcs = rng.integers(0, 28, size=num_ue).astype(np.int32)
+    sinr = rng.normal(15.0, 5.0, size=num_ue).astype(np.float32)
+    return UEState(rb=rb, mcs=mcs, sinr_db=sinr)
+
+
+def make_ue_state_edge(num_ue: int, seed: int, max_rb: int = 4) -> UEState:
+    """UE state with tiny RB counts (including unscheduled UEs, R_e = 0) so that
+    per-UE caps and the demand-above-capacity case are exercised."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    rb = rng.integers(0, max_rb + 1, size=num_ue).astype(np.int32)
+    mcs = rng.integers(0, 28, size=num_ue).astype(np.int32)
+    sinr = rng.normal(15.0, 5.0, size=num_ue).astype(np.float32)
+    return UEState(rb=rb, mcs=mcs, sinr_db=sinr)
+
+
+def ue_seed(i: int) -> int:
+    return UE_SEED_BASE + i
+
+
+def serving_cell_configs(num_cells: int = 64, seed: int = 424242) -> List[Tuple[TreeConfig, int]]:
+    """Per-cell shapes of the serving mix: E ~ U{4..16}, K ~ U{2,3,4}, two hidden
+    layers of 256 or 512, bf16. Returns (config, weight seed) per cell."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    cells = []
+    for j in range(num_cells):
+        e = int(rng.integers(4, 17))
+        k = int(rng.choice([2, 3, 4]))
+        h = int(rng.choice([256, 512]))
+        cells.append((TreeConfig(num_ue=e, max_arrival=k, hidden=(h, h), precision="bf16"), 100_000 + j))
+    return cells
+
+
+def poisson_arrivals(rate_per_s: float, count: int, seed: int = 424242) -> np.ndarray:
+    """Arrival times (s) of a Poisson request stream."""
+    rng = np.random.Generator(np.random.PCG64(seed + 1))
+    return np.cumsum(rng.exponential(1.0 / rate_per_s, size=count))
+
+
+def random_sequences(cfg: TreeConfig, count: int, seed: int) -> np.ndarray:
+    """Random arrival sequences k_1..k_M, each k in {0..K}."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.integers(0, cfg.max_arrival + 1, size=(count, cfg.num_minislots)).astype(np.int32)
+
+
+def sample_nodes(cfg: TreeConfig, count: int, seed: int) -> np.ndarray:
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return np.sort(rng.choice(cfg.num_nodes, size=min(count, cfg.num_nodes), replace=False)).astype(np.int64)

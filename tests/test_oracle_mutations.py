@@ -1,0 +1,92 @@
+"""The oracle's pins must catch plausible mistakes.
+
+Each case below plants one mistake in a copy of the oracle's C source (a
+dropped term, a wrong sign, index or scale, a transposed operand, a broken tie
+rule), compiles it to a temporary library and runs the pin tests against it.
+At least one pin must fail for every mutant. The mistakes live only in the
+temporary copies; the oracle itself is untouched.
+"""
+import contextlib
+import os
+
+import pytest
+
+import oracle
+from tests import test_oracle_alloc as ta
+from tests import test_oracle_mlp as tm
+from tests import test_oracle_tree as tt
+
+SRC = open(oracle._SRC).read()
+
+MUTANTS = {
+    "feature c scale": ("x[3 * E + e] = c[e] / 64.0;", "x[3 * E + e] = c[e] / 32.0;"),
+    "feature tau/k swapped": ("x[4 * E] = tau / 8.0;\n    x[4 * E + 1] = k / 8.0;",
+                              "x[4 * E] = k / 8.0;\n    x[4 * E + 1] = tau / 8.0;"),
+    "bias dropped": ("acc += (double)f->b[l][o];", "acc += 0.0;"),
+    "relu on output layer": ("g[o] = (l + 1 < f->num_layers && acc < 0.0) ? 0.0 : acc;",
+                             "g[o] = (acc < 0.0) ? 0.0 : acc;"),
+    "transposed weights": ("acc += quantize((double)wrow[i], f->precision, s_w) * h[i];",
+                           "acc += quantize((double)f->w[l][(int64_t)i * out + o], f->precision, s_w) * h[i];"),
+    "softmax sign": ("p[e] = exp(d);", "p[e] = exp(-d);"),
+    "softmax not normalised": ("p[e] /= sum;", "p[e] /= 1.0;"),
+    "capped demand not removed": ("rem -= R[e];", "rem -= 0;"),
+    "cap test reversed": ("s * p[e] >= (double)R[e]", "s * p[e] <= (double)R[e]"),
+    "demand ignores RBs per arrival": ("int64_t demand = (int64_t)U * k;", "int64_t demand = k;"),
+    "tie to higher index": ("if (frac > best_frac) {", "if (frac >= best_frac) {"),
+    "cap ignored in rounding": ("if (picked[e] || a[e] >= R[e])", "if (picked[e])"),
+    "smallest remainder first": ("double frac = x[e] - floor(x[e]);", "double frac = 1.0 - (x[e] - floor(x[e]));"),
+    "wrong parent index": ("parent = poff + i / (K + 1);", "parent = poff + i / K;"),
+    "state not carried": ("state[node * E + e] = c_in[e] + a[e];", "state[node * E + e] = a[e];"),
+    "arrival digit off by one": ("const int32_t k = (int32_t)(i % (K + 1));",
+                                 "const int32_t k = (int32_t)((i + 1) % (K + 1));"),
+    "level offset": ("return (ipow64(K + 1, tau) - 1) / K;", "return ipow64(K + 1, tau) / K;"),
+    "bf16 mantissa": ("return round_sig(v, 8, -126 - 7);", "return round_sig(v, 7, -126 - 7);"),
+    "e4m3 saturation": ("if (r > 448.0)\n        r = 448.0;", "if (r > 480.0)\n        r = 480.0;"),
+    "rollout state": ("            c[e] += a[e];", "            c[e] += 0;"),
+}
+
+PINS = [
+    ta.test_table6_rp_first_packet,
+    lambda: ta.test_hand_split_uncapped(2, 3, [2, 2, 1, 1]),
+    ta.test_hand_split_cap_and_tie,
+    ta.test_hand_demand_above_capacity,
+    ta.test_softmax_properties,
+    ta.test_capped_scale_kkt,
+    ta.test_largest_remainder_tie_goes_to_lower_index,
+    tm.test_features_layout_by_hand,
+    lambda: tm.test_mlp_matches_numpy((32, 48, 16)),
+    tm.test_relu_only_on_hidden_layers,
+    tm.test_bf16_rounding_matches_torch,
+    tm.test_e4m3_rounding_matches_torch_and_saturates,
+    tt.test_node_counts_by_enumeration,
+    lambda: tt.test_tree_equals_brute_force_rollouts(False),
+    lambda: tt.test_invariants_tiny_workload(True),
+    tt.test_depth_one_is_the_papers_codebook,
+]
+
+
+@contextlib.contextmanager
+def _swapped(lib_obj):
+    saved = oracle._lib
+    oracle._lib = lib_obj
+    try:
+        yield
+    finally:
+        oracle._lib = saved
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_mutant(name, tmp_path):
+    old, new = MUTANTS[name]
+    assert SRC.count(old) == 1, f"mutation site of '{name}' not found exactly once"
+    src = tmp_path / "mutant.c"
+    src.write_text(SRC.replace(old, new))
+    so = oracle.compile_oracle(str(tmp_path / "libmutant.so"), str(src))
+    caught = []
+    with _swapped(oracle._load(so)):
+        for pin in PINS:
+            try:
+                pin()
+            except (AssertionError, ValueError):
+                caught.append(getattr(pin, "__name__", "lambda"))
+    assert caught, f"no pin catches the planted mistake '{name}'"

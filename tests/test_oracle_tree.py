@@ -1,0 +1,160 @@
+"""Pins of the oracle's tree expansion and state carry.
+
+- Brute force: every arrival sequence of a small tree is rolled out mini-slot
+  by mini-slot (the O-RU's view, Alg. 3) and every prefix must equal the tree
+  node that the BFS index formula names.
+- Node counts against enumeration of all prefixes.
+- M = 1 is the paper's own E x floor(N/L) codebook (Sec. IV-C, Alg. 2): one
+  branch per arrival count j = 1..K evaluated from the scheduling vector
+  alone.
+- Invariants at every node (sum, caps, zero branch, monotone state).
+- With the actor's output fixed to ln R_e by its bias, every node splits in
+  proportion to R_e: the RP benchmark of Sec. VII.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2506_00167_amd import workload as wl
+
+SMALL = wl.TreeConfig(num_ue=4, max_arrival=2, hidden=(32, 32))
+
+
+def test_node_counts_by_enumeration():
+    for K in (1, 2, 3, 4):
+        for M in (1, 2, 3, 5):
+            prefixes = sum((K + 1) ** t for t in range(M + 1))
+            assert oracle.num_nodes(K, M) == prefixes
+            offs = [oracle.level_offset(K, t) for t in range(M + 2)]
+            assert offs[0] == 0 and all(offs[t + 1] - offs[t] == (K + 1) ** t for t in range(M + 1))
+
+
+def test_node_index_is_bijection():
+    K, M = 2, 4
+    seen = set()
+    for tau in range(M + 1):
+        for seq in itertools.product(range(K + 1), repeat=tau):
+            seen.add(oracle.node_index(K, seq))
+    assert seen == set(range(oracle.num_nodes(K, M)))
+
+
+@pytest.mark.parametrize("edge", [False, True])
+def test_tree_equals_brute_force_rollouts(edge):
+    cfg = SMALL
+    weights = wl.make_weights(cfg, seed=21)
+    ue = (wl.make_ue_state_edge if edge else wl.make_ue_state)(cfg.num_ue, seed=22)
+    actor = oracle.Actor(weights)
+    alloc, logits, marg = oracle.build_tree(cfg, weights, ue, actor=actor)
+    K, M = cfg.max_arrival, cfg.num_minislots
+    for seq in itertools.product(range(K + 1), repeat=M):
+        out = oracle.rollout(cfg, weights, ue, seq, actor=actor)
+        for tau in range(1, M + 1):
+            node = oracle.node_index(K, seq[:tau])
+            assert alloc[node].tolist() == out[tau - 1].tolist(), (seq, tau)
+
+
+def test_depth_one_is_the_papers_codebook():
+    cfg = wl.PAPER_DEPTH1
+    weights = wl.make_weights(cfg, seed=wl.WEIGHT_SEEDS["paper-depth1"])
+    ue = wl.make_ue_state(cfg.num_ue, seed=23)
+    alloc, logits, _ = oracle.build_tree(cfg, weights, ue)
+    assert alloc.shape == (1 + cfg.max_arrival + 1, cfg.num_ue)
+    assert not alloc[0].any() and not alloc[1].any()  # root and the j = 0 branch
+    for j in range(1, cfg.max_arrival + 1):
+        x = oracle.features(ue, np.zeros(cfg.num_ue, np.int32), tau=1, k=j)
+        z = oracle.mlp(weights, x)
+        a, _, _ = oracle.allocate(z, ue.rb, cfg.rb_per_unit, j)
+        assert alloc[1 + j].tolist() == a.tolist()
+        assert np.allclose(logits[1 + j], z, rtol=0, atol=0)
+
+
+def _check_invariants(cfg, ue, alloc):
+    K, M, U, E = cfg.max_arrival, cfg.num_minislots, cfg.rb_per_unit, cfg.num_ue
+    R = ue.rb.astype(np.int64)
+    state = np.zeros((cfg.num_nodes, E), np.int64)
+    assert not alloc[0].any()
+    for tau in range(1, M + 1):
+        off, poff = oracle.level_offset(K, tau), oracle.level_offset(K, tau - 1)
+        for i in range((K + 1) ** tau):
+            node, parent, k = off + i, poff + i // (K + 1), i % (K + 1)
+            a = alloc[node].astype(np.int64)
+            assert a.sum() == min(U * k, R.sum())
+            assert np.all(a <= R)
+            if k == 0:
+                assert not a.any()
+            state[node] = state[parent] + a
+            assert np.all(state[node] >= state[parent])
+            assert np.all(state[node] <= tau * U * K)
+
+
+@pytest.mark.parametrize("edge", [False, True])
+def test_invariants_tiny_workload(edge):
+    cfg = wl.TINY
+    weights = wl.make_weights(cfg, seed=wl.WEIGHT_SEEDS["tiny-e4k2"])
+    ue = (wl.make_ue_state_edge if edge else wl.make_ue_state)(cfg.num_ue, seed=wl.ue_seed(0))
+    alloc, _, _ = oracle.build_tree(cfg, weights, ue)
+    _check_invariants(cfg, ue, alloc)
+
+
+def test_conditioned_on_own_tree_is_identity():
+    cfg = SMALL
+    weights = wl.make_weights(cfg, seed=24)
+    ue = wl.make_ue_state(cfg.num_ue, seed=25)
+    actor = oracle.Actor(weights)
+    alloc, logits, marg = oracle.build_tree(cfg, weights, ue, actor=actor)
+    a2, l2, m2 = oracle.eval_conditioned(cfg, weights, ue, alloc, actor=actor)
+    assert np.array_equal(a2, alloc.astype(np.int32))
+    assert np.array_equal(l2, logits)
+    assert np.array_equal(m2, marg)
+
+
+def test_conditioned_uses_given_parent_state():
+    # change the allocation of one level-1 node: its children must be
+    # recomputed from the changed state, others must not move
+    cfg = SMALL
+    weights = wl.make_weights(cfg, seed=26)
+    ue = wl.make_ue_state(cfg.num_ue, seed=27)
+    alloc, _, _ = oracle.build_tree(cfg, weights, ue)
+    given = alloc.copy()
+    node = oracle.node_index(cfg.max_arrival, (2,))
+    given[node] = [4, 0, 0, 0]
+    a2, _, _ = oracle.eval_conditioned(cfg, weights, ue, given)
+    # the node itself is recomputed from the root state and is unchanged
+    assert a2[node].tolist() == alloc[node].tolist()
+    for k in range(1, cfg.max_arrival + 1):
+        child = oracle.node_index(cfg.max_arrival, (2, k))
+        ref = oracle.rollout(cfg, weights, ue, [2, k])  # own path
+        c = np.array([4, 0, 0, 0], np.int32)
+        x = oracle.features(ue, c, tau=2, k=k)
+        expect, _, _ = oracle.allocate(oracle.mlp(weights, x), ue.rb, cfg.rb_per_unit, k)
+        assert a2[child].tolist() == expect.tolist()
+        assert alloc[child].tolist() == ref[1].tolist()
+    other = oracle.node_index(cfg.max_arrival, (1, 1))
+    assert a2[other].tolist() == alloc[other].tolist()
+
+
+def test_rp_actor_splits_in_proportion():
+    # zero weights, output bias ln R: softmax gives R_e / sum R at every node
+    cfg = wl.TreeConfig(num_ue=5, max_arrival=3, num_minislots=3, hidden=(16,))
+    R = np.array([3, 9, 4, 12, 7], np.int32)
+    ue = wl.UEState(rb=R, mcs=np.zeros(5, np.int32), sinr_db=np.zeros(5, np.float32))
+    weights = [(np.zeros((16, cfg.d_in), np.float32), np.zeros(16, np.float32)),
+               (np.zeros((5, 16), np.float32), np.log(R).astype(np.float32))]
+    alloc, _, _ = oracle.build_tree(cfg, weights, ue)
+    p = R.astype(np.float64) / R.sum()
+    for k in range(1, 4):
+        T = 2 * k
+        node = oracle.node_index(3, (k,))
+        x = T * p
+        f = np.floor(x)
+        order = sorted(range(5), key=lambda e: (-(x[e] - f[e]), e))
+        expect = f.copy()
+        for e in order[: int(T - f.sum())]:
+            expect[e] += 1
+        # the bias went through float32, so compare away from ties only
+        assert alloc[node].tolist() == expect.astype(int).tolist()
+        # every node at every depth with the same k has the same split
+        for seq in itertools.product(range(4), repeat=2):
+            assert alloc[oracle.node_index(3, seq + (k,))].tolist() == alloc[node].tolist()
