@@ -1,0 +1,184 @@
+/*
+ * cyrus.h - C ABI of the MI355X puncturing-codebook builder.
+ *
+ * The builder is the real-time O-DU step of Cyrus+ (arXiv 2506.00167,
+ * Sec. IV-C "RT O-DU", Sec. V-B, Alg. 2): once per slot it evaluates the
+ * actor network f_a on every node of the tree of URLLC arrival sequences over
+ * the slot's M mini-slots (arrival counts k in {0..K}, K = floor(N/L),
+ * Sec. III-A), carries each eMBB UE's punctured-RB state down the tree, and
+ * turns every node's output into an integer per-UE puncturing vector
+ * (softmax, the KL projection of Eqs. (6)-(7), largest-remainder rounding).
+ * The O-RU then reads one row per mini-slot (Alg. 3): cyrus_codebook_lookup.
+ *
+ * Conventions for every entry point:
+ *  - Status: int, CYRUS_OK (0) or a negative CYRUS_E* code. On error nothing
+ *    is enqueued on the stream, outputs are left untouched, and
+ *    cyrus_last_error() returns a thread-local message.
+ *  - No exceptions or aborts cross this boundary.
+ *  - Host pointers are plain CPU memory; "device" pointers are HIP device
+ *    memory of the current device. Streams are hipStream_t passed as void*
+ *    (NULL = the default stream).
+ *  - The library never allocates device memory: the caller provides one
+ *    device workspace and one pinned host buffer per codebook, sized by
+ *    cyrus_codebook_workspace_size, which must outlive the handle.
+ *  - A handle is used by one host thread at a time.
+ *
+ * Node order (BFS): level tau (1..M) starts at O_tau = ((K+1)^tau - 1)/K;
+ * the node for arrival prefix (k_1..k_tau) is O_tau + sum_t k_t (K+1)^(tau-t).
+ * Node 0 is the root (start of the slot). nodes = ((K+1)^(M+1) - 1)/K.
+ */
+#ifndef CYRUS_H
+#define CYRUS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ status codes */
+#define CYRUS_OK 0
+#define CYRUS_EINVAL (-1)      /* null pointer or malformed argument */
+#define CYRUS_ERANGE (-2)      /* a size or value outside the supported range */
+#define CYRUS_EWORKSPACE (-3)  /* workspace or pinned buffer too small / misaligned */
+#define CYRUS_EDEVICE (-4)     /* a HIP runtime call failed */
+#define CYRUS_ENOTREADY (-5)   /* lookup/export before any build */
+#define CYRUS_EUNSUPPORTED (-6)/* shape/precision combination not provided */
+
+/* ------------------------------------------------------------ precisions */
+#define CYRUS_FP32 0     /* layer GEMMs in FP32 on MFMA */
+#define CYRUS_BF16 1     /* BF16 operands, FP32 accumulation */
+#define CYRUS_FP8_E4M3 2 /* OCP E4M3 operands, power-of-two per-tensor scales,
+                            FP32 accumulation */
+
+/* ------------------------------------------------------------ flags */
+#define CYRUS_FLAG_EXPORT_LOGITS 1u      /* keep the FP32 logits of every node */
+#define CYRUS_FLAG_LEVEL_KERNEL 2u       /* force the one-launch-per-level path */
+
+#define CYRUS_MAX_HIDDEN 4
+#define CYRUS_MAX_LAYERS (CYRUS_MAX_HIDDEN + 1)
+#define CYRUS_MAX_UE 32
+
+/* Tree and actor shape.
+ *   num_ue        E in [1, 32]: eMBB UEs of the cell (Sec. III-A).
+ *   max_arrival   K in [1, 7]: floor(N/L), the largest number of URLLC
+ *                 packets punctured in one mini-slot (Sec. III-A).
+ *   num_minislots M in [1, 7]: mini-slots per slot (7 in NR, Sec. III-A).
+ *   rb_per_unit   U >= 1: RBs one URLLC packet needs (L in RB units).
+ *                 M*K*U must not exceed 255 (the carried state is 8-bit).
+ *   num_hidden    hidden layers of f_a, in [1, 4]; hidden[i] their widths,
+ *                 each a multiple of 128 and at most 512.
+ *   precision     CYRUS_FP32, CYRUS_BF16 or CYRUS_FP8_E4M3.
+ *   flags         CYRUS_FLAG_*.
+ * The actor's input width is 4E+2 and its output width is E. */
+typedef struct {
+    int32_t num_ue;
+    int32_t max_arrival;
+    int32_t num_minislots;
+    int32_t rb_per_unit;
+    int32_t num_hidden;
+    int32_t hidden[CYRUS_MAX_HIDDEN];
+    int32_t precision;
+    uint32_t flags;
+} cyrus_config;
+
+/* Actor parameters f_a in canonical FP32, host memory, read during the call.
+ *   w[l]  row-major [out_l][in_l] (in_0 = 4E+2, out_last = E)
+ *   b[l]  [out_l]
+ *   act_scale  FP8 only: num_hidden+1 positive powers of two, the scale of each
+ *              layer's input (input / scale is rounded to E4M3); NULL otherwise.
+ * Weight scales for FP8 are derived by the library (smallest power of two that
+ * keeps max|w|/scale <= 448). */
+typedef struct {
+    const float* w[CYRUS_MAX_LAYERS];
+    const float* b[CYRUS_MAX_LAYERS];
+    const float* act_scale;
+} cyrus_weights;
+
+/* Per-UE scheduling state of one TTI, host arrays of E entries (Sec. III-A:
+ * the eMBB scheduling vector s(t), here in RBs, plus channel features).
+ *   rb       RBs scheduled to UE e in this TTI, in [0, 255] (0 = unscheduled)
+ *   mcs      MCS index
+ *   sinr_db  SINR in dB */
+typedef struct {
+    const int32_t* rb;
+    const int32_t* mcs;
+    const float* sinr_db;
+} cyrus_ue_state;
+
+typedef struct cyrus_codebook cyrus_codebook;
+
+/* Sizes of the two caller-owned buffers for `cfg`: device workspace (align 256)
+ * and pinned host buffer (align 64). */
+int cyrus_codebook_workspace_size(const cyrus_config* cfg, size_t* device_bytes, size_t* host_bytes);
+
+/* Create a builder bound to the current device. Copies (and for BF16/FP8
+ * rounds) the weights into the workspace; blocks until that copy is done.
+ * device_ws / host_pinned: caller-owned, at least the sizes above; host_pinned
+ * must be page-locked memory. *out receives the handle. */
+int cyrus_codebook_create(const cyrus_config* cfg, const cyrus_weights* w, void* device_ws, size_t ws_bytes,
+                          void* host_pinned, size_t host_bytes, void* stream, cyrus_codebook** out);
+
+/* Policy refresh from the Near-RT RIC (Alg. 1 pushes the updated f_a to the
+ * O-DU): loads new weights into the idle half of a double buffer on `stream`,
+ * waits for the copy, then makes them current. Builds enqueued before the call
+ * keep the old weights. */
+int cyrus_codebook_set_weights(cyrus_codebook* cb, const cyrus_weights* w, void* stream);
+
+/* Alg. 2 for one TTI: s(t) in, codebook B*(t) out. Asynchronous on `stream`:
+ * host UE arrays are copied into the pinned buffer before returning, then
+ * host-to-device copy, kernels and device-to-host copy of the codebook (and the
+ * logits if exported) into the pinned buffer are enqueued and an event is
+ * recorded. */
+int cyrus_codebook_build(cyrus_codebook* cb, const cyrus_ue_state* ue, void* stream);
+
+/* Device-resident variant: the UE state is already in device memory as
+ * int32 rb[E], int32 mcs[E], float sinr_db[E] (contiguous, 4-byte aligned) and
+ * the codebook stays in the device workspace (cyrus_codebook_device_alloc);
+ * nothing is copied to the host. Records the same event. */
+int cyrus_codebook_build_device(cyrus_codebook* cb, const void* ue_device, void* stream);
+
+/* Build n codebooks in shared launches on one stream (cells batched per
+ * launch). All handles must share a precision. ue_device: n pointers to
+ * device UE states laid out as for cyrus_codebook_build_device. Results stay
+ * on the device; each handle's event is recorded after the last launch. */
+int cyrus_codebook_build_batch(cyrus_codebook* const* cbs, const void* const* ue_device, int32_t n,
+                               void* stream);
+
+/* Block until the last build of this handle has finished. */
+int cyrus_codebook_wait(cyrus_codebook* cb);
+
+/* Alg. 3, one mini-slot: the puncturing vector (E bytes, RBs per UE) for
+ * mini-slot tau in [1, M] after arrivals k_1..k_tau (arrivals[0..tau-1], each
+ * in [0, K], already capped by the O-RU controller). Waits for the last host
+ * build once, then reads the pinned mirror. */
+int cyrus_codebook_lookup(cyrus_codebook* cb, const uint8_t* arrivals, int32_t tau, uint8_t* alloc_out);
+
+/* Copy the whole codebook to host memory: alloc [nodes][E] bytes; logits
+ * [nodes][E] FP32 or NULL (needs CYRUS_FLAG_EXPORT_LOGITS). Waits for the
+ * last build; after a device build it copies from the workspace. */
+int cyrus_codebook_export(cyrus_codebook* cb, uint8_t* alloc, float* logits);
+
+/* Device address of the codebook array [nodes][E] inside the workspace. */
+const uint8_t* cyrus_codebook_device_alloc(const cyrus_codebook* cb);
+
+/* Number of tree nodes (root included); -1 for a NULL handle. */
+int64_t cyrus_codebook_num_nodes(const cyrus_codebook* cb);
+
+/* Which kernel family builds this codebook: "subtree" (one launch, one
+ * workgroup per subtree, actor weights held in registers) or "level" (one
+ * launch per mini-slot level). */
+const char* cyrus_codebook_kernel_path(const cyrus_codebook* cb);
+
+/* Release the handle (not the caller-owned buffers). Waits for pending work. */
+void cyrus_codebook_destroy(cyrus_codebook* cb);
+
+const char* cyrus_status_string(int status);
+const char* cyrus_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CYRUS_H */

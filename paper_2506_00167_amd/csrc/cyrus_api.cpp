@@ -1,0 +1,563 @@
+// Host side of the C ABI declared in include/cyrus.h: validation, workspace
+// carving, weight packing, build orchestration on HIP streams, lookup.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "cyrus.h"
+#include "cyrus_internal.h"
+#include "cyrus_kernels.h"
+#include "cyrus_host.h"
+
+using namespace cyrus;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int status, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return status;
+}
+
+#define HIP_TRY(call)                                                                                                  \
+    do {                                                                                                               \
+        hipError_t e_ = (call);                                                                                        \
+        if (e_ != hipSuccess)                                                                                          \
+            return fail(CYRUS_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));                                 \
+    } while (0)
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+bool is_pow2_float(float v)
+{
+    if (!(v > 0.f) || !std::isfinite(v))
+        return false;
+    int e;
+    return std::frexp(v, &e) == 0.5f;
+}
+
+}  // namespace
+
+namespace cyrus {
+
+int validate_config(const cyrus_config* cfg)
+{
+    if (!cfg)
+        return fail(CYRUS_EINVAL, "config is NULL");
+    if (cfg->num_ue < 1 || cfg->num_ue > CYRUS_MAX_UE)
+        return fail(CYRUS_ERANGE, "num_ue %d outside [1, %d]", cfg->num_ue, CYRUS_MAX_UE);
+    if (cfg->max_arrival < 1 || cfg->max_arrival > 7)
+        return fail(CYRUS_ERANGE, "max_arrival %d outside [1, 7]", cfg->max_arrival);
+    if (cfg->num_minislots < 1 || cfg->num_minislots > 7)
+        return fail(CYRUS_ERANGE, "num_minislots %d outside [1, 7]", cfg->num_minislots);
+    if (cfg->rb_per_unit < 1)
+        return fail(CYRUS_ERANGE, "rb_per_unit %d < 1", cfg->rb_per_unit);
+    if ((int64_t)cfg->num_minislots * cfg->max_arrival * cfg->rb_per_unit > 255)
+        return fail(CYRUS_ERANGE, "M*K*U = %d exceeds the 8-bit state range",
+                    cfg->num_minislots * cfg->max_arrival * cfg->rb_per_unit);
+    if (cfg->num_hidden < 1 || cfg->num_hidden > CYRUS_MAX_HIDDEN)
+        return fail(CYRUS_ERANGE, "num_hidden %d outside [1, %d]", cfg->num_hidden, CYRUS_MAX_HIDDEN);
+    for (int i = 0; i < cfg->num_hidden; ++i)
+        if (cfg->hidden[i] < 128 || cfg->hidden[i] > 512 || cfg->hidden[i] % 128 != 0)
+            return fail(CYRUS_ERANGE, "hidden[%d] = %d is not a multiple of 128 in [128, 512]", i, cfg->hidden[i]);
+    if (cfg->precision != CYRUS_FP32 && cfg->precision != CYRUS_BF16 && cfg->precision != CYRUS_FP8_E4M3)
+        return fail(CYRUS_EINVAL, "unknown precision %d", cfg->precision);
+    if (cfg->flags & ~(CYRUS_FLAG_EXPORT_LOGITS | CYRUS_FLAG_LEVEL_KERNEL))
+        return fail(CYRUS_EINVAL, "unknown flags 0x%x", cfg->flags);
+    return CYRUS_OK;
+}
+
+Shape make_shape(const cyrus_config* cfg)
+{
+    Shape s{};
+    s.E = cfg->num_ue;
+    s.K = cfg->max_arrival;
+    s.M = cfg->num_minislots;
+    s.prec = cfg->precision;
+    s.n_layers = cfg->num_hidden + 1;
+    s.dims[0] = 4 * s.E + 2;
+    for (int i = 0; i < cfg->num_hidden; ++i)
+        s.dims[i + 1] = cfg->hidden[i];
+    s.dims[s.n_layers] = s.E;
+    const int kc = prec_chunk(s.prec);
+    s.w_bytes = 0;
+    s.staging_floats = 0;
+    for (int l = 0; l < s.n_layers; ++l) {
+        s.in_pad[l] = (int)align_up(s.dims[l], kc);
+        s.out_pad[l] = (int)align_up(s.dims[l + 1], 16);
+        s.w_off[l] = s.w_bytes;
+        s.w_bytes += align_up((size_t)s.in_pad[l] * s.out_pad[l] * prec_esize(s.prec), 256);
+        s.staging_floats = std::max(s.staging_floats, (size_t)s.in_pad[l] * s.out_pad[l]);
+    }
+    for (int l = 0; l < s.n_layers; ++l) {
+        s.b_off[l] = s.w_bytes;
+        s.w_bytes += align_up((size_t)s.out_pad[l] * 4, 256);
+    }
+    s.nodes = (ipow(s.K + 1, s.M + 1) - 1) / s.K;
+    s.export_logits = (cfg->flags & CYRUS_FLAG_EXPORT_LOGITS) != 0;
+
+    size_t off = 0;
+    s.off_w[0] = off;
+    off += align_up(s.w_bytes, 256);
+    s.off_w[1] = off;
+    off += align_up(s.w_bytes, 256);
+    s.off_staging = off;
+    off += align_up(s.staging_floats * 4, 256);
+    s.off_ue = off;
+    off += align_up(3 * kMaxUE * 4, 256);
+    s.off_alloc = off;
+    off += align_up((size_t)s.nodes * s.E, 256);
+    s.off_state = off;
+    off += align_up((size_t)s.nodes * s.E, 256);
+    s.off_logits = off;
+    if (s.export_logits)
+        off += align_up((size_t)s.nodes * s.E * 4, 256);
+    s.off_batch = off;
+    off += align_up(batch_area_bytes(), 256);
+    s.device_bytes = off;
+
+    size_t h = 0;
+    s.hoff_ue = h;
+    h += align_up(3 * kMaxUE * 4, 64);
+    s.hoff_alloc = h;
+    h += align_up((size_t)s.nodes * s.E, 64);
+    s.hoff_logits = h;
+    if (s.export_logits)
+        h += align_up((size_t)s.nodes * s.E * 4, 64);
+    s.hoff_batch = h;
+    h += align_up(batch_area_bytes(), 64);
+    s.host_bytes = h;
+    return s;
+}
+
+size_t batch_area_bytes() { return align_up(sizeof(DevTree) * kMaxBatch, 256) + (size_t)7 * (3 * kMaxBatch + 1) * 4; }
+
+void pack_fragments(const float* w, int out, int in, int out_pad, int in_pad, int prec, float* dst)
+{
+    const int kc = prec_chunk(prec), per = kc / 4, nch = in_pad / kc, ntiles = out_pad / 16;
+    for (int nt = 0; nt < ntiles; ++nt)
+        for (int ch = 0; ch < nch; ++ch)
+            for (int lane = 0; lane < 64; ++lane) {
+                const int n = nt * 16 + (lane & 15);
+                for (int j = 0; j < per; ++j) {
+                    const int k = ch * kc + (lane >> 4) * per + j;
+                    dst[(((size_t)nt * nch + ch) * 64 + lane) * per + j] =
+                        (n < out && k < in) ? w[(size_t)n * in + k] : 0.f;
+                }
+            }
+}
+
+float e4m3_weight_scale(const float* w, size_t n)
+{
+    float amax = 0.f;
+    for (size_t i = 0; i < n; ++i)
+        amax = std::max(amax, std::fabs(w[i]));
+    if (amax == 0.f)
+        return 1.f;
+    float s = 1.f;
+    while (amax / s > 448.f)
+        s *= 2.f;
+    while (amax / (s * 0.5f) <= 448.f)
+        s *= 0.5f;
+    return s;
+}
+
+int choose_rtt(const DevTree& t, int prec, int max_rtt)
+{
+    for (int r = max_rtt; r >= 1; r /= 2) {
+        if (prec == kFP32 && r > 4)
+            continue;
+        if (level_lds_bytes(t, prec, r) <= 160 * 1024)
+            return r;
+    }
+    return 0;
+}
+
+}  // namespace cyrus
+
+
+namespace cyrus {
+
+DevTree make_devtree(const cyrus_codebook* cb, const int32_t* ue_dev)
+{
+    const Shape& s = cb->s;
+    DevTree t{};
+    t.E = s.E;
+    t.K = s.K;
+    t.M = s.M;
+    t.U = cb->cfg.rb_per_unit;
+    t.n_layers = s.n_layers;
+    t.in_dim0 = s.dims[0];
+    const uint8_t* wb = cb->ws + s.off_w[cb->active];
+    for (int l = 0; l < s.n_layers; ++l) {
+        t.in_pad[l] = s.in_pad[l];
+        t.out_pad[l] = s.out_pad[l];
+        t.w[l] = wb + s.w_off[l];
+        t.b[l] = reinterpret_cast<const float*>(wb + s.b_off[l]);
+        t.deq[l] = cb->deq[l];
+        t.inv_in_scale[l] = cb->inv_in[l];
+    }
+    t.ue = ue_dev;
+    t.alloc = cb->ws + s.off_alloc;
+    t.state = cb->ws + s.off_state;
+    t.logits = s.export_logits ? reinterpret_cast<float*>(cb->ws + s.off_logits) : nullptr;
+    return t;
+}
+
+int codebook_path(const cyrus_codebook* cb) { return cb->path; }
+int codebook_rtt(const cyrus_codebook* cb) { return cb->rtt; }
+const Shape& codebook_shape(const cyrus_codebook* cb) { return cb->s; }
+
+}  // namespace cyrus
+
+static int load_weights(cyrus_codebook* cb, const cyrus_weights* w, hipStream_t stream, int target)
+{
+    const Shape& s = cb->s;
+    if (!w)
+        return fail(CYRUS_EINVAL, "weights are NULL");
+    for (int l = 0; l < s.n_layers; ++l)
+        if (!w->w[l] || !w->b[l])
+            return fail(CYRUS_EINVAL, "weights or bias of layer %d is NULL", l);
+    float a_scale[kMaxLayers], w_scale[kMaxLayers];
+    for (int l = 0; l < s.n_layers; ++l) {
+        a_scale[l] = 1.f;
+        w_scale[l] = 1.f;
+    }
+    if (s.prec == CYRUS_FP8_E4M3) {
+        if (!w->act_scale)
+            return fail(CYRUS_EINVAL, "FP8 needs act_scale (one power of two per layer input)");
+        for (int l = 0; l < s.n_layers; ++l) {
+            if (!is_pow2_float(w->act_scale[l]))
+                return fail(CYRUS_ERANGE, "act_scale[%d] = %g is not a positive power of two", l,
+                            (double)w->act_scale[l]);
+            a_scale[l] = w->act_scale[l];
+            w_scale[l] = e4m3_weight_scale(w->w[l], (size_t)s.dims[l] * s.dims[l + 1]);
+        }
+    }
+    for (int l = 0; l < s.n_layers; ++l)
+        for (size_t i = 0; i < (size_t)s.dims[l] * s.dims[l + 1]; ++i)
+            if (!std::isfinite(w->w[l][i]))
+                return fail(CYRUS_EINVAL, "weight %zu of layer %d is not finite", i, l);
+
+    uint8_t* wb = cb->ws + s.off_w[target];
+    float* staging = reinterpret_cast<float*>(cb->ws + s.off_staging);
+    cb->pack.assign(s.staging_floats, 0.f);
+    std::vector<float> bias;
+    for (int l = 0; l < s.n_layers; ++l) {
+        const size_t n = (size_t)s.in_pad[l] * s.out_pad[l];
+        pack_fragments(w->w[l], s.dims[l + 1], s.dims[l], s.out_pad[l], s.in_pad[l], s.prec, cb->pack.data());
+        HIP_TRY(hipMemcpyAsync(staging, cb->pack.data(), n * 4, hipMemcpyHostToDevice, stream));
+        HIP_TRY(launch_convert_weights(s.prec, staging, wb + s.w_off[l], (int64_t)n, 1.f / w_scale[l], stream));
+        bias.assign(s.out_pad[l], 0.f);
+        std::memcpy(bias.data(), w->b[l], sizeof(float) * s.dims[l + 1]);
+        HIP_TRY(hipMemcpyAsync(wb + s.b_off[l], bias.data(), bias.size() * 4, hipMemcpyHostToDevice, stream));
+        // the host staging vectors are reused by the next layer
+        HIP_TRY(hipStreamSynchronize(stream));
+    }
+    for (int l = 0; l < s.n_layers; ++l) {
+        cb->deq[l] = w_scale[l] * a_scale[l];
+        cb->inv_in[l] = 1.f / a_scale[l];
+    }
+    cb->active = target;
+    return CYRUS_OK;
+}
+
+static int enqueue_kernels(cyrus_codebook* cb, const int32_t* ue_dev, hipStream_t stream)
+{
+    const DevTree t = make_devtree(cb, ue_dev);
+    if (cb->path == 1)
+        HIP_TRY(launch_subtree(t, cb->s.prec, stream));
+    else
+        for (int tau = 1; tau <= cb->s.M; ++tau)
+            HIP_TRY(launch_level(t, cb->s.prec, cb->rtt, tau, stream));
+    return CYRUS_OK;
+}
+
+extern "C" {
+
+int cyrus_codebook_workspace_size(const cyrus_config* cfg, size_t* device_bytes, size_t* host_bytes)
+{
+    int rc = validate_config(cfg);
+    if (rc)
+        return rc;
+    if (!device_bytes || !host_bytes)
+        return fail(CYRUS_EINVAL, "output pointers are NULL");
+    const Shape s = make_shape(cfg);
+    *device_bytes = s.device_bytes;
+    *host_bytes = s.host_bytes;
+    return CYRUS_OK;
+}
+
+int cyrus_codebook_create(const cyrus_config* cfg, const cyrus_weights* w, void* device_ws, size_t ws_bytes,
+                          void* host_pinned, size_t host_bytes, void* stream, cyrus_codebook** out)
+{
+    int rc = validate_config(cfg);
+    if (rc)
+        return rc;
+    if (!out || !device_ws || !host_pinned)
+        return fail(CYRUS_EINVAL, "out, device_ws or host_pinned is NULL");
+    const Shape s = make_shape(cfg);
+    if (ws_bytes < s.device_bytes || host_bytes < s.host_bytes)
+        return fail(CYRUS_EWORKSPACE, "workspace %zu/%zu bytes, need %zu/%zu", ws_bytes, host_bytes, s.device_bytes,
+                    s.host_bytes);
+    if (reinterpret_cast<uintptr_t>(device_ws) % 256 || reinterpret_cast<uintptr_t>(host_pinned) % 64)
+        return fail(CYRUS_EWORKSPACE, "workspace must be 256-byte aligned and the host buffer 64-byte aligned");
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, device_ws) != hipSuccess || attr.type != hipMemoryTypeDevice) {
+        (void)hipGetLastError();
+        return fail(CYRUS_EWORKSPACE, "device_ws is not device memory");
+    }
+    if (hipPointerGetAttributes(&attr, host_pinned) != hipSuccess || attr.type != hipMemoryTypeHost) {
+        (void)hipGetLastError();
+        return fail(CYRUS_EWORKSPACE, "host_pinned is not page-locked host memory");
+    }
+    cyrus_codebook* cb = new (std::nothrow) cyrus_codebook();
+    if (!cb)
+        return fail(CYRUS_EINVAL, "out of host memory");
+    cb->cfg = *cfg;
+    cb->s = s;
+    cb->ws = static_cast<uint8_t*>(device_ws);
+    cb->host = static_cast<uint8_t*>(host_pinned);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    auto cleanup = [&](int status) {
+        if (cb->ev_staged)
+            (void)hipEventDestroy(cb->ev_staged);
+        if (cb->ev_done)
+            (void)hipEventDestroy(cb->ev_done);
+        delete cb;
+        return status;
+    };
+    if (hipGetDevice(&cb->device) != hipSuccess || hipEventCreateWithFlags(&cb->ev_staged, hipEventDisableTiming) ||
+        hipEventCreateWithFlags(&cb->ev_done, hipEventDisableTiming))
+        return cleanup(fail(CYRUS_EDEVICE, "event creation failed"));
+    // root row: punctures nothing, state zero
+    if (hipMemsetAsync(cb->ws + s.off_alloc, 0, s.E, st) != hipSuccess ||
+        hipMemsetAsync(cb->ws + s.off_state, 0, s.E, st) != hipSuccess ||
+        (s.export_logits && hipMemsetAsync(cb->ws + s.off_logits, 0, (size_t)s.E * 4, st) != hipSuccess))
+        return cleanup(fail(CYRUS_EDEVICE, "workspace clear failed"));
+    rc = load_weights(cb, w, st, 0);
+    if (rc)
+        return cleanup(rc);
+    const DevTree t = make_devtree(cb, nullptr);
+    cb->path = (!(cfg->flags & CYRUS_FLAG_LEVEL_KERNEL) && subtree_supported(t, s.prec)) ? 1 : 0;
+    cb->rtt = choose_rtt(t, s.prec, 4);
+    if (cb->rtt == 0)
+        return cleanup(fail(CYRUS_EUNSUPPORTED, "shape does not fit the level kernel's LDS"));
+    *out = cb;
+    return CYRUS_OK;
+}
+
+int cyrus_codebook_set_weights(cyrus_codebook* cb, const cyrus_weights* w, void* stream)
+{
+    if (!cb)
+        return fail(CYRUS_EINVAL, "handle is NULL");
+    HIP_TRY(hipSetDevice(cb->device));
+    return load_weights(cb, w, static_cast<hipStream_t>(stream), 1 - cb->active);
+}
+
+static int stage_ue(cyrus_codebook* cb, const cyrus_ue_state* ue)
+{
+    const int E = cb->s.E;
+    if (!ue || !ue->rb || !ue->mcs || !ue->sinr_db)
+        return fail(CYRUS_EINVAL, "UE state or one of its arrays is NULL");
+    for (int e = 0; e < E; ++e) {
+        if (ue->rb[e] < 0 || ue->rb[e] > 255)
+            return fail(CYRUS_ERANGE, "rb[%d] = %d outside [0, 255]", e, ue->rb[e]);
+        if (!std::isfinite(ue->sinr_db[e]))
+            return fail(CYRUS_EINVAL, "sinr_db[%d] is not finite", e);
+    }
+    if (cb->staged_recorded)
+        HIP_TRY(hipEventSynchronize(cb->ev_staged));
+    int32_t* st = reinterpret_cast<int32_t*>(cb->host + cb->s.hoff_ue);
+    for (int e = 0; e < E; ++e) {
+        st[e] = ue->rb[e];
+        st[E + e] = ue->mcs[e];
+        std::memcpy(&st[2 * E + e], &ue->sinr_db[e], 4);
+    }
+    return CYRUS_OK;
+}
+
+int cyrus_codebook_build(cyrus_codebook* cb, const cyrus_ue_state* ue, void* stream)
+{
+    if (!cb)
+        return fail(CYRUS_EINVAL, "handle is NULL");
+    HIP_TRY(hipSetDevice(cb->device));
+    int rc = stage_ue(cb, ue);
+    if (rc)
+        return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const Shape& s = cb->s;
+    int32_t* ue_dev = reinterpret_cast<int32_t*>(cb->ws + s.off_ue);
+    HIP_TRY(hipMemcpyAsync(ue_dev, cb->host + s.hoff_ue, (size_t)3 * s.E * 4, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipEventRecord(cb->ev_staged, st));
+    cb->staged_recorded = true;
+    rc = enqueue_kernels(cb, ue_dev, st);
+    if (rc)
+        return rc;
+    HIP_TRY(hipMemcpyAsync(cb->host + s.hoff_alloc, cb->ws + s.off_alloc, (size_t)s.nodes * s.E,
+                           hipMemcpyDeviceToHost, st));
+    if (s.export_logits)
+        HIP_TRY(hipMemcpyAsync(cb->host + s.hoff_logits, cb->ws + s.off_logits, (size_t)s.nodes * s.E * 4,
+                               hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipEventRecord(cb->ev_done, st));
+    cb->built = cb->pending = cb->mirror_valid = true;
+    return CYRUS_OK;
+}
+
+int cyrus_codebook_build_device(cyrus_codebook* cb, const void* ue_device, void* stream)
+{
+    if (!cb || !ue_device)
+        return fail(CYRUS_EINVAL, "handle or UE pointer is NULL");
+    if (reinterpret_cast<uintptr_t>(ue_device) % 4)
+        return fail(CYRUS_EINVAL, "UE state must be 4-byte aligned");
+    HIP_TRY(hipSetDevice(cb->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    int rc = enqueue_kernels(cb, static_cast<const int32_t*>(ue_device), st);
+    if (rc)
+        return rc;
+    HIP_TRY(hipEventRecord(cb->ev_done, st));
+    cb->built = cb->pending = true;
+    cb->mirror_valid = false;
+    return CYRUS_OK;
+}
+
+int cyrus_codebook_wait(cyrus_codebook* cb)
+{
+    if (!cb)
+        return fail(CYRUS_EINVAL, "handle is NULL");
+    if (cb->pending) {
+        HIP_TRY(hipEventSynchronize(cb->ev_done));
+        cb->pending = false;
+    }
+    return CYRUS_OK;
+}
+
+static int sync_mirror(cyrus_codebook* cb)
+{
+    if (!cb->built)
+        return fail(CYRUS_ENOTREADY, "no build has been enqueued on this handle");
+    int rc = cyrus_codebook_wait(cb);
+    if (rc)
+        return rc;
+    if (!cb->mirror_valid) {
+        const Shape& s = cb->s;
+        HIP_TRY(hipSetDevice(cb->device));
+        HIP_TRY(hipMemcpy(cb->host + s.hoff_alloc, cb->ws + s.off_alloc, (size_t)s.nodes * s.E,
+                          hipMemcpyDeviceToHost));
+        if (s.export_logits)
+            HIP_TRY(hipMemcpy(cb->host + s.hoff_logits, cb->ws + s.off_logits, (size_t)s.nodes * s.E * 4,
+                              hipMemcpyDeviceToHost));
+        cb->mirror_valid = true;
+    }
+    return CYRUS_OK;
+}
+
+int cyrus_codebook_lookup(cyrus_codebook* cb, const uint8_t* arrivals, int32_t tau, uint8_t* alloc_out)
+{
+    if (!cb || !alloc_out || (tau > 0 && !arrivals))
+        return fail(CYRUS_EINVAL, "NULL argument");
+    const Shape& s = cb->s;
+    if (tau < 1 || tau > s.M)
+        return fail(CYRUS_ERANGE, "tau %d outside [1, %d]", tau, s.M);
+    int64_t idx = 0;
+    for (int i = 0; i < tau; ++i) {
+        if (arrivals[i] > s.K)
+            return fail(CYRUS_ERANGE, "arrivals[%d] = %d exceeds K = %d", i, arrivals[i], s.K);
+        idx = idx * (s.K + 1) + arrivals[i];
+    }
+    int rc = sync_mirror(cb);
+    if (rc)
+        return rc;
+    const int64_t node = (ipow(s.K + 1, tau) - 1) / s.K + idx;
+    std::memcpy(alloc_out, cb->host + s.hoff_alloc + node * s.E, s.E);
+    return CYRUS_OK;
+}
+
+int cyrus_codebook_export(cyrus_codebook* cb, uint8_t* alloc, float* logits)
+{
+    if (!cb || !alloc)
+        return fail(CYRUS_EINVAL, "NULL argument");
+    const Shape& s = cb->s;
+    if (logits && !s.export_logits)
+        return fail(CYRUS_EINVAL, "logits requested but CYRUS_FLAG_EXPORT_LOGITS is not set");
+    int rc = sync_mirror(cb);
+    if (rc)
+        return rc;
+    std::memcpy(alloc, cb->host + s.hoff_alloc, (size_t)s.nodes * s.E);
+    if (logits)
+        std::memcpy(logits, cb->host + s.hoff_logits, (size_t)s.nodes * s.E * 4);
+    return CYRUS_OK;
+}
+
+const uint8_t* cyrus_codebook_device_alloc(const cyrus_codebook* cb)
+{
+    return cb ? cb->ws + cb->s.off_alloc : nullptr;
+}
+
+int64_t cyrus_codebook_num_nodes(const cyrus_codebook* cb) { return cb ? cb->s.nodes : -1; }
+
+const char* cyrus_codebook_kernel_path(const cyrus_codebook* cb)
+{
+    if (!cb)
+        return "none";
+    return cb->path == 1 ? "subtree" : "level";
+}
+
+void cyrus_codebook_destroy(cyrus_codebook* cb)
+{
+    if (!cb)
+        return;
+    (void)hipSetDevice(cb->device);
+    if (cb->pending)
+        (void)hipEventSynchronize(cb->ev_done);
+    if (cb->staged_recorded)
+        (void)hipEventSynchronize(cb->ev_staged);
+    (void)hipEventDestroy(cb->ev_staged);
+    (void)hipEventDestroy(cb->ev_done);
+    delete cb;
+}
+
+const char* cyrus_status_string(int status)
+{
+    switch (status) {
+    case CYRUS_OK:
+        return "ok";
+    case CYRUS_EINVAL:
+        return "invalid argument";
+    case CYRUS_ERANGE:
+        return "value out of range";
+    case CYRUS_EWORKSPACE:
+        return "workspace too small or misplaced";
+    case CYRUS_EDEVICE:
+        return "HIP runtime error";
+    case CYRUS_ENOTREADY:
+        return "no build yet";
+    case CYRUS_EUNSUPPORTED:
+        return "unsupported shape";
+    default:
+        return "unknown status";
+    }
+}
+
+const char* cyrus_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"
+
+// Shared with the batch builder.
+namespace cyrus {
+int set_error(int status, const char* msg) { return fail(status, "%s", msg); }
+}  // namespace cyrus

@@ -1,0 +1,153 @@
+// Several cells' codebooks built in shared launches: one batched level launch
+// per mini-slot level covers the evaluated nodes of every codebook at that
+// level, so small trees of many cells fill the GPU together.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+
+#include "cyrus.h"
+#include "cyrus_host.h"
+#include "cyrus_kernels.h"
+
+using namespace cyrus;
+
+namespace {
+
+int hip_fail(hipError_t e, const char* what)
+{
+    char buf[256];
+    snprintf(buf, sizeof buf, "%s failed: %s", what, hipGetErrorString(e));
+    return set_error(CYRUS_EDEVICE, buf);
+}
+
+}  // namespace
+
+namespace cyrus {
+
+// Level-launch descriptors of one batch, in the pinned staging area of the
+// first handle: DevTree[kMaxBatch], then per level slot the entry lists.
+struct BatchLayout {
+    size_t trees, slot0, slot_bytes;
+};
+
+static BatchLayout batch_layout()
+{
+    BatchLayout b;
+    b.trees = 0;
+    b.slot0 = (sizeof(DevTree) * kMaxBatch + 255) / 256 * 256;
+    b.slot_bytes = (size_t)(3 * kMaxBatch + 1) * 4;
+    return b;
+}
+
+int build_batch_levels(cyrus_codebook* const* cbs, const DevTree* trees, int n, hipStream_t st)
+{
+    cyrus_codebook* host_cb = cbs[0];
+    const int prec = host_cb->s.prec;
+    // one row-tile count and LDS size valid for every member
+    int rtt = 0;
+    for (int r = (prec == kFP32 ? 4 : 8); r >= 1 && !rtt; r /= 2) {
+        size_t worst = 0;
+        for (int i = 0; i < n; ++i)
+            worst = std::max(worst, level_lds_bytes(trees[i], prec, r));
+        if (worst <= 160 * 1024)
+            rtt = r;
+    }
+    if (!rtt)
+        return set_error(CYRUS_EUNSUPPORTED, "batch does not fit the level kernel's LDS");
+    size_t buf = 0;
+    for (int i = 0; i < n; ++i)
+        buf = std::max(buf, level_buf_bytes(trees[i], prec, rtt));
+    const size_t lds = 2 * buf + (size_t)16 * rtt * kLogitStride * 4 + (kMaxUE + 4) * 4;
+
+    const BatchLayout L = batch_layout();
+    uint8_t* hbase = host_cb->host + host_cb->s.hoff_batch;
+    uint8_t* dbase = host_cb->ws + host_cb->s.off_batch;
+    if (host_cb->staged_recorded) {
+        hipError_t e = hipEventSynchronize(host_cb->ev_staged);
+        if (e != hipSuccess)
+            return hip_fail(e, "hipEventSynchronize");
+    }
+    std::memcpy(hbase + L.trees, trees, sizeof(DevTree) * n);
+    int max_m = 0;
+    for (int i = 0; i < n; ++i)
+        max_m = std::max(max_m, trees[i].M);
+    int blocks[8] = {0}, entries[8] = {0};
+    for (int tau = 1; tau <= max_m; ++tau) {
+        int32_t* slot = reinterpret_cast<int32_t*>(hbase + L.slot0 + (tau - 1) * L.slot_bytes);
+        int32_t* ent_tree = slot;
+        int32_t* ent_tau = slot + kMaxBatch;
+        int32_t* prefix = slot + 2 * kMaxBatch;
+        int j = 0, total = 0;
+        for (int i = 0; i < n; ++i) {
+            if (trees[i].M < tau)
+                continue;
+            const int64_t n_eval = trees[i].K * ipow(trees[i].K + 1, tau - 1);
+            ent_tree[j] = i;
+            ent_tau[j] = tau;
+            prefix[j] = total;
+            total += (int)((n_eval + 16 * rtt - 1) / (16 * rtt));
+            ++j;
+        }
+        prefix[j] = total;
+        blocks[tau] = total;
+        entries[tau] = j;
+    }
+    const size_t bytes = L.slot0 + (size_t)max_m * L.slot_bytes;
+    hipError_t e = hipMemcpyAsync(dbase, hbase, bytes, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess)
+        return hip_fail(e, "hipMemcpyAsync(batch descriptors)");
+    e = hipEventRecord(host_cb->ev_staged, st);
+    if (e != hipSuccess)
+        return hip_fail(e, "hipEventRecord");
+    host_cb->staged_recorded = true;
+    const DevTree* dtrees = reinterpret_cast<const DevTree*>(dbase + L.trees);
+    for (int tau = 1; tau <= max_m; ++tau) {
+        const int32_t* slot = reinterpret_cast<const int32_t*>(dbase + L.slot0 + (tau - 1) * L.slot_bytes);
+        e = launch_level_batch(dtrees, slot, slot + kMaxBatch, slot + 2 * kMaxBatch, entries[tau], blocks[tau], prec,
+                               rtt, (int)buf, lds, st);
+        if (e != hipSuccess)
+            return hip_fail(e, "level batch launch");
+    }
+    return CYRUS_OK;
+}
+
+}  // namespace cyrus
+
+extern "C" int cyrus_codebook_build_batch(cyrus_codebook* const* cbs, const void* const* ue_device, int32_t n,
+                                          void* stream)
+{
+    if (!cbs || !ue_device)
+        return set_error(CYRUS_EINVAL, "NULL argument");
+    if (n < 1 || n > kMaxBatch)
+        return set_error(CYRUS_ERANGE, "batch size outside [1, 128]");
+    DevTree trees[kMaxBatch];
+    for (int i = 0; i < n; ++i) {
+        if (!cbs[i] || !ue_device[i])
+            return set_error(CYRUS_EINVAL, "NULL handle or UE pointer in the batch");
+        if (cbs[i]->s.prec != cbs[0]->s.prec)
+            return set_error(CYRUS_EINVAL, "all codebooks of a batch must share a precision");
+        if (cbs[i]->device != cbs[0]->device)
+            return set_error(CYRUS_EINVAL, "all codebooks of a batch must live on one device");
+        for (int j = 0; j < i; ++j)
+            if (cbs[j] == cbs[i])
+                return set_error(CYRUS_EINVAL, "a codebook appears twice in one batch");
+        trees[i] = make_devtree(cbs[i], static_cast<const int32_t*>(ue_device[i]));
+    }
+    hipError_t e = hipSetDevice(cbs[0]->device);
+    if (e != hipSuccess)
+        return hip_fail(e, "hipSetDevice");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    int rc = build_batch_levels(cbs, trees, n, st);
+    if (rc)
+        return rc;
+    for (int i = 0; i < n; ++i) {
+        e = hipEventRecord(cbs[i]->ev_done, st);
+        if (e != hipSuccess)
+            return hip_fail(e, "hipEventRecord");
+        cbs[i]->built = cbs[i]->pending = true;
+        cbs[i]->mirror_valid = false;
+    }
+    return CYRUS_OK;
+}

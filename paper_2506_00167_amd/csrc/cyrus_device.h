@@ -1,0 +1,246 @@
+// Device-side building blocks of the codebook builder for gfx950 (CDNA4).
+//
+// Matrix layout used by every layer (the "transposed" form): a layer computes
+// H_out^T = W * H_in^T with the weights as the MFMA A operand (M = output
+// neurons, 16 per tile) and the node activations as the B operand (N = 16
+// node rows per tile). The 16x16 FP32 accumulator then holds, in lane
+// (g = lane/16, c = lane%16), the outputs of neurons 4g..4g+3 for node row c,
+// which are written back as 4 consecutive values of that row.
+//
+// Both operands are fed with one 16-byte load per lane per "chunk" of the
+// reduction dimension. Lane group g covers k in [g*kc/4, (g+1)*kc/4) of the
+// chunk, contiguous, so a B fragment is 16 contiguous bytes of a row held in
+// LDS and an A fragment is 16 contiguous bytes of a pre-packed weight block:
+//   FP32  chunk = 16 k: 4 x v_mfma_f32_16x16x4_f32, element j of the lane's
+//                       float4 feeds instruction j
+//   BF16  chunk = 32 k: 1 x v_mfma_f32_16x16x32_bf16
+//   FP8   chunk = 64 k: 2 x v_mfma_f32_16x16x32_fp8_fp8, bytes 0-7 and 8-15
+// Packed weights: [n_tile][chunk][lane][16 bytes], 1 KiB per (tile, chunk),
+// so one wave reads a fragment with a single coalesced 1 KiB load.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "cyrus_internal.h"
+
+namespace cyrus {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+template <int P>
+struct Traits;
+template <>
+struct Traits<kFP32> {
+    static constexpr int kEsize = 4;
+    static constexpr int kChunk = 16;
+};
+template <>
+struct Traits<kBF16> {
+    static constexpr int kEsize = 2;
+    static constexpr int kChunk = 32;
+};
+template <>
+struct Traits<kFP8> {
+    static constexpr int kEsize = 1;
+    static constexpr int kChunk = 64;
+};
+
+// One reduction chunk: acc += A_chunk * B_chunk.
+template <int P>
+__device__ __forceinline__ void mma_chunk(const uint4& a, const uint4& b, floatx4& acc);
+
+template <>
+__device__ __forceinline__ void mma_chunk<kFP32>(const uint4& a, const uint4& b, floatx4& acc)
+{
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.x), __uint_as_float(b.x), acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.y), __uint_as_float(b.y), acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.z), __uint_as_float(b.z), acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.w), __uint_as_float(b.w), acc, 0, 0, 0);
+}
+
+template <>
+__device__ __forceinline__ void mma_chunk<kBF16>(const uint4& a, const uint4& b, floatx4& acc)
+{
+    bf16x8 av, bv;
+    __builtin_memcpy(&av, &a, 16);
+    __builtin_memcpy(&bv, &b, 16);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+}
+
+template <>
+__device__ __forceinline__ void mma_chunk<kFP8>(const uint4& a, const uint4& b, floatx4& acc)
+{
+    long a0 = (long)(((uint64_t)a.y << 32) | a.x), a1 = (long)(((uint64_t)a.w << 32) | a.z);
+    long b0 = (long)(((uint64_t)b.y << 32) | b.x), b1 = (long)(((uint64_t)b.w << 32) | b.z);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a0, b0, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a1, b1, acc, 0, 0, 0);
+}
+
+// float -> bfloat16 bits, round to nearest even (inputs are finite).
+__device__ __forceinline__ uint32_t bf16_bits(float v)
+{
+    uint32_t u = __float_as_uint(v);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+
+// Four floats -> four OCP E4M3 bytes (hardware round to nearest even), with
+// explicit saturation at +-448.
+__device__ __forceinline__ uint32_t e4m3x4(float v0, float v1, float v2, float v3)
+{
+    v0 = fminf(fmaxf(v0, -448.f), 448.f);
+    v1 = fminf(fmaxf(v1, -448.f), 448.f);
+    v2 = fminf(fmaxf(v2, -448.f), 448.f);
+    v3 = fminf(fmaxf(v3, -448.f), 448.f);
+    int lo = __builtin_amdgcn_cvt_pk_fp8_f32(v0, v1, 0, false);
+    return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(v2, v3, lo, true);
+}
+
+// Store four consecutive activations of one row in the storage type of P.
+// `inv_scale` is the reciprocal of the next layer's FP8 input scale.
+template <int P>
+__device__ __forceinline__ void store4(uint8_t* dst, float v0, float v1, float v2, float v3, float inv_scale);
+
+template <>
+__device__ __forceinline__ void store4<kFP32>(uint8_t* dst, float v0, float v1, float v2, float v3, float)
+{
+    *reinterpret_cast<floatx4*>(dst) = floatx4{v0, v1, v2, v3};
+}
+
+template <>
+__device__ __forceinline__ void store4<kBF16>(uint8_t* dst, float v0, float v1, float v2, float v3, float)
+{
+    uint2 w;
+    w.x = bf16_bits(v0) | (bf16_bits(v1) << 16);
+    w.y = bf16_bits(v2) | (bf16_bits(v3) << 16);
+    *reinterpret_cast<uint2*>(dst) = w;
+}
+
+template <>
+__device__ __forceinline__ void store4<kFP8>(uint8_t* dst, float v0, float v1, float v2, float v3, float inv_scale)
+{
+    *reinterpret_cast<uint32_t*>(dst) = e4m3x4(v0 * inv_scale, v1 * inv_scale, v2 * inv_scale, v3 * inv_scale);
+}
+
+// Store one activation (feature assembly, padding).
+template <int P>
+__device__ __forceinline__ void store1(uint8_t* dst, float v, float inv_scale);
+template <>
+__device__ __forceinline__ void store1<kFP32>(uint8_t* dst, float v, float)
+{
+    *reinterpret_cast<float*>(dst) = v;
+}
+template <>
+__device__ __forceinline__ void store1<kBF16>(uint8_t* dst, float v, float)
+{
+    *reinterpret_cast<uint16_t*>(dst) = (uint16_t)bf16_bits(v);
+}
+template <>
+__device__ __forceinline__ void store1<kFP8>(uint8_t* dst, float v, float inv_scale)
+{
+    v = fminf(fmaxf(v * inv_scale, -448.f), 448.f);
+    *dst = (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(v, 0.f, 0, false) & 0xff);
+}
+
+// ---------------------------------------------------------------------------
+// Feasibility enforcer for one node, FP32 (softmax, capped proportional split
+// of T = min(U k, sum R) as the KL projection, largest-remainder rounding with
+// ties to the lower UE index). EMAX bounds E so the per-UE arrays stay in
+// registers. z: logits (LDS, stride 1). Writes a[e] for e < E.
+template <int EMAX>
+__device__ __forceinline__ void enforce(int E, const float* z, const int* R, int rsum, int demand, int* a)
+{
+    float p[EMAX], x[EMAX];
+    float zmax = -3.0e38f;
+#pragma unroll
+    for (int e = 0; e < EMAX; ++e)
+        if (e < E)
+            zmax = fmaxf(zmax, z[e]);
+    float sum = 0.f;
+#pragma unroll
+    for (int e = 0; e < EMAX; ++e) {
+        p[e] = 0.f;
+        if (e < E) {
+            p[e] = expf(fmaxf(z[e] - zmax, -80.f));
+            sum += p[e];
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < EMAX; ++e)
+        p[e] = p[e] / sum;
+
+    const int T = demand < rsum ? demand : rsum;
+    if (T >= rsum) {
+#pragma unroll
+        for (int e = 0; e < EMAX; ++e)
+            if (e < E)
+                a[e] = R[e];
+        return;
+    }
+    // capped proportional split: grow the capped set until stable
+    uint32_t capped = 0;
+    float s = 0.f;
+    for (int pass = 0; pass <= EMAX; ++pass) {
+        float rem = (float)T, psum = 0.f;
+#pragma unroll
+        for (int e = 0; e < EMAX; ++e) {
+            if (e < E) {
+                if (capped & (1u << e))
+                    rem -= (float)R[e];
+                else
+                    psum += p[e];
+            }
+        }
+        s = rem / psum;
+        uint32_t grow = 0;
+#pragma unroll
+        for (int e = 0; e < EMAX; ++e)
+            if (e < E && !(capped & (1u << e)) && s * p[e] >= (float)R[e])
+                grow |= 1u << e;
+        if (!grow)
+            break;
+        capped |= grow;
+    }
+    int fsum = 0;
+    float frac[EMAX];
+    int fl[EMAX];
+#pragma unroll
+    for (int e = 0; e < EMAX; ++e) {
+        x[e] = (capped & (1u << e)) ? (float)R[e] : s * p[e];
+        float f = floorf(x[e]);
+        fl[e] = (int)f;
+        frac[e] = x[e] - f;
+        if (e < E)
+            fsum += fl[e];
+    }
+    const int r = T - fsum;
+    // rank of every eligible UE in (fraction desc, index asc); the top r get
+    // one more unit
+#pragma unroll
+    for (int e = 0; e < EMAX; ++e) {
+        if (e >= E)
+            continue;
+        const bool elig = fl[e] < R[e];
+        int rank = 0;
+#pragma unroll
+        for (int q = 0; q < EMAX; ++q) {
+            if (q < E && q != e && fl[q] < R[q] && (frac[q] > frac[e] || (frac[q] == frac[e] && q < e)))
+                ++rank;
+        }
+        a[e] = fl[e] + ((elig && rank < r) ? 1 : 0);
+    }
+}
+
+__device__ __forceinline__ void enforce_any(int E, const float* z, const int* R, int rsum, int demand, int* a)
+{
+    if (E <= 8)
+        enforce<8>(E, z, R, rsum, demand, a);
+    else if (E <= 16)
+        enforce<16>(E, z, R, rsum, demand, a);
+    else
+        enforce<32>(E, z, R, rsum, demand, a);
+}
+
+}  // namespace cyrus

@@ -1,0 +1,74 @@
+// Host-side internals shared by the C ABI translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "cyrus.h"
+#include "cyrus_internal.h"
+
+struct cyrus_codebook;
+
+namespace cyrus {
+
+constexpr int kMaxBatch = 128;  // codebooks per batched launch
+
+// Derived sizes and the workspace carving of one configuration.
+struct Shape {
+    int E, K, M, prec, n_layers;
+    int dims[kMaxLayers + 1];
+    int in_pad[kMaxLayers], out_pad[kMaxLayers];
+    size_t w_off[kMaxLayers], b_off[kMaxLayers];
+    size_t w_bytes;          // one weight buffer (packed weights + biases)
+    size_t staging_floats;   // FP32 staging for the largest layer
+    int64_t nodes;
+    bool export_logits;
+    // device workspace offsets
+    size_t off_w[2], off_staging, off_ue, off_alloc, off_state, off_logits, off_batch, device_bytes;
+    // pinned host offsets
+    size_t hoff_ue, hoff_alloc, hoff_logits, hoff_batch, host_bytes;
+};
+
+int validate_config(const cyrus_config* cfg);
+Shape make_shape(const cyrus_config* cfg);
+size_t batch_area_bytes();
+void pack_fragments(const float* w, int out, int in, int out_pad, int in_pad, int prec, float* dst);
+float e4m3_weight_scale(const float* w, size_t n);
+int choose_rtt(const DevTree& t, int prec, int max_rtt);
+DevTree make_devtree(const cyrus_codebook* cb, const int32_t* ue_dev);
+int codebook_path(const cyrus_codebook* cb);
+int codebook_rtt(const cyrus_codebook* cb);
+const Shape& codebook_shape(const cyrus_codebook* cb);
+int set_error(int status, const char* msg);
+
+// Subtree (single-launch latency) path.
+bool subtree_supported(const DevTree& t, int prec);
+hipError_t launch_subtree(const DevTree& t, int prec, hipStream_t s);
+
+}  // namespace cyrus
+
+// The opaque handle of the C ABI.
+struct cyrus_codebook {
+    cyrus_config cfg;
+    cyrus::Shape s;
+    int device = 0;
+    uint8_t* ws = nullptr;
+    uint8_t* host = nullptr;
+    int active = 0;
+    float deq[cyrus::kMaxLayers];
+    float inv_in[cyrus::kMaxLayers];
+    hipEvent_t ev_staged = nullptr;
+    hipEvent_t ev_done = nullptr;
+    bool staged_recorded = false;
+    bool built = false;
+    bool pending = false;
+    bool mirror_valid = false;
+    int path = 0;  // 0 level, 1 subtree
+    int rtt = 1;
+    std::vector<float> pack;  // host FP32 fragment staging
+};
+

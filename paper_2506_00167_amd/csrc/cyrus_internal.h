@@ -1,0 +1,46 @@
+// Internal types shared by the host library and the kernels.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+namespace cyrus {
+
+constexpr int kWaves = 8;                 // waves per workgroup
+constexpr int kThreads = kWaves * 64;     // threads per workgroup
+constexpr int kMaxLayers = 5;
+constexpr int kMaxUE = 32;
+constexpr int kLogitStride = kMaxUE + 1;  // LDS row stride of the logits (bank-conflict free)
+
+enum Prec { kFP32 = 0, kBF16 = 1, kFP8 = 2 };
+
+inline constexpr int prec_esize(int p) { return p == kFP32 ? 4 : (p == kBF16 ? 2 : 1); }
+inline constexpr int prec_chunk(int p) { return p == kFP32 ? 16 : (p == kBF16 ? 32 : 64); }
+
+// Everything a kernel needs to build one codebook; passed by value or read
+// from a device array in batched launches.
+struct DevTree {
+    int32_t E, K, M, U;
+    int32_t n_layers;                 // hidden layers + output layer
+    int32_t in_dim0;                  // 4E + 2
+    int32_t in_pad[kMaxLayers];       // layer input width padded to the k-chunk
+    int32_t out_pad[kMaxLayers];      // layer output width padded to 16
+    const uint8_t* w[kMaxLayers];     // packed weight fragments
+    const float* b[kMaxLayers];       // biases, out_pad entries (zero padded)
+    float deq[kMaxLayers];            // FP8: weight scale * input scale; else 1
+    float inv_in_scale[kMaxLayers];   // FP8: 1 / input scale of layer l; else 1
+    const int32_t* ue;                // rb[E], mcs[E], sinr_db[E] (float bits)
+    uint8_t* alloc;                   // [nodes][E]
+    uint8_t* state;                   // [nodes][E] punctured RBs so far, after the node
+    float* logits;                    // [nodes][E] or null
+};
+
+inline int64_t ipow(int64_t b, int e)
+{
+    int64_t r = 1;
+    for (int i = 0; i < e; ++i)
+        r *= b;
+    return r;
+}
+
+}  // namespace cyrus

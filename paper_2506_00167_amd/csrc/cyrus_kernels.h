@@ -1,0 +1,23 @@
+// Host-callable launchers of the device kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "cyrus_internal.h"
+
+namespace cyrus {
+
+// Level path: one launch per level tau. rtt = row tiles of 16 per workgroup.
+size_t level_buf_bytes(const DevTree& t, int prec, int rtt);
+size_t level_lds_bytes(const DevTree& t, int prec, int rtt);
+hipError_t launch_level(const DevTree& t, int prec, int rtt, int tau, hipStream_t s);
+// Batched: entry j is codebook ent_tree[j] at level ent_tau[j], owning
+// workgroups [prefix[j], prefix[j+1]) of an nblocks = prefix[n] launch.
+hipError_t launch_level_batch(const DevTree* trees, const int* ent_tree, const int* ent_tau, const int* prefix, int n,
+                              int nblocks, int prec, int rtt, int buf, size_t lds, hipStream_t s);
+
+// FP32 fragment-ordered weights -> packed storage of `prec`.
+hipError_t launch_convert_weights(int prec, const float* src, uint8_t* dst, int64_t n_floats, float inv_w_scale,
+                                  hipStream_t s);
+
+}  // namespace cyrus

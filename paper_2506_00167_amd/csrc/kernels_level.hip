@@ -1,0 +1,362 @@
+// Level kernels: one launch per mini-slot level tau, one workgroup per tile of
+// RT = 16*RTT evaluated nodes of that level (the k > 0 children of the nodes
+// of level tau-1). Each workgroup assembles the node features, runs the whole
+// actor MLP on MFMA with the activations in LDS and the weight fragments read
+// from global memory (L2-resident after the first touch), then applies the
+// feasibility enforcer and writes the nodes' puncturing vectors and states.
+// This is the general path (any width, depth, precision, cells batched per
+// launch); the latency path for small trees is kernels_subtree.hip.
+#include "cyrus_device.h"
+#include "cyrus_kernels.h"
+
+namespace cyrus {
+
+__device__ __forceinline__ int64_t dev_level_offset(int K, int tau)
+{
+    int64_t p = 1;
+    for (int i = 0; i < tau; ++i)
+        p *= (K + 1);
+    return (p - 1) / K;
+}
+
+// Writes one evaluated node and, for its first k, the k = 0 sibling (which
+// punctures nothing and passes the parent state on unchanged).
+template <int EMAX>
+__device__ __forceinline__ void finish_node(const DevTree& t, const float* z, const int* R, int rsum, int64_t node,
+                                            int64_t parent, int64_t sibling0, int k)
+{
+    int a[EMAX];
+    enforce<EMAX>(t.E, z, R, rsum, t.U * k, a);
+    const uint8_t* cin = t.state + parent * t.E;
+#pragma unroll
+    for (int e = 0; e < EMAX; ++e) {
+        if (e < t.E) {
+            const uint8_t c = cin[e];
+            t.alloc[node * t.E + e] = (uint8_t)a[e];
+            t.state[node * t.E + e] = (uint8_t)(c + a[e]);
+            if (t.logits)
+                t.logits[node * t.E + e] = z[e];
+            if (sibling0 >= 0) {
+                t.alloc[sibling0 * t.E + e] = 0;
+                t.state[sibling0 * t.E + e] = c;
+                if (t.logits)
+                    t.logits[sibling0 * t.E + e] = 0.f;
+            }
+        }
+    }
+}
+
+// Actor forward pass over `nrows` node rows whose features are in bufA.
+// Leaves the FP32 logits in zl[row * kLogitStride + e].
+template <int P, int RTT>
+__device__ void run_mlp(const DevTree& t, int nrows, uint8_t* bufA, uint8_t* bufB, float* zl)
+{
+    constexpr int kc = Traits<P>::kChunk, es = Traits<P>::kEsize, RT = 16 * RTT;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, c16 = lane & 15;
+    const int art = (nrows + 15) >> 4;
+    uint8_t* in = bufA;
+    uint8_t* out = bufB;
+    for (int l = 0; l + 1 < t.n_layers; ++l) {
+        const int nch = t.in_pad[l] / kc;
+        const int sin = t.in_pad[l] * es + 16;
+        const int sout = t.out_pad[l] * es + 16;
+        const int ntile = t.out_pad[l] >> 4;
+        const uint4* wl = reinterpret_cast<const uint4*>(t.w[l]);
+        const float deq = t.deq[l];
+        const float inv_next = t.inv_in_scale[l + 1];
+        for (int nt = wave; nt < ntile; nt += kWaves) {
+            floatx4 acc[RTT];
+#pragma unroll
+            for (int rt = 0; rt < RTT; ++rt)
+                acc[rt] = floatx4{0.f, 0.f, 0.f, 0.f};
+            const uint4* wp = wl + (size_t)nt * nch * 64 + lane;
+            const uint8_t* bp = in + c16 * sin + g * (kc / 4) * es;
+            for (int ch = 0; ch < nch; ++ch) {
+                const uint4 a = wp[(size_t)ch * 64];
+#pragma unroll
+                for (int rt = 0; rt < RTT; ++rt) {
+                    if (rt < art) {
+                        const uint4 b = *reinterpret_cast<const uint4*>(bp + rt * 16 * sin + ch * kc * es);
+                        mma_chunk<P>(a, b, acc[rt]);
+                    }
+                }
+            }
+            const float* bias = t.b[l] + nt * 16 + g * 4;
+            const float b0 = bias[0], b1 = bias[1], b2 = bias[2], b3 = bias[3];
+#pragma unroll
+            for (int rt = 0; rt < RTT; ++rt) {
+                if (rt < art) {
+                    const float v0 = fmaxf(acc[rt][0] * deq + b0, 0.f);
+                    const float v1 = fmaxf(acc[rt][1] * deq + b1, 0.f);
+                    const float v2 = fmaxf(acc[rt][2] * deq + b2, 0.f);
+                    const float v3 = fmaxf(acc[rt][3] * deq + b3, 0.f);
+                    store4<P>(out + (rt * 16 + c16) * sout + (nt * 16 + g * 4) * es, v0, v1, v2, v3, inv_next);
+                }
+            }
+        }
+        __syncthreads();
+        uint8_t* tmp = in;
+        in = out;
+        out = tmp;
+    }
+    // Output layer: the reduction dimension is split across the waves; each
+    // wave leaves a partial logit tile, summed in wave order below.
+    {
+        const int l = t.n_layers - 1;
+        const int nch = t.in_pad[l] / kc;
+        const int sin = t.in_pad[l] * es + 16;
+        const int opad = t.out_pad[l];
+        const int ntile = opad >> 4;
+        const int cpw = (nch + kWaves - 1) / kWaves;
+        const int c0 = wave * cpw, c1 = min(nch, c0 + cpw);
+        float* part = reinterpret_cast<float*>(out);
+        const uint4* wl = reinterpret_cast<const uint4*>(t.w[l]);
+        for (int nt = 0; nt < ntile; ++nt) {
+            floatx4 acc[RTT];
+#pragma unroll
+            for (int rt = 0; rt < RTT; ++rt)
+                acc[rt] = floatx4{0.f, 0.f, 0.f, 0.f};
+            const uint4* wp = wl + (size_t)nt * nch * 64 + lane;
+            const uint8_t* bp = in + c16 * sin + g * (kc / 4) * es;
+            for (int ch = c0; ch < c1; ++ch) {
+                const uint4 a = wp[(size_t)ch * 64];
+#pragma unroll
+                for (int rt = 0; rt < RTT; ++rt) {
+                    if (rt < art) {
+                        const uint4 b = *reinterpret_cast<const uint4*>(bp + rt * 16 * sin + ch * kc * es);
+                        mma_chunk<P>(a, b, acc[rt]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int rt = 0; rt < RTT; ++rt)
+                if (rt < art)
+                    *reinterpret_cast<floatx4*>(part + (size_t)(wave * RT + rt * 16 + c16) * opad + nt * 16 + g * 4) =
+                        acc[rt];
+        }
+        __syncthreads();
+        const int E = t.E;
+        const float deq = t.deq[l];
+        for (int idx = threadIdx.x; idx < nrows * E; idx += kThreads) {
+            const int row = idx / E, e = idx - row * E;
+            float s = 0.f;
+            for (int w = 0; w < kWaves; ++w)
+                s += part[(size_t)(w * RT + row) * opad + e];
+            zl[row * kLogitStride + e] = s * deq + t.b[l][e];
+        }
+        __syncthreads();
+    }
+}
+
+// One tile of evaluated rows [row0, row0 + nrows) of level tau.
+template <int P, int RTT>
+__device__ void level_tile(const DevTree& t, int tau, int row0, int nrows, uint8_t* smem, int bufsize)
+{
+    constexpr int es = Traits<P>::kEsize, RT = 16 * RTT;
+    uint8_t* bufA = smem;
+    uint8_t* bufB = smem + bufsize;
+    float* zl = reinterpret_cast<float*>(smem + 2 * bufsize);
+    int* R = reinterpret_cast<int*>(zl + RT * kLogitStride);
+    int* rsum_lds = R + kMaxUE;
+    const int E = t.E, K = t.K;
+    if (threadIdx.x < E)
+        R[threadIdx.x] = t.ue[threadIdx.x];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int s = 0;
+        for (int e = 0; e < E; ++e)
+            s += R[e];
+        *rsum_lds = s;
+    }
+    const int64_t off = dev_level_offset(K, tau), poff = dev_level_offset(K, tau - 1);
+
+    // features of every row, zero padded to the k-chunk and to whole row tiles
+    const int in0 = t.in_pad[0], d_in = t.in_dim0, s0 = in0 * es + 16;
+    const int nrows_pad = ((nrows + 15) >> 4) << 4;
+    const float inv0 = t.inv_in_scale[0];
+    for (int idx = threadIdx.x; idx < nrows_pad * in0; idx += kThreads) {
+        const int row = idx / in0, f = idx - row * in0;
+        float v = 0.f;
+        if (row < nrows && f < d_in) {
+            const int r = row0 + row, p = r / K, k = r - p * K + 1;
+            if (f < E)
+                v = (float)R[f] * (1.f / 32.f);
+            else if (f < 2 * E)
+                v = (float)t.ue[f] * (1.f / 32.f);
+            else if (f < 3 * E)
+                v = __int_as_float(t.ue[f]) * (1.f / 32.f);
+            else if (f < 4 * E)
+                v = (float)t.state[(poff + p) * E + (f - 3 * E)] * (1.f / 64.f);
+            else if (f == 4 * E)
+                v = (float)tau * (1.f / 8.f);
+            else
+                v = (float)k * (1.f / 8.f);
+        }
+        store1<P>(bufA + row * s0 + f * es, v, inv0);
+    }
+    __syncthreads();
+    run_mlp<P, RTT>(t, nrows, bufA, bufB, zl);
+
+    if (threadIdx.x < nrows) {
+        const int row = threadIdx.x, r = row0 + row, p = r / K, k = r - p * K + 1;
+        const int64_t node = off + (int64_t)p * (K + 1) + k, parent = poff + p;
+        const int64_t sib = (k == 1) ? off + (int64_t)p * (K + 1) : -1;
+        const float* z = zl + row * kLogitStride;
+        const int rsum = *rsum_lds;
+        if (E <= 8)
+            finish_node<8>(t, z, R, rsum, node, parent, sib, k);
+        else if (E <= 16)
+            finish_node<16>(t, z, R, rsum, node, parent, sib, k);
+        else
+            finish_node<32>(t, z, R, rsum, node, parent, sib, k);
+    }
+}
+
+template <int P, int RTT>
+__global__ __launch_bounds__(kThreads) void level_kernel(DevTree t, int tau, int n_eval, int bufsize)
+{
+    extern __shared__ __align__(16) uint8_t smem[];
+    const int row0 = blockIdx.x * 16 * RTT;
+    const int nrows = min(16 * RTT, n_eval - row0);
+    if (nrows <= 0)
+        return;
+    level_tile<P, RTT>(t, tau, row0, nrows, smem, bufsize);
+}
+
+// Batched level launch over several codebooks (cells), each at its own level:
+// entry j of the launch is codebook ent_tree[j] at level ent_tau[j] and owns
+// workgroups [prefix[j], prefix[j+1]).
+template <int P, int RTT>
+__global__ __launch_bounds__(kThreads) void level_kernel_batch(const DevTree* trees, const int* ent_tree,
+                                                               const int* ent_tau, const int* prefix, int n,
+                                                               int bufsize)
+{
+    extern __shared__ __align__(16) uint8_t smem[];
+    const int b = blockIdx.x;
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (prefix[mid] <= b)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const DevTree t = trees[ent_tree[lo]];
+    const int tau = ent_tau[lo];
+    const int n_eval = (int)(t.K * (dev_level_offset(t.K, tau) - dev_level_offset(t.K, tau - 1)));
+    const int row0 = (b - prefix[lo]) * 16 * RTT;
+    const int nrows = min(16 * RTT, n_eval - row0);
+    if (nrows <= 0)
+        return;
+    level_tile<P, RTT>(t, tau, row0, nrows, smem, bufsize);
+}
+
+// Converts FP32 fragment-ordered weights into the storage type of P, in place
+// of the packed buffer (elementwise; FP8 with its power-of-two scale).
+template <int P>
+__global__ void convert_weights(const float* src, uint8_t* dst, int64_t n4, float inv_w_scale)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n4)
+        return;
+    const floatx4 v = reinterpret_cast<const floatx4*>(src)[i];
+    store4<P>(dst + i * 4 * Traits<P>::kEsize, v[0], v[1], v[2], v[3], inv_w_scale);
+}
+
+// ------------------------------------------------------------------ launch
+
+size_t level_buf_bytes(const DevTree& t, int prec, int rtt)
+{
+    const int es = prec_esize(prec), rt = 16 * rtt;
+    size_t stride = 0;
+    for (int l = 0; l < t.n_layers; ++l) {
+        const size_t s = (size_t)t.in_pad[l] * es + 16;
+        stride = s > stride ? s : stride;
+    }
+    size_t buf = stride * rt;
+    const size_t part = (size_t)kWaves * rt * t.out_pad[t.n_layers - 1] * 4;
+    if (part > buf)
+        buf = part;
+    return (buf + 15) & ~(size_t)15;
+}
+
+size_t level_lds_bytes(const DevTree& t, int prec, int rtt)
+{
+    return 2 * level_buf_bytes(t, prec, rtt) + (size_t)16 * rtt * kLogitStride * 4 + (kMaxUE + 4) * 4;
+}
+
+template <int P, int RTT>
+static hipError_t launch_level_t(const DevTree& t, int tau, hipStream_t s)
+{
+    const int n_eval = (int)(t.K * ipow(t.K + 1, tau - 1));
+    const int grid = (n_eval + 16 * RTT - 1) / (16 * RTT);
+    const int buf = (int)level_buf_bytes(t, P, RTT);
+    const size_t lds = level_lds_bytes(t, P, RTT);
+    static bool attr = false;
+    if (!attr) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&level_kernel<P, RTT>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        attr = true;
+    }
+    hipLaunchKernelGGL((level_kernel<P, RTT>), dim3(grid), dim3(kThreads), lds, s, t, tau, n_eval, buf);
+    return hipGetLastError();
+}
+
+template <int P, int RTT>
+static hipError_t launch_level_batch_t(const DevTree* trees, const int* ent_tree, const int* ent_tau,
+                                       const int* prefix, int n, int nblocks, int buf, size_t lds, hipStream_t s)
+{
+    static bool attr = false;
+    if (!attr) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&level_kernel_batch<P, RTT>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        attr = true;
+    }
+    hipLaunchKernelGGL((level_kernel_batch<P, RTT>), dim3(nblocks), dim3(kThreads), lds, s, trees, ent_tree, ent_tau,
+                       prefix, n, buf);
+    return hipGetLastError();
+}
+
+hipError_t launch_level(const DevTree& t, int prec, int rtt, int tau, hipStream_t s)
+{
+#define CYRUS_LEVEL_CASE(P, R)                                                                                         \
+    if (prec == P && rtt == R)                                                                                         \
+        return launch_level_t<P, R>(t, tau, s);
+    CYRUS_LEVEL_CASE(kFP32, 1) CYRUS_LEVEL_CASE(kFP32, 2) CYRUS_LEVEL_CASE(kFP32, 4)
+    CYRUS_LEVEL_CASE(kBF16, 1) CYRUS_LEVEL_CASE(kBF16, 2) CYRUS_LEVEL_CASE(kBF16, 4) CYRUS_LEVEL_CASE(kBF16, 8)
+    CYRUS_LEVEL_CASE(kFP8, 1) CYRUS_LEVEL_CASE(kFP8, 2) CYRUS_LEVEL_CASE(kFP8, 4) CYRUS_LEVEL_CASE(kFP8, 8)
+#undef CYRUS_LEVEL_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_level_batch(const DevTree* trees, const int* ent_tree, const int* ent_tau, const int* prefix, int n,
+                              int nblocks, int prec, int rtt, int buf, size_t lds, hipStream_t s)
+{
+#define CYRUS_LEVEL_CASE(P, R)                                                                                         \
+    if (prec == P && rtt == R)                                                                                         \
+        return launch_level_batch_t<P, R>(trees, ent_tree, ent_tau, prefix, n, nblocks, buf, lds, s);
+    CYRUS_LEVEL_CASE(kFP32, 1) CYRUS_LEVEL_CASE(kFP32, 2) CYRUS_LEVEL_CASE(kFP32, 4)
+    CYRUS_LEVEL_CASE(kBF16, 1) CYRUS_LEVEL_CASE(kBF16, 2) CYRUS_LEVEL_CASE(kBF16, 4) CYRUS_LEVEL_CASE(kBF16, 8)
+    CYRUS_LEVEL_CASE(kFP8, 1) CYRUS_LEVEL_CASE(kFP8, 2) CYRUS_LEVEL_CASE(kFP8, 4) CYRUS_LEVEL_CASE(kFP8, 8)
+#undef CYRUS_LEVEL_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_convert_weights(int prec, const float* src, uint8_t* dst, int64_t n_floats, float inv_w_scale,
+                                  hipStream_t s)
+{
+    const int64_t n4 = n_floats / 4;
+    const int block = 256;
+    const int grid = (int)((n4 + block - 1) / block);
+    if (grid == 0)
+        return hipSuccess;
+    if (prec == kFP32)
+        hipLaunchKernelGGL(convert_weights<kFP32>, dim3(grid), dim3(block), 0, s, src, dst, n4, inv_w_scale);
+    else if (prec == kBF16)
+        hipLaunchKernelGGL(convert_weights<kBF16>, dim3(grid), dim3(block), 0, s, src, dst, n4, inv_w_scale);
+    else
+        hipLaunchKernelGGL(convert_weights<kFP8>, dim3(grid), dim3(block), 0, s, src, dst, n4, inv_w_scale);
+    return hipGetLastError();
+}
+
+}  // namespace cyrus

@@ -1,0 +1,317 @@
+"""Python binding of libcyrus (the C ABI in include/cyrus.h).
+
+Argument marshalling only: every step of the codebook build runs in the HIP
+library. PyTorch provides the device workspace, the pinned host buffer and the
+stream handle. The functions named like the C entry points are one-to-one
+wrappers; ``Codebook`` owns the buffers of one builder.
+
+The library must be built first (``python -m paper_2506_00167_amd.build``);
+loading fails loudly if it is missing, there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+from .workload import TreeConfig, UEState
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libcyrus.so")
+
+CYRUS_OK = 0
+STATUS = {0: "OK", -1: "EINVAL", -2: "ERANGE", -3: "EWORKSPACE", -4: "EDEVICE", -5: "ENOTREADY", -6: "EUNSUPPORTED"}
+PRECISION = {"fp32": 0, "bf16": 1, "fp8": 2}
+FLAG_EXPORT_LOGITS = 1
+FLAG_LEVEL_KERNEL = 2
+MAX_HIDDEN = 4
+MAX_LAYERS = 5
+
+SYMBOLS = (
+    "cyrus_codebook_workspace_size", "cyrus_codebook_create", "cyrus_codebook_set_weights",
+    "cyrus_codebook_build", "cyrus_codebook_build_device", "cyrus_codebook_build_batch",
+    "cyrus_codebook_wait", "cyrus_codebook_lookup", "cyrus_codebook_export", "cyrus_codebook_device_alloc",
+    "cyrus_codebook_num_nodes", "cyrus_codebook_kernel_path", "cyrus_codebook_destroy",
+    "cyrus_status_string", "cyrus_last_error",
+)
+
+
+class CyrusError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__(f"{where}: {STATUS.get(status, status)} ({status}): {msg}")
+        self.status = status
+
+
+class cyrus_config(ctypes.Structure):
+    _fields_ = [("num_ue", ctypes.c_int32), ("max_arrival", ctypes.c_int32), ("num_minislots", ctypes.c_int32),
+                ("rb_per_unit", ctypes.c_int32), ("num_hidden", ctypes.c_int32),
+                ("hidden", ctypes.c_int32 * MAX_HIDDEN), ("precision", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+_f32p = ctypes.POINTER(ctypes.c_float)
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_u8p = ctypes.POINTER(ctypes.c_uint8)
+
+
+class cyrus_weights(ctypes.Structure):
+    _fields_ = [("w", _f32p * MAX_LAYERS), ("b", _f32p * MAX_LAYERS), ("act_scale", _f32p)]
+
+
+class cyrus_ue_state(ctypes.Structure):
+    _fields_ = [("rb", _i32p), ("mcs", _i32p), ("sinr_db", _f32p)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libcyrus.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2506_00167_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, sz = ctypes.c_void_p, ctypes.c_size_t
+        L.cyrus_codebook_workspace_size.argtypes = [ctypes.POINTER(cyrus_config), ctypes.POINTER(sz),
+                                                    ctypes.POINTER(sz)]
+        L.cyrus_codebook_create.argtypes = [ctypes.POINTER(cyrus_config), ctypes.POINTER(cyrus_weights), vp, sz, vp,
+                                            sz, vp, ctypes.POINTER(vp)]
+        L.cyrus_codebook_set_weights.argtypes = [vp, ctypes.POINTER(cyrus_weights), vp]
+        L.cyrus_codebook_build.argtypes = [vp, ctypes.POINTER(cyrus_ue_state), vp]
+        L.cyrus_codebook_build_device.argtypes = [vp, vp, vp]
+        L.cyrus_codebook_build_batch.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_int32, vp]
+        L.cyrus_codebook_wait.argtypes = [vp]
+        L.cyrus_codebook_lookup.argtypes = [vp, _u8p, ctypes.c_int32, _u8p]
+        L.cyrus_codebook_export.argtypes = [vp, _u8p, _f32p]
+        L.cyrus_codebook_device_alloc.argtypes = [vp]
+        L.cyrus_codebook_device_alloc.restype = vp
+        L.cyrus_codebook_num_nodes.argtypes = [vp]
+        L.cyrus_codebook_num_nodes.restype = ctypes.c_int64
+        L.cyrus_codebook_kernel_path.argtypes = [vp]
+        L.cyrus_codebook_kernel_path.restype = ctypes.c_char_p
+        L.cyrus_codebook_destroy.argtypes = [vp]
+        L.cyrus_codebook_destroy.restype = None
+        L.cyrus_status_string.argtypes = [ctypes.c_int]
+        L.cyrus_status_string.restype = ctypes.c_char_p
+        L.cyrus_last_error.argtypes = []
+        L.cyrus_last_error.restype = ctypes.c_char_p
+        for name in SYMBOLS:
+            if name not in ("cyrus_codebook_device_alloc", "cyrus_codebook_num_nodes", "cyrus_codebook_kernel_path",
+                            "cyrus_codebook_destroy", "cyrus_status_string", "cyrus_last_error"):
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, where: str):
+    if rc != CYRUS_OK:
+        raise CyrusError(rc, where, lib().cyrus_last_error().decode())
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def make_config(cfg: TreeConfig, export_logits: bool = False, force_level: bool = False) -> cyrus_config:
+    c = cyrus_config()
+    c.num_ue = cfg.num_ue
+    c.max_arrival = cfg.max_arrival
+    c.num_minislots = cfg.num_minislots
+    c.rb_per_unit = cfg.rb_per_unit
+    c.num_hidden = len(cfg.hidden)
+    for i, h in enumerate(cfg.hidden):
+        c.hidden[i] = h
+    c.precision = PRECISION[cfg.precision]
+    c.flags = (FLAG_EXPORT_LOGITS if export_logits else 0) | (FLAG_LEVEL_KERNEL if force_level else 0)
+    return c
+
+
+class _WeightsView:
+    """Keeps the float32 arrays referenced while the C struct points at them."""
+
+    def __init__(self, weights, act_scale=None):
+        self.arrays = []
+        self.struct = cyrus_weights()
+        for l, (w, b) in enumerate(weights):
+            w = np.ascontiguousarray(w, dtype=np.float32)
+            b = np.ascontiguousarray(b, dtype=np.float32)
+            self.arrays += [w, b]
+            self.struct.w[l] = w.ctypes.data_as(_f32p)
+            self.struct.b[l] = b.ctypes.data_as(_f32p)
+        if act_scale is not None:
+            a = np.ascontiguousarray(act_scale, dtype=np.float32)
+            self.arrays.append(a)
+            self.struct.act_scale = a.ctypes.data_as(_f32p)
+
+
+# ------------------------------------------------------- same-name wrappers
+
+def cyrus_codebook_workspace_size(cfg: cyrus_config):
+    d, h = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(lib().cyrus_codebook_workspace_size(ctypes.byref(cfg), ctypes.byref(d), ctypes.byref(h)),
+           "cyrus_codebook_workspace_size")
+    return d.value, h.value
+
+
+def cyrus_codebook_create(cfg: cyrus_config, w: cyrus_weights, ws_ptr: int, ws_bytes: int, host_ptr: int,
+                          host_bytes: int, stream) -> int:
+    out = ctypes.c_void_p()
+    _check(lib().cyrus_codebook_create(ctypes.byref(cfg), ctypes.byref(w), ws_ptr, ws_bytes, host_ptr, host_bytes,
+                                       _stream_ptr(stream), ctypes.byref(out)), "cyrus_codebook_create")
+    return out.value
+
+
+def cyrus_codebook_set_weights(h: int, w: cyrus_weights, stream) -> None:
+    _check(lib().cyrus_codebook_set_weights(h, ctypes.byref(w), _stream_ptr(stream)), "cyrus_codebook_set_weights")
+
+
+def cyrus_codebook_build(h: int, ue: cyrus_ue_state, stream) -> None:
+    _check(lib().cyrus_codebook_build(h, ctypes.byref(ue), _stream_ptr(stream)), "cyrus_codebook_build")
+
+
+def cyrus_codebook_build_device(h: int, ue_dev_ptr: int, stream) -> None:
+    _check(lib().cyrus_codebook_build_device(h, ue_dev_ptr, _stream_ptr(stream)), "cyrus_codebook_build_device")
+
+
+def cyrus_codebook_build_batch(handles: Sequence[int], ue_dev_ptrs: Sequence[int], stream) -> None:
+    n = len(handles)
+    hs = (ctypes.c_void_p * n)(*handles)
+    us = (ctypes.c_void_p * n)(*ue_dev_ptrs)
+    _check(lib().cyrus_codebook_build_batch(hs, us, n, _stream_ptr(stream)), "cyrus_codebook_build_batch")
+
+
+def cyrus_codebook_wait(h: int) -> None:
+    _check(lib().cyrus_codebook_wait(h), "cyrus_codebook_wait")
+
+
+def cyrus_codebook_lookup(h: int, arrivals: Sequence[int], num_ue: int) -> np.ndarray:
+    arr = np.ascontiguousarray(arrivals, dtype=np.uint8)
+    out = np.zeros(num_ue, dtype=np.uint8)
+    _check(lib().cyrus_codebook_lookup(h, arr.ctypes.data_as(_u8p), arr.size, out.ctypes.data_as(_u8p)),
+           "cyrus_codebook_lookup")
+    return out
+
+
+def cyrus_codebook_export(h: int, nodes: int, num_ue: int, logits: bool):
+    alloc = np.zeros((nodes, num_ue), dtype=np.uint8)
+    lg = np.zeros((nodes, num_ue), dtype=np.float32) if logits else None
+    _check(lib().cyrus_codebook_export(h, alloc.ctypes.data_as(_u8p), None if lg is None else lg.ctypes.data_as(_f32p)),
+           "cyrus_codebook_export")
+    return alloc, lg
+
+
+def cyrus_codebook_device_alloc(h: int) -> int:
+    return lib().cyrus_codebook_device_alloc(h)
+
+
+def cyrus_codebook_num_nodes(h: int) -> int:
+    return lib().cyrus_codebook_num_nodes(h)
+
+
+def cyrus_codebook_kernel_path(h: int) -> str:
+    return lib().cyrus_codebook_kernel_path(h).decode()
+
+
+def cyrus_codebook_destroy(h: int) -> None:
+    lib().cyrus_codebook_destroy(h)
+
+
+def cyrus_status_string(status: int) -> str:
+    return lib().cyrus_status_string(status).decode()
+
+
+def cyrus_last_error() -> str:
+    return lib().cyrus_last_error().decode()
+
+
+# ------------------------------------------------------------- convenience
+
+def ue_struct(ue: UEState):
+    rb = np.ascontiguousarray(ue.rb, dtype=np.int32)
+    mcs = np.ascontiguousarray(ue.mcs, dtype=np.int32)
+    sinr = np.ascontiguousarray(ue.sinr_db, dtype=np.float32)
+    s = cyrus_ue_state(rb.ctypes.data_as(_i32p), mcs.ctypes.data_as(_i32p), sinr.ctypes.data_as(_f32p))
+    return s, (rb, mcs, sinr)
+
+
+def ue_device_tensor(ue: UEState, device="cuda"):
+    """Device copy of a UE state in the layout of cyrus_codebook_build_device:
+    int32 rb[E], int32 mcs[E], float32 sinr_db[E] (as raw bits)."""
+    import torch
+    packed = np.concatenate([np.asarray(ue.rb, np.int32), np.asarray(ue.mcs, np.int32),
+                             np.asarray(ue.sinr_db, np.float32).view(np.int32)])
+    return torch.from_numpy(packed).to(device)
+
+
+class Codebook:
+    """One codebook builder with its caller-owned buffers (torch device memory
+    for the workspace, pinned host memory for the mirror)."""
+
+    def __init__(self, cfg: TreeConfig, weights, act_scale=None, export_logits: bool = False,
+                 force_level: bool = False, device: str = "cuda", stream=None):
+        import torch
+        self.cfg = cfg
+        self.device = torch.device(device)
+        self.cconf = make_config(cfg, export_logits, force_level)
+        self.export_logits = export_logits
+        self.ws_bytes, self.host_bytes = cyrus_codebook_workspace_size(self.cconf)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        self.host = torch.empty(self.host_bytes, dtype=torch.uint8, pin_memory=True)
+        self._w = _WeightsView(weights, act_scale)
+        self.stream = stream
+        with torch.cuda.device(self.device):
+            self.handle = cyrus_codebook_create(self.cconf, self._w.struct, self.ws.data_ptr(), self.ws_bytes,
+                                                self.host.data_ptr(), self.host_bytes, stream)
+        self.num_nodes = cyrus_codebook_num_nodes(self.handle)
+        self._ue_keep = None
+
+    @property
+    def kernel_path(self) -> str:
+        return cyrus_codebook_kernel_path(self.handle)
+
+    def set_weights(self, weights, act_scale=None):
+        self._w = _WeightsView(weights, act_scale)
+        cyrus_codebook_set_weights(self.handle, self._w.struct, self.stream)
+
+    def build(self, ue: UEState):
+        s, keep = ue_struct(ue)
+        cyrus_codebook_build(self.handle, s, self.stream)
+        return self
+
+    def build_device(self, ue_dev):
+        self._ue_keep = ue_dev
+        cyrus_codebook_build_device(self.handle, ue_dev.data_ptr(), self.stream)
+        return self
+
+    def wait(self):
+        cyrus_codebook_wait(self.handle)
+
+    def lookup(self, arrivals) -> np.ndarray:
+        return cyrus_codebook_lookup(self.handle, arrivals, self.cfg.num_ue)
+
+    def export(self):
+        return cyrus_codebook_export(self.handle, self.num_nodes, self.cfg.num_ue, self.export_logits)
+
+    def device_alloc_ptr(self) -> int:
+        return cyrus_codebook_device_alloc(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            cyrus_codebook_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def build_batch(codebooks: Sequence[Codebook], ue_devs, stream=None):
+    cyrus_codebook_build_batch([c.handle for c in codebooks], [u.data_ptr() for u in ue_devs], stream)
