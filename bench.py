@@ -1,0 +1,225 @@
+"""Benchmark of the puncturing-codebook builder on one MI355X.
+
+One step = one whole codebook build (every level of the arrival tree: feature
+assembly, actor MLP on MFMA, softmax, capped split, largest remainder) for the
+E=8, K=3, M=7 tree with a 34->256->256->8 actor (21,845 nodes, 16,383 actor
+evaluations), one codebook per launch, UE state already resident in HBM.
+
+Prints ONE JSON line. `value` is codebook nodes per second of the FP32 build
+(the headline precision); the same line carries the build-latency
+distribution against the 125 us numerology-3 slot (device-resident and
+host-inclusive, i.e. s(t) in host memory -> codebook in pinned host memory),
+the BF16 and FP8 legs, the roofline of the dominant kernel and the FP64 CPU
+oracle's rate on a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import glob
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_2506_00167_amd import workload as wl  # noqa: E402
+
+PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp8": 5000.0}
+SLOT_US = 125.0
+WORKLOAD = "tree-e8k3"
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2506_00167_amd", "csrc", "*"))):
+        h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel: str, precision: str):
+    """HBM bytes per launch measured with rocprofv3 counters, if the summary
+    was taken on the current kernel sources; otherwise None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    data = json.load(open(path))
+    entry = data.get(f"{kernel}/{WORKLOAD}/{precision}")
+    if not entry or entry.get("source_hash") != kernel_source_hash():
+        return None
+    return entry.get("bytes_per_launch")
+
+
+def fp8_act_scales(name: str, seed: int):
+    path = os.path.join(ROOT, "tests", "golden", "fp8_act_scales.json")
+    data = json.load(open(path))
+    return data[f"{name}/{seed}"]
+
+
+def pct(a, q):
+    return float(np.percentile(np.asarray(a), q))
+
+
+def run_leg(precision: str, steps: int, warmup: int, latency_builds: int, stream):
+    import torch
+    from paper_2506_00167_amd import cyrus
+
+    cfg = wl.WORKLOADS[WORKLOAD].with_precision(precision)
+    seed = wl.WEIGHT_SEEDS[WORKLOAD]
+    weights = wl.make_weights(cfg, seed)
+    act = fp8_act_scales(WORKLOAD, seed) if precision == "fp8" else None
+    cb = cyrus.Codebook(cfg, weights, act_scale=act, stream=stream)
+    ues = [wl.make_ue_state(cfg.num_ue, wl.ue_seed(i)) for i in range(64)]
+    ue_dev = [cyrus.ue_device_tensor(u) for u in ues]
+    torch.cuda.synchronize()
+
+    # throughput: back-to-back builds, device-resident inputs
+    for i in range(warmup):
+        cb.build_device(ue_dev[i % 64])
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        for i in range(steps):
+            ev[i][0].record(stream)
+            cb.build_device(ue_dev[i % 64])
+            ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    dev_us = np.array([a.elapsed_time(b) * 1e3 for a, b in ev])
+
+    # latency: one build at a time, host clock around enqueue + completion
+    lat_dev, lat_host = [], []
+    for i in range(latency_builds):
+        t = time.perf_counter()
+        cb.build_device(ue_dev[i % 64])
+        cb.wait()
+        lat_dev.append((time.perf_counter() - t) * 1e6)
+    for i in range(latency_builds):
+        u = ues[i % 64]
+        t = time.perf_counter()
+        cb.build(u)
+        cb.wait()
+        lat_host.append((time.perf_counter() - t) * 1e6)
+    path = cb.kernel_path
+    cb.close()
+
+    flops = cfg.flops_per_codebook
+    avg_us = float(dev_us.mean())
+    achieved = flops / (avg_us * 1e-6) / 1e12
+    return {
+        "precision": precision,
+        "kernel": f"{path}",
+        "nodes_per_s": cfg.num_nodes * steps / wall,
+        "evals_per_s": cfg.num_evals * steps / wall,
+        "ms_per_step": wall / steps * 1e3,
+        "device_us_mean": avg_us,
+        "device_us_p50": pct(dev_us, 50),
+        "device_us_p99": pct(dev_us, 99),
+        "latency_device_resident_us": {"p50": pct(lat_dev, 50), "p99": pct(lat_dev, 99),
+                                       "p99.9": pct(lat_dev, 99.9), "max": float(np.max(lat_dev)),
+                                       "misses_over_125us": int(np.sum(np.asarray(lat_dev) > SLOT_US)),
+                                       "builds": latency_builds},
+        "latency_host_inclusive_us": {"p50": pct(lat_host, 50), "p99": pct(lat_host, 99),
+                                      "p99.9": pct(lat_host, 99.9), "max": float(np.max(lat_host)),
+                                      "misses_over_125us": int(np.sum(np.asarray(lat_host) > SLOT_US)),
+                                      "builds": latency_builds},
+        "achieved_tflops": achieved,
+        "peak_tflops": PEAK_TFLOPS[precision],
+        "mfma_frac": achieved / PEAK_TFLOPS[precision],
+        "flops_per_launch": flops,
+    }
+
+
+def cpu_baseline(seconds: float):
+    """The FP64 oracle, single-threaded, on whole codebooks of the same
+    workload until `seconds` of CPU work have been spent."""
+    import oracle
+
+    cfg = wl.WORKLOADS[WORKLOAD]
+    weights = wl.make_weights(cfg, wl.WEIGHT_SEEDS[WORKLOAD])
+    actor = oracle.Actor(weights)
+    n = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        oracle.build_tree(cfg, weights, wl.make_ue_state(cfg.num_ue, wl.ue_seed(n)), actor=actor)
+        n += 1
+    dt = time.perf_counter() - t0
+    return {"value": cfg.num_nodes * n / dt, "unit": "nodes/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n} whole {WORKLOAD} codebooks (FP64, single thread), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--latency-builds", type=int, default=2000)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--legs", default="fp32,bf16,fp8")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: the codebook build of one cell fits one MI355X and this build has "
+              f"no multi-GPU path (asked for --gpus {args.gpus})", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2506_00167_amd import cyrus
+
+    cyrus.lib()  # fail loudly if the HIP library is missing
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    legs = {}
+    for prec in args.legs.split(","):
+        legs[prec] = run_leg(prec, args.steps, args.warmup, args.latency_builds, stream)
+        print(f"[bench] {prec}: {legs[prec]['nodes_per_s']:.4g} nodes/s, device {legs[prec]['device_us_mean']:.1f} us, "
+              f"p99 host {legs[prec]['latency_host_inclusive_us']['p99']:.1f} us", file=sys.stderr, flush=True)
+    head = legs["fp32"]
+    cfg = wl.WORKLOADS[WORKLOAD]
+    out = {
+        "metric": "codebook nodes/sec and p99 build latency vs 125us slot, BF16 vs FP32",
+        "value": head["nodes_per_s"],
+        "unit": "nodes/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{WORKLOAD}: E=8 K=3 M=7 actor 34->256->256->8, one codebook per launch, "
+                               f"{cfg.num_nodes} nodes, {cfg.num_evals} evaluations",
+                   "nodes": cfg.num_nodes, "evals": cfg.num_evals, "parallelism": "single GPU"},
+        "p99_build_latency_us": head["latency_device_resident_us"]["p99"],
+        "p99_build_latency_host_inclusive_us": head["latency_host_inclusive_us"]["p99"],
+        "slot_us": SLOT_US,
+        "roofline": {
+            "bound": "mfma",
+            "kernel": head["kernel"],
+            "achieved": head["achieved_tflops"],
+            "peak": PEAK_TFLOPS["fp32"],
+            "unit": "TFLOP/s",
+            "frac": head["mfma_frac"],
+            "traffic": load_traffic(head["kernel"], "fp32"),
+            "flops_per_launch": head["flops_per_launch"],
+            "avg_launch_us": head["device_us_mean"],
+        },
+        "legs": legs,
+    }
+    if "bf16" in legs:
+        out["bf16_vs_fp32_speedup"] = legs["bf16"]["nodes_per_s"] / head["nodes_per_s"]
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

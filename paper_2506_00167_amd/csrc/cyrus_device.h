@@ -233,6 +233,78 @@ __device__ __forceinline__ void enforce(int E, const float* z, const int* R, int
     }
 }
 
+// Lane-parallel enforcer: a group of G lanes (G a power of two >= E, G <= 64)
+// handles one node, lane e of the group UE e. Softmax, the capped split and
+// largest remainder use butterfly reductions inside the group; the extra unit
+// goes to UE e if it is eligible and fewer than r eligible UEs rank above it
+// (larger fraction, or equal fraction and lower index). Every lane of the group
+// must call this with the same row. Returns a_e (0 for lanes e >= E).
+template <int G>
+__device__ __forceinline__ float group_sum(float v)
+{
+#pragma unroll
+    for (int m = G / 2; m >= 1; m >>= 1)
+        v += __shfl_xor(v, m, G);
+    return v;
+}
+
+template <int G>
+__device__ __forceinline__ float group_max(float v)
+{
+#pragma unroll
+    for (int m = G / 2; m >= 1; m >>= 1)
+        v = fmaxf(v, __shfl_xor(v, m, G));
+    return v;
+}
+
+template <int G>
+__device__ __forceinline__ int group_isum(int v)
+{
+#pragma unroll
+    for (int m = G / 2; m >= 1; m >>= 1)
+        v += __shfl_xor(v, m, G);
+    return v;
+}
+
+template <int G>
+__device__ __forceinline__ int enforce_group(int E, int e, float z, int R, int rsum, int demand)
+{
+    const bool live = e < E;
+    const float zmax = group_max<G>(live ? z : -3.0e38f);
+    float p = live ? expf(fmaxf(z - zmax, -80.f)) : 0.f;
+    const float sum = group_sum<G>(p);
+    p = p / sum;
+    const int T = demand < rsum ? demand : rsum;
+    if (T >= rsum)
+        return live ? R : 0;
+    bool capped = !live;
+    float s = 0.f;
+    for (int pass = 0; pass <= G; ++pass) {
+        const float rem = (float)T - group_sum<G>((live && capped) ? (float)R : 0.f);
+        const float psum = group_sum<G>(capped ? 0.f : p);
+        s = rem / psum;
+        const bool grow = !capped && s * p >= (float)R;
+        if (group_isum<G>(grow ? 1 : 0) == 0)
+            break;
+        capped = capped || grow;
+    }
+    const float x = !live ? 0.f : (capped ? (float)R : s * p);
+    const float fl = floorf(x);
+    const int f = (int)fl;
+    const float frac = x - fl;
+    const int r = T - group_isum<G>(f);
+    const bool elig = live && f < R;
+    int rank = 0;
+#pragma unroll
+    for (int q = 0; q < G; ++q) {
+        const float fq = __shfl(frac, q, G);
+        const int eq = __shfl(elig ? 1 : 0, q, G);
+        if (q != e && eq && (fq > frac || (fq == frac && q < e)))
+            ++rank;
+    }
+    return f + ((elig && rank < r) ? 1 : 0);
+}
+
 __device__ __forceinline__ void enforce_any(int E, const float* z, const int* R, int rsum, int demand, int* a)
 {
     if (E <= 8)

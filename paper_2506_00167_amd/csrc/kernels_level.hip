@@ -49,7 +49,7 @@ __device__ __forceinline__ void finish_node(const DevTree& t, const float* z, co
 // Actor forward pass over `nrows` node rows whose features are in bufA.
 // Leaves the FP32 logits in zl[row * kLogitStride + e].
 template <int P, int RTT>
-__device__ void run_mlp(const DevTree& t, int nrows, uint8_t* bufA, uint8_t* bufB, float* zl)
+__device__ __forceinline__ void run_mlp(const DevTree& t, int nrows, uint8_t* bufA, uint8_t* bufB, float* zl)
 {
     constexpr int kc = Traits<P>::kChunk, es = Traits<P>::kEsize, RT = 16 * RTT;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, c16 = lane & 15;
@@ -150,7 +150,7 @@ __device__ void run_mlp(const DevTree& t, int nrows, uint8_t* bufA, uint8_t* buf
 
 // One tile of evaluated rows [row0, row0 + nrows) of level tau.
 template <int P, int RTT>
-__device__ void level_tile(const DevTree& t, int tau, int row0, int nrows, uint8_t* smem, int bufsize)
+__device__ __forceinline__ void level_tile(const DevTree& t, int tau, int row0, int nrows, uint8_t* smem, int bufsize)
 {
     constexpr int es = Traits<P>::kEsize, RT = 16 * RTT;
     uint8_t* bufA = smem;
@@ -241,7 +241,7 @@ __global__ __launch_bounds__(kThreads) void level_kernel_batch(const DevTree* tr
         else
             hi = mid - 1;
     }
-    const DevTree t = trees[ent_tree[lo]];
+    const DevTree& t = trees[ent_tree[lo]];
     const int tau = ent_tau[lo];
     const int n_eval = (int)(t.K * (dev_level_offset(t.K, tau) - dev_level_offset(t.K, tau - 1)));
     const int row0 = (b - prefix[lo]) * 16 * RTT;

@@ -1,11 +1,602 @@
-// Subtree kernel: placeholder until the single-launch latency path lands.
+// Subtree kernel: the whole codebook in ONE launch, for actors whose weights
+// fit in the register file of one CU (hidden width 128 or 256, up to two
+// hidden layers, E <= 16).
+//
+// The tree is cut at level L: workgroup r (one per CU) owns the subtree below
+// node r of level L. It first walks the L ancestors of that node from the
+// root (one evaluation each, recomputed redundantly by the workgroups that
+// share them; the first descendant writes them), then expands its subtree
+// level by level with workgroup barriers only. Nodes below different level-L
+// nodes never interact, so no grid-wide synchronisation is needed.
+//
+// Every wave loads its share of the actor into registers once (the MFMA A
+// fragments of its output-neuron tiles, plus its slice of the output layer's
+// reduction dimension); afterwards each level step only moves node
+// activations through LDS.
 #include "cyrus_device.h"
 #include "cyrus_host.h"
 
 namespace cyrus {
 
-bool subtree_supported(const DevTree&, int) { return false; }
+namespace {
 
-hipError_t launch_subtree(const DevTree&, int, hipStream_t) { return hipErrorInvalidValue; }
+// Row tiles per pass: 64 rows for BF16/FP8; 48 for FP32, whose register-
+// resident weights leave room for fewer accumulators.
+template <int P>
+struct Rows {
+    static constexpr int kRTT = (P == kFP32) ? 3 : 4;
+    static constexpr int kRT = 16 * kRTT;
+};
+constexpr int kRTmax = 64;
+
+__device__ __forceinline__ int64_t sub_level_offset(int K, int tau)
+{
+    int64_t p = 1;
+    for (int i = 0; i < tau; ++i)
+        p *= (K + 1);
+    return (p - 1) / K;
+}
+
+__device__ __forceinline__ int ipow_dev(int b, int e)
+{
+    int r = 1;
+    for (int i = 0; i < e; ++i)
+        r *= b;
+    return r;
+}
+
+// Register-resident fragments of one wave.
+//   T     output-neuron tiles of 16 per hidden layer owned by this wave
+//   CH1   chunks of the first layer's (padded) input, upper bound
+//   CHH   chunks of a hidden layer's input (H / chunk)
+//   NHH   hidden->hidden layers (0 or 1)
+template <int P, int T, int CH1, int CHH, int NHH>
+struct WaveWeights {
+    static constexpr int CPW = (CHH + kWaves - 1) / kWaves;  // output-layer chunks per wave
+    uint4 w1[T][CH1];
+    uint4 wh[NHH > 0 ? T : 1][NHH > 0 ? CHH : 1];
+    uint4 wo[CPW];
+};
+
+template <int P, int T, int CH1, int CHH, int NHH>
+__device__ __forceinline__ void load_weights(const DevTree& t, WaveWeights<P, T, CH1, CHH, NHH>& W, int wave,
+                                             int lane)
+{
+    using WW = WaveWeights<P, T, CH1, CHH, NHH>;
+    constexpr int kc = Traits<P>::kChunk;
+    const int nch1 = t.in_pad[0] / kc;
+    const uint4* g1 = reinterpret_cast<const uint4*>(t.w[0]);
+#pragma unroll
+    for (int tt = 0; tt < T; ++tt) {
+        const int nt = wave + kWaves * tt;
+#pragma unroll
+        for (int c = 0; c < CH1; ++c)
+            W.w1[tt][c] = (c < nch1) ? g1[((size_t)nt * nch1 + c) * 64 + lane] : uint4{0, 0, 0, 0};
+    }
+    if constexpr (NHH > 0) {
+        const uint4* gh = reinterpret_cast<const uint4*>(t.w[1]);
+#pragma unroll
+        for (int tt = 0; tt < T; ++tt) {
+            const int nt = wave + kWaves * tt;
+#pragma unroll
+            for (int c = 0; c < CHH; ++c)
+                W.wh[tt][c] = gh[((size_t)nt * CHH + c) * 64 + lane];
+        }
+    }
+    const uint4* go = reinterpret_cast<const uint4*>(t.w[NHH + 1]);
+#pragma unroll
+    for (int j = 0; j < WW::CPW; ++j) {
+        const int c = wave * WW::CPW + j;
+        W.wo[j] = (c < CHH) ? go[(size_t)c * 64 + lane] : uint4{0, 0, 0, 0};
+    }
+}
+
+// One layer with register-resident A fragments: out = act(A * in) for the
+// wave's T neuron tiles over `art` row tiles.
+template <int P, int T, int NCH>
+__device__ __forceinline__ void layer_regs(const uint4 (&A)[T][NCH], int nch, const uint8_t* in, int sin,
+                                           uint8_t* out, int sout, const float* bias, float deq, float inv_next,
+                                           int art, int wave, int g, int c16)
+{
+    constexpr int kc = Traits<P>::kChunk, es = Traits<P>::kEsize, kRTT = Rows<P>::kRTT;
+    floatx4 acc[T][kRTT];
+#pragma unroll
+    for (int tt = 0; tt < T; ++tt)
+#pragma unroll
+        for (int rt = 0; rt < kRTT; ++rt)
+            acc[tt][rt] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const uint8_t* bp = in + c16 * sin + g * (kc / 4) * es;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+        if (c < nch) {
+#pragma unroll
+            for (int rt = 0; rt < kRTT; ++rt) {
+                if (rt < art) {
+                    const uint4 b = *reinterpret_cast<const uint4*>(bp + rt * 16 * sin + c * kc * es);
+#pragma unroll
+                    for (int tt = 0; tt < T; ++tt)
+                        mma_chunk<P>(A[tt][c], b, acc[tt][rt]);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int tt = 0; tt < T; ++tt) {
+        const int nt = wave + kWaves * tt;
+        const float* bb = bias + nt * 16 + g * 4;
+        const float b0 = bb[0], b1 = bb[1], b2 = bb[2], b3 = bb[3];
+#pragma unroll
+        for (int rt = 0; rt < kRTT; ++rt) {
+            if (rt < art) {
+                store4<P>(out + (rt * 16 + c16) * sout + (nt * 16 + g * 4) * es,
+                          fmaxf(acc[tt][rt][0] * deq + b0, 0.f), fmaxf(acc[tt][rt][1] * deq + b1, 0.f),
+                          fmaxf(acc[tt][rt][2] * deq + b2, 0.f), fmaxf(acc[tt][rt][3] * deq + b3, 0.f), inv_next);
+            }
+        }
+    }
+}
+
+// FP32, few rows: the same register-resident fragments used as a GEMV on
+// the vector ALU. Lane (g, i) holds W[n0 + i][16c + 4g + j]; it multiplies its
+// four weights of every chunk with the matching inputs (an LDS broadcast),
+// and the four lane groups are summed with two butterfly steps, so each lane
+// ends with the whole dot product of neuron n0 + i. `relu` selects the hidden
+// epilogue; the output layer leaves per-wave partial sums instead.
+template <int T, int NCH>
+__device__ __forceinline__ void layer_valu(const uint4 (&A)[T][NCH], int nch, const float* in, int sin_f, int nrows,
+                                           float* out, int sout_f, const float* bias, int wave, int g, int c16)
+{
+    for (int r = 0; r < nrows; ++r) {
+        float acc[T];
+#pragma unroll
+        for (int tt = 0; tt < T; ++tt)
+            acc[tt] = 0.f;
+        const float* hr = in + r * sin_f + 4 * g;
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            if (c < nch) {
+                const floatx4 h = *reinterpret_cast<const floatx4*>(hr + 16 * c);
+#pragma unroll
+                for (int tt = 0; tt < T; ++tt) {
+                    acc[tt] = fmaf(__uint_as_float(A[tt][c].x), h[0], acc[tt]);
+                    acc[tt] = fmaf(__uint_as_float(A[tt][c].y), h[1], acc[tt]);
+                    acc[tt] = fmaf(__uint_as_float(A[tt][c].z), h[2], acc[tt]);
+                    acc[tt] = fmaf(__uint_as_float(A[tt][c].w), h[3], acc[tt]);
+                }
+            }
+        }
+#pragma unroll
+        for (int tt = 0; tt < T; ++tt) {
+            float v = acc[tt];
+            v += __shfl_xor(v, 16);
+            v += __shfl_xor(v, 32);
+            const int n = (wave + kWaves * tt) * 16 + c16;
+            if (g == 0)
+                out[r * sout_f + n] = fmaxf(v + bias[n], 0.f);
+        }
+    }
+}
+
+// Actor forward pass over nrows <= 64 rows whose features are in bufA;
+// logits end in zl. bias: LDS copy of every layer's bias (bias_off[l]).
+template <int P, int T, int CH1, int CHH, int NHH>
+__device__ __forceinline__ void mlp_regs(const DevTree& t, const WaveWeights<P, T, CH1, CHH, NHH>& W, int nrows,
+                                         uint8_t* bufA, uint8_t* bufB, float* zl, const float* bias,
+                                         const int* bias_off)
+{
+    using WW = WaveWeights<P, T, CH1, CHH, NHH>;
+    constexpr int kc = Traits<P>::kChunk, es = Traits<P>::kEsize, kRTT = Rows<P>::kRTT, kRT = Rows<P>::kRT;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, c16 = lane & 15;
+    const int art = (nrows + 15) >> 4;
+    const int s0 = t.in_pad[0] * es + 16, sh = CHH * kc * es + 16;
+    const int nch1 = t.in_pad[0] / kc;
+    const bool valu = (P == kFP32) && nrows <= 4;
+    if constexpr (P == kFP32) {
+        if (valu)
+            layer_valu<T, CH1>(W.w1, nch1, reinterpret_cast<const float*>(bufA), s0 / 4, nrows,
+                               reinterpret_cast<float*>(bufB), sh / 4, bias + bias_off[0], wave, g, c16);
+    }
+    if (!valu)
+        layer_regs<P, T, CH1>(W.w1, nch1, bufA, s0, bufB, sh, bias + bias_off[0], t.deq[0], t.inv_in_scale[1], art,
+                              wave, g, c16);
+    __syncthreads();
+    uint8_t* in = bufB;
+    uint8_t* out = bufA;
+    if constexpr (NHH > 0) {
+        if constexpr (P == kFP32) {
+            if (valu)
+                layer_valu<T, CHH>(W.wh, CHH, reinterpret_cast<const float*>(bufB), sh / 4, nrows,
+                                   reinterpret_cast<float*>(bufA), sh / 4, bias + bias_off[1], wave, g, c16);
+        }
+        if (!valu)
+            layer_regs<P, T, CHH>(W.wh, CHH, bufB, sh, bufA, sh, bias + bias_off[1], t.deq[1], t.inv_in_scale[2],
+                                  art, wave, g, c16);
+        __syncthreads();
+        in = bufA;
+        out = bufB;
+    }
+    // output layer: this wave's slice of the reduction, partial tile to LDS
+    float* part = reinterpret_cast<float*>(out);
+    if (valu) {
+        for (int r = 0; r < nrows; ++r) {
+            float acc = 0.f;
+            const float* hr = reinterpret_cast<const float*>(in) + r * (sh / 4) + 4 * g;
+#pragma unroll
+            for (int j = 0; j < WW::CPW; ++j) {
+                const int c = wave * WW::CPW + j;
+                if (c < CHH) {
+                    const floatx4 h = *reinterpret_cast<const floatx4*>(hr + 16 * c);
+                    acc = fmaf(__uint_as_float(W.wo[j].x), h[0], acc);
+                    acc = fmaf(__uint_as_float(W.wo[j].y), h[1], acc);
+                    acc = fmaf(__uint_as_float(W.wo[j].z), h[2], acc);
+                    acc = fmaf(__uint_as_float(W.wo[j].w), h[3], acc);
+                }
+            }
+            acc += __shfl_xor(acc, 16);
+            acc += __shfl_xor(acc, 32);
+            if (g == 0)
+                part[(size_t)(wave * kRT + r) * 16 + c16] = acc;
+        }
+    } else {
+        floatx4 acc[kRTT];
+#pragma unroll
+        for (int rt = 0; rt < kRTT; ++rt)
+            acc[rt] = floatx4{0.f, 0.f, 0.f, 0.f};
+        const uint8_t* bp = in + c16 * sh + g * (kc / 4) * es;
+#pragma unroll
+        for (int j = 0; j < WW::CPW; ++j) {
+            const int c = wave * WW::CPW + j;
+            if (c < CHH) {
+#pragma unroll
+                for (int rt = 0; rt < kRTT; ++rt)
+                    if (rt < art) {
+                        const uint4 b = *reinterpret_cast<const uint4*>(bp + rt * 16 * sh + c * kc * es);
+                        mma_chunk<P>(W.wo[j], b, acc[rt]);
+                    }
+            }
+        }
+#pragma unroll
+        for (int rt = 0; rt < kRTT; ++rt)
+            if (rt < art)
+                *reinterpret_cast<floatx4*>(part + (size_t)(wave * kRT + rt * 16 + c16) * 16 + g * 4) = acc[rt];
+    }
+    __syncthreads();
+    const int E = t.E;
+    const float deq = t.deq[NHH + 1];
+    const float* bo = bias + bias_off[NHH + 1];
+    for (int idx = threadIdx.x; idx < nrows * E; idx += kThreads) {
+        const int row = idx / E, e = idx - row * E;
+        float s = 0.f;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w)
+            s += part[(size_t)(w * kRT + row) * 16 + e];
+        zl[row * kLogitStride + e] = s * deq + bo[e];
+    }
+    __syncthreads();
+}
+
+struct SubtreeSmem {
+    uint8_t* bufA;
+    uint8_t* bufB;
+    float* zl;
+    int* R;         // kMaxUE
+    int* misc;      // [0] = sum R, [1..kMaxLayers] = bias offsets
+    float* statf;   // 3 * kMaxUE static features: R/32, MCS/32, SINR/32
+    float* bias;    // every layer's bias, out_pad each
+    uint8_t* st0;   // states of the previous level (local nodes), E bytes each
+    uint8_t* st1;   // states of the current level
+};
+
+// Feature rows for `nrows` nodes: state from state_of(row), level tau,
+// arrival arrival_of(row).
+template <int P, class StateOf, class ArrivalOf>
+__device__ __forceinline__ void write_features(const DevTree& t, const SubtreeSmem& sm, int nrows, int tau,
+                                               StateOf state_of, ArrivalOf arrival_of)
+{
+    constexpr int es = Traits<P>::kEsize;
+    const int E = t.E, in0 = t.in_pad[0], d_in = t.in_dim0, s0 = in0 * es + 16;
+    const int nrows_pad = ((nrows + 15) >> 4) << 4;
+    const float inv0 = t.inv_in_scale[0];
+    for (int idx = threadIdx.x; idx < nrows_pad * in0; idx += kThreads) {
+        const int row = idx / in0, f = idx - row * in0;
+        float v = 0.f;
+        if (row < nrows && f < d_in) {
+            if (f < 3 * E)
+                v = sm.statf[f];
+            else if (f < 4 * E)
+                v = (float)state_of(row)[f - 3 * E] * (1.f / 64.f);
+            else if (f == 4 * E)
+                v = (float)tau * (1.f / 8.f);
+            else
+                v = (float)arrival_of(row) * (1.f / 8.f);
+        }
+        store1<P>(sm.bufA + row * s0 + f * es, v, inv0);
+    }
+}
+
+// Enforcer over `nrows` rows, G lanes per row: row r has arrival k_of(r),
+// input state cin_of(r), and writes its state to sout_of(r) (LDS) and, if
+// node_of(r) >= 0, alloc/state/logits of that node to global memory.
+template <int G, class KOf, class CinOf, class SoutOf, class NodeOf>
+__device__ __forceinline__ void finish_rows(const DevTree& t, const SubtreeSmem& sm, int nrows, KOf k_of, CinOf cin_of,
+                                            SoutOf sout_of, NodeOf node_of)
+{
+    const int E = t.E;
+    for (int base = 0; base < nrows; base += kThreads / G) {
+        const int row = base + (int)threadIdx.x / G, e = (int)threadIdx.x % G;
+        const bool active = row < nrows;  // uniform within a group
+        if (active) {
+            const float z = e < E ? sm.zl[row * kLogitStride + e] : 0.f;
+            const int k = k_of(row);
+            const int R = e < E ? sm.R[e] : 0;
+            const int a = enforce_group<G>(E, e, z, R, sm.misc[0], t.U * k);
+            if (e < E) {
+                const uint8_t st = (uint8_t)(cin_of(row)[e] + a);
+                sout_of(row)[e] = st;
+                const int64_t node = node_of(row);
+                if (node >= 0) {
+                    t.alloc[node * E + e] = (uint8_t)a;
+                    t.state[node * E + e] = st;
+                    if (t.logits)
+                        t.logits[node * E + e] = z;
+                }
+            }
+        }
+    }
+}
+
+template <int P, int T, int CH1, int CHH, int NHH, int G>
+__device__ __forceinline__ void subtree_body(const DevTree& t, int split, int bufsize, int stbytes, uint8_t* smem)
+{
+    SubtreeSmem sm;
+    sm.bufA = smem;
+    sm.bufB = smem + bufsize;
+    sm.zl = reinterpret_cast<float*>(smem + 2 * bufsize);
+    sm.R = reinterpret_cast<int*>(sm.zl + kRTmax * kLogitStride);
+    sm.misc = sm.R + kMaxUE;
+    sm.statf = reinterpret_cast<float*>(sm.misc + 8);
+    sm.bias = sm.statf + 3 * kMaxUE;
+    int nbias = 0;
+    for (int l = 0; l < t.n_layers; ++l)
+        nbias += t.out_pad[l];
+    sm.st0 = reinterpret_cast<uint8_t*>(sm.bias + nbias);
+    sm.st1 = sm.st0 + stbytes;
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int E = t.E, K = t.K, M = t.M, K1 = K + 1;
+    const int r = blockIdx.x;
+
+    WaveWeights<P, T, CH1, CHH, NHH> W;
+    load_weights(t, W, wave, lane);
+
+    if (threadIdx.x < E) {
+        const int e = threadIdx.x;
+        sm.R[e] = t.ue[e];
+        sm.statf[e] = (float)t.ue[e] * (1.f / 32.f);
+        sm.statf[E + e] = (float)t.ue[E + e] * (1.f / 32.f);
+        sm.statf[2 * E + e] = __int_as_float(t.ue[2 * E + e]) * (1.f / 32.f);
+        sm.st0[e] = 0;  // root state
+    }
+    if (threadIdx.x == 0) {
+        int off = 0;
+        for (int l = 0; l < t.n_layers; ++l) {
+            sm.misc[1 + l] = off;
+            off += t.out_pad[l];
+        }
+    }
+    {
+        int off = 0;
+        for (int l = 0; l < t.n_layers; ++l) {
+            for (int i = threadIdx.x; i < t.out_pad[l]; i += kThreads)
+                sm.bias[off + i] = t.b[l][i];
+            off += t.out_pad[l];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int s = 0;
+        for (int e = 0; e < E; ++e)
+            s += sm.R[e];
+        sm.misc[0] = s;
+    }
+    __syncthreads();
+    const int* bias_off = sm.misc + 1;
+
+    // ---- ancestors of subtree root r, levels 1..split (state in st0[0..E))
+    for (int tau = 1; tau <= split; ++tau) {
+        const int below = ipow_dev(K1, split - tau);
+        const int idx = r / below;  // index of the ancestor within level tau
+        const int k = idx % K1;
+        const int64_t node = sub_level_offset(K, tau) + idx;
+        const bool owner = (r % below) == 0;
+        if (k > 0) {
+            write_features<P>(t, sm, 1, tau, [&](int) { return sm.st0; }, [&](int) { return k; });
+            __syncthreads();
+            mlp_regs<P, T, CH1, CHH, NHH>(t, W, 1, sm.bufA, sm.bufB, sm.zl, sm.bias, bias_off);
+            finish_rows<G>(
+                t, sm, 1, [&](int) { return k; }, [&](int) { return sm.st0; }, [&](int) { return sm.st1; },
+                [&](int) { return owner ? node : (int64_t)-1; });
+        } else if (threadIdx.x < E) {
+            sm.st1[threadIdx.x] = sm.st0[threadIdx.x];
+            if (owner) {
+                t.alloc[node * E + threadIdx.x] = 0;
+                t.state[node * E + threadIdx.x] = sm.st0[threadIdx.x];
+                if (t.logits)
+                    t.logits[node * E + threadIdx.x] = 0.f;
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < E)
+            sm.st0[threadIdx.x] = sm.st1[threadIdx.x];
+        __syncthreads();
+    }
+
+    // ---- subtree levels split+1..M; st0 holds the previous level's states
+    for (int tau = split + 1; tau <= M; ++tau) {
+        const int d = tau - split;
+        const int width = ipow_dev(K1, d);
+        const int n_eval = K * (width / K1);
+        const int64_t base = sub_level_offset(K, tau) + (int64_t)r * width;
+        uint8_t* prev = sm.st0;
+        uint8_t* cur = sm.st1;
+        constexpr int kRT = Rows<P>::kRT;
+        for (int j0 = 0; j0 < n_eval; j0 += kRT) {
+            const int nrows = min(kRT, n_eval - j0);
+            write_features<P>(
+                t, sm, nrows, tau, [&](int row) { return prev + ((j0 + row) / K) * E; },
+                [&](int row) { return (j0 + row) % K + 1; });
+            __syncthreads();
+            mlp_regs<P, T, CH1, CHH, NHH>(t, W, nrows, sm.bufA, sm.bufB, sm.zl, sm.bias, bias_off);
+            finish_rows<G>(
+                t, sm, nrows, [&](int row) { return (j0 + row) % K + 1; },
+                [&](int row) { return prev + ((j0 + row) / K) * E; },
+                [&](int row) {
+                    const int j = j0 + row;
+                    return cur + ((j / K) * K1 + j % K + 1) * E;
+                },
+                [&](int row) {
+                    const int j = j0 + row;
+                    return base + (j / K) * K1 + j % K + 1;
+                });
+            __syncthreads();
+        }
+        // k = 0 children: nothing punctured, parent state passed on
+        for (int idx = threadIdx.x; idx < (width / K1) * E; idx += kThreads) {
+            const int p = idx / E, e = idx - p * E, q = p * K1;
+            const uint8_t st = prev[p * E + e];
+            cur[q * E + e] = st;
+            t.alloc[(base + q) * E + e] = 0;
+            t.state[(base + q) * E + e] = st;
+            if (t.logits)
+                t.logits[(base + q) * E + e] = 0.f;
+        }
+        __syncthreads();
+        uint8_t* tmp = sm.st0;
+        sm.st0 = sm.st1;
+        sm.st1 = tmp;
+    }
+}
+
+template <int P, int T, int CH1, int CHH, int NHH>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 2))) void subtree_kernel(
+    DevTree t, int split, int bufsize, int stbytes)
+{
+    extern __shared__ __align__(16) uint8_t smem[];
+    if (t.E <= 8)
+        subtree_body<P, T, CH1, CHH, NHH, 8>(t, split, bufsize, stbytes, smem);
+    else
+        subtree_body<P, T, CH1, CHH, NHH, 16>(t, split, bufsize, stbytes, smem);
+}
+
+struct SubtreePlan {
+    int split;    // level L of the subtree roots
+    int grid;     // (K+1)^L workgroups
+    int bufsize;  // one ping-pong buffer
+    int stbytes;  // one level of subtree states
+    size_t lds;
+};
+
+int g_num_cu = 0;
+
+int num_cus()
+{
+    if (g_num_cu == 0) {
+        int dev = 0, n = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
+            g_num_cu = n;
+        else
+            g_num_cu = 256;
+    }
+    return g_num_cu;
+}
+
+bool plan_subtree(const DevTree& t, int prec, SubtreePlan& pl)
+{
+    if (t.E > 16 || t.n_layers < 2 || t.n_layers > 3)
+        return false;
+    const int H = t.out_pad[0];
+    if (H != 128 && H != 256)
+        return false;
+    if (t.n_layers == 3 && t.out_pad[1] != H)
+        return false;
+    const int kc = prec_chunk(prec), es = prec_esize(prec);
+    const int ch1_max = prec == kFP32 ? 5 : (prec == kBF16 ? 3 : 2);
+    if (t.in_pad[0] / kc > ch1_max)
+        return false;
+    const int ncu = num_cus();
+    int split = 0;
+    while (split + 1 <= t.M - 1 && ipow(t.K + 1, split + 1) <= ncu)
+        ++split;
+    const int64_t width_max = ipow(t.K + 1, t.M - split);
+    const int64_t st = width_max * t.E;
+    if (st > 16 * 1024)
+        return false;
+    // the biggest subtree level must not serialise too many passes
+    if (t.K * ipow(t.K + 1, t.M - split - 1) > 8 * kRTmax)
+        return false;
+    size_t stride = (size_t)t.in_pad[0] * es + 16;
+    stride = std::max(stride, (size_t)H * es + 16);
+    size_t buf = std::max(stride * kRTmax, (size_t)kWaves * kRTmax * 16 * 4);
+    buf = (buf + 15) & ~(size_t)15;
+    pl.split = split;
+    pl.grid = (int)ipow(t.K + 1, split);
+    pl.bufsize = (int)buf;
+    pl.stbytes = (int)((st + 15) & ~15);
+    size_t nbias = 0;
+    for (int l = 0; l < t.n_layers; ++l)
+        nbias += t.out_pad[l];
+    pl.lds = 2 * buf + (size_t)kRTmax * kLogitStride * 4 + (kMaxUE + 8) * 4 + 3 * kMaxUE * 4 + nbias * 4 +
+             2 * (size_t)pl.stbytes;
+    return pl.lds <= 160 * 1024;
+}
+
+template <int P, int T, int CH1, int CHH, int NHH>
+hipError_t launch_t(const DevTree& t, const SubtreePlan& pl, hipStream_t s)
+{
+    static bool attr = false;
+    if (!attr) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&subtree_kernel<P, T, CH1, CHH, NHH>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        attr = true;
+    }
+    hipLaunchKernelGGL((subtree_kernel<P, T, CH1, CHH, NHH>), dim3(pl.grid), dim3(kThreads), pl.lds, s, t, pl.split,
+                       pl.bufsize, pl.stbytes);
+    return hipGetLastError();
+}
+
+template <int P, int CH1>
+hipError_t dispatch_width(const DevTree& t, const SubtreePlan& pl, hipStream_t s)
+{
+    constexpr int kc = Traits<P>::kChunk;
+    const int H = t.out_pad[0];
+    const bool two = t.n_layers == 3;
+    if (H == 256)
+        return two ? launch_t<P, 2, CH1, 256 / kc, 1>(t, pl, s) : launch_t<P, 2, CH1, 256 / kc, 0>(t, pl, s);
+    return two ? launch_t<P, 1, CH1, 128 / kc, 1>(t, pl, s) : launch_t<P, 1, CH1, 128 / kc, 0>(t, pl, s);
+}
+
+}  // namespace
+
+bool subtree_supported(const DevTree& t, int prec)
+{
+    SubtreePlan pl;
+    return plan_subtree(t, prec, pl);
+}
+
+hipError_t launch_subtree(const DevTree& t, int prec, hipStream_t s)
+{
+    SubtreePlan pl;
+    if (!plan_subtree(t, prec, pl))
+        return hipErrorInvalidValue;
+    const int nch1 = t.in_pad[0] / prec_chunk(prec);
+    // register arrays are sized by the first layer's chunk count (rounded up)
+    if (prec == kFP32)
+        return nch1 <= 2 ? dispatch_width<kFP32, 2>(t, pl, s)
+                         : (nch1 <= 3 ? dispatch_width<kFP32, 3>(t, pl, s) : dispatch_width<kFP32, 5>(t, pl, s));
+    if (prec == kBF16)
+        return nch1 <= 2 ? dispatch_width<kBF16, 2>(t, pl, s) : dispatch_width<kBF16, 3>(t, pl, s);
+    return nch1 <= 1 ? dispatch_width<kFP8, 1>(t, pl, s) : dispatch_width<kFP8, 2>(t, pl, s);
+}
 
 }  // namespace cyrus

@@ -78,6 +78,16 @@ def test_shapes_fp32(shape):
         cb.close()
 
 
+def test_latency_path_is_selected():
+    for cfg in (wl.TINY, wl.TREE_E8K3, wl.PAPER_DEPTH1, wl.TREE_E8K3.with_precision("bf16")):
+        cb = cyrus.Codebook(cfg, wl.make_weights(cfg, 1), act_scale=None)
+        assert cb.kernel_path == "subtree", cfg
+        cb.close()
+    cb = cyrus.Codebook(wl.TREE_E8K3, wl.make_weights(wl.TREE_E8K3, 1), force_level=True)
+    assert cb.kernel_path == "level"
+    cb.close()
+
+
 def test_lookup_matches_export_and_oracle_rollouts():
     cfg = wl.TREE_E8K3
     weights = wl.make_weights(cfg, wl.WEIGHT_SEEDS["tree-e8k3"])
