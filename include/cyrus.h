@@ -177,6 +177,64 @@ void cyrus_codebook_destroy(cyrus_codebook* cb);
 const char* cyrus_status_string(int status);
 const char* cyrus_last_error(void);
 
+/* ------------------------------------------------------------------------
+ * Serving engine: continuous batching of codebook requests from many cells.
+ *
+ * Each cell is a cyrus_codebook handle (its actor weights stay resident in its
+ * workspace). A request is one TTI of one cell (Alg. 2 for that cell). The
+ * engine advances every admitted request by one tree level per step, in ONE
+ * batched launch whatever the requests' shapes and current levels, and admits
+ * waiting requests (FIFO) between steps as device-pool memory and batch slots
+ * free up, so requests that arrive while others are on the GPU join the next
+ * launch. A request's tree (allocations and states) lives in the engine's
+ * device pool until its codebook has been copied to the engine's pinned host
+ * pool; results are bit-identical to the same request built alone by the
+ * engine. All cells of an engine must share one precision; every step uses the
+ * level kernel.
+ *
+ * device_pool / host_pool: caller-owned device memory (align 256) and pinned
+ * host memory (align 64) from which requests are admitted.
+ * max_active: requests batched per step, in [1, 128].
+ * A handle is used by one host thread at a time. */
+typedef struct cyrus_engine cyrus_engine;
+
+#define CYRUS_REQ_WAITING 0  /* queued, not admitted (memory or batch full) */
+#define CYRUS_REQ_RUNNING 1  /* admitted, levels in flight */
+#define CYRUS_REQ_DONE 2     /* codebook in the host pool, result() may copy it */
+
+int cyrus_engine_create(void* device_pool, size_t device_bytes, void* host_pool, size_t host_bytes,
+                        int32_t max_active, void* stream, cyrus_engine** out);
+
+/* Queue one request for `cell`; the UE arrays are copied before returning.
+ * *ticket receives an id (increasing from 0). */
+int cyrus_engine_submit(cyrus_engine* eng, cyrus_codebook* cell, const cyrus_ue_state* ue, int64_t* ticket);
+
+/* One engine iteration: retire requests whose codebook copy finished, admit
+ * waiting requests that fit, then enqueue one batched level launch for all
+ * running requests (and the host copies of the ones that reached level M).
+ * Never blocks on the GPU except to reuse a descriptor slot still in flight.
+ * Outputs (nullable): running and waiting request counts after the step. */
+int cyrus_engine_step(cyrus_engine* eng, int32_t* running, int32_t* waiting);
+
+/* Status of a ticket (CYRUS_REQ_*); *latency_us (nullable) receives, once
+ * done, the time from submit to the step that observed completion. */
+int cyrus_engine_poll(cyrus_engine* eng, int64_t ticket, int32_t* status, double* latency_us);
+
+/* Tickets that became done since the previous call (at most `cap`), with
+ * their latencies in microseconds (nullable); *n receives the count. */
+int cyrus_engine_completed(cyrus_engine* eng, int64_t* tickets, double* latency_us, int32_t cap, int32_t* n);
+
+/* Copy a finished request's codebook ([nodes][E] bytes) and release its slot. */
+int cyrus_engine_result(cyrus_engine* eng, int64_t ticket, uint8_t* alloc, size_t bytes);
+
+/* Counters: [0] submitted, [1] completed, [2] steps launched, [3] admissions
+ * deferred for memory, [4] admissions deferred for batch slots,
+ * [5] device-pool bytes in use, [6] peak device-pool bytes in use. */
+int cyrus_engine_stats(const cyrus_engine* eng, int64_t* counters, int32_t n);
+
+/* Waits for all enqueued work, then frees the engine (not the pools). */
+void cyrus_engine_destroy(cyrus_engine* eng);
+
 #ifdef __cplusplus
 }
 #endif

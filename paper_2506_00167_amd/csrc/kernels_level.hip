@@ -6,6 +6,8 @@
 // feasibility enforcer and writes the nodes' puncturing vectors and states.
 // This is the general path (any width, depth, precision, cells batched per
 // launch); the latency path for small trees is kernels_subtree.hip.
+#include <algorithm>
+
 #include "cyrus_device.h"
 #include "cyrus_kernels.h"
 
@@ -225,30 +227,33 @@ __global__ __launch_bounds__(kThreads) void level_kernel(DevTree t, int tau, int
 
 // Batched level launch over several codebooks (cells), each at its own level:
 // entry j of the launch is codebook ent_tree[j] at level ent_tau[j] and owns
-// workgroups [prefix[j], prefix[j+1]).
+// row tiles [prefix[j], prefix[j+1]) of the prefix[n] tiles of the launch.
+// Persistent: a grid of at most one workgroup per CU strides over the tiles.
 template <int P, int RTT>
 __global__ __launch_bounds__(kThreads) void level_kernel_batch(const DevTree* trees, const int* ent_tree,
                                                                const int* ent_tau, const int* prefix, int n,
                                                                int bufsize)
 {
     extern __shared__ __align__(16) uint8_t smem[];
-    const int b = blockIdx.x;
-    int lo = 0, hi = n - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (prefix[mid] <= b)
-            lo = mid;
-        else
-            hi = mid - 1;
+    const int total = prefix[n];
+    for (int b = blockIdx.x; b < total; b += gridDim.x) {
+        int lo = 0, hi = n - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (prefix[mid] <= b)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const DevTree& t = trees[ent_tree[lo]];
+        const int tau = ent_tau[lo];
+        const int n_eval = (int)(t.K * (dev_level_offset(t.K, tau) - dev_level_offset(t.K, tau - 1)));
+        const int row0 = (b - prefix[lo]) * 16 * RTT;
+        const int nrows = min(16 * RTT, n_eval - row0);
+        if (nrows > 0)
+            level_tile<P, RTT>(t, tau, row0, nrows, smem, bufsize);
+        __syncthreads();  // LDS is reused by the next tile
     }
-    const DevTree& t = trees[ent_tree[lo]];
-    const int tau = ent_tau[lo];
-    const int n_eval = (int)(t.K * (dev_level_offset(t.K, tau) - dev_level_offset(t.K, tau - 1)));
-    const int row0 = (b - prefix[lo]) * 16 * RTT;
-    const int nrows = min(16 * RTT, n_eval - row0);
-    if (nrows <= 0)
-        return;
-    level_tile<P, RTT>(t, tau, row0, nrows, smem, bufsize);
 }
 
 // Converts FP32 fragment-ordered weights into the storage type of P, in place
@@ -312,7 +317,17 @@ static hipError_t launch_level_batch_t(const DevTree* trees, const int* ent_tree
                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         attr = true;
     }
-    hipLaunchKernelGGL((level_kernel_batch<P, RTT>), dim3(nblocks), dim3(kThreads), lds, s, trees, ent_tree, ent_tau,
+    static int ncu = 0;
+    if (ncu == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
+            ncu = 256;
+    }
+    const int grid = std::min(nblocks, ncu * std::max(1, (int)((160 * 1024) / lds)));
+    if (grid < 1)
+        return hipSuccess;
+    hipLaunchKernelGGL((level_kernel_batch<P, RTT>), dim3(grid), dim3(kThreads), lds, s, trees, ent_tree, ent_tau,
                        prefix, n, buf);
     return hipGetLastError();
 }

@@ -34,7 +34,10 @@ SYMBOLS = (
     "cyrus_codebook_wait", "cyrus_codebook_lookup", "cyrus_codebook_export", "cyrus_codebook_device_alloc",
     "cyrus_codebook_num_nodes", "cyrus_codebook_kernel_path", "cyrus_codebook_destroy",
     "cyrus_status_string", "cyrus_last_error",
+    "cyrus_engine_create", "cyrus_engine_submit", "cyrus_engine_step", "cyrus_engine_poll",
+    "cyrus_engine_completed", "cyrus_engine_result", "cyrus_engine_stats", "cyrus_engine_destroy",
 )
+REQ_WAITING, REQ_RUNNING, REQ_DONE = 0, 1, 2
 
 
 class CyrusError(RuntimeError):
@@ -96,9 +99,21 @@ def lib():
         L.cyrus_status_string.restype = ctypes.c_char_p
         L.cyrus_last_error.argtypes = []
         L.cyrus_last_error.restype = ctypes.c_char_p
+        L.cyrus_engine_create.argtypes = [vp, sz, vp, sz, ctypes.c_int32, vp, ctypes.POINTER(vp)]
+        L.cyrus_engine_submit.argtypes = [vp, vp, ctypes.POINTER(cyrus_ue_state), ctypes.POINTER(ctypes.c_int64)]
+        L.cyrus_engine_step.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+        L.cyrus_engine_poll.argtypes = [vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32),
+                                        ctypes.POINTER(ctypes.c_double)]
+        L.cyrus_engine_completed.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
+                                             ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+        L.cyrus_engine_result.argtypes = [vp, ctypes.c_int64, _u8p, sz]
+        L.cyrus_engine_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]
+        L.cyrus_engine_destroy.argtypes = [vp]
+        L.cyrus_engine_destroy.restype = None
         for name in SYMBOLS:
             if name not in ("cyrus_codebook_device_alloc", "cyrus_codebook_num_nodes", "cyrus_codebook_kernel_path",
-                            "cyrus_codebook_destroy", "cyrus_status_string", "cyrus_last_error"):
+                            "cyrus_codebook_destroy", "cyrus_status_string", "cyrus_last_error",
+                            "cyrus_engine_destroy"):
                 getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -315,3 +330,107 @@ class Codebook:
 
 def build_batch(codebooks: Sequence[Codebook], ue_devs, stream=None):
     cyrus_codebook_build_batch([c.handle for c in codebooks], [u.data_ptr() for u in ue_devs], stream)
+
+
+# ------------------------------------------------------------ serving engine
+
+def cyrus_engine_create(dev_ptr: int, dev_bytes: int, host_ptr: int, host_bytes: int, max_active: int,
+                        stream) -> int:
+    out = ctypes.c_void_p()
+    _check(lib().cyrus_engine_create(dev_ptr, dev_bytes, host_ptr, host_bytes, max_active, _stream_ptr(stream),
+                                     ctypes.byref(out)), "cyrus_engine_create")
+    return out.value
+
+
+def cyrus_engine_submit(eng: int, cell: int, ue: cyrus_ue_state) -> int:
+    t = ctypes.c_int64()
+    _check(lib().cyrus_engine_submit(eng, cell, ctypes.byref(ue), ctypes.byref(t)), "cyrus_engine_submit")
+    return t.value
+
+
+def cyrus_engine_step(eng: int):
+    r, w = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().cyrus_engine_step(eng, ctypes.byref(r), ctypes.byref(w)), "cyrus_engine_step")
+    return r.value, w.value
+
+
+def cyrus_engine_poll(eng: int, ticket: int):
+    st, lat = ctypes.c_int32(), ctypes.c_double()
+    _check(lib().cyrus_engine_poll(eng, ticket, ctypes.byref(st), ctypes.byref(lat)), "cyrus_engine_poll")
+    return st.value, lat.value
+
+
+def cyrus_engine_completed(eng: int, cap: int = 256):
+    t = (ctypes.c_int64 * cap)()
+    lat = (ctypes.c_double * cap)()
+    n = ctypes.c_int32()
+    _check(lib().cyrus_engine_completed(eng, t, lat, cap, ctypes.byref(n)), "cyrus_engine_completed")
+    return [(t[i], lat[i]) for i in range(n.value)]
+
+
+def cyrus_engine_result(eng: int, ticket: int, nodes: int, num_ue: int) -> np.ndarray:
+    out = np.zeros((nodes, num_ue), dtype=np.uint8)
+    _check(lib().cyrus_engine_result(eng, ticket, out.ctypes.data_as(_u8p), out.nbytes), "cyrus_engine_result")
+    return out
+
+
+def cyrus_engine_stats(eng: int) -> dict:
+    c = (ctypes.c_int64 * 7)()
+    _check(lib().cyrus_engine_stats(eng, c, 7), "cyrus_engine_stats")
+    keys = ("submitted", "completed", "steps", "deferred_memory", "deferred_batch", "pool_bytes_used",
+            "pool_bytes_peak")
+    return dict(zip(keys, list(c)))
+
+
+def cyrus_engine_destroy(eng: int) -> None:
+    lib().cyrus_engine_destroy(eng)
+
+
+class Engine:
+    """Continuous-batching engine over caller-owned pools (torch device memory
+    and pinned host memory). Cells are Codebook objects (their weights)."""
+
+    def __init__(self, device_pool_bytes: int, host_pool_bytes: int, max_active: int = 64, device: str = "cuda",
+                 stream=None):
+        import torch
+        self.dpool = torch.empty(device_pool_bytes, dtype=torch.uint8, device=device)
+        self.hpool = torch.empty(host_pool_bytes, dtype=torch.uint8, pin_memory=True)
+        self.stream = stream
+        self.handle = cyrus_engine_create(self.dpool.data_ptr(), device_pool_bytes, self.hpool.data_ptr(),
+                                          host_pool_bytes, max_active, stream)
+        self._cells = {}
+
+    def submit(self, cell: Codebook, ue: UEState) -> int:
+        s, keep = ue_struct(ue)
+        t = cyrus_engine_submit(self.handle, cell.handle, s)
+        self._cells[t] = cell
+        return t
+
+    def step(self):
+        return cyrus_engine_step(self.handle)
+
+    def poll(self, ticket: int):
+        return cyrus_engine_poll(self.handle, ticket)
+
+    def completed(self):
+        """[(ticket, latency_us)] of requests finished since the last call."""
+        return cyrus_engine_completed(self.handle)
+
+    def result(self, ticket: int) -> np.ndarray:
+        cell = self._cells.pop(ticket)
+        return cyrus_engine_result(self.handle, ticket, cell.num_nodes, cell.cfg.num_ue)
+
+    def stats(self) -> dict:
+        return cyrus_engine_stats(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            cyrus_engine_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+

@@ -1,0 +1,139 @@
+"""Serving workload: a Poisson stream of codebook requests from many simulated
+cells, fed to the continuous-batching engine of libcyrus.
+
+Each cell has its own shape (E UEs, arrival alphabet 0..K, hidden width) and
+its own actor weights, resident on the GPU in a Codebook handle. A request is
+one TTI of one cell. Latency is measured from the request's scheduled arrival
+time to the moment the host observes its codebook in pinned memory, and is
+reported against the 125 us slot of numerology 3.
+
+CLI: python -m paper_2506_00167_amd.serving [--requests N] [--loads 0.25,0.5,...]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+
+from . import cyrus
+from . import workload as wl
+
+SLOT_US = 125.0
+
+
+def make_cells(num_cells: int = 64, seed: int = 424242, device: str = "cuda", stream=None):
+    cells = []
+    for cfg, wseed in wl.serving_cell_configs(num_cells, seed):
+        cells.append(cyrus.Codebook(cfg, wl.make_weights(cfg, wseed), force_level=True, device=device,
+                                    stream=stream))
+    return cells
+
+
+def make_requests(cells, n: int, seed: int = 7):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for i in range(n):
+        c = int(rng.integers(0, len(cells)))
+        out.append((c, wl.make_ue_state(cells[c].cfg.num_ue, 9_000_000 + i)))
+    return out
+
+
+def default_engine(max_active: int = 64, pool_mib: int = 256, stream=None):
+    return cyrus.Engine(pool_mib << 20, pool_mib << 20, max_active=max_active, stream=stream)
+
+
+def run_stream(engine, cells, requests, arrivals_s, keep_results: bool = False):
+    """Submit requests at their arrival times while stepping the engine.
+    Returns latency statistics (us), throughput and engine counters."""
+    n = len(requests)
+    t0 = time.perf_counter()
+    sub_wall = {}
+    lat_engine = {}
+    results = {}
+    i = 0
+    idle_steps = 0
+    while len(lat_engine) < n:
+        now = time.perf_counter() - t0
+        while i < n and arrivals_s[i] <= now:
+            c, ue = requests[i]
+            t = engine.submit(cells[c], ue)
+            sub_wall[t] = (i, time.perf_counter() - t0)
+            i += 1
+        running, waiting = engine.step()
+        for t, l in engine.completed():
+            lat_engine[t] = l
+            r = engine.result(t)
+            if keep_results:
+                results[sub_wall[t][0]] = r
+        if running == 0 and waiting == 0 and i < n and len(lat_engine) == i:
+            idle_steps += 1
+            while time.perf_counter() - t0 < arrivals_s[i]:
+                pass
+    wall = time.perf_counter() - t0
+    lat = []
+    for t, l in lat_engine.items():
+        idx, s = sub_wall[t]
+        lat.append(l + (s - arrivals_s[idx]) * 1e6)  # count queueing before submit too
+    lat = np.array(lat)
+    nodes = sum(cells[c].num_nodes for c, _ in requests)
+    flops = sum(cells[c].cfg.flops_per_codebook for c, _ in requests)
+    span = wall - arrivals_s[0]
+    out = {
+        "requests": n,
+        "offered_req_per_s": n / max(arrivals_s[-1] - arrivals_s[0], 1e-9),
+        "served_req_per_s": n / span,
+        "nodes_per_s": nodes / span,
+        "tflops": flops / span / 1e12,
+        "latency_us": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                       "p99.9": float(np.percentile(lat, 99.9)), "max": float(lat.max()),
+                       "mean": float(lat.mean())},
+        "misses_over_125us": int((lat > SLOT_US).sum()),
+        "engine": engine.stats(),
+    }
+    if keep_results:
+        out["results"] = results
+    return out
+
+
+def saturation(engine, cells, requests):
+    """Everything submitted at t = 0: the engine's sustained throughput."""
+    return run_stream(engine, cells, requests, np.zeros(len(requests)))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--cells", type=int, default=64)
+    ap.add_argument("--requests", type=int, default=2000)
+    ap.add_argument("--loads", default="0.25,0.5,0.75,0.9")
+    ap.add_argument("--max-active", type=int, default=64)
+    ap.add_argument("--pool-mib", type=int, default=256)
+    args = ap.parse_args()
+    import torch
+    cyrus.lib()
+    stream = torch.cuda.Stream()
+    cells = make_cells(args.cells, stream=stream)
+    torch.cuda.synchronize()
+    eng = default_engine(args.max_active, args.pool_mib, stream=stream)
+    warm = make_requests(cells, 200, seed=1)
+    saturation(eng, cells, warm)
+    reqs = make_requests(cells, args.requests, seed=2)
+    sat = saturation(eng, cells, reqs)
+    print(json.dumps({"mode": "saturation", **sat}), flush=True)
+    rate_sat = sat["served_req_per_s"]
+    for load in [float(x) for x in args.loads.split(",")]:
+        arr = wl.poisson_arrivals(load * rate_sat, args.requests, seed=424242)
+        arr = arr - arr[0]
+        res = run_stream(eng, cells, make_requests(cells, args.requests, seed=3), arr)
+        print(json.dumps({"mode": "poisson", "load": load, **res}), flush=True)
+    # one request per cell per slot (8000 slots/s per cell)
+    per_slot = 8000.0 * args.cells
+    print(json.dumps({"mode": "note", "one_request_per_cell_per_slot_req_per_s": per_slot,
+                      "ratio_to_saturation": per_slot / rate_sat}), flush=True)
+    eng.close()
+
+
+if __name__ == "__main__":
+    sys.exit(main())
