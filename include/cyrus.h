@@ -127,10 +127,12 @@ int cyrus_codebook_create(const cyrus_config* cfg, const cyrus_weights* w, void*
 int cyrus_codebook_set_weights(cyrus_codebook* cb, const cyrus_weights* w, void* stream);
 
 /* Alg. 2 for one TTI: s(t) in, codebook B*(t) out. Asynchronous on `stream`:
- * host UE arrays are copied into the pinned buffer before returning, then
- * host-to-device copy, kernels and device-to-host copy of the codebook (and the
- * logits if exported) into the pinned buffer are enqueued and an event is
- * recorded. */
+ * host UE arrays are copied into the pinned buffer before returning; then, on
+ * the single-launch path, one kernel reads them from the pinned buffer and
+ * writes the codebook (and the logits if exported) straight into the pinned
+ * mirror; on the level path, host-to-device copy, kernels and device-to-host
+ * copy are enqueued. An event is recorded either way. The device array
+ * (cyrus_codebook_device_alloc) is only written by device builds. */
 int cyrus_codebook_build(cyrus_codebook* cb, const cyrus_ue_state* ue, void* stream);
 
 /* Device-resident variant: the UE state is already in device memory as
@@ -154,6 +156,19 @@ int cyrus_codebook_wait(cyrus_codebook* cb);
  * in [0, K], already capped by the O-RU controller). Waits for the last host
  * build once, then reads the pinned mirror. */
 int cyrus_codebook_lookup(cyrus_codebook* cb, const uint8_t* arrivals, int32_t tau, uint8_t* alloc_out);
+
+/* O-RU side of one slot: the controller caps the URLLC packets punctured in
+ * a mini-slot at K and carries the rest to the next one (Sec. III-A:
+ * k_tau = min(K, a_tau + q_{tau-1}), q_tau = a_tau + q_{tau-1} - k_tau,
+ * q_0 = carry_in), and Alg. 3 reads each mini-slot's puncturing vector from the
+ * codebook for the served prefix.
+ *   raw_arrivals  [num_minislots] packets arriving per mini-slot (>= 0)
+ *   served        [num_minislots] out: packets punctured per mini-slot
+ *   y             [num_minislots][E] out: the puncturing matrix Y(t)
+ *   carry_out     out: packets still buffered after the slot
+ * Waits for the last build like lookup. */
+int cyrus_codebook_assemble(cyrus_codebook* cb, const int32_t* raw_arrivals, int32_t carry_in, uint8_t* served,
+                            uint8_t* y, int32_t* carry_out);
 
 /* Copy the whole codebook to host memory: alloc [nodes][E] bytes; logits
  * [nodes][E] FP32 or NULL (needs CYRUS_FLAG_EXPORT_LOGITS). Waits for the

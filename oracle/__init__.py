@@ -95,6 +95,9 @@ def _load(path: str = _LIB_PATH):
     lib.oracle_rollout.restype = ctypes.c_int
     lib.oracle_rollout.argtypes = [ctypes.POINTER(_Tree), ctypes.POINTER(_Actor), _i32p, _i32p,
                                    _f32p, _i32p, ctypes.c_int32, _i32p, _f64p]
+    lib.oracle_oru_assemble.restype = ctypes.c_int
+    lib.oracle_oru_assemble.argtypes = [ctypes.POINTER(_Tree), ctypes.POINTER(_Actor), _i32p, _i32p, _f32p, _i32p,
+                                        ctypes.c_int32, ctypes.c_int32, _i32p, _i32p, _i32p]
     return lib
 
 
@@ -309,3 +312,18 @@ def node_index(K: int, seq) -> int:
     for k in seq:
         i = i * (K + 1) + int(k)
     return level_offset(K, tau) + i
+
+
+def oru_assemble(cfg, weights, ue, raw, carry_in: int = 0, actor: Actor | None = None):
+    """Controller capping/buffering plus Alg. 3: returns (served [len], Y [len,E], carry_out)."""
+    f = actor or Actor(weights)
+    rb, mcs, sinr = _ue_arrays(ue)
+    raw = _c(raw, np.int32)
+    served = np.zeros(raw.size, dtype=np.int32)
+    y = np.zeros((raw.size, cfg.num_ue), dtype=np.int32)
+    co = ctypes.c_int32()
+    t = _tree(cfg)
+    _check(f.lib.oracle_oru_assemble(ctypes.byref(t), ctypes.byref(f.struct), _p(rb, _i32p), _p(mcs, _i32p),
+                                     _p(sinr, _f32p), _p(raw, _i32p), raw.size, int(carry_in), _p(served, _i32p),
+                                     _p(y, _i32p), ctypes.byref(co)), "oru_assemble")
+    return served, y, co.value

@@ -602,3 +602,28 @@ int oracle_rollout(const oracle_tree* t, const oracle_actor* f, const int32_t* r
     }
     return ORACLE_OK;
 }
+
+/* O-RU side of one slot (the controller of the simulator, Sec. III-A and
+ * Sec. VI-A, then Alg. 3): at most K packets are punctured in a mini-slot and
+ * the rest wait for the next one, so the served count is
+ * k_tau = min(K, a_tau + q_{tau-1}) with backlog q_tau = a_tau + q_{tau-1} - k_tau
+ * (q_0 = carry_in). The puncturing vector of mini-slot tau is the codebook
+ * entry of the served prefix, here obtained by a sequential roll-out.
+ * raw: [len] arrivals; served: [len]; y: [len][E]; *carry_out = q_len. */
+int oracle_oru_assemble(const oracle_tree* t, const oracle_actor* f, const int32_t* rb, const int32_t* mcs,
+                        const float* sinr, const int32_t* raw, int32_t len, int32_t carry_in, int32_t* served,
+                        int32_t* y, int32_t* carry_out)
+{
+    if (!t || len < 0 || len > t->num_minislots || carry_in < 0)
+        return ORACLE_EINVAL;
+    int32_t q = carry_in;
+    for (int32_t tau = 0; tau < len; ++tau) {
+        if (raw[tau] < 0)
+            return ORACLE_EINVAL;
+        int32_t want = raw[tau] + q;
+        served[tau] = want < t->max_arrival ? want : t->max_arrival;
+        q = want - served[tau];
+    }
+    *carry_out = q;
+    return oracle_rollout(t, f, rb, mcs, sinr, served, len, y, NULL);
+}

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -276,15 +277,19 @@ static int load_weights(cyrus_codebook* cb, const cyrus_weights* w, hipStream_t 
     return CYRUS_OK;
 }
 
-static int enqueue_kernels(cyrus_codebook* cb, const int32_t* ue_dev, hipStream_t stream)
+static int enqueue_tree(cyrus_codebook* cb, const DevTree& t, hipStream_t stream)
 {
-    const DevTree t = make_devtree(cb, ue_dev);
     if (cb->path == 1)
         HIP_TRY(launch_subtree(t, cb->s.prec, stream));
     else
         for (int tau = 1; tau <= cb->s.M; ++tau)
             HIP_TRY(launch_level(t, cb->s.prec, cb->rtt, tau, stream));
     return CYRUS_OK;
+}
+
+static int enqueue_kernels(cyrus_codebook* cb, const int32_t* ue_dev, hipStream_t stream)
+{
+    return enqueue_tree(cb, make_devtree(cb, ue_dev), stream);
 }
 
 extern "C" {
@@ -317,13 +322,14 @@ int cyrus_codebook_create(const cyrus_config* cfg, const cyrus_weights* w, void*
     if (reinterpret_cast<uintptr_t>(device_ws) % 256 || reinterpret_cast<uintptr_t>(host_pinned) % 64)
         return fail(CYRUS_EWORKSPACE, "workspace must be 256-byte aligned and the host buffer 64-byte aligned");
     hipPointerAttribute_t attr;
-    if (hipPointerGetAttributes(&attr, device_ws) != hipSuccess || attr.type != hipMemoryTypeDevice) {
+    if (hipPointerGetAttributes(&attr, device_ws) != hipSuccess ||
+        (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged && attr.type != hipMemoryTypeUnified)) {
         (void)hipGetLastError();
-        return fail(CYRUS_EWORKSPACE, "device_ws is not device memory");
+        return fail(CYRUS_EWORKSPACE, "device_ws is not device memory known to this HIP runtime");
     }
     if (hipPointerGetAttributes(&attr, host_pinned) != hipSuccess || attr.type != hipMemoryTypeHost) {
         (void)hipGetLastError();
-        return fail(CYRUS_EWORKSPACE, "host_pinned is not page-locked host memory");
+        return fail(CYRUS_EWORKSPACE, "host_pinned is not page-locked host memory known to this HIP runtime");
     }
     cyrus_codebook* cb = new (std::nothrow) cyrus_codebook();
     if (!cb)
@@ -341,6 +347,10 @@ int cyrus_codebook_create(const cyrus_config* cfg, const cyrus_weights* w, void*
         delete cb;
         return status;
     };
+    if (hipHostGetDevicePointer(reinterpret_cast<void**>(&cb->host_dev), host_pinned, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        cb->host_dev = nullptr;
+    }
     if (hipGetDevice(&cb->device) != hipSuccess || hipEventCreateWithFlags(&cb->ev_staged, hipEventDisableTiming) ||
         hipEventCreateWithFlags(&cb->ev_done, hipEventDisableTiming))
         return cleanup(fail(CYRUS_EDEVICE, "event creation failed"));
@@ -349,6 +359,11 @@ int cyrus_codebook_create(const cyrus_config* cfg, const cyrus_weights* w, void*
         hipMemsetAsync(cb->ws + s.off_state, 0, s.E, st) != hipSuccess ||
         (s.export_logits && hipMemsetAsync(cb->ws + s.off_logits, 0, (size_t)s.E * 4, st) != hipSuccess))
         return cleanup(fail(CYRUS_EDEVICE, "workspace clear failed"));
+    // the pinned mirror starts as an all-zero codebook: the single-launch path
+    // writes it directly and never writes the root row
+    std::memset(cb->host + s.hoff_alloc, 0, (size_t)s.nodes * s.E);
+    if (s.export_logits)
+        std::memset(cb->host + s.hoff_logits, 0, (size_t)s.nodes * s.E * 4);
     rc = load_weights(cb, w, st, 0);
     if (rc)
         return cleanup(rc);
@@ -401,6 +416,21 @@ int cyrus_codebook_build(cyrus_codebook* cb, const cyrus_ue_state* ue, void* str
         return rc;
     hipStream_t st = static_cast<hipStream_t>(stream);
     const Shape& s = cb->s;
+    if (cb->path == 1 && cb->host_dev) {
+        // one launch, no copies: the kernel reads s(t) from the pinned buffer
+        // and writes the codebook (and logits) straight into the pinned mirror
+        DevTree t = make_devtree(cb, reinterpret_cast<const int32_t*>(cb->host_dev + s.hoff_ue));
+        t.alloc = cb->host_dev + s.hoff_alloc;
+        t.logits = s.export_logits ? reinterpret_cast<float*>(cb->host_dev + s.hoff_logits) : nullptr;
+        rc = enqueue_tree(cb, t, st);
+        if (rc)
+            return rc;
+        HIP_TRY(hipEventRecord(cb->ev_staged, st));
+        cb->staged_recorded = true;
+        HIP_TRY(hipEventRecord(cb->ev_done, st));
+        cb->built = cb->pending = cb->mirror_valid = true;
+        return CYRUS_OK;
+    }
     int32_t* ue_dev = reinterpret_cast<int32_t*>(cb->ws + s.off_ue);
     HIP_TRY(hipMemcpyAsync(ue_dev, cb->host + s.hoff_ue, (size_t)3 * s.E * 4, hipMemcpyHostToDevice, st));
     HIP_TRY(hipEventRecord(cb->ev_staged, st));
@@ -484,6 +514,34 @@ int cyrus_codebook_lookup(cyrus_codebook* cb, const uint8_t* arrivals, int32_t t
         return rc;
     const int64_t node = (ipow(s.K + 1, tau) - 1) / s.K + idx;
     std::memcpy(alloc_out, cb->host + s.hoff_alloc + node * s.E, s.E);
+    return CYRUS_OK;
+}
+
+int cyrus_codebook_assemble(cyrus_codebook* cb, const int32_t* raw_arrivals, int32_t carry_in, uint8_t* served,
+                            uint8_t* y, int32_t* carry_out)
+{
+    if (!cb || !raw_arrivals || !served || !y || !carry_out)
+        return fail(CYRUS_EINVAL, "NULL argument");
+    const Shape& s = cb->s;
+    if (carry_in < 0)
+        return fail(CYRUS_ERANGE, "carry_in %d < 0", carry_in);
+    for (int tau = 0; tau < s.M; ++tau)
+        if (raw_arrivals[tau] < 0)
+            return fail(CYRUS_ERANGE, "raw_arrivals[%d] = %d < 0", tau, raw_arrivals[tau]);
+    int rc = sync_mirror(cb);
+    if (rc)
+        return rc;
+    int64_t backlog = carry_in, idx = 0;
+    for (int tau = 1; tau <= s.M; ++tau) {
+        const int64_t want = raw_arrivals[tau - 1] + backlog;
+        const int k = (int)std::min<int64_t>(want, s.K);
+        backlog = want - k;
+        served[tau - 1] = (uint8_t)k;
+        idx = idx * (s.K + 1) + k;
+        const int64_t node = (ipow(s.K + 1, tau) - 1) / s.K + idx;
+        std::memcpy(y + (size_t)(tau - 1) * s.E, cb->host + s.hoff_alloc + node * s.E, s.E);
+    }
+    *carry_out = (int32_t)std::min<int64_t>(backlog, INT32_MAX);
     return CYRUS_OK;
 }
 

@@ -59,7 +59,7 @@ int build_batch_levels(cyrus_codebook* const* cbs, const DevTree* trees, int n, 
     size_t buf = 0;
     for (int i = 0; i < n; ++i)
         buf = std::max(buf, level_buf_bytes(trees[i], prec, rtt));
-    const size_t lds = 2 * buf + (size_t)16 * rtt * kLogitStride * 4 + (kMaxUE + 4) * 4;
+    const size_t lds = level_lds_for_buf(buf, rtt);
 
     const BatchLayout L = batch_layout();
     uint8_t* hbase = host_cb->host + host_cb->s.hoff_batch;

@@ -305,6 +305,100 @@ __device__ __forceinline__ int enforce_group(int E, int e, float z, int R, int r
     return f + ((elig && rank < r) ? 1 : 0);
 }
 
+// ---------------------------------------------------------------------------
+// Groups of 8 or 16 lanes on the DPP fabric: butterfly all-reductions with
+// quad permutations (xor 1, xor 2), the half-row mirror (lane i <-> 7-i) and
+// the row mirror (lane i <-> 15-i). Every lane of the group ends with the same
+// value (each step adds two partial sums in either order).
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+constexpr int kDppXor1 = 0xB1;        // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;        // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141;  // row_half_mirror
+constexpr int kDppMirror = 0x140;      // row_mirror
+
+template <int G>
+__device__ __forceinline__ float dsum(float v)
+{
+    static_assert(G == 8 || G == 16, "DPP groups are 8 or 16 lanes");
+    v += dpp_f<kDppXor1>(v);
+    v += dpp_f<kDppXor2>(v);
+    v += dpp_f<kDppHalfMirror>(v);
+    if constexpr (G == 16)
+        v += dpp_f<kDppMirror>(v);
+    return v;
+}
+template <int G>
+__device__ __forceinline__ float dmax(float v)
+{
+    v = fmaxf(v, dpp_f<kDppXor1>(v));
+    v = fmaxf(v, dpp_f<kDppXor2>(v));
+    v = fmaxf(v, dpp_f<kDppHalfMirror>(v));
+    if constexpr (G == 16)
+        v = fmaxf(v, dpp_f<kDppMirror>(v));
+    return v;
+}
+template <int G>
+__device__ __forceinline__ int disum(int v)
+{
+    v += dpp_i<kDppXor1>(v);
+    v += dpp_i<kDppXor2>(v);
+    v += dpp_i<kDppHalfMirror>(v);
+    if constexpr (G == 16)
+        v += dpp_i<kDppMirror>(v);
+    return v;
+}
+
+// Same enforcer as enforce_group for groups of 8 or 16 lanes aligned to
+// 8/16-lane boundaries, with DPP reductions; the remainder ranks go through
+// `rank_row` (G floats of LDS private to this group).
+template <int G>
+__device__ __forceinline__ int enforce_dpp(int E, int e, float z, int R, int rsum, int demand, float* rank_row)
+{
+    const bool live = e < E;
+    const float zmax = dmax<G>(live ? z : -3.0e38f);
+    float p = live ? expf(fmaxf(z - zmax, -80.f)) : 0.f;
+    const float sum = dsum<G>(p);
+    p = p / sum;
+    const int T = demand < rsum ? demand : rsum;
+    if (T >= rsum)
+        return live ? R : 0;
+    bool capped = !live;
+    float s = 0.f;
+    for (int pass = 0; pass <= G; ++pass) {
+        const float rem = (float)T - dsum<G>((live && capped) ? (float)R : 0.f);
+        const float psum = dsum<G>(capped ? 0.f : p);
+        s = rem / psum;
+        const bool grow = !capped && s * p >= (float)R;
+        if (disum<G>(grow ? 1 : 0) == 0)
+            break;
+        capped = capped || grow;
+    }
+    const float x = !live ? 0.f : (capped ? (float)R : s * p);
+    const float fl = floorf(x);
+    const int f = (int)fl;
+    const float frac = x - fl;
+    const int r = T - disum<G>(f);
+    const bool elig = live && f < R;
+    rank_row[e] = elig ? frac : -1.f;  // ineligible UEs never rank above an eligible one
+    int rank = 0;
+#pragma unroll
+    for (int q = 0; q < G; ++q) {
+        const float fq = rank_row[q];
+        if (q != e && (fq > frac || (fq == frac && q < e)))
+            ++rank;
+    }
+    return f + ((elig && rank < r) ? 1 : 0);
+}
+
 __device__ __forceinline__ void enforce_any(int E, const float* z, const int* R, int rsum, int demand, int* a)
 {
     if (E <= 8)

@@ -245,7 +245,7 @@ int launch_step(cyrus_engine* e)
     size_t buf = 0;
     for (int i = 0; i < n; ++i)
         buf = std::max(buf, level_buf_bytes(trees[i], e->prec, rtt));
-    const size_t lds = 2 * buf + (size_t)16 * rtt * kLogitStride * 4 + (kMaxUE + 4) * 4;
+    const size_t lds = level_lds_for_buf(buf, rtt);
 
     uint8_t* h = e->hpool + e->slot_hoff[slot];
     uint8_t* d = e->dpool + e->slot_doff[slot];

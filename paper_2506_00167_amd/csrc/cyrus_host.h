@@ -58,6 +58,7 @@ struct cyrus_codebook {
     int device = 0;
     uint8_t* ws = nullptr;
     uint8_t* host = nullptr;
+    uint8_t* host_dev = nullptr;  // device-side address of the pinned buffer (null: not mapped)
     int active = 0;
     float deq[cyrus::kMaxLayers];
     float inv_in[cyrus::kMaxLayers];

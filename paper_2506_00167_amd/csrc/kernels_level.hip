@@ -13,6 +13,8 @@
 
 namespace cyrus {
 
+constexpr int kPF = 4;  // weight-fragment chunks per prefetch group
+
 __device__ __forceinline__ int64_t dev_level_offset(int K, int tau)
 {
     int64_t p = 1;
@@ -21,28 +23,40 @@ __device__ __forceinline__ int64_t dev_level_offset(int K, int tau)
     return (p - 1) / K;
 }
 
-// Writes one evaluated node and, for its first k, the k = 0 sibling (which
-// punctures nothing and passes the parent state on unchanged).
-template <int EMAX>
-__device__ __forceinline__ void finish_node(const DevTree& t, const float* z, const int* R, int rsum, int64_t node,
-                                            int64_t parent, int64_t sibling0, int k)
+// Enforcer for the rows of a tile, G lanes per row (lane e = UE e). Each
+// evaluated node writes its allocation and state; the first child (k = 1) of
+// every parent also writes the k = 0 sibling, which punctures nothing and
+// passes the parent state on unchanged.
+template <int G>
+__device__ __forceinline__ void finish_rows_level(const DevTree& t, const float* zl, const int* R, int rsum, int row0,
+                                                  int nrows, int64_t off, int64_t poff)
 {
-    int a[EMAX];
-    enforce<EMAX>(t.E, z, R, rsum, t.U * k, a);
-    const uint8_t* cin = t.state + parent * t.E;
-#pragma unroll
-    for (int e = 0; e < EMAX; ++e) {
-        if (e < t.E) {
-            const uint8_t c = cin[e];
-            t.alloc[node * t.E + e] = (uint8_t)a[e];
-            t.state[node * t.E + e] = (uint8_t)(c + a[e]);
-            if (t.logits)
-                t.logits[node * t.E + e] = z[e];
-            if (sibling0 >= 0) {
-                t.alloc[sibling0 * t.E + e] = 0;
-                t.state[sibling0 * t.E + e] = c;
+    const int E = t.E, K = t.K;
+    for (int base = 0; base < nrows; base += kThreads / G) {
+        const int row = base + (int)threadIdx.x / G, e = (int)threadIdx.x % G;
+        if (row < nrows) {
+            const int r = row0 + row, p = r / K, k = r - p * K + 1;
+            float* zrow = const_cast<float*>(zl) + row * kLogitStride;
+            const float z = e < E ? zrow[e] : 0.f;
+            int a;
+            if constexpr (G <= 16)
+                a = enforce_dpp<G>(E, e, z, e < E ? R[e] : 0, rsum, t.U * k, zrow);  // row reused for ranks
+            else
+                a = enforce_group<G>(E, e, z, e < E ? R[e] : 0, rsum, t.U * k);
+            if (e < E) {
+                const int64_t node = off + (int64_t)p * (K + 1) + k, parent = poff + p;
+                const uint8_t c = t.state[parent * E + e];
+                t.alloc[node * E + e] = (uint8_t)a;
+                t.state[node * E + e] = (uint8_t)(c + a);
                 if (t.logits)
-                    t.logits[sibling0 * t.E + e] = 0.f;
+                    t.logits[node * E + e] = z;
+                if (k == 1) {
+                    const int64_t sib = off + (int64_t)p * (K + 1);
+                    t.alloc[sib * E + e] = 0;
+                    t.state[sib * E + e] = c;
+                    if (t.logits)
+                        t.logits[sib * E + e] = 0.f;
+                }
             }
         }
     }
@@ -73,25 +87,42 @@ __device__ __forceinline__ void run_mlp(const DevTree& t, int nrows, uint8_t* bu
                 acc[rt] = floatx4{0.f, 0.f, 0.f, 0.f};
             const uint4* wp = wl + (size_t)nt * nch * 64 + lane;
             const uint8_t* bp = in + c16 * sin + g * (kc / 4) * es;
-            for (int ch = 0; ch < nch; ++ch) {
-                const uint4 a = wp[(size_t)ch * 64];
+            const floatx4 bias = *reinterpret_cast<const floatx4*>(t.b[l] + nt * 16 + g * 4);
+            // weight fragments stream from L2 in groups of kPF chunks; the
+            // next group is in flight while the current one feeds the MFMAs
+            uint4 a[kPF];
 #pragma unroll
-                for (int rt = 0; rt < RTT; ++rt) {
-                    if (rt < art) {
-                        const uint4 b = *reinterpret_cast<const uint4*>(bp + rt * 16 * sin + ch * kc * es);
-                        mma_chunk<P>(a, b, acc[rt]);
+            for (int j = 0; j < kPF; ++j)
+                a[j] = (j < nch) ? wp[(size_t)j * 64] : uint4{0, 0, 0, 0};
+            for (int c0 = 0; c0 < nch; c0 += kPF) {
+                uint4 nx[kPF];
+#pragma unroll
+                for (int j = 0; j < kPF; ++j)
+                    nx[j] = (c0 + kPF + j < nch) ? wp[(size_t)(c0 + kPF + j) * 64] : uint4{0, 0, 0, 0};
+#pragma unroll
+                for (int j = 0; j < kPF; ++j) {
+                    if (c0 + j < nch) {
+#pragma unroll
+                        for (int rt = 0; rt < RTT; ++rt) {
+                            if (rt < art) {
+                                const uint4 b =
+                                    *reinterpret_cast<const uint4*>(bp + rt * 16 * sin + (c0 + j) * kc * es);
+                                mma_chunk<P>(a[j], b, acc[rt]);
+                            }
+                        }
                     }
                 }
+#pragma unroll
+                for (int j = 0; j < kPF; ++j)
+                    a[j] = nx[j];
             }
-            const float* bias = t.b[l] + nt * 16 + g * 4;
-            const float b0 = bias[0], b1 = bias[1], b2 = bias[2], b3 = bias[3];
 #pragma unroll
             for (int rt = 0; rt < RTT; ++rt) {
                 if (rt < art) {
-                    const float v0 = fmaxf(acc[rt][0] * deq + b0, 0.f);
-                    const float v1 = fmaxf(acc[rt][1] * deq + b1, 0.f);
-                    const float v2 = fmaxf(acc[rt][2] * deq + b2, 0.f);
-                    const float v3 = fmaxf(acc[rt][3] * deq + b3, 0.f);
+                    const float v0 = fmaxf(acc[rt][0] * deq + bias[0], 0.f);
+                    const float v1 = fmaxf(acc[rt][1] * deq + bias[1], 0.f);
+                    const float v2 = fmaxf(acc[rt][2] * deq + bias[2], 0.f);
+                    const float v3 = fmaxf(acc[rt][3] * deq + bias[3], 0.f);
                     store4<P>(out + (rt * 16 + c16) * sout + (nt * 16 + g * 4) * es, v0, v1, v2, v3, inv_next);
                 }
             }
@@ -120,13 +151,22 @@ __device__ __forceinline__ void run_mlp(const DevTree& t, int nrows, uint8_t* bu
                 acc[rt] = floatx4{0.f, 0.f, 0.f, 0.f};
             const uint4* wp = wl + (size_t)nt * nch * 64 + lane;
             const uint8_t* bp = in + c16 * sin + g * (kc / 4) * es;
-            for (int ch = c0; ch < c1; ++ch) {
-                const uint4 a = wp[(size_t)ch * 64];
+            for (int cb = c0; cb < c1; cb += kPF) {
+                uint4 a[kPF];
 #pragma unroll
-                for (int rt = 0; rt < RTT; ++rt) {
-                    if (rt < art) {
-                        const uint4 b = *reinterpret_cast<const uint4*>(bp + rt * 16 * sin + ch * kc * es);
-                        mma_chunk<P>(a, b, acc[rt]);
+                for (int j = 0; j < kPF; ++j)
+                    a[j] = (cb + j < c1) ? wp[(size_t)(cb + j) * 64] : uint4{0, 0, 0, 0};
+#pragma unroll
+                for (int j = 0; j < kPF; ++j) {
+                    if (cb + j < c1) {
+#pragma unroll
+                        for (int rt = 0; rt < RTT; ++rt) {
+                            if (rt < art) {
+                                const uint4 b =
+                                    *reinterpret_cast<const uint4*>(bp + rt * 16 * sin + (cb + j) * kc * es);
+                                mma_chunk<P>(a[j], b, acc[rt]);
+                            }
+                        }
                     }
                 }
             }
@@ -160,9 +200,15 @@ __device__ __forceinline__ void level_tile(const DevTree& t, int tau, int row0, 
     float* zl = reinterpret_cast<float*>(smem + 2 * bufsize);
     int* R = reinterpret_cast<int*>(zl + RT * kLogitStride);
     int* rsum_lds = R + kMaxUE;
+    float* statf = reinterpret_cast<float*>(rsum_lds + 4);  // R/32, MCS/32, SINR/32
     const int E = t.E, K = t.K;
-    if (threadIdx.x < E)
-        R[threadIdx.x] = t.ue[threadIdx.x];
+    if (threadIdx.x < E) {
+        const int e = threadIdx.x;
+        R[e] = t.ue[e];
+        statf[e] = (float)t.ue[e] * (1.f / 32.f);
+        statf[E + e] = (float)t.ue[E + e] * (1.f / 32.f);
+        statf[2 * E + e] = __int_as_float(t.ue[2 * E + e]) * (1.f / 32.f);
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
         int s = 0;
@@ -181,12 +227,8 @@ __device__ __forceinline__ void level_tile(const DevTree& t, int tau, int row0, 
         float v = 0.f;
         if (row < nrows && f < d_in) {
             const int r = row0 + row, p = r / K, k = r - p * K + 1;
-            if (f < E)
-                v = (float)R[f] * (1.f / 32.f);
-            else if (f < 2 * E)
-                v = (float)t.ue[f] * (1.f / 32.f);
-            else if (f < 3 * E)
-                v = __int_as_float(t.ue[f]) * (1.f / 32.f);
+            if (f < 3 * E)
+                v = statf[f];
             else if (f < 4 * E)
                 v = (float)t.state[(poff + p) * E + (f - 3 * E)] * (1.f / 64.f);
             else if (f == 4 * E)
@@ -199,19 +241,12 @@ __device__ __forceinline__ void level_tile(const DevTree& t, int tau, int row0, 
     __syncthreads();
     run_mlp<P, RTT>(t, nrows, bufA, bufB, zl);
 
-    if (threadIdx.x < nrows) {
-        const int row = threadIdx.x, r = row0 + row, p = r / K, k = r - p * K + 1;
-        const int64_t node = off + (int64_t)p * (K + 1) + k, parent = poff + p;
-        const int64_t sib = (k == 1) ? off + (int64_t)p * (K + 1) : -1;
-        const float* z = zl + row * kLogitStride;
-        const int rsum = *rsum_lds;
-        if (E <= 8)
-            finish_node<8>(t, z, R, rsum, node, parent, sib, k);
-        else if (E <= 16)
-            finish_node<16>(t, z, R, rsum, node, parent, sib, k);
-        else
-            finish_node<32>(t, z, R, rsum, node, parent, sib, k);
-    }
+    if (E <= 8)
+        finish_rows_level<8>(t, zl, R, *rsum_lds, row0, nrows, off, poff);
+    else if (E <= 16)
+        finish_rows_level<16>(t, zl, R, *rsum_lds, row0, nrows, off, poff);
+    else
+        finish_rows_level<32>(t, zl, R, *rsum_lds, row0, nrows, off, poff);
 }
 
 template <int P, int RTT>
@@ -285,10 +320,12 @@ size_t level_buf_bytes(const DevTree& t, int prec, int rtt)
     return (buf + 15) & ~(size_t)15;
 }
 
-size_t level_lds_bytes(const DevTree& t, int prec, int rtt)
+size_t level_lds_for_buf(size_t buf, int rtt)
 {
-    return 2 * level_buf_bytes(t, prec, rtt) + (size_t)16 * rtt * kLogitStride * 4 + (kMaxUE + 4) * 4;
+    return 2 * buf + (size_t)16 * rtt * kLogitStride * 4 + (kMaxUE + 4) * 4 + 3 * kMaxUE * 4;
 }
+
+size_t level_lds_bytes(const DevTree& t, int prec, int rtt) { return level_lds_for_buf(level_buf_bytes(t, prec, rtt), rtt); }
 
 template <int P, int RTT>
 static hipError_t launch_level_t(const DevTree& t, int tau, hipStream_t s)

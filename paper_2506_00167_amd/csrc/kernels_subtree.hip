@@ -177,12 +177,13 @@ __device__ __forceinline__ void layer_valu(const uint4 (&A)[T][NCH], int nch, co
     }
 }
 
-// Actor forward pass over nrows <= 64 rows whose features are in bufA;
-// logits end in zl. bias: LDS copy of every layer's bias (bias_off[l]).
+// Actor forward pass over nrows <= 64 rows whose features are in bufA. The
+// output layer's reduction is split over the waves: it leaves one partial
+// logit tile per wave, [wave][row][16] floats, in the buffer returned (the
+// enforcer adds them up). bias: LDS copy of every layer's bias.
 template <int P, int T, int CH1, int CHH, int NHH>
-__device__ __forceinline__ void mlp_regs(const DevTree& t, const WaveWeights<P, T, CH1, CHH, NHH>& W, int nrows,
-                                         uint8_t* bufA, uint8_t* bufB, float* zl, const float* bias,
-                                         const int* bias_off)
+__device__ __forceinline__ float* mlp_regs(const DevTree& t, const WaveWeights<P, T, CH1, CHH, NHH>& W, int nrows,
+                                           uint8_t* bufA, uint8_t* bufB, const float* bias, const int* bias_off)
 {
     using WW = WaveWeights<P, T, CH1, CHH, NHH>;
     constexpr int kc = Traits<P>::kChunk, es = Traits<P>::kEsize, kRTT = Rows<P>::kRTT, kRT = Rows<P>::kRT;
@@ -261,18 +262,7 @@ __device__ __forceinline__ void mlp_regs(const DevTree& t, const WaveWeights<P, 
                 *reinterpret_cast<floatx4*>(part + (size_t)(wave * kRT + rt * 16 + c16) * 16 + g * 4) = acc[rt];
     }
     __syncthreads();
-    const int E = t.E;
-    const float deq = t.deq[NHH + 1];
-    const float* bo = bias + bias_off[NHH + 1];
-    for (int idx = threadIdx.x; idx < nrows * E; idx += kThreads) {
-        const int row = idx / E, e = idx - row * E;
-        float s = 0.f;
-#pragma unroll
-        for (int w = 0; w < kWaves; ++w)
-            s += part[(size_t)(w * kRT + row) * 16 + e];
-        zl[row * kLogitStride + e] = s * deq + bo[e];
-    }
-    __syncthreads();
+    return part;
 }
 
 struct SubtreeSmem {
@@ -288,7 +278,7 @@ struct SubtreeSmem {
 };
 
 // Feature rows for `nrows` nodes: state from state_of(row), level tau,
-// arrival arrival_of(row).
+// arrival arrival_of(row). Eight rows per pass, 64 threads per row.
 template <int P, class StateOf, class ArrivalOf>
 __device__ __forceinline__ void write_features(const DevTree& t, const SubtreeSmem& sm, int nrows, int tau,
                                                StateOf state_of, ArrivalOf arrival_of)
@@ -296,42 +286,58 @@ __device__ __forceinline__ void write_features(const DevTree& t, const SubtreeSm
     constexpr int es = Traits<P>::kEsize;
     const int E = t.E, in0 = t.in_pad[0], d_in = t.in_dim0, s0 = in0 * es + 16;
     const int nrows_pad = ((nrows + 15) >> 4) << 4;
-    const float inv0 = t.inv_in_scale[0];
-    for (int idx = threadIdx.x; idx < nrows_pad * in0; idx += kThreads) {
-        const int row = idx / in0, f = idx - row * in0;
-        float v = 0.f;
-        if (row < nrows && f < d_in) {
-            if (f < 3 * E)
-                v = sm.statf[f];
-            else if (f < 4 * E)
-                v = (float)state_of(row)[f - 3 * E] * (1.f / 64.f);
-            else if (f == 4 * E)
-                v = (float)tau * (1.f / 8.f);
-            else
-                v = (float)arrival_of(row) * (1.f / 8.f);
+    const float inv0 = t.inv_in_scale[0], ftau = (float)tau * (1.f / 8.f);
+    const int f0 = threadIdx.x & 63;
+    for (int row = threadIdx.x >> 6; row < nrows_pad; row += kThreads / 64) {
+        const bool live = row < nrows;
+        const uint8_t* st = live ? state_of(row) : nullptr;
+        const float fk = live ? (float)arrival_of(row) * (1.f / 8.f) : 0.f;
+        uint8_t* dst = sm.bufA + row * s0;
+        for (int f = f0; f < in0; f += 64) {
+            float v = 0.f;
+            if (live && f < d_in) {
+                if (f < 3 * E)
+                    v = sm.statf[f];
+                else if (f < 4 * E)
+                    v = (float)st[f - 3 * E] * (1.f / 64.f);
+                else
+                    v = (f == 4 * E) ? ftau : fk;
+            }
+            store1<P>(dst + f * es, v, inv0);
         }
-        store1<P>(sm.bufA + row * s0 + f * es, v, inv0);
     }
 }
 
-// Enforcer over `nrows` rows, G lanes per row: row r has arrival k_of(r),
-// input state cin_of(r), and writes its state to sout_of(r) (LDS) and, if
-// node_of(r) >= 0, alloc/state/logits of that node to global memory.
-template <int G, class KOf, class CinOf, class SoutOf, class NodeOf>
-__device__ __forceinline__ void finish_rows(const DevTree& t, const SubtreeSmem& sm, int nrows, KOf k_of, CinOf cin_of,
-                                            SoutOf sout_of, NodeOf node_of)
+// Enforcer over `nrows` rows, G lanes per row (lane e = UE e). Each lane first
+// adds up its logit from the per-wave partial tiles (fixed wave order) plus
+// the bias. Row r has arrival k_of(r), input state cin_of(r); it writes its
+// state to sout_of(r) (LDS) and, when node_of(r) >= 0, alloc/state/logits of
+// that node to global memory; when sib_of(r) >= 0 (the first child of a
+// parent) it also writes that k = 0 sibling: nothing punctured, parent state
+// passed on, into sib_st_of(r).
+template <int G, int RT, class KOf, class CinOf, class SoutOf, class NodeOf, class SibOf, class SibStOf>
+__device__ __forceinline__ void finish_rows(const DevTree& t, const SubtreeSmem& sm, const float* part, float deq,
+                                            const float* bo, int nrows, KOf k_of, CinOf cin_of, SoutOf sout_of,
+                                            NodeOf node_of, SibOf sib_of, SibStOf sib_st_of)
 {
     const int E = t.E;
     for (int base = 0; base < nrows; base += kThreads / G) {
         const int row = base + (int)threadIdx.x / G, e = (int)threadIdx.x % G;
-        const bool active = row < nrows;  // uniform within a group
-        if (active) {
-            const float z = e < E ? sm.zl[row * kLogitStride + e] : 0.f;
+        if (row < nrows) {
+            float z = 0.f;
+            if (e < E) {
+                float acc = 0.f;
+#pragma unroll
+                for (int w = 0; w < kWaves; ++w)
+                    acc += part[(size_t)(w * RT + row) * 16 + e];
+                z = acc * deq + bo[e];
+            }
             const int k = k_of(row);
             const int R = e < E ? sm.R[e] : 0;
-            const int a = enforce_group<G>(E, e, z, R, sm.misc[0], t.U * k);
+            const int a = enforce_dpp<G>(E, e, z, R, sm.misc[0], t.U * k, sm.zl + row * kLogitStride);
             if (e < E) {
-                const uint8_t st = (uint8_t)(cin_of(row)[e] + a);
+                const uint8_t c = cin_of(row)[e];
+                const uint8_t st = (uint8_t)(c + a);
                 sout_of(row)[e] = st;
                 const int64_t node = node_of(row);
                 if (node >= 0) {
@@ -339,6 +345,14 @@ __device__ __forceinline__ void finish_rows(const DevTree& t, const SubtreeSmem&
                     t.state[node * E + e] = st;
                     if (t.logits)
                         t.logits[node * E + e] = z;
+                }
+                const int64_t sib = sib_of(row);
+                if (sib >= 0) {
+                    sib_st_of(row)[e] = c;
+                    t.alloc[sib * E + e] = 0;
+                    t.state[sib * E + e] = c;
+                    if (t.logits)
+                        t.logits[sib * E + e] = 0.f;
                 }
             }
         }
@@ -401,8 +415,12 @@ __device__ __forceinline__ void subtree_body(const DevTree& t, int split, int bu
     }
     __syncthreads();
     const int* bias_off = sm.misc + 1;
+    const float deq_out = t.deq[NHH + 1];
+    const float* bias_out = sm.bias + bias_off[NHH + 1];
+    constexpr int kRT = Rows<P>::kRT;
 
-    // ---- ancestors of subtree root r, levels 1..split (state in st0[0..E))
+    // ---- ancestors of subtree root r, levels 1..split. The current state is
+    // sm.st0[0..E); a k = 0 ancestor punctures nothing and leaves it as is.
     for (int tau = 1; tau <= split; ++tau) {
         const int below = ipow_dev(K1, split - tau);
         const int idx = r / below;  // index of the ancestor within level tau
@@ -412,26 +430,25 @@ __device__ __forceinline__ void subtree_body(const DevTree& t, int split, int bu
         if (k > 0) {
             write_features<P>(t, sm, 1, tau, [&](int) { return sm.st0; }, [&](int) { return k; });
             __syncthreads();
-            mlp_regs<P, T, CH1, CHH, NHH>(t, W, 1, sm.bufA, sm.bufB, sm.zl, sm.bias, bias_off);
-            finish_rows<G>(
-                t, sm, 1, [&](int) { return k; }, [&](int) { return sm.st0; }, [&](int) { return sm.st1; },
-                [&](int) { return owner ? node : (int64_t)-1; });
-        } else if (threadIdx.x < E) {
-            sm.st1[threadIdx.x] = sm.st0[threadIdx.x];
-            if (owner) {
-                t.alloc[node * E + threadIdx.x] = 0;
-                t.state[node * E + threadIdx.x] = sm.st0[threadIdx.x];
-                if (t.logits)
-                    t.logits[node * E + threadIdx.x] = 0.f;
-            }
+            const float* part = mlp_regs<P, T, CH1, CHH, NHH>(t, W, 1, sm.bufA, sm.bufB, sm.bias, bias_off);
+            finish_rows<G, kRT>(
+                t, sm, part, deq_out, bias_out, 1, [&](int) { return k; }, [&](int) { return sm.st0; },
+                [&](int) { return sm.st1; }, [&](int) { return owner ? node : (int64_t)-1; },
+                [&](int) { return (int64_t)-1; }, [&](int) { return sm.st1; });
+            __syncthreads();
+            uint8_t* tmp = sm.st0;
+            sm.st0 = sm.st1;
+            sm.st1 = tmp;
+        } else if (owner && threadIdx.x < E) {
+            t.alloc[node * E + threadIdx.x] = 0;
+            t.state[node * E + threadIdx.x] = sm.st0[threadIdx.x];
+            if (t.logits)
+                t.logits[node * E + threadIdx.x] = 0.f;
         }
-        __syncthreads();
-        if (threadIdx.x < E)
-            sm.st0[threadIdx.x] = sm.st1[threadIdx.x];
-        __syncthreads();
     }
 
     // ---- subtree levels split+1..M; st0 holds the previous level's states
+    const float invK = 1.0f / (float)K;
     for (int tau = split + 1; tau <= M; ++tau) {
         const int d = tau - split;
         const int width = ipow_dev(K1, d);
@@ -439,38 +456,23 @@ __device__ __forceinline__ void subtree_body(const DevTree& t, int split, int bu
         const int64_t base = sub_level_offset(K, tau) + (int64_t)r * width;
         uint8_t* prev = sm.st0;
         uint8_t* cur = sm.st1;
-        constexpr int kRT = Rows<P>::kRT;
         for (int j0 = 0; j0 < n_eval; j0 += kRT) {
             const int nrows = min(kRT, n_eval - j0);
+            // row j of the level: parent p = j / K, arrival k = j % K + 1
+            auto parent_of = [&](int row) { return (int)(((float)(j0 + row) + 0.5f) * invK); };
+            auto k_of = [&](int row) { return j0 + row - parent_of(row) * K + 1; };
             write_features<P>(
-                t, sm, nrows, tau, [&](int row) { return prev + ((j0 + row) / K) * E; },
-                [&](int row) { return (j0 + row) % K + 1; });
+                t, sm, nrows, tau, [&](int row) { return prev + parent_of(row) * E; }, k_of);
             __syncthreads();
-            mlp_regs<P, T, CH1, CHH, NHH>(t, W, nrows, sm.bufA, sm.bufB, sm.zl, sm.bias, bias_off);
-            finish_rows<G>(
-                t, sm, nrows, [&](int row) { return (j0 + row) % K + 1; },
-                [&](int row) { return prev + ((j0 + row) / K) * E; },
-                [&](int row) {
-                    const int j = j0 + row;
-                    return cur + ((j / K) * K1 + j % K + 1) * E;
-                },
-                [&](int row) {
-                    const int j = j0 + row;
-                    return base + (j / K) * K1 + j % K + 1;
-                });
+            const float* part = mlp_regs<P, T, CH1, CHH, NHH>(t, W, nrows, sm.bufA, sm.bufB, sm.bias, bias_off);
+            finish_rows<G, kRT>(
+                t, sm, part, deq_out, bias_out, nrows, k_of, [&](int row) { return prev + parent_of(row) * E; },
+                [&](int row) { return cur + (parent_of(row) * K1 + k_of(row)) * E; },
+                [&](int row) { return base + parent_of(row) * K1 + k_of(row); },
+                [&](int row) { return k_of(row) == 1 ? base + parent_of(row) * K1 : (int64_t)-1; },
+                [&](int row) { return cur + parent_of(row) * K1 * E; });
             __syncthreads();
         }
-        // k = 0 children: nothing punctured, parent state passed on
-        for (int idx = threadIdx.x; idx < (width / K1) * E; idx += kThreads) {
-            const int p = idx / E, e = idx - p * E, q = p * K1;
-            const uint8_t st = prev[p * E + e];
-            cur[q * E + e] = st;
-            t.alloc[(base + q) * E + e] = 0;
-            t.state[(base + q) * E + e] = st;
-            if (t.logits)
-                t.logits[(base + q) * E + e] = 0.f;
-        }
-        __syncthreads();
         uint8_t* tmp = sm.st0;
         sm.st0 = sm.st1;
         sm.st1 = tmp;

@@ -31,7 +31,7 @@ MAX_LAYERS = 5
 SYMBOLS = (
     "cyrus_codebook_workspace_size", "cyrus_codebook_create", "cyrus_codebook_set_weights",
     "cyrus_codebook_build", "cyrus_codebook_build_device", "cyrus_codebook_build_batch",
-    "cyrus_codebook_wait", "cyrus_codebook_lookup", "cyrus_codebook_export", "cyrus_codebook_device_alloc",
+    "cyrus_codebook_wait", "cyrus_codebook_lookup", "cyrus_codebook_assemble", "cyrus_codebook_export", "cyrus_codebook_device_alloc",
     "cyrus_codebook_num_nodes", "cyrus_codebook_kernel_path", "cyrus_codebook_destroy",
     "cyrus_status_string", "cyrus_last_error",
     "cyrus_engine_create", "cyrus_engine_submit", "cyrus_engine_step", "cyrus_engine_poll",
@@ -74,6 +74,10 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2506_00167_amd.build`")
+        # torch brings its own HIP runtime; loading it first makes libcyrus
+        # bind to that same runtime (one runtime per process, so pointers
+        # allocated by torch are known to the library)
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         vp, sz = ctypes.c_void_p, ctypes.c_size_t
         L.cyrus_codebook_workspace_size.argtypes = [ctypes.POINTER(cyrus_config), ctypes.POINTER(sz),
@@ -87,6 +91,7 @@ def lib():
         L.cyrus_codebook_wait.argtypes = [vp]
         L.cyrus_codebook_lookup.argtypes = [vp, _u8p, ctypes.c_int32, _u8p]
         L.cyrus_codebook_export.argtypes = [vp, _u8p, _f32p]
+        L.cyrus_codebook_assemble.argtypes = [vp, _i32p, ctypes.c_int32, _u8p, _u8p, ctypes.POINTER(ctypes.c_int32)]
         L.cyrus_codebook_device_alloc.argtypes = [vp]
         L.cyrus_codebook_device_alloc.restype = vp
         L.cyrus_codebook_num_nodes.argtypes = [vp]
@@ -213,6 +218,16 @@ def cyrus_codebook_lookup(h: int, arrivals: Sequence[int], num_ue: int) -> np.nd
     return out
 
 
+def cyrus_codebook_assemble(h: int, raw, carry_in: int, num_minislots: int, num_ue: int):
+    raw = np.ascontiguousarray(raw, dtype=np.int32)
+    served = np.zeros(num_minislots, dtype=np.uint8)
+    y = np.zeros((num_minislots, num_ue), dtype=np.uint8)
+    co = ctypes.c_int32()
+    _check(lib().cyrus_codebook_assemble(h, raw.ctypes.data_as(_i32p), int(carry_in), served.ctypes.data_as(_u8p),
+                                         y.ctypes.data_as(_u8p), ctypes.byref(co)), "cyrus_codebook_assemble")
+    return served, y, co.value
+
+
 def cyrus_codebook_export(h: int, nodes: int, num_ue: int, logits: bool):
     alloc = np.zeros((nodes, num_ue), dtype=np.uint8)
     lg = np.zeros((nodes, num_ue), dtype=np.float32) if logits else None
@@ -309,6 +324,10 @@ class Codebook:
 
     def lookup(self, arrivals) -> np.ndarray:
         return cyrus_codebook_lookup(self.handle, arrivals, self.cfg.num_ue)
+
+    def assemble(self, raw_arrivals, carry_in: int = 0):
+        """Controller + Alg. 3: (served [M], Y [M,E], carry_out)."""
+        return cyrus_codebook_assemble(self.handle, raw_arrivals, carry_in, self.cfg.num_minislots, self.cfg.num_ue)
 
     def export(self):
         return cyrus_codebook_export(self.handle, self.num_nodes, self.cfg.num_ue, self.export_logits)

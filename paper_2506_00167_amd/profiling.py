@@ -1,0 +1,138 @@
+"""Programs to run under rocprofv3, and summaries of what it records.
+
+  python -m paper_2506_00167_amd.profiling build --precision fp32 --builds 50
+      C2 codebook builds (device-resident UE state), one launch each.
+  python -m paper_2506_00167_amd.profiling stress --iters 5
+      the 32-cell FP8 batch.
+  python -m paper_2506_00167_amd.profiling copy --mib 256 --reps 5
+      a plain device-to-device copy of known size: the calibration of the
+      FETCH_SIZE / WRITE_SIZE counters (bytes the counters report per byte the
+      copy must move).
+  python -m paper_2506_00167_amd.profiling summarize DIR --kernel SUBSTR [--copy-dir DIR --copy-mib N]
+      reads rocprofv3 CSV output (kernel_stats / kernel_trace / counter
+      collection) and prints a short text summary.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import os
+import sys
+
+
+def _build(args):
+    import torch
+    from . import cyrus
+    from . import workload as wl
+    cfg = wl.WORKLOADS[args.workload].with_precision(args.precision)
+    act = None
+    if args.precision == "fp8":
+        import json
+        root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+        act = json.load(open(os.path.join(root, "tests", "golden", "fp8_act_scales.json")))[
+            f"{args.workload}/{wl.WEIGHT_SEEDS[args.workload]}"]
+    cb = cyrus.Codebook(cfg, wl.make_weights(cfg, wl.WEIGHT_SEEDS[args.workload]), act_scale=act,
+                        force_level=args.level)
+    ue = cyrus.ue_device_tensor(wl.make_ue_state(cfg.num_ue, wl.ue_seed(0)))
+    for _ in range(args.builds):
+        cb.build_device(ue)
+    torch.cuda.synchronize()
+    print(f"{args.builds} builds of {args.workload}/{args.precision} on the {cb.kernel_path} path")
+
+
+def _stress(args):
+    from . import stress
+    print(stress.run(args.iters, warmup=1))
+
+
+def _copy(args):
+    import torch
+    n = args.mib << 20
+    src = torch.empty(n, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    src.fill_(1)
+    torch.cuda.synchronize()
+    for _ in range(args.reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(f"{args.reps} copies of {args.mib} MiB")
+
+
+def _rows(d, pattern):
+    out = []
+    for p in glob.glob(os.path.join(d, "**", pattern), recursive=True):
+        with open(p, newline="") as f:
+            out += list(csv.DictReader(f))
+    return out
+
+
+def _counter_per_dispatch(d, kernel):
+    """Average counter values (as recorded) per dispatch of kernels matching `kernel`."""
+    rows = _rows(d, "*counter_collection.csv")
+    acc = {}
+    for r in rows:
+        if kernel not in r.get("Kernel_Name", ""):
+            continue
+        name = r.get("Counter_Name")
+        acc.setdefault(name, {}).setdefault(r.get("Dispatch_Id"), 0.0)
+        acc[name][r.get("Dispatch_Id")] += float(r.get("Counter_Value", 0))
+    return {k: sum(v.values()) / len(v) for k, v in acc.items() if v}
+
+
+def _summarize(args):
+    lines = [f"# rocprofv3 summary: kernels matching '{args.kernel}'", ""]
+    stats = _rows(args.dir, "*kernel_stats.csv")
+    for r in stats:
+        if args.kernel in r.get("Name", ""):
+            lines.append(f"kernel_stats: name={r['Name'][:120]} calls={r.get('Calls')} "
+                         f"avg_ns={r.get('AverageNs')} min_ns={r.get('MinNs')} max_ns={r.get('MaxNs')} "
+                         f"total_ns={r.get('TotalDurationNs')}")
+    trace = [r for r in _rows(args.dir, "*kernel_trace.csv") if args.kernel in r.get("Kernel_Name", "")]
+    if trace:
+        durs = [int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in trace]
+        durs.sort()
+        lines.append(f"kernel_trace: dispatches={len(durs)} avg_us={sum(durs) / len(durs) / 1e3:.2f} "
+                     f"p50_us={durs[len(durs) // 2] / 1e3:.2f} max_us={durs[-1] / 1e3:.2f} "
+                     f"grid={trace[0].get('Grid_Size_X', trace[0].get('Grid_Size', '?'))} "
+                     f"wg={trace[0].get('Workgroup_Size_X', trace[0].get('Workgroup_Size', '?'))} "
+                     f"lds={trace[0].get('LDS_Block_Size', trace[0].get('Lds_Size', '?'))} "
+                     f"vgpr={trace[0].get('VGPR_Count', '?')} agpr={trace[0].get('Accum_VGPR_Count', '?')} "
+                     f"sgpr={trace[0].get('SGPR_Count', '?')} scratch={trace[0].get('Scratch_Size', '?')}")
+    pmc = _counter_per_dispatch(args.dir, args.kernel)
+    for k, v in sorted(pmc.items()):
+        lines.append(f"counter {k}: {v:.1f} per dispatch")
+    if args.copy_dir:
+        cp = _counter_per_dispatch(args.copy_dir, args.copy_kernel)
+        moved = args.copy_mib * 1024.0  # KiB each way
+        for k, v in sorted(cp.items()):
+            lines.append(f"copy calibration {k}: {v:.1f} per dispatch for {moved:.0f} KiB moved -> "
+                         f"factor {moved / v if v else float('nan'):.4f} KiB per unit")
+    print("\n".join(lines))
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    b = sub.add_parser("build")
+    b.add_argument("--workload", default="tree-e8k3")
+    b.add_argument("--precision", default="fp32")
+    b.add_argument("--builds", type=int, default=50)
+    b.add_argument("--level", action="store_true")
+    s = sub.add_parser("stress")
+    s.add_argument("--iters", type=int, default=5)
+    c = sub.add_parser("copy")
+    c.add_argument("--mib", type=int, default=256)
+    c.add_argument("--reps", type=int, default=5)
+    m = sub.add_parser("summarize")
+    m.add_argument("dir")
+    m.add_argument("--kernel", required=True)
+    m.add_argument("--copy-dir")
+    m.add_argument("--copy-kernel", default="copy")
+    m.add_argument("--copy-mib", type=int, default=256)
+    args = ap.parse_args(argv)
+    {"build": _build, "stress": _stress, "copy": _copy, "summarize": _summarize}[args.cmd](args)
+
+
+if __name__ == "__main__":
+    sys.exit(main())

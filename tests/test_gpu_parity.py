@@ -179,3 +179,22 @@ def test_errors_do_not_enqueue():
     with pytest.raises(cyrus.CyrusError):
         cb.lookup([1] * 8)  # deeper than M
     cb.close()
+
+
+def test_oru_assemble_matches_oracle():
+    cfg = wl.TREE_E8K3
+    weights = wl.make_weights(cfg, wl.WEIGHT_SEEDS["tree-e8k3"])
+    ue = wl.make_ue_state(cfg.num_ue, wl.ue_seed(5))
+    cb, alloc, _ = _build(cfg, weights, ue)
+    rng = np.random.default_rng(10)
+    for _ in range(100):
+        # URLLC arrivals per mini-slot: 12 URLLC UEs, each with a packet w.p. 0.08
+        raw = rng.binomial(12, 0.08, size=cfg.num_minislots) * int(rng.integers(1, 4))
+        c_in = int(rng.integers(0, 3))
+        served, y, carry = cb.assemble(raw, c_in)
+        o_served, _, o_carry = oracle.oru_assemble(cfg, weights, ue, raw, c_in)
+        assert served.tolist() == o_served.tolist() and carry == o_carry
+        for tau in range(1, cfg.num_minislots + 1):
+            node = oracle.node_index(cfg.max_arrival, served[:tau])
+            assert y[tau - 1].tolist() == alloc[node].tolist()
+    cb.close()

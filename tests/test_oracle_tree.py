@@ -158,3 +158,27 @@ def test_rp_actor_splits_in_proportion():
         # every node at every depth with the same k has the same split
         for seq in itertools.product(range(4), repeat=2):
             assert alloc[oracle.node_index(3, seq + (k,))].tolist() == alloc[node].tolist()
+
+
+def test_controller_caps_and_buffers_by_hand():
+    # K = 2: at most two packets per mini-slot, the rest waits (Sec. III-A)
+    cfg = wl.TreeConfig(num_ue=4, max_arrival=2, hidden=(32,))
+    weights = wl.make_weights(cfg, 71)
+    ue = wl.make_ue_state(cfg.num_ue, 72)
+    served, y, carry = oracle.oru_assemble(cfg, weights, ue, [3, 0, 5, 0, 0, 1, 0])
+    assert served.tolist() == [2, 1, 2, 2, 1, 1, 0] and carry == 0
+    served, y, carry = oracle.oru_assemble(cfg, weights, ue, [0, 4, 4, 0, 0, 0, 0], carry_in=1)
+    assert served.tolist() == [1, 2, 2, 2, 2, 0, 0] and carry == 0
+    served, y, carry = oracle.oru_assemble(cfg, weights, ue, [9, 0, 0, 0, 0, 0, 0])
+    assert served.tolist() == [2, 2, 2, 2, 1, 0, 0] and carry == 0
+    served, y, carry = oracle.oru_assemble(cfg, weights, ue, [20, 0, 0, 0, 0, 0, 0])
+    assert served.tolist() == [2] * 7 and carry == 6
+    rng = np.random.default_rng(9)
+    for _ in range(50):
+        raw = rng.binomial(12, 0.08, size=7) * rng.integers(1, 3)
+        c_in = int(rng.integers(0, 3))
+        served, y, carry = oracle.oru_assemble(cfg, weights, ue, raw, carry_in=c_in)
+        assert raw.sum() + c_in == served.sum() + carry
+        assert served.max() <= cfg.max_arrival
+        ref = oracle.rollout(cfg, weights, ue, served)
+        assert np.array_equal(y, ref)
