@@ -98,7 +98,8 @@ Shape make_shape(const cyrus_config* cfg)
     s.w_bytes = 0;
     s.staging_floats = 0;
     for (int l = 0; l < s.n_layers; ++l) {
-        s.in_pad[l] = (int)align_up(s.dims[l], kc);
+        // FP8 reads its input in pairs of chunks (one 16x16x128 MFMA step)
+        s.in_pad[l] = (int)align_up(s.dims[l], s.prec == kFP8 ? 2 * kc : kc);
         s.out_pad[l] = (int)align_up(s.dims[l + 1], 16);
         s.w_off[l] = s.w_bytes;
         s.w_bytes += align_up((size_t)s.in_pad[l] * s.out_pad[l] * prec_esize(s.prec), 256);

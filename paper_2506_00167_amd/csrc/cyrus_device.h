@@ -78,6 +78,42 @@ __device__ __forceinline__ void mma_chunk<kFP8>(const uint4& a, const uint4& b, 
     acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a1, b1, acc, 0, 0, 0);
 }
 
+// Two consecutive chunks at once. For FP8 this is one gfx950
+// v_mfma_scale_f32_16x16x128_f8f6f4 (E4M3 operands, unit E8M0 scales) at twice
+// the rate of the 16x16x32 form: each lane supplies its 16 bytes of chunk c
+// followed by its 16 bytes of chunk c+1, for A and B alike, so whichever
+// reduction index the instruction assigns to a (lane group, byte) position, A
+// and B agree on it and the 128-term dot products are the same sums.
+template <int P>
+__device__ __forceinline__ void mma_pair(const uint4& a0, const uint4& a1, const uint4& b0, const uint4& b1,
+                                         floatx4& acc)
+{
+    mma_chunk<P>(a0, b0, acc);
+    mma_chunk<P>(a1, b1, acc);
+}
+
+typedef int intx8 __attribute__((ext_vector_type(8)));
+
+template <>
+__device__ __forceinline__ void mma_pair<kFP8>(const uint4& a0, const uint4& a1, const uint4& b0, const uint4& b1,
+                                               floatx4& acc)
+{
+    const intx8 a = {(int)a0.x, (int)a0.y, (int)a0.z, (int)a0.w, (int)a1.x, (int)a1.y, (int)a1.z, (int)a1.w};
+    const intx8 b = {(int)b0.x, (int)b0.y, (int)b0.z, (int)b0.w, (int)b1.x, (int)b1.y, (int)b1.z, (int)b1.w};
+    acc = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b, acc, 0, 0, 0, 127, 0, 127);
+}
+
+// Workgroup barrier that orders LDS only: waits for this wave's LDS operations
+// (lgkmcnt = 0) and meets the other waves, but leaves global loads and stores in
+// flight (vmcnt and expcnt at their maximum in the gfx9 s_waitcnt encoding).
+// For code whose waves exchange data through LDS only: global results are
+// write-only and global loads are waited for by the compiler before use.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    __builtin_amdgcn_s_barrier();
+}
+
 // float -> bfloat16 bits, round to nearest even (inputs are finite).
 __device__ __forceinline__ uint32_t bf16_bits(float v)
 {
@@ -364,13 +400,13 @@ template <int G>
 __device__ __forceinline__ int enforce_dpp(int E, int e, float z, int R, int rsum, int demand, float* rank_row)
 {
     const bool live = e < E;
-    const float zmax = dmax<G>(live ? z : -3.0e38f);
-    float p = live ? expf(fmaxf(z - zmax, -80.f)) : 0.f;
-    const float sum = dsum<G>(p);
-    p = p / sum;
     const int T = demand < rsum ? demand : rsum;
     if (T >= rsum)
         return live ? R : 0;
+    // the split only needs the softmax up to its normalisation: with
+    // w_e = exp(z_e - max z), x_e = min(R_e, s' w_e) where s' absorbs 1/sum w
+    const float zmax = dmax<G>(live ? z : -3.0e38f);
+    const float p = live ? expf(fmaxf(z - zmax, -80.f)) : 0.f;
     bool capped = !live;
     float s = 0.f;
     for (int pass = 0; pass <= G; ++pass) {

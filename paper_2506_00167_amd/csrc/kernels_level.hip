@@ -5,7 +5,9 @@
 // from global memory (L2-resident after the first touch), then applies the
 // feasibility enforcer and writes the nodes' puncturing vectors and states.
 // This is the general path (any width, depth, precision, cells batched per
-// launch); the latency path for small trees is kernels_subtree.hip.
+// launch); the latency path for small trees is kernels_subtree.hip. Within a
+// launch, workgroups read only what earlier launches wrote (the parent
+// level's states), so waves meet at LDS-only barriers.
 #include <algorithm>
 
 #include "cyrus_device.h"
@@ -13,7 +15,8 @@
 
 namespace cyrus {
 
-constexpr int kPF = 4;  // weight-fragment chunks per prefetch group
+constexpr int kPF = 4;   // output-layer weight chunks loaded per group
+constexpr int kTMax = 4; // neuron tiles a wave accumulates at once
 
 __device__ __forceinline__ int64_t dev_level_offset(int K, int tau)
 {
@@ -80,54 +83,74 @@ __device__ __forceinline__ void run_mlp(const DevTree& t, int nrows, uint8_t* bu
         const uint4* wl = reinterpret_cast<const uint4*>(t.w[l]);
         const float deq = t.deq[l];
         const float inv_next = t.inv_in_scale[l + 1];
-        for (int nt = wave; nt < ntile; nt += kWaves) {
-            floatx4 acc[RTT];
+        // this wave owns neuron tiles wave, wave + 8, ...; up to kTMax of them
+        // accumulate together so each activation fragment read from LDS feeds
+        // every tile of the wave
+        const int T = (ntile - wave + kWaves - 1) / kWaves;
+        for (int tt0 = 0; tt0 < T; tt0 += kTMax) {
+            floatx4 acc[kTMax][RTT];
 #pragma unroll
-            for (int rt = 0; rt < RTT; ++rt)
-                acc[rt] = floatx4{0.f, 0.f, 0.f, 0.f};
-            const uint4* wp = wl + (size_t)nt * nch * 64 + lane;
+            for (int tt = 0; tt < kTMax; ++tt)
+#pragma unroll
+                for (int rt = 0; rt < RTT; ++rt)
+                    acc[tt][rt] = floatx4{0.f, 0.f, 0.f, 0.f};
+            const uint4* wp[kTMax];
+#pragma unroll
+            for (int tt = 0; tt < kTMax; ++tt)
+                wp[tt] = wl + (size_t)(wave + kWaves * min(tt0 + tt, T - 1)) * nch * 64 + lane;
             const uint8_t* bp = in + c16 * sin + g * (kc / 4) * es;
-            const floatx4 bias = *reinterpret_cast<const floatx4*>(t.b[l] + nt * 16 + g * 4);
-            // weight fragments stream from L2 in groups of kPF chunks; the
-            // next group is in flight while the current one feeds the MFMAs
-            uint4 a[kPF];
+            // weight fragments stream from L2 one chunk pair ahead of the MFMAs
+            uint4 a0[kTMax], a1[kTMax];
 #pragma unroll
-            for (int j = 0; j < kPF; ++j)
-                a[j] = (j < nch) ? wp[(size_t)j * 64] : uint4{0, 0, 0, 0};
-            for (int c0 = 0; c0 < nch; c0 += kPF) {
-                uint4 nx[kPF];
+            for (int tt = 0; tt < kTMax; ++tt) {
+                a0[tt] = wp[tt][0];
+                a1[tt] = (nch > 1) ? wp[tt][64] : uint4{0, 0, 0, 0};
+            }
+            for (int c = 0; c < nch; c += 2) {
+                uint4 n0[kTMax], n1[kTMax];
 #pragma unroll
-                for (int j = 0; j < kPF; ++j)
-                    nx[j] = (c0 + kPF + j < nch) ? wp[(size_t)(c0 + kPF + j) * 64] : uint4{0, 0, 0, 0};
+                for (int tt = 0; tt < kTMax; ++tt) {
+                    n0[tt] = (c + 2 < nch) ? wp[tt][(size_t)(c + 2) * 64] : uint4{0, 0, 0, 0};
+                    n1[tt] = (c + 3 < nch) ? wp[tt][(size_t)(c + 3) * 64] : uint4{0, 0, 0, 0};
+                }
 #pragma unroll
-                for (int j = 0; j < kPF; ++j) {
-                    if (c0 + j < nch) {
+                for (int rt = 0; rt < RTT; ++rt) {
+                    if (rt < art) {
+                        const uint8_t* brow = bp + rt * 16 * sin + c * kc * es;
+                        const uint4 b0 = *reinterpret_cast<const uint4*>(brow);
+                        const uint4 b1 =
+                            (c + 1 < nch) ? *reinterpret_cast<const uint4*>(brow + kc * es) : uint4{0, 0, 0, 0};
 #pragma unroll
-                        for (int rt = 0; rt < RTT; ++rt) {
-                            if (rt < art) {
-                                const uint4 b =
-                                    *reinterpret_cast<const uint4*>(bp + rt * 16 * sin + (c0 + j) * kc * es);
-                                mma_chunk<P>(a[j], b, acc[rt]);
-                            }
-                        }
+                        for (int tt = 0; tt < kTMax; ++tt)
+                            if (tt0 + tt < T)
+                                mma_pair<P>(a0[tt], a1[tt], b0, b1, acc[tt][rt]);
                     }
                 }
 #pragma unroll
-                for (int j = 0; j < kPF; ++j)
-                    a[j] = nx[j];
+                for (int tt = 0; tt < kTMax; ++tt) {
+                    a0[tt] = n0[tt];
+                    a1[tt] = n1[tt];
+                }
             }
 #pragma unroll
-            for (int rt = 0; rt < RTT; ++rt) {
-                if (rt < art) {
-                    const float v0 = fmaxf(acc[rt][0] * deq + bias[0], 0.f);
-                    const float v1 = fmaxf(acc[rt][1] * deq + bias[1], 0.f);
-                    const float v2 = fmaxf(acc[rt][2] * deq + bias[2], 0.f);
-                    const float v3 = fmaxf(acc[rt][3] * deq + bias[3], 0.f);
-                    store4<P>(out + (rt * 16 + c16) * sout + (nt * 16 + g * 4) * es, v0, v1, v2, v3, inv_next);
+            for (int tt = 0; tt < kTMax; ++tt) {
+                if (tt0 + tt >= T)
+                    continue;
+                const int nt = wave + kWaves * (tt0 + tt);
+                const floatx4 bias = *reinterpret_cast<const floatx4*>(t.b[l] + nt * 16 + g * 4);
+#pragma unroll
+                for (int rt = 0; rt < RTT; ++rt) {
+                    if (rt < art) {
+                        const float v0 = fmaxf(acc[tt][rt][0] * deq + bias[0], 0.f);
+                        const float v1 = fmaxf(acc[tt][rt][1] * deq + bias[1], 0.f);
+                        const float v2 = fmaxf(acc[tt][rt][2] * deq + bias[2], 0.f);
+                        const float v3 = fmaxf(acc[tt][rt][3] * deq + bias[3], 0.f);
+                        store4<P>(out + (rt * 16 + c16) * sout + (nt * 16 + g * 4) * es, v0, v1, v2, v3, inv_next);
+                    }
                 }
             }
         }
-        __syncthreads();
+        lds_barrier();
         uint8_t* tmp = in;
         in = out;
         out = tmp;
@@ -176,7 +199,7 @@ __device__ __forceinline__ void run_mlp(const DevTree& t, int nrows, uint8_t* bu
                     *reinterpret_cast<floatx4*>(part + (size_t)(wave * RT + rt * 16 + c16) * opad + nt * 16 + g * 4) =
                         acc[rt];
         }
-        __syncthreads();
+        lds_barrier();
         const int E = t.E;
         const float deq = t.deq[l];
         for (int idx = threadIdx.x; idx < nrows * E; idx += kThreads) {
@@ -186,7 +209,7 @@ __device__ __forceinline__ void run_mlp(const DevTree& t, int nrows, uint8_t* bu
                 s += part[(size_t)(w * RT + row) * opad + e];
             zl[row * kLogitStride + e] = s * deq + t.b[l][e];
         }
-        __syncthreads();
+        lds_barrier();
     }
 }
 
@@ -209,7 +232,7 @@ __device__ __forceinline__ void level_tile(const DevTree& t, int tau, int row0, 
         statf[E + e] = (float)t.ue[E + e] * (1.f / 32.f);
         statf[2 * E + e] = __int_as_float(t.ue[2 * E + e]) * (1.f / 32.f);
     }
-    __syncthreads();
+    lds_barrier();
     if (threadIdx.x == 0) {
         int s = 0;
         for (int e = 0; e < E; ++e)
@@ -238,7 +261,7 @@ __device__ __forceinline__ void level_tile(const DevTree& t, int tau, int row0, 
         }
         store1<P>(bufA + row * s0 + f * es, v, inv0);
     }
-    __syncthreads();
+    lds_barrier();
     run_mlp<P, RTT>(t, nrows, bufA, bufB, zl);
 
     if (E <= 8)
@@ -287,7 +310,7 @@ __global__ __launch_bounds__(kThreads) void level_kernel_batch(const DevTree* tr
         const int nrows = min(16 * RTT, n_eval - row0);
         if (nrows > 0)
             level_tile<P, RTT>(t, tau, row0, nrows, smem, bufsize);
-        __syncthreads();  // LDS is reused by the next tile
+        lds_barrier();  // LDS is reused by the next tile
     }
 }
 

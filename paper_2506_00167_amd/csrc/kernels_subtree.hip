@@ -12,7 +12,9 @@
 // Every wave loads its share of the actor into registers once (the MFMA A
 // fragments of its output-neuron tiles, plus its slice of the output layer's
 // reduction dimension); afterwards each level step only moves node
-// activations through LDS.
+// activations through LDS. Waves meet at LDS-only barriers: the kernel never
+// reads back what it writes to global memory, so codebook stores (to HBM or,
+// for host builds, to pinned host memory) stay in flight across steps.
 #include "cyrus_device.h"
 #include "cyrus_host.h"
 
@@ -106,16 +108,36 @@ __device__ __forceinline__ void layer_regs(const uint4 (&A)[T][NCH], int nch, co
         for (int rt = 0; rt < kRTT; ++rt)
             acc[tt][rt] = floatx4{0.f, 0.f, 0.f, 0.f};
     const uint8_t* bp = in + c16 * sin + g * (kc / 4) * es;
+    if constexpr (P == kFP8 && NCH % 2 == 0) {
+        // chunk pairs: one 16x16x128 MFMA per pair (nch is even for FP8)
 #pragma unroll
-    for (int c = 0; c < NCH; ++c) {
-        if (c < nch) {
+        for (int c = 0; c < NCH; c += 2) {
+            if (c < nch) {
 #pragma unroll
-            for (int rt = 0; rt < kRTT; ++rt) {
-                if (rt < art) {
-                    const uint4 b = *reinterpret_cast<const uint4*>(bp + rt * 16 * sin + c * kc * es);
+                for (int rt = 0; rt < kRTT; ++rt) {
+                    if (rt < art) {
+                        const uint8_t* brow = bp + rt * 16 * sin + c * kc * es;
+                        const uint4 b0 = *reinterpret_cast<const uint4*>(brow);
+                        const uint4 b1 = *reinterpret_cast<const uint4*>(brow + kc * es);
 #pragma unroll
-                    for (int tt = 0; tt < T; ++tt)
-                        mma_chunk<P>(A[tt][c], b, acc[tt][rt]);
+                        for (int tt = 0; tt < T; ++tt)
+                            mma_pair<P>(A[tt][c], A[tt][c + 1], b0, b1, acc[tt][rt]);
+                    }
+                }
+            }
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            if (c < nch) {
+#pragma unroll
+                for (int rt = 0; rt < kRTT; ++rt) {
+                    if (rt < art) {
+                        const uint4 b = *reinterpret_cast<const uint4*>(bp + rt * 16 * sin + c * kc * es);
+#pragma unroll
+                        for (int tt = 0; tt < T; ++tt)
+                            mma_chunk<P>(A[tt][c], b, acc[tt][rt]);
+                    }
                 }
             }
         }
@@ -200,7 +222,7 @@ __device__ __forceinline__ float* mlp_regs(const DevTree& t, const WaveWeights<P
     if (!valu)
         layer_regs<P, T, CH1>(W.w1, nch1, bufA, s0, bufB, sh, bias + bias_off[0], t.deq[0], t.inv_in_scale[1], art,
                               wave, g, c16);
-    __syncthreads();
+    lds_barrier();
     uint8_t* in = bufB;
     uint8_t* out = bufA;
     if constexpr (NHH > 0) {
@@ -212,7 +234,7 @@ __device__ __forceinline__ float* mlp_regs(const DevTree& t, const WaveWeights<P
         if (!valu)
             layer_regs<P, T, CHH>(W.wh, CHH, bufB, sh, bufA, sh, bias + bias_off[1], t.deq[1], t.inv_in_scale[2],
                                   art, wave, g, c16);
-        __syncthreads();
+        lds_barrier();
         in = bufA;
         out = bufB;
     }
@@ -261,7 +283,7 @@ __device__ __forceinline__ float* mlp_regs(const DevTree& t, const WaveWeights<P
             if (rt < art)
                 *reinterpret_cast<floatx4*>(part + (size_t)(wave * kRT + rt * 16 + c16) * 16 + g * 4) = acc[rt];
     }
-    __syncthreads();
+    lds_barrier();
     return part;
 }
 
@@ -285,7 +307,10 @@ __device__ __forceinline__ void write_features(const DevTree& t, const SubtreeSm
 {
     constexpr int es = Traits<P>::kEsize;
     const int E = t.E, in0 = t.in_pad[0], d_in = t.in_dim0, s0 = in0 * es + 16;
-    const int nrows_pad = ((nrows + 15) >> 4) << 4;
+    // MFMA passes read whole 16-row tiles: rows past nrows are zeroed so they
+    // stay finite (each output row depends on its own input row only); the
+    // FP32 VALU path for a few rows reads nothing past nrows
+    const int nrows_pad = (P == kFP32 && nrows <= 4) ? nrows : ((nrows + 15) >> 4) << 4;
     const float inv0 = t.inv_in_scale[0], ftau = (float)tau * (1.f / 8.f);
     const int f0 = threadIdx.x & 63;
     for (int row = threadIdx.x >> 6; row < nrows_pad; row += kThreads / 64) {
@@ -406,14 +431,14 @@ __device__ __forceinline__ void subtree_body(const DevTree& t, int split, int bu
             off += t.out_pad[l];
         }
     }
-    __syncthreads();
+    lds_barrier();
     if (threadIdx.x == 0) {
         int s = 0;
         for (int e = 0; e < E; ++e)
             s += sm.R[e];
         sm.misc[0] = s;
     }
-    __syncthreads();
+    lds_barrier();
     const int* bias_off = sm.misc + 1;
     const float deq_out = t.deq[NHH + 1];
     const float* bias_out = sm.bias + bias_off[NHH + 1];
@@ -429,13 +454,13 @@ __device__ __forceinline__ void subtree_body(const DevTree& t, int split, int bu
         const bool owner = (r % below) == 0;
         if (k > 0) {
             write_features<P>(t, sm, 1, tau, [&](int) { return sm.st0; }, [&](int) { return k; });
-            __syncthreads();
+            lds_barrier();
             const float* part = mlp_regs<P, T, CH1, CHH, NHH>(t, W, 1, sm.bufA, sm.bufB, sm.bias, bias_off);
             finish_rows<G, kRT>(
                 t, sm, part, deq_out, bias_out, 1, [&](int) { return k; }, [&](int) { return sm.st0; },
                 [&](int) { return sm.st1; }, [&](int) { return owner ? node : (int64_t)-1; },
                 [&](int) { return (int64_t)-1; }, [&](int) { return sm.st1; });
-            __syncthreads();
+            lds_barrier();
             uint8_t* tmp = sm.st0;
             sm.st0 = sm.st1;
             sm.st1 = tmp;
@@ -463,7 +488,7 @@ __device__ __forceinline__ void subtree_body(const DevTree& t, int split, int bu
             auto k_of = [&](int row) { return j0 + row - parent_of(row) * K + 1; };
             write_features<P>(
                 t, sm, nrows, tau, [&](int row) { return prev + parent_of(row) * E; }, k_of);
-            __syncthreads();
+            lds_barrier();
             const float* part = mlp_regs<P, T, CH1, CHH, NHH>(t, W, nrows, sm.bufA, sm.bufB, sm.bias, bias_off);
             finish_rows<G, kRT>(
                 t, sm, part, deq_out, bias_out, nrows, k_of, [&](int row) { return prev + parent_of(row) * E; },
@@ -471,7 +496,7 @@ __device__ __forceinline__ void subtree_body(const DevTree& t, int split, int bu
                 [&](int row) { return base + parent_of(row) * K1 + k_of(row); },
                 [&](int row) { return k_of(row) == 1 ? base + parent_of(row) * K1 : (int64_t)-1; },
                 [&](int row) { return cur + parent_of(row) * K1 * E; });
-            __syncthreads();
+            lds_barrier();
         }
         uint8_t* tmp = sm.st0;
         sm.st0 = sm.st1;
