@@ -180,8 +180,9 @@ float e4m3_weight_scale(const float* w, size_t n)
 
 int choose_rtt(const DevTree& t, int prec, int max_rtt)
 {
-    for (int r = max_rtt; r >= 1; r /= 2) {
-        if (prec == kFP32 && r > 4)
+    const int cands[] = {6, 4, 2, 1};
+    for (int r : cands) {
+        if (r > max_rtt || (prec == kFP32 && r > 4))
             continue;
         if (level_lds_bytes(t, prec, r) <= 160 * 1024)
             return r;

@@ -47,7 +47,10 @@ int build_batch_levels(cyrus_codebook* const* cbs, const DevTree* trees, int n, 
     const int prec = host_cb->s.prec;
     // one row-tile count and LDS size valid for every member
     int rtt = 0;
-    for (int r = (prec == kFP32 ? 4 : 8); r >= 1 && !rtt; r /= 2) {
+    const int cands[] = {6, 4, 2, 1};  // row tiles per workgroup (FP32 stops at 4)
+    for (int r : cands) {
+        if (rtt || (prec == kFP32 && r > 4))
+            continue;
         size_t worst = 0;
         for (int i = 0; i < n; ++i)
             worst = std::max(worst, level_lds_bytes(trees[i], prec, r));

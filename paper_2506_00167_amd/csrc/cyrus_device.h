@@ -29,6 +29,32 @@ namespace cyrus {
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
+// Weight fragments live in device global memory. Reading them through a
+// global-address-space pointer makes the compiler emit global (not flat)
+// loads: flat loads also count against the LDS wait counter, so every wait
+// for an LDS read would otherwise drain the weight prefetch as well.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) const u32x4 guint4;
+__device__ __forceinline__ const guint4* as_global(const void* p)
+{
+    return (const guint4*)(p);
+}
+typedef __attribute__((address_space(1))) uint8_t gu8;
+typedef __attribute__((address_space(1))) float gf32;
+__device__ __forceinline__ gu8* as_global_mut(uint8_t* p) { return (gu8*)(p); }
+__device__ __forceinline__ gf32* as_global_mut(float* p) { return (gf32*)(p); }
+// Read-only view of device data through a global-address-space pointer.
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* gptr(const T* p)
+{
+    return (const __attribute__((address_space(1))) T*)(p);
+}
+__device__ __forceinline__ uint4 gld(const guint4* p)
+{
+    const u32x4 v = *p;
+    return uint4{v[0], v[1], v[2], v[3]};
+}
+
 template <int P>
 struct Traits;
 template <>

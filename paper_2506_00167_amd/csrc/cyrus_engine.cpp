@@ -233,7 +233,10 @@ int launch_step(cyrus_engine* e)
         trees[i].logits = nullptr;
     }
     int rtt = 0;
-    for (int cand = (e->prec == kFP32 ? 4 : 4); cand >= 1 && !rtt; cand /= 2) {
+    const int cands[] = {6, 4, 2, 1};  // row tiles per workgroup (FP32 stops at 4)
+    for (int cand : cands) {
+        if (rtt || (e->prec == kFP32 && cand > 4))
+            continue;
         size_t worst = 0;
         for (int i = 0; i < n; ++i)
             worst = std::max(worst, level_lds_bytes(trees[i], e->prec, cand));

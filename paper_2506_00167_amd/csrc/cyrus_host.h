@@ -15,7 +15,7 @@ struct cyrus_codebook;
 
 namespace cyrus {
 
-constexpr int kMaxBatch = 128;  // codebooks per batched launch
+constexpr int kMaxBatch = kMaxEntries;  // codebooks per batched launch
 
 // Derived sizes and the workspace carving of one configuration.
 struct Shape {

@@ -11,6 +11,7 @@ constexpr int kThreads = kWaves * 64;     // threads per workgroup
 constexpr int kMaxLayers = 5;
 constexpr int kMaxUE = 32;
 constexpr int kLogitStride = kMaxUE + 1;  // LDS row stride of the logits (bank-conflict free)
+constexpr int kMaxEntries = 128;          // (codebook, level) entries per batched level launch
 
 enum Prec { kFP32 = 0, kBF16 = 1, kFP8 = 2 };
 

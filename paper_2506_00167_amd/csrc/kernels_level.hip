@@ -15,8 +15,7 @@
 
 namespace cyrus {
 
-constexpr int kPF = 4;   // output-layer weight chunks loaded per group
-constexpr int kTMax = 4; // neuron tiles a wave accumulates at once
+constexpr int kPF = 4;  // output-layer weight chunks loaded per group
 
 __device__ __forceinline__ int64_t dev_level_offset(int K, int tau)
 {
@@ -32,9 +31,16 @@ __device__ __forceinline__ int64_t dev_level_offset(int K, int tau)
 // passes the parent state on unchanged.
 template <int G>
 __device__ __forceinline__ void finish_rows_level(const DevTree& t, const float* zl, const int* R, int rsum, int row0,
-                                                  int nrows, int64_t off, int64_t poff)
+                                                  int nrows, int64_t off, const uint8_t* pst, int p_lo)
 {
-    const int E = t.E, K = t.K;
+    // Every field of t is read once, before the first store: the output
+    // pointers could alias the tree descriptor in global memory, so a field
+    // read after a store would be fetched again from memory.
+    const int E = t.E, K = t.K, U = t.U;
+    gu8* const alloc = as_global_mut(t.alloc);
+    gu8* const state = as_global_mut(t.state);
+    gf32* const logits = as_global_mut(t.logits);
+    const bool with_logits = t.logits != nullptr;
     for (int base = 0; base < nrows; base += kThreads / G) {
         const int row = base + (int)threadIdx.x / G, e = (int)threadIdx.x % G;
         if (row < nrows) {
@@ -43,23 +49,122 @@ __device__ __forceinline__ void finish_rows_level(const DevTree& t, const float*
             const float z = e < E ? zrow[e] : 0.f;
             int a;
             if constexpr (G <= 16)
-                a = enforce_dpp<G>(E, e, z, e < E ? R[e] : 0, rsum, t.U * k, zrow);  // row reused for ranks
+                a = enforce_dpp<G>(E, e, z, e < E ? R[e] : 0, rsum, U * k, zrow);  // row reused for ranks
             else
-                a = enforce_group<G>(E, e, z, e < E ? R[e] : 0, rsum, t.U * k);
+                a = enforce_group<G>(E, e, z, e < E ? R[e] : 0, rsum, U * k);
             if (e < E) {
-                const int64_t node = off + (int64_t)p * (K + 1) + k, parent = poff + p;
-                const uint8_t c = t.state[parent * E + e];
-                t.alloc[node * E + e] = (uint8_t)a;
-                t.state[node * E + e] = (uint8_t)(c + a);
-                if (t.logits)
-                    t.logits[node * E + e] = z;
+                const int64_t node = off + (int64_t)p * (K + 1) + k;
+                const uint8_t c = pst[(p - p_lo) * E + e];
+                alloc[node * E + e] = (uint8_t)a;
+                state[node * E + e] = (uint8_t)(c + a);
+                if (with_logits)
+                    logits[node * E + e] = z;
                 if (k == 1) {
                     const int64_t sib = off + (int64_t)p * (K + 1);
-                    t.alloc[sib * E + e] = 0;
-                    t.state[sib * E + e] = c;
-                    if (t.logits)
-                        t.logits[sib * E + e] = 0.f;
+                    alloc[sib * E + e] = 0;
+                    state[sib * E + e] = c;
+                    if (with_logits)
+                        logits[sib * E + e] = 0.f;
                 }
+            }
+        }
+    }
+}
+
+// One hidden layer, out = ReLU(W in + b), for the T neuron tiles this wave
+// owns (tiles wave, wave + 8, ...). The reduction runs over chunk pairs; the
+// weight fragments of the next pair are requested before the MFMAs of the
+// current one, and the loop body has no branches (clamped addresses, whole
+// row tiles; rows past the tile's live rows are computed and discarded), so
+// the loads stay in flight behind the matrix work.
+template <int P, int RTT, int T>
+__device__ __forceinline__ void hidden_layer(const DevTree& t, int l, const uint8_t* in, uint8_t* out, int art)
+{
+    constexpr int kc = Traits<P>::kChunk, es = Traits<P>::kEsize;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, c16 = lane & 15;
+    const int nch = t.in_pad[l] / kc;
+    const int sin = t.in_pad[l] * es + 16;
+    const int sout = t.out_pad[l] * es + 16;
+    const guint4* wl = as_global(t.w[l]);
+    floatx4 acc[T][RTT];
+#pragma unroll
+    for (int tt = 0; tt < T; ++tt)
+#pragma unroll
+        for (int rt = 0; rt < RTT; ++rt)
+            acc[tt][rt] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const guint4* wp[T];
+#pragma unroll
+    for (int tt = 0; tt < T; ++tt)
+        wp[tt] = wl + (size_t)(wave + kWaves * tt) * nch * 64 + lane;
+    const uint8_t* bp = in + c16 * sin + g * (kc / 4) * es;
+    const int npair = nch >> 1;
+    // two register sets in ping-pong: while one pair's fragments feed the
+    // MFMAs, the other set is being loaded, so each wait only covers loads
+    // issued one step earlier
+    uint4 x0[T], x1[T], y0[T], y1[T];
+#define CYRUS_LOAD_PAIR(D0, D1, Q)                                                                                     \
+    {                                                                                                                  \
+        const int c_ = min((Q), max(npair - 1, 0)) * 2; /* clamped: past the end reloads the last pair */             \
+        _Pragma("unroll") for (int tt = 0; tt < T; ++tt)                                                              \
+        {                                                                                                              \
+            D0[tt] = gld(wp[tt] + (size_t)c_ * 64);                                                                          \
+            D1[tt] = gld(wp[tt] + (size_t)(c_ + 1) * 64);                                                                    \
+        }                                                                                                              \
+    }
+#define CYRUS_MMA_PAIRS(S0, S1, Q)                                                                                     \
+    {                                                                                                                  \
+        const uint8_t* bq_ = bp + 2 * (Q) * kc * es;                                                                   \
+        _Pragma("unroll") for (int rt = 0; rt < RTT; ++rt)                                                            \
+        {                                                                                                              \
+            const uint4 b0_ = *reinterpret_cast<const uint4*>(bq_ + rt * 16 * sin);                                    \
+            const uint4 b1_ = *reinterpret_cast<const uint4*>(bq_ + rt * 16 * sin + kc * es);                          \
+            _Pragma("unroll") for (int tt = 0; tt < T; ++tt) mma_pair<P>(S0[tt], S1[tt], b0_, b1_, acc[tt][rt]);      \
+        }                                                                                                              \
+    }
+    if (npair > 0)
+        CYRUS_LOAD_PAIR(x0, x1, 0)
+    int q = 0;
+    for (; q + 1 < npair; q += 2) {
+        CYRUS_LOAD_PAIR(y0, y1, q + 1)
+        __builtin_amdgcn_sched_barrier(0);  // the next pair's loads go out before this pair's MFMAs
+        CYRUS_MMA_PAIRS(x0, x1, q)
+        CYRUS_LOAD_PAIR(x0, x1, q + 2)
+        __builtin_amdgcn_sched_barrier(0);
+        CYRUS_MMA_PAIRS(y0, y1, q + 1)
+    }
+    if (q < npair)
+        CYRUS_MMA_PAIRS(x0, x1, q)
+#undef CYRUS_LOAD_PAIR
+#undef CYRUS_MMA_PAIRS
+    if (nch & 1) {  // odd chunk count (FP32/BF16 first layer): one last chunk
+        const int c = nch - 1;
+        const uint8_t* bq = bp + c * kc * es;
+        uint4 a0[T];
+#pragma unroll
+        for (int tt = 0; tt < T; ++tt)
+            a0[tt] = gld(wp[tt] + (size_t)c * 64);
+#pragma unroll
+        for (int rt = 0; rt < RTT; ++rt) {
+            const uint4 b0 = *reinterpret_cast<const uint4*>(bq + rt * 16 * sin);
+#pragma unroll
+            for (int tt = 0; tt < T; ++tt)
+                mma_chunk<P>(a0[tt], b0, acc[tt][rt]);
+        }
+    }
+    const float deq = t.deq[l];
+    const float inv_next = t.inv_in_scale[l + 1];
+#pragma unroll
+    for (int tt = 0; tt < T; ++tt) {
+        const int nt = wave + kWaves * tt;
+        const floatx4 bias = *gptr(reinterpret_cast<const floatx4*>(t.b[l] + nt * 16 + g * 4));
+#pragma unroll
+        for (int rt = 0; rt < RTT; ++rt) {
+            if (rt < art) {
+                const float v0 = fmaxf(acc[tt][rt][0] * deq + bias[0], 0.f);
+                const float v1 = fmaxf(acc[tt][rt][1] * deq + bias[1], 0.f);
+                const float v2 = fmaxf(acc[tt][rt][2] * deq + bias[2], 0.f);
+                const float v3 = fmaxf(acc[tt][rt][3] * deq + bias[3], 0.f);
+                store4<P>(out + (rt * 16 + c16) * sout + (nt * 16 + g * 4) * es, v0, v1, v2, v3, inv_next);
             }
         }
     }
@@ -76,79 +181,20 @@ __device__ __forceinline__ void run_mlp(const DevTree& t, int nrows, uint8_t* bu
     uint8_t* in = bufA;
     uint8_t* out = bufB;
     for (int l = 0; l + 1 < t.n_layers; ++l) {
-        const int nch = t.in_pad[l] / kc;
-        const int sin = t.in_pad[l] * es + 16;
-        const int sout = t.out_pad[l] * es + 16;
-        const int ntile = t.out_pad[l] >> 4;
-        const uint4* wl = reinterpret_cast<const uint4*>(t.w[l]);
-        const float deq = t.deq[l];
-        const float inv_next = t.inv_in_scale[l + 1];
-        // this wave owns neuron tiles wave, wave + 8, ...; up to kTMax of them
-        // accumulate together so each activation fragment read from LDS feeds
-        // every tile of the wave
-        const int T = (ntile - wave + kWaves - 1) / kWaves;
-        for (int tt0 = 0; tt0 < T; tt0 += kTMax) {
-            floatx4 acc[kTMax][RTT];
-#pragma unroll
-            for (int tt = 0; tt < kTMax; ++tt)
-#pragma unroll
-                for (int rt = 0; rt < RTT; ++rt)
-                    acc[tt][rt] = floatx4{0.f, 0.f, 0.f, 0.f};
-            const uint4* wp[kTMax];
-#pragma unroll
-            for (int tt = 0; tt < kTMax; ++tt)
-                wp[tt] = wl + (size_t)(wave + kWaves * min(tt0 + tt, T - 1)) * nch * 64 + lane;
-            const uint8_t* bp = in + c16 * sin + g * (kc / 4) * es;
-            // weight fragments stream from L2 one chunk pair ahead of the MFMAs
-            uint4 a0[kTMax], a1[kTMax];
-#pragma unroll
-            for (int tt = 0; tt < kTMax; ++tt) {
-                a0[tt] = wp[tt][0];
-                a1[tt] = (nch > 1) ? wp[tt][64] : uint4{0, 0, 0, 0};
-            }
-            for (int c = 0; c < nch; c += 2) {
-                uint4 n0[kTMax], n1[kTMax];
-#pragma unroll
-                for (int tt = 0; tt < kTMax; ++tt) {
-                    n0[tt] = (c + 2 < nch) ? wp[tt][(size_t)(c + 2) * 64] : uint4{0, 0, 0, 0};
-                    n1[tt] = (c + 3 < nch) ? wp[tt][(size_t)(c + 3) * 64] : uint4{0, 0, 0, 0};
-                }
-#pragma unroll
-                for (int rt = 0; rt < RTT; ++rt) {
-                    if (rt < art) {
-                        const uint8_t* brow = bp + rt * 16 * sin + c * kc * es;
-                        const uint4 b0 = *reinterpret_cast<const uint4*>(brow);
-                        const uint4 b1 =
-                            (c + 1 < nch) ? *reinterpret_cast<const uint4*>(brow + kc * es) : uint4{0, 0, 0, 0};
-#pragma unroll
-                        for (int tt = 0; tt < kTMax; ++tt)
-                            if (tt0 + tt < T)
-                                mma_pair<P>(a0[tt], a1[tt], b0, b1, acc[tt][rt]);
-                    }
-                }
-#pragma unroll
-                for (int tt = 0; tt < kTMax; ++tt) {
-                    a0[tt] = n0[tt];
-                    a1[tt] = n1[tt];
-                }
-            }
-#pragma unroll
-            for (int tt = 0; tt < kTMax; ++tt) {
-                if (tt0 + tt >= T)
-                    continue;
-                const int nt = wave + kWaves * (tt0 + tt);
-                const floatx4 bias = *reinterpret_cast<const floatx4*>(t.b[l] + nt * 16 + g * 4);
-#pragma unroll
-                for (int rt = 0; rt < RTT; ++rt) {
-                    if (rt < art) {
-                        const float v0 = fmaxf(acc[tt][rt][0] * deq + bias[0], 0.f);
-                        const float v1 = fmaxf(acc[tt][rt][1] * deq + bias[1], 0.f);
-                        const float v2 = fmaxf(acc[tt][rt][2] * deq + bias[2], 0.f);
-                        const float v3 = fmaxf(acc[tt][rt][3] * deq + bias[3], 0.f);
-                        store4<P>(out + (rt * 16 + c16) * sout + (nt * 16 + g * 4) * es, v0, v1, v2, v3, inv_next);
-                    }
-                }
-            }
+        const int T = (t.out_pad[l] >> 4) / kWaves;  // neuron tiles per wave (hidden widths are multiples of 128)
+        switch (T) {
+        case 1:
+            hidden_layer<P, RTT, 1>(t, l, in, out, art);
+            break;
+        case 2:
+            hidden_layer<P, RTT, 2>(t, l, in, out, art);
+            break;
+        case 3:
+            hidden_layer<P, RTT, 3>(t, l, in, out, art);
+            break;
+        default:
+            hidden_layer<P, RTT, 4>(t, l, in, out, art);
+            break;
         }
         lds_barrier();
         uint8_t* tmp = in;
@@ -166,19 +212,19 @@ __device__ __forceinline__ void run_mlp(const DevTree& t, int nrows, uint8_t* bu
         const int cpw = (nch + kWaves - 1) / kWaves;
         const int c0 = wave * cpw, c1 = min(nch, c0 + cpw);
         float* part = reinterpret_cast<float*>(out);
-        const uint4* wl = reinterpret_cast<const uint4*>(t.w[l]);
+        const guint4* wl = as_global(t.w[l]);
         for (int nt = 0; nt < ntile; ++nt) {
             floatx4 acc[RTT];
 #pragma unroll
             for (int rt = 0; rt < RTT; ++rt)
                 acc[rt] = floatx4{0.f, 0.f, 0.f, 0.f};
-            const uint4* wp = wl + (size_t)nt * nch * 64 + lane;
+            const guint4* wp = wl + (size_t)nt * nch * 64 + lane;
             const uint8_t* bp = in + c16 * sin + g * (kc / 4) * es;
             for (int cb = c0; cb < c1; cb += kPF) {
                 uint4 a[kPF];
 #pragma unroll
                 for (int j = 0; j < kPF; ++j)
-                    a[j] = (cb + j < c1) ? wp[(size_t)(cb + j) * 64] : uint4{0, 0, 0, 0};
+                    a[j] = (cb + j < c1) ? gld(wp + (size_t)(cb + j) * 64) : uint4{0, 0, 0, 0};
 #pragma unroll
                 for (int j = 0; j < kPF; ++j) {
                     if (cb + j < c1) {
@@ -207,69 +253,133 @@ __device__ __forceinline__ void run_mlp(const DevTree& t, int nrows, uint8_t* bu
             float s = 0.f;
             for (int w = 0; w < kWaves; ++w)
                 s += part[(size_t)(w * RT + row) * opad + e];
-            zl[row * kLogitStride + e] = s * deq + t.b[l][e];
+            zl[row * kLogitStride + e] = s * deq + gptr(t.b[l])[e];
         }
         lds_barrier();
     }
 }
 
+// LDS of a level workgroup: two activation buffers of `bufsize` bytes, the
+// FP32 logits of the tile, the UE radio state, the parent states of the
+// tile's rows and, in batched launches, the entry tables of the launch.
+__host__ __device__ constexpr int pst_bytes(int rtt) { return ((16 * rtt + 2) * kMaxUE + 15) & ~15; }
+
+struct LevelSmem {
+    uint8_t* bufA;
+    uint8_t* bufB;
+    float* zl;      // [RT][kLogitStride]
+    int* R;         // [kMaxUE]
+    int* rsum;      // [4]
+    float* statf;   // [3 * kMaxUE] R/32, MCS/32, SINR/32
+    uint8_t* pst;   // [(RT + 2) * kMaxUE] states of the parents of the tile's rows
+    int* tab;       // [3 * (kMaxEntries + 1)] ent_tree, ent_tau, prefix
+};
+
+template <int RTT>
+__device__ __forceinline__ LevelSmem level_smem(uint8_t* smem, int bufsize)
+{
+    LevelSmem m;
+    m.bufA = smem;
+    m.bufB = smem + bufsize;
+    m.zl = reinterpret_cast<float*>(smem + 2 * bufsize);
+    m.R = reinterpret_cast<int*>(m.zl + 16 * RTT * kLogitStride);
+    m.rsum = m.R + kMaxUE;
+    m.statf = reinterpret_cast<float*>(m.rsum + 4);
+    m.pst = reinterpret_cast<uint8_t*>(m.statf + 3 * kMaxUE);
+    m.tab = reinterpret_cast<int*>(m.pst + pst_bytes(RTT));
+    return m;
+}
+
 // One tile of evaluated rows [row0, row0 + nrows) of level tau.
 template <int P, int RTT>
-__device__ __forceinline__ void level_tile(const DevTree& t, int tau, int row0, int nrows, uint8_t* smem, int bufsize)
+__device__ __forceinline__ void level_tile(const DevTree& t, int tau, int row0, int nrows, const LevelSmem& m)
 {
-    constexpr int es = Traits<P>::kEsize, RT = 16 * RTT;
-    uint8_t* bufA = smem;
-    uint8_t* bufB = smem + bufsize;
-    float* zl = reinterpret_cast<float*>(smem + 2 * bufsize);
-    int* R = reinterpret_cast<int*>(zl + RT * kLogitStride);
-    int* rsum_lds = R + kMaxUE;
-    float* statf = reinterpret_cast<float*>(rsum_lds + 4);  // R/32, MCS/32, SINR/32
+    constexpr int es = Traits<P>::kEsize, F = 16 / es;  // features per 16-byte LDS segment
+    constexpr int kPstIters = (pst_bytes(RTT) + kThreads - 1) / kThreads;
     const int E = t.E, K = t.K;
-    if (threadIdx.x < E) {
+    const int64_t off = dev_level_offset(K, tau), poff = dev_level_offset(K, tau - 1);
+    // Stage the tile's inputs in LDS with independent loads in flight
+    // together: the states of the parents of rows row0..row0+nrows-1 (one
+    // contiguous range of the parent level) and the UE radio state.
+    const int p_lo = row0 / K;
+    const int npb = ((row0 + nrows - 1) / K - p_lo + 1) * E;
+    const auto* sp = gptr(t.state + (poff + p_lo) * E);
+    uint8_t pv[kPstIters];
+#pragma unroll
+    for (int j = 0; j < kPstIters; ++j) {
+        const int i = (int)threadIdx.x + j * kThreads;
+        pv[j] = i < npb ? sp[i] : (uint8_t)0;
+    }
+    if (threadIdx.x < 64) {  // wave 0: UE state, and the sum of R by shuffles
         const int e = threadIdx.x;
-        R[e] = t.ue[e];
-        statf[e] = (float)t.ue[e] * (1.f / 32.f);
-        statf[E + e] = (float)t.ue[E + e] * (1.f / 32.f);
-        statf[2 * E + e] = __int_as_float(t.ue[2 * E + e]) * (1.f / 32.f);
+        int r = 0;
+        if (e < E) {
+            const auto* ue = gptr(t.ue);
+            r = ue[e];
+            const int mcs = ue[E + e], sinr = ue[2 * E + e];
+            m.R[e] = r;
+            m.statf[e] = (float)r * (1.f / 32.f);
+            m.statf[E + e] = (float)mcs * (1.f / 32.f);
+            m.statf[2 * E + e] = __int_as_float(sinr) * (1.f / 32.f);
+        }
+#pragma unroll
+        for (int o = 16; o > 0; o >>= 1)
+            r += __shfl_xor(r, o, 32);
+        if (e == 0)
+            *m.rsum = r;
+    }
+#pragma unroll
+    for (int j = 0; j < kPstIters; ++j) {
+        const int i = (int)threadIdx.x + j * kThreads;
+        if (i < npb)
+            m.pst[i] = pv[j];
     }
     lds_barrier();
-    if (threadIdx.x == 0) {
-        int s = 0;
-        for (int e = 0; e < E; ++e)
-            s += R[e];
-        *rsum_lds = s;
-    }
-    const int64_t off = dev_level_offset(K, tau), poff = dev_level_offset(K, tau - 1);
 
-    // features of every row, zero padded to the k-chunk and to whole row tiles
+    // features of every row, zero padded to the k-chunk and to whole row
+    // tiles, written one 16-byte segment (F features) at a time
     const int in0 = t.in_pad[0], d_in = t.in_dim0, s0 = in0 * es + 16;
+    const int nseg = in0 / F;
     const int nrows_pad = ((nrows + 15) >> 4) << 4;
     const float inv0 = t.inv_in_scale[0];
-    for (int idx = threadIdx.x; idx < nrows_pad * in0; idx += kThreads) {
-        const int row = idx / in0, f = idx - row * in0;
-        float v = 0.f;
-        if (row < nrows && f < d_in) {
-            const int r = row0 + row, p = r / K, k = r - p * K + 1;
-            if (f < 3 * E)
-                v = statf[f];
-            else if (f < 4 * E)
-                v = (float)t.state[(poff + p) * E + (f - 3 * E)] * (1.f / 64.f);
-            else if (f == 4 * E)
-                v = (float)tau * (1.f / 8.f);
-            else
-                v = (float)k * (1.f / 8.f);
+    const float ftau = (float)tau * (1.f / 8.f);
+    for (int idx = threadIdx.x; idx < nrows_pad * nseg; idx += kThreads) {
+        const int row = idx / nseg, f0 = (idx - row * nseg) * F;
+        const int r = row0 + row, p = r / K, k = r - p * K + 1;
+        const bool live = row < nrows;
+        const uint8_t* ps = m.pst + (p - p_lo) * E;
+        float v[F];
+#pragma unroll
+        for (int j = 0; j < F; ++j) {
+            const int f = f0 + j;
+            float x = 0.f;
+            if (live && f < d_in) {
+                if (f < 3 * E)
+                    x = m.statf[f];
+                else if (f < 4 * E)
+                    x = (float)ps[f - 3 * E] * (1.f / 64.f);
+                else if (f == 4 * E)
+                    x = ftau;
+                else
+                    x = (float)k * (1.f / 8.f);
+            }
+            v[j] = x;
         }
-        store1<P>(bufA + row * s0 + f * es, v, inv0);
+        uint8_t* dst = m.bufA + row * s0 + f0 * es;
+#pragma unroll
+        for (int j = 0; j < F; j += 4)
+            store4<P>(dst + j * es, v[j], v[j + 1], v[j + 2], v[j + 3], inv0);
     }
     lds_barrier();
-    run_mlp<P, RTT>(t, nrows, bufA, bufB, zl);
+    run_mlp<P, RTT>(t, nrows, m.bufA, m.bufB, m.zl);
 
+    const int rsum = *m.rsum;
     if (E <= 8)
-        finish_rows_level<8>(t, zl, R, *rsum_lds, row0, nrows, off, poff);
+        finish_rows_level<8>(t, m.zl, m.R, rsum, row0, nrows, off, m.pst, p_lo);
     else if (E <= 16)
-        finish_rows_level<16>(t, zl, R, *rsum_lds, row0, nrows, off, poff);
+        finish_rows_level<16>(t, m.zl, m.R, rsum, row0, nrows, off, m.pst, p_lo);
     else
-        finish_rows_level<32>(t, zl, R, *rsum_lds, row0, nrows, off, poff);
+        finish_rows_level<32>(t, m.zl, m.R, rsum, row0, nrows, off, m.pst, p_lo);
 }
 
 template <int P, int RTT>
@@ -280,36 +390,50 @@ __global__ __launch_bounds__(kThreads) void level_kernel(DevTree t, int tau, int
     const int nrows = min(16 * RTT, n_eval - row0);
     if (nrows <= 0)
         return;
-    level_tile<P, RTT>(t, tau, row0, nrows, smem, bufsize);
+    level_tile<P, RTT>(t, tau, row0, nrows, level_smem<RTT>(smem, bufsize));
 }
 
 // Batched level launch over several codebooks (cells), each at its own level:
 // entry j of the launch is codebook ent_tree[j] at level ent_tau[j] and owns
 // row tiles [prefix[j], prefix[j+1]) of the prefix[n] tiles of the launch.
-// Persistent: a grid of at most one workgroup per CU strides over the tiles.
+// Persistent: a grid of at most one workgroup per CU strides over the tiles;
+// the entry tables are copied to LDS once and searched there.
 template <int P, int RTT>
-__global__ __launch_bounds__(kThreads) void level_kernel_batch(const DevTree* trees, const int* ent_tree,
-                                                               const int* ent_tau, const int* prefix, int n,
-                                                               int bufsize)
+__global__ __launch_bounds__(kThreads) void level_kernel_batch(const DevTree* __restrict__ trees,
+                                                               const int* __restrict__ ent_tree,
+                                                               const int* __restrict__ ent_tau,
+                                                               const int* __restrict__ prefix, int n, int bufsize)
 {
     extern __shared__ __align__(16) uint8_t smem[];
-    const int total = prefix[n];
+    const LevelSmem m = level_smem<RTT>(smem, bufsize);
+    int* s_tree = m.tab;
+    int* s_tau = m.tab + kMaxEntries;
+    int* s_prefix = m.tab + 2 * kMaxEntries;
+    for (int i = threadIdx.x; i <= n; i += kThreads) {
+        s_prefix[i] = prefix[i];
+        if (i < n) {
+            s_tree[i] = ent_tree[i];
+            s_tau[i] = ent_tau[i];
+        }
+    }
+    lds_barrier();
+    const int total = s_prefix[n];
     for (int b = blockIdx.x; b < total; b += gridDim.x) {
         int lo = 0, hi = n - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
-            if (prefix[mid] <= b)
+            if (s_prefix[mid] <= b)
                 lo = mid;
             else
                 hi = mid - 1;
         }
-        const DevTree& t = trees[ent_tree[lo]];
-        const int tau = ent_tau[lo];
+        const DevTree& t = trees[s_tree[lo]];
+        const int tau = s_tau[lo];
         const int n_eval = (int)(t.K * (dev_level_offset(t.K, tau) - dev_level_offset(t.K, tau - 1)));
-        const int row0 = (b - prefix[lo]) * 16 * RTT;
+        const int row0 = (b - s_prefix[lo]) * 16 * RTT;
         const int nrows = min(16 * RTT, n_eval - row0);
         if (nrows > 0)
-            level_tile<P, RTT>(t, tau, row0, nrows, smem, bufsize);
+            level_tile<P, RTT>(t, tau, row0, nrows, m);
         lds_barrier();  // LDS is reused by the next tile
     }
 }
@@ -345,7 +469,8 @@ size_t level_buf_bytes(const DevTree& t, int prec, int rtt)
 
 size_t level_lds_for_buf(size_t buf, int rtt)
 {
-    return 2 * buf + (size_t)16 * rtt * kLogitStride * 4 + (kMaxUE + 4) * 4 + 3 * kMaxUE * 4;
+    return 2 * buf + (size_t)16 * rtt * kLogitStride * 4 + (kMaxUE + 4) * 4 + 3 * kMaxUE * 4 + pst_bytes(rtt) +
+           3 * (kMaxEntries + 1) * 4;
 }
 
 size_t level_lds_bytes(const DevTree& t, int prec, int rtt) { return level_lds_for_buf(level_buf_bytes(t, prec, rtt), rtt); }
@@ -398,8 +523,8 @@ hipError_t launch_level(const DevTree& t, int prec, int rtt, int tau, hipStream_
     if (prec == P && rtt == R)                                                                                         \
         return launch_level_t<P, R>(t, tau, s);
     CYRUS_LEVEL_CASE(kFP32, 1) CYRUS_LEVEL_CASE(kFP32, 2) CYRUS_LEVEL_CASE(kFP32, 4)
-    CYRUS_LEVEL_CASE(kBF16, 1) CYRUS_LEVEL_CASE(kBF16, 2) CYRUS_LEVEL_CASE(kBF16, 4) CYRUS_LEVEL_CASE(kBF16, 8)
-    CYRUS_LEVEL_CASE(kFP8, 1) CYRUS_LEVEL_CASE(kFP8, 2) CYRUS_LEVEL_CASE(kFP8, 4) CYRUS_LEVEL_CASE(kFP8, 8)
+    CYRUS_LEVEL_CASE(kBF16, 1) CYRUS_LEVEL_CASE(kBF16, 2) CYRUS_LEVEL_CASE(kBF16, 4) CYRUS_LEVEL_CASE(kBF16, 6)
+    CYRUS_LEVEL_CASE(kFP8, 1) CYRUS_LEVEL_CASE(kFP8, 2) CYRUS_LEVEL_CASE(kFP8, 4) CYRUS_LEVEL_CASE(kFP8, 6)
 #undef CYRUS_LEVEL_CASE
     return hipErrorInvalidValue;
 }
@@ -411,8 +536,8 @@ hipError_t launch_level_batch(const DevTree* trees, const int* ent_tree, const i
     if (prec == P && rtt == R)                                                                                         \
         return launch_level_batch_t<P, R>(trees, ent_tree, ent_tau, prefix, n, nblocks, buf, lds, s);
     CYRUS_LEVEL_CASE(kFP32, 1) CYRUS_LEVEL_CASE(kFP32, 2) CYRUS_LEVEL_CASE(kFP32, 4)
-    CYRUS_LEVEL_CASE(kBF16, 1) CYRUS_LEVEL_CASE(kBF16, 2) CYRUS_LEVEL_CASE(kBF16, 4) CYRUS_LEVEL_CASE(kBF16, 8)
-    CYRUS_LEVEL_CASE(kFP8, 1) CYRUS_LEVEL_CASE(kFP8, 2) CYRUS_LEVEL_CASE(kFP8, 4) CYRUS_LEVEL_CASE(kFP8, 8)
+    CYRUS_LEVEL_CASE(kBF16, 1) CYRUS_LEVEL_CASE(kBF16, 2) CYRUS_LEVEL_CASE(kBF16, 4) CYRUS_LEVEL_CASE(kBF16, 6)
+    CYRUS_LEVEL_CASE(kFP8, 1) CYRUS_LEVEL_CASE(kFP8, 2) CYRUS_LEVEL_CASE(kFP8, 4) CYRUS_LEVEL_CASE(kFP8, 6)
 #undef CYRUS_LEVEL_CASE
     return hipErrorInvalidValue;
 }

@@ -11,6 +11,12 @@
   python -m paper_2506_00167_amd.profiling summarize DIR --kernel SUBSTR [--copy-dir DIR --copy-mib N]
       reads rocprofv3 CSV output (kernel_stats / kernel_trace / counter
       collection) and prints a short text summary.
+  python -m paper_2506_00167_amd.profiling traffic --fetch DIR --write DIR --copy-fetch DIR --copy-write DIR
+         --kernel SUBSTR --key KERNEL/WORKLOAD/PRECISION [--copy-mib N]
+      HBM bytes per launch of the kernel from a FETCH_SIZE run and a
+      WRITE_SIZE run, each scaled by what the same counter reports for the
+      plain copy of known size; stored in profiles/traffic.json with the hash
+      of the kernel sources the counters were taken on.
 """
 from __future__ import annotations
 
@@ -111,6 +117,32 @@ def _summarize(args):
     print("\n".join(lines))
 
 
+def _traffic(args):
+    import json
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    sys.path.insert(0, root)
+    from bench import kernel_source_hash
+    fetch = _counter_per_dispatch(args.fetch, args.kernel).get("FETCH_SIZE")
+    write = _counter_per_dispatch(args.write, args.kernel).get("WRITE_SIZE")
+    cf = _counter_per_dispatch(args.copy_fetch, args.copy_kernel).get("FETCH_SIZE")
+    cw = _counter_per_dispatch(args.copy_write, args.copy_kernel).get("WRITE_SIZE")
+    if None in (fetch, write, cf, cw):
+        raise SystemExit(f"missing counters: fetch={fetch} write={write} copy_fetch={cf} copy_write={cw}")
+    moved_kib = args.copy_mib * 1024.0
+    f_factor, w_factor = moved_kib / cf, moved_kib / cw
+    entry = {"fetch_kib": fetch * f_factor, "write_kib": write * w_factor,
+             "bytes_per_launch": (fetch * f_factor + write * w_factor) * 1024.0,
+             "fetch_factor": f_factor, "write_factor": w_factor,
+             "raw_fetch_size": fetch, "raw_write_size": write, "source_hash": kernel_source_hash()}
+    path = os.path.join(root, "profiles", "traffic.json")
+    data = json.load(open(path)) if os.path.exists(path) else {}
+    data[args.key] = entry
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    print(json.dumps({args.key: entry}))
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -130,8 +162,15 @@ def main(argv=None):
     m.add_argument("--copy-dir")
     m.add_argument("--copy-kernel", default="copy")
     m.add_argument("--copy-mib", type=int, default=256)
+    t = sub.add_parser("traffic")
+    for k in ("fetch", "write", "copy_fetch", "copy_write"):
+        t.add_argument("--" + k.replace("_", "-"), dest=k, required=True)
+    t.add_argument("--kernel", required=True)
+    t.add_argument("--key", required=True)
+    t.add_argument("--copy-kernel", default="copy")
+    t.add_argument("--copy-mib", type=int, default=256)
     args = ap.parse_args(argv)
-    {"build": _build, "stress": _stress, "copy": _copy, "summarize": _summarize}[args.cmd](args)
+    {"build": _build, "stress": _stress, "copy": _copy, "summarize": _summarize, "traffic": _traffic}[args.cmd](args)
 
 
 if __name__ == "__main__":
