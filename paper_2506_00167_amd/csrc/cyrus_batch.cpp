@@ -46,23 +46,10 @@ int build_batch_levels(cyrus_codebook* const* cbs, const DevTree* trees, int n, 
     cyrus_codebook* host_cb = cbs[0];
     const int prec = host_cb->s.prec;
     // one row-tile count and LDS size valid for every member
-    int rtt = 0;
-    const int cands[] = {6, 4, 2, 1};  // row tiles per workgroup (FP32 stops at 4)
-    for (int r : cands) {
-        if (rtt || (prec == kFP32 && r > 4))
-            continue;
-        size_t worst = 0;
-        for (int i = 0; i < n; ++i)
-            worst = std::max(worst, level_lds_bytes(trees[i], prec, r));
-        if (worst <= 160 * 1024)
-            rtt = r;
-    }
-    if (!rtt)
+    int rtt = 0, buf = 0;
+    size_t lds = 0;
+    if (!plan_level_batch(trees, n, prec, &rtt, &buf, &lds))
         return set_error(CYRUS_EUNSUPPORTED, "batch does not fit the level kernel's LDS");
-    size_t buf = 0;
-    for (int i = 0; i < n; ++i)
-        buf = std::max(buf, level_buf_bytes(trees[i], prec, rtt));
-    const size_t lds = level_lds_for_buf(buf, rtt);
 
     const BatchLayout L = batch_layout();
     uint8_t* hbase = host_cb->host + host_cb->s.hoff_batch;
@@ -109,7 +96,7 @@ int build_batch_levels(cyrus_codebook* const* cbs, const DevTree* trees, int n, 
     for (int tau = 1; tau <= max_m; ++tau) {
         const int32_t* slot = reinterpret_cast<const int32_t*>(dbase + L.slot0 + (tau - 1) * L.slot_bytes);
         e = launch_level_batch(dtrees, slot, slot + kMaxBatch, slot + 2 * kMaxBatch, entries[tau], blocks[tau], prec,
-                               rtt, (int)buf, lds, st);
+                               rtt, buf, lds, st);
         if (e != hipSuccess)
             return hip_fail(e, "level batch launch");
     }

@@ -232,23 +232,10 @@ int launch_step(cyrus_engine* e)
         trees[i].state = dbase + tree;
         trees[i].logits = nullptr;
     }
-    int rtt = 0;
-    const int cands[] = {6, 4, 2, 1};  // row tiles per workgroup (FP32 stops at 4)
-    for (int cand : cands) {
-        if (rtt || (e->prec == kFP32 && cand > 4))
-            continue;
-        size_t worst = 0;
-        for (int i = 0; i < n; ++i)
-            worst = std::max(worst, level_lds_bytes(trees[i], e->prec, cand));
-        if (worst <= 160 * 1024)
-            rtt = cand;
-    }
-    if (!rtt)
+    int rtt = 0, buf = 0;
+    size_t lds = 0;
+    if (!plan_level_batch(trees, n, e->prec, &rtt, &buf, &lds))
         return set_error(CYRUS_EUNSUPPORTED, "batch does not fit the level kernel's LDS");
-    size_t buf = 0;
-    for (int i = 0; i < n; ++i)
-        buf = std::max(buf, level_buf_bytes(trees[i], e->prec, rtt));
-    const size_t lds = level_lds_for_buf(buf, rtt);
 
     uint8_t* h = e->hpool + e->slot_hoff[slot];
     uint8_t* d = e->dpool + e->slot_doff[slot];
@@ -273,7 +260,7 @@ int launch_step(cyrus_engine* e)
         return hip_err(err, "descriptor copy");
     const int32_t* dent = reinterpret_cast<const int32_t*>(d + ent_off);
     err = launch_level_batch(reinterpret_cast<const DevTree*>(d), dent, dent + kMaxBatch, dent + 2 * kMaxBatch, n,
-                             total, e->prec, rtt, (int)buf, lds, e->stream);
+                             total, e->prec, rtt, buf, lds, e->stream);
     if (err != hipSuccess)
         return hip_err(err, "batched level launch");
     // requests that reached their last level: codebook to the host pool

@@ -10,8 +10,9 @@ namespace cyrus {
 // Level path: one launch per level tau. rtt = row tiles of 16 per workgroup.
 size_t level_buf_bytes(const DevTree& t, int prec, int rtt);
 size_t level_lds_bytes(const DevTree& t, int prec, int rtt);
-// LDS bytes of a level workgroup whose two activation buffers have `buf` bytes.
-size_t level_lds_for_buf(size_t buf, int rtt);
+// Row tiles per workgroup (rtt), activation-buffer bytes and LDS bytes of one
+// batched level launch over trees[0..n): the largest rtt whose LDS fits.
+bool plan_level_batch(const DevTree* trees, int n, int prec, int* rtt, int* buf, size_t* lds);
 hipError_t launch_level(const DevTree& t, int prec, int rtt, int tau, hipStream_t s);
 // Batched: entry j is codebook ent_tree[j] at level ent_tau[j], owning
 // workgroups [prefix[j], prefix[j+1]) of an nblocks = prefix[n] launch.

@@ -78,7 +78,8 @@ __device__ __forceinline__ void finish_rows_level(const DevTree& t, const float*
 // row tiles; rows past the tile's live rows are computed and discarded), so
 // the loads stay in flight behind the matrix work.
 template <int P, int RTT, int T>
-__device__ __forceinline__ void hidden_layer(const DevTree& t, int l, const uint8_t* in, uint8_t* out, int art)
+__device__ __forceinline__ void hidden_layer(const DevTree& t, int l, const uint8_t* in, uint8_t* out,
+                                             const float* bias_l, int art)
 {
     constexpr int kc = Traits<P>::kChunk, es = Traits<P>::kEsize;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, c16 = lane & 15;
@@ -156,7 +157,7 @@ __device__ __forceinline__ void hidden_layer(const DevTree& t, int l, const uint
 #pragma unroll
     for (int tt = 0; tt < T; ++tt) {
         const int nt = wave + kWaves * tt;
-        const floatx4 bias = *gptr(reinterpret_cast<const floatx4*>(t.b[l] + nt * 16 + g * 4));
+        const floatx4 bias = *reinterpret_cast<const floatx4*>(bias_l + nt * 16 + g * 4);
 #pragma unroll
         for (int rt = 0; rt < RTT; ++rt) {
             if (rt < art) {
@@ -170,10 +171,12 @@ __device__ __forceinline__ void hidden_layer(const DevTree& t, int l, const uint
     }
 }
 
-// Actor forward pass over `nrows` node rows whose features are in bufA.
+// Actor forward pass over `nrows` node rows whose features are in bufA, with
+// the biases of all layers staged in LDS (layer after layer, out_pad each).
 // Leaves the FP32 logits in zl[row * kLogitStride + e].
 template <int P, int RTT>
-__device__ __forceinline__ void run_mlp(const DevTree& t, int nrows, uint8_t* bufA, uint8_t* bufB, float* zl)
+__device__ __forceinline__ void run_mlp(const DevTree& t, int nrows, uint8_t* bufA, uint8_t* bufB, float* zl,
+                                        const float* bias)
 {
     constexpr int kc = Traits<P>::kChunk, es = Traits<P>::kEsize, RT = 16 * RTT;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, c16 = lane & 15;
@@ -184,19 +187,20 @@ __device__ __forceinline__ void run_mlp(const DevTree& t, int nrows, uint8_t* bu
         const int T = (t.out_pad[l] >> 4) / kWaves;  // neuron tiles per wave (hidden widths are multiples of 128)
         switch (T) {
         case 1:
-            hidden_layer<P, RTT, 1>(t, l, in, out, art);
+            hidden_layer<P, RTT, 1>(t, l, in, out, bias, art);
             break;
         case 2:
-            hidden_layer<P, RTT, 2>(t, l, in, out, art);
+            hidden_layer<P, RTT, 2>(t, l, in, out, bias, art);
             break;
         case 3:
-            hidden_layer<P, RTT, 3>(t, l, in, out, art);
+            hidden_layer<P, RTT, 3>(t, l, in, out, bias, art);
             break;
         default:
-            hidden_layer<P, RTT, 4>(t, l, in, out, art);
+            hidden_layer<P, RTT, 4>(t, l, in, out, bias, art);
             break;
         }
         lds_barrier();
+        bias += t.out_pad[l];
         uint8_t* tmp = in;
         in = out;
         out = tmp;
@@ -253,7 +257,7 @@ __device__ __forceinline__ void run_mlp(const DevTree& t, int nrows, uint8_t* bu
             float s = 0.f;
             for (int w = 0; w < kWaves; ++w)
                 s += part[(size_t)(w * RT + row) * opad + e];
-            zl[row * kLogitStride + e] = s * deq + gptr(t.b[l])[e];
+            zl[row * kLogitStride + e] = s * deq + bias[e];
         }
         lds_barrier();
     }
@@ -261,8 +265,13 @@ __device__ __forceinline__ void run_mlp(const DevTree& t, int nrows, uint8_t* bu
 
 // LDS of a level workgroup: two activation buffers of `bufsize` bytes, the
 // FP32 logits of the tile, the UE radio state, the parent states of the
-// tile's rows and, in batched launches, the entry tables of the launch.
+// tile's rows, the row-independent feature template, the entry tables of a
+// batched launch and, last (its size depends on the tree), the biases of
+// every layer.
+constexpr int kMaxIn0 = 256;  // widest padded first-layer input (E = 32, FP8 chunk pairs)
+
 __host__ __device__ constexpr int pst_bytes(int rtt) { return ((16 * rtt + 2) * kMaxUE + 15) & ~15; }
+__host__ __device__ constexpr int tab_bytes() { return (3 * (kMaxEntries + 1) * 4 + 15) & ~15; }
 
 struct LevelSmem {
     uint8_t* bufA;
@@ -270,9 +279,10 @@ struct LevelSmem {
     float* zl;      // [RT][kLogitStride]
     int* R;         // [kMaxUE]
     int* rsum;      // [4]
-    float* statf;   // [3 * kMaxUE] R/32, MCS/32, SINR/32
+    float* tmpl;    // [kMaxIn0] features common to every row (UE radio state, tau), zero elsewhere
     uint8_t* pst;   // [(RT + 2) * kMaxUE] states of the parents of the tile's rows
     int* tab;       // [3 * (kMaxEntries + 1)] ent_tree, ent_tau, prefix
+    float* bias;    // [sum of out_pad] biases of all layers
 };
 
 template <int RTT>
@@ -284,9 +294,10 @@ __device__ __forceinline__ LevelSmem level_smem(uint8_t* smem, int bufsize)
     m.zl = reinterpret_cast<float*>(smem + 2 * bufsize);
     m.R = reinterpret_cast<int*>(m.zl + 16 * RTT * kLogitStride);
     m.rsum = m.R + kMaxUE;
-    m.statf = reinterpret_cast<float*>(m.rsum + 4);
-    m.pst = reinterpret_cast<uint8_t*>(m.statf + 3 * kMaxUE);
+    m.tmpl = reinterpret_cast<float*>(m.rsum + 4);
+    m.pst = reinterpret_cast<uint8_t*>(m.tmpl + kMaxIn0);
     m.tab = reinterpret_cast<int*>(m.pst + pst_bytes(RTT));
+    m.bias = reinterpret_cast<float*>(reinterpret_cast<uint8_t*>(m.tab) + tab_bytes());
     return m;
 }
 
@@ -296,11 +307,15 @@ __device__ __forceinline__ void level_tile(const DevTree& t, int tau, int row0, 
 {
     constexpr int es = Traits<P>::kEsize, F = 16 / es;  // features per 16-byte LDS segment
     constexpr int kPstIters = (pst_bytes(RTT) + kThreads - 1) / kThreads;
-    const int E = t.E, K = t.K;
+    constexpr int kBiasBatch = 4;  // float4 bias loads in flight per thread
+    const int E = t.E, K = t.K, nl = t.n_layers;
+    const int in0 = t.in_pad[0], d_in = t.in_dim0;
     const int64_t off = dev_level_offset(K, tau), poff = dev_level_offset(K, tau - 1);
-    // Stage the tile's inputs in LDS with independent loads in flight
-    // together: the states of the parents of rows row0..row0+nrows-1 (one
-    // contiguous range of the parent level) and the UE radio state.
+
+    // Stage the tile's inputs in LDS, every global load issued before the
+    // first LDS store: the states of the parents of rows row0..row0+nrows-1
+    // (one contiguous range of the parent level), the UE radio state (as the
+    // feature template and R), and the biases of all layers.
     const int p_lo = row0 / K;
     const int npb = ((row0 + nrows - 1) / K - p_lo + 1) * E;
     const auto* sp = gptr(t.state + (poff + p_lo) * E);
@@ -310,22 +325,52 @@ __device__ __forceinline__ void level_tile(const DevTree& t, int tau, int row0, 
         const int i = (int)threadIdx.x + j * kThreads;
         pv[j] = i < npb ? sp[i] : (uint8_t)0;
     }
-    if (threadIdx.x < 64) {  // wave 0: UE state, and the sum of R by shuffles
-        const int e = threadIdx.x;
-        int r = 0;
-        if (e < E) {
-            const auto* ue = gptr(t.ue);
-            r = ue[e];
-            const int mcs = ue[E + e], sinr = ue[2 * E + e];
-            m.R[e] = r;
-            m.statf[e] = (float)r * (1.f / 32.f);
-            m.statf[E + e] = (float)mcs * (1.f / 32.f);
-            m.statf[2 * E + e] = __int_as_float(sinr) * (1.f / 32.f);
+    const int f = threadIdx.x;  // feature index of the template
+    int uev = 0;
+    if (f < 3 * E)
+        uev = gptr(t.ue)[f];
+    int nb4 = 0;
+    for (int l = 0; l < nl; ++l)
+        nb4 += t.out_pad[l] >> 2;
+    for (int i0 = 0; i0 < nb4; i0 += kBiasBatch * kThreads) {
+        floatx4 bv[kBiasBatch];
+#pragma unroll
+        for (int j = 0; j < kBiasBatch; ++j) {
+            const int i = i0 + j * kThreads + (int)threadIdx.x;
+            if (i < nb4) {
+                int l = 0, st = 0;
+                while (l + 1 < nl && i >= st + (t.out_pad[l] >> 2)) {
+                    st += t.out_pad[l] >> 2;
+                    ++l;
+                }
+                bv[j] = gptr(reinterpret_cast<const floatx4*>(t.b[l]))[i - st];
+            }
         }
+#pragma unroll
+        for (int j = 0; j < kBiasBatch; ++j) {
+            const int i = i0 + j * kThreads + (int)threadIdx.x;
+            if (i < nb4)
+                reinterpret_cast<floatx4*>(m.bias)[i] = bv[j];
+        }
+    }
+    if (f < in0) {
+        float v = 0.f;
+        if (f < 2 * E)
+            v = (float)uev * (1.f / 32.f);
+        else if (f < 3 * E)
+            v = __int_as_float(uev) * (1.f / 32.f);
+        else if (f == 4 * E)
+            v = (float)tau * (1.f / 8.f);
+        m.tmpl[f] = v;  // parent state and k are filled in per row
+    }
+    if (threadIdx.x < 64) {  // wave 0 holds R (f < E <= 32): sum by shuffles
+        int r = f < E ? uev : 0;
+        if (f < E)
+            m.R[f] = r;
 #pragma unroll
         for (int o = 16; o > 0; o >>= 1)
             r += __shfl_xor(r, o, 32);
-        if (e == 0)
+        if (f == 0)
             *m.rsum = r;
     }
 #pragma unroll
@@ -336,42 +381,48 @@ __device__ __forceinline__ void level_tile(const DevTree& t, int tau, int row0, 
     }
     lds_barrier();
 
-    // features of every row, zero padded to the k-chunk and to whole row
-    // tiles, written one 16-byte segment (F features) at a time
-    const int in0 = t.in_pad[0], d_in = t.in_dim0, s0 = in0 * es + 16;
+    // Features of every row, zero padded to the k-chunk and to whole row
+    // tiles, one 16-byte segment (F features) per step: the template, with
+    // the parent state (features 3E..4E-1) and k/8 (feature 4E+1) of the row.
+    const int s0 = in0 * es + 16;
     const int nseg = in0 / F;
     const int nrows_pad = ((nrows + 15) >> 4) << 4;
     const float inv0 = t.inv_in_scale[0];
-    const float ftau = (float)tau * (1.f / 8.f);
     for (int idx = threadIdx.x; idx < nrows_pad * nseg; idx += kThreads) {
         const int row = idx / nseg, f0 = (idx - row * nseg) * F;
         const int r = row0 + row, p = r / K, k = r - p * K + 1;
         const bool live = row < nrows;
-        const uint8_t* ps = m.pst + (p - p_lo) * E;
+        const uint8_t* ps = m.pst + (live ? p - p_lo : 0) * E;
+        const float kf = (float)k * (1.f / 8.f);
         float v[F];
 #pragma unroll
-        for (int j = 0; j < F; ++j) {
-            const int f = f0 + j;
-            float x = 0.f;
-            if (live && f < d_in) {
-                if (f < 3 * E)
-                    x = m.statf[f];
-                else if (f < 4 * E)
-                    x = (float)ps[f - 3 * E] * (1.f / 64.f);
-                else if (f == 4 * E)
-                    x = ftau;
-                else
-                    x = (float)k * (1.f / 8.f);
+        for (int j = 0; j < F; j += 4) {
+            const floatx4 q = *reinterpret_cast<const floatx4*>(m.tmpl + f0 + j);
+            v[j] = q[0];
+            v[j + 1] = q[1];
+            v[j + 2] = q[2];
+            v[j + 3] = q[3];
+        }
+        if (f0 < 4 * E + 2 && f0 + F > 3 * E) {  // segment holds row-dependent features
+#pragma unroll
+            for (int j = 0; j < F; ++j) {
+                const int fj = f0 + j;
+                const int si = min(max(fj - 3 * E, 0), E - 1);
+                const float sv = (float)ps[si] * (1.f / 64.f);
+                v[j] = (fj >= 3 * E && fj < 4 * E) ? sv : (fj == 4 * E + 1 ? kf : v[j]);
             }
-            v[j] = x;
         }
         uint8_t* dst = m.bufA + row * s0 + f0 * es;
 #pragma unroll
-        for (int j = 0; j < F; j += 4)
-            store4<P>(dst + j * es, v[j], v[j + 1], v[j + 2], v[j + 3], inv0);
+        for (int j = 0; j < F; j += 4) {
+            if (live)
+                store4<P>(dst + j * es, v[j], v[j + 1], v[j + 2], v[j + 3], inv0);
+            else
+                store4<P>(dst + j * es, 0.f, 0.f, 0.f, 0.f, inv0);
+        }
     }
     lds_barrier();
-    run_mlp<P, RTT>(t, nrows, m.bufA, m.bufB, m.zl);
+    run_mlp<P, RTT>(t, nrows, m.bufA, m.bufB, m.zl, m.bias);
 
     const int rsum = *m.rsum;
     if (E <= 8)
@@ -467,13 +518,46 @@ size_t level_buf_bytes(const DevTree& t, int prec, int rtt)
     return (buf + 15) & ~(size_t)15;
 }
 
-size_t level_lds_for_buf(size_t buf, int rtt)
+size_t level_bias_bytes(const DevTree& t)
 {
-    return 2 * buf + (size_t)16 * rtt * kLogitStride * 4 + (kMaxUE + 4) * 4 + 3 * kMaxUE * 4 + pst_bytes(rtt) +
-           3 * (kMaxEntries + 1) * 4;
+    size_t n = 0;
+    for (int l = 0; l < t.n_layers; ++l)
+        n += (size_t)t.out_pad[l] * 4;
+    return n;
 }
 
-size_t level_lds_bytes(const DevTree& t, int prec, int rtt) { return level_lds_for_buf(level_buf_bytes(t, prec, rtt), rtt); }
+size_t level_lds_for_buf(size_t buf, size_t bias_bytes, int rtt)
+{
+    return 2 * buf + (size_t)16 * rtt * kLogitStride * 4 + (kMaxUE + 4) * 4 + kMaxIn0 * 4 + pst_bytes(rtt) +
+           tab_bytes() + bias_bytes;
+}
+
+size_t level_lds_bytes(const DevTree& t, int prec, int rtt)
+{
+    return level_lds_for_buf(level_buf_bytes(t, prec, rtt), level_bias_bytes(t), rtt);
+}
+
+bool plan_level_batch(const DevTree* trees, int n, int prec, int* rtt, int* buf, size_t* lds)
+{
+    const int cands[] = {6, 4, 2, 1};  // row tiles per workgroup, largest first (FP32 stops at 4)
+    for (int r : cands) {
+        if (prec == kFP32 && r > 4)
+            continue;
+        size_t b = 0, bias = 0;
+        for (int i = 0; i < n; ++i) {
+            b = std::max(b, level_buf_bytes(trees[i], prec, r));
+            bias = std::max(bias, level_bias_bytes(trees[i]));
+        }
+        const size_t need = level_lds_for_buf(b, bias, r);
+        if (need <= 160 * 1024) {
+            *rtt = r;
+            *buf = (int)b;
+            *lds = need;
+            return true;
+        }
+    }
+    return false;
+}
 
 template <int P, int RTT>
 static hipError_t launch_level_t(const DevTree& t, int tau, hipStream_t s)
