@@ -140,12 +140,18 @@ __device__ __forceinline__ void lds_barrier()
     __builtin_amdgcn_s_barrier();
 }
 
-// float -> bfloat16 bits, round to nearest even (inputs are finite).
+// float -> bfloat16 bits, round to nearest even (gfx950 hardware conversion).
 __device__ __forceinline__ uint32_t bf16_bits(float v)
 {
-    uint32_t u = __float_as_uint(v);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return u >> 16;
+    return (uint32_t)__builtin_bit_cast(uint16_t, (__bf16)v);
+}
+
+// Two floats -> two BF16 (low half = v0), one gfx950 v_cvt_pk_bf16_f32.
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float floatx2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t bf16x2_bits(float v0, float v1)
+{
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((floatx2{v0, v1}), bf16x2));
 }
 
 // Four floats -> four OCP E4M3 bytes (hardware round to nearest even), with
@@ -175,8 +181,8 @@ template <>
 __device__ __forceinline__ void store4<kBF16>(uint8_t* dst, float v0, float v1, float v2, float v3, float)
 {
     uint2 w;
-    w.x = bf16_bits(v0) | (bf16_bits(v1) << 16);
-    w.y = bf16_bits(v2) | (bf16_bits(v3) << 16);
+    w.x = bf16x2_bits(v0, v1);
+    w.y = bf16x2_bits(v2, v3);
     *reinterpret_cast<uint2*>(dst) = w;
 }
 
@@ -184,6 +190,35 @@ template <>
 __device__ __forceinline__ void store4<kFP8>(uint8_t* dst, float v0, float v1, float v2, float v3, float inv_scale)
 {
     *reinterpret_cast<uint32_t*>(dst) = e4m3x4(v0 * inv_scale, v1 * inv_scale, v2 * inv_scale, v3 * inv_scale);
+}
+
+// Store four consecutive hidden-layer outputs v = W x + b, already in the
+// next layer's input scale, as ReLU(v) in the storage type of P (FP8: also
+// saturated at E4M3's largest finite value, 448).
+template <int P>
+__device__ __forceinline__ void store_act4(uint8_t* dst, float v0, float v1, float v2, float v3);
+
+template <>
+__device__ __forceinline__ void store_act4<kFP32>(uint8_t* dst, float v0, float v1, float v2, float v3)
+{
+    *reinterpret_cast<floatx4*>(dst) = floatx4{fmaxf(v0, 0.f), fmaxf(v1, 0.f), fmaxf(v2, 0.f), fmaxf(v3, 0.f)};
+}
+
+template <>
+__device__ __forceinline__ void store_act4<kBF16>(uint8_t* dst, float v0, float v1, float v2, float v3)
+{
+    store4<kBF16>(dst, fmaxf(v0, 0.f), fmaxf(v1, 0.f), fmaxf(v2, 0.f), fmaxf(v3, 0.f), 1.f);
+}
+
+template <>
+__device__ __forceinline__ void store_act4<kFP8>(uint8_t* dst, float v0, float v1, float v2, float v3)
+{
+    v0 = fminf(fmaxf(v0, 0.f), 448.f);
+    v1 = fminf(fmaxf(v1, 0.f), 448.f);
+    v2 = fminf(fmaxf(v2, 0.f), 448.f);
+    v3 = fminf(fmaxf(v3, 0.f), 448.f);
+    const int lo = __builtin_amdgcn_cvt_pk_fp8_f32(v0, v1, 0, false);
+    *reinterpret_cast<uint32_t*>(dst) = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(v2, v3, lo, true);
 }
 
 // Store one activation (feature assembly, padding).

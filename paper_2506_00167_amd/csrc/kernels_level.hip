@@ -152,27 +152,27 @@ __device__ __forceinline__ void hidden_layer(const DevTree& t, int l, const uint
                 mma_chunk<P>(a0[tt], b0, acc[tt][rt]);
         }
     }
-    const float deq = t.deq[l];
-    const float inv_next = t.inv_in_scale[l + 1];
+    // Epilogue in the next layer's input scale: the staged bias is already
+    // multiplied by it, and deq times it is exact (both are powers of two;
+    // 1 outside FP8), so fma(acc, c1, bias) equals the scaled (deq acc + b).
+    const float c1 = t.deq[l] * t.inv_in_scale[l + 1];
 #pragma unroll
     for (int tt = 0; tt < T; ++tt) {
         const int nt = wave + kWaves * tt;
         const floatx4 bias = *reinterpret_cast<const floatx4*>(bias_l + nt * 16 + g * 4);
 #pragma unroll
         for (int rt = 0; rt < RTT; ++rt) {
-            if (rt < art) {
-                const float v0 = fmaxf(acc[tt][rt][0] * deq + bias[0], 0.f);
-                const float v1 = fmaxf(acc[tt][rt][1] * deq + bias[1], 0.f);
-                const float v2 = fmaxf(acc[tt][rt][2] * deq + bias[2], 0.f);
-                const float v3 = fmaxf(acc[tt][rt][3] * deq + bias[3], 0.f);
-                store4<P>(out + (rt * 16 + c16) * sout + (nt * 16 + g * 4) * es, v0, v1, v2, v3, inv_next);
-            }
+            if (rt < art)
+                store_act4<P>(out + (rt * 16 + c16) * sout + (nt * 16 + g * 4) * es,
+                              fmaf(acc[tt][rt][0], c1, bias[0]), fmaf(acc[tt][rt][1], c1, bias[1]),
+                              fmaf(acc[tt][rt][2], c1, bias[2]), fmaf(acc[tt][rt][3], c1, bias[3]));
         }
     }
 }
 
 // Actor forward pass over `nrows` node rows whose features are in bufA, with
-// the biases of all layers staged in LDS (layer after layer, out_pad each).
+// the biases of all layers staged in LDS (layer after layer, out_pad each;
+// a hidden layer's already in the next layer's input scale).
 // Leaves the FP32 logits in zl[row * kLogitStride + e].
 template <int P, int RTT>
 __device__ __forceinline__ void run_mlp(const DevTree& t, int nrows, uint8_t* bufA, uint8_t* bufB, float* zl,
@@ -344,6 +344,10 @@ __device__ __forceinline__ void level_tile(const DevTree& t, int tau, int row0, 
                     ++l;
                 }
                 bv[j] = gptr(reinterpret_cast<const floatx4*>(t.b[l]))[i - st];
+                if (l + 1 < nl) {  // hidden layer: in the next layer's input scale (a power of two)
+                    const float sc = t.inv_in_scale[l + 1];
+                    bv[j] = floatx4{bv[j][0] * sc, bv[j][1] * sc, bv[j][2] * sc, bv[j][3] * sc};
+                }
             }
         }
 #pragma unroll
