@@ -391,14 +391,17 @@ __device__ __forceinline__ int enforce_group(int E, int e, float z, int R, int r
     const float frac = x - fl;
     const int r = T - group_isum<G>(f);
     const bool elig = live && f < R;
+    // ineligible UEs carry -1 and never rank above an eligible one; q = e
+    // counts for neither test, so the count needs no branch
+    const float mine = elig ? frac : -1.f;
+    float fq[G];
+#pragma unroll
+    for (int q = 0; q < G; ++q)
+        fq[q] = __shfl(mine, q, G);
     int rank = 0;
 #pragma unroll
-    for (int q = 0; q < G; ++q) {
-        const float fq = __shfl(frac, q, G);
-        const int eq = __shfl(elig ? 1 : 0, q, G);
-        if (q != e && eq && (fq > frac || (fq == frac && q < e)))
-            ++rank;
-    }
+    for (int q = 0; q < G; ++q)
+        rank += (fq[q] > frac || (fq[q] == frac && q < e)) ? 1 : 0;
     return f + ((elig && rank < r) ? 1 : 0);
 }
 
@@ -486,13 +489,17 @@ __device__ __forceinline__ int enforce_dpp(int E, int e, float z, int R, int rsu
     const int r = T - disum<G>(f);
     const bool elig = live && f < R;
     rank_row[e] = elig ? frac : -1.f;  // ineligible UEs never rank above an eligible one
+    // rank = UEs ahead of e (larger remainder, or equal with a lower index);
+    // q = e counts for neither, so the count needs no branch, and every read
+    // is issued before the first comparison
+    float fq[G];
+#pragma unroll
+    for (int q = 0; q < G; ++q)
+        fq[q] = rank_row[q];
     int rank = 0;
 #pragma unroll
-    for (int q = 0; q < G; ++q) {
-        const float fq = rank_row[q];
-        if (q != e && (fq > frac || (fq == frac && q < e)))
-            ++rank;
-    }
+    for (int q = 0; q < G; ++q)
+        rank += (fq[q] > frac || (fq[q] == frac && q < e)) ? 1 : 0;
     return f + ((elig && rank < r) ? 1 : 0);
 }
 
