@@ -17,7 +17,6 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 from __future__ import annotations
 
 import argparse
-import glob
 import hashlib
 import json
 import os
@@ -36,10 +35,18 @@ SLOT_US = 125.0
 WORKLOAD = "tree-e8k3"
 
 
-def kernel_source_hash() -> str:
+# Sources each kernel path is compiled from: HBM traffic measured on them is
+# reported only while they are unchanged.
+KERNEL_SOURCES = {
+    "subtree": ["kernels_subtree.hip", "cyrus_device.h", "cyrus_internal.h"],
+    "level": ["kernels_level.hip", "cyrus_device.h", "cyrus_internal.h"],
+}
+
+
+def kernel_source_hash(kernel: str = "subtree") -> str:
     h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2506_00167_amd", "csrc", "*"))):
-        h.update(open(p, "rb").read())
+    for name in KERNEL_SOURCES[kernel]:
+        h.update(open(os.path.join(ROOT, "paper_2506_00167_amd", "csrc", name), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -51,7 +58,7 @@ def load_traffic(kernel: str, precision: str):
         return None
     data = json.load(open(path))
     entry = data.get(f"{kernel}/{WORKLOAD}/{precision}")
-    if not entry or entry.get("source_hash") != kernel_source_hash():
+    if not entry or kernel not in KERNEL_SOURCES or entry.get("source_hash") != kernel_source_hash(kernel):
         return None
     return entry.get("bytes_per_launch")
 
@@ -66,32 +73,43 @@ def pct(a, q):
     return float(np.percentile(np.asarray(a), q))
 
 
-def run_leg(precision: str, steps: int, warmup: int, latency_builds: int, stream):
+def run_leg(precision: str, steps: int, warmup: int, latency_builds: int, stream, workload: str = WORKLOAD):
     import torch
     from paper_2506_00167_amd import cyrus
 
-    cfg = wl.WORKLOADS[WORKLOAD].with_precision(precision)
-    seed = wl.WEIGHT_SEEDS[WORKLOAD]
+    cfg = wl.WORKLOADS[workload].with_precision(precision)
+    seed = wl.WEIGHT_SEEDS[workload]
     weights = wl.make_weights(cfg, seed)
-    act = fp8_act_scales(WORKLOAD, seed) if precision == "fp8" else None
+    act = fp8_act_scales(workload, seed) if precision == "fp8" else None
     cb = cyrus.Codebook(cfg, weights, act_scale=act, stream=stream)
     ues = [wl.make_ue_state(cfg.num_ue, wl.ue_seed(i)) for i in range(64)]
     ue_dev = [cyrus.ue_device_tensor(u) for u in ues]
     torch.cuda.synchronize()
 
-    # throughput: back-to-back builds, device-resident inputs
+    # throughput: back-to-back builds, device-resident inputs, one event pair
+    # on the build stream around the whole timed region
     for i in range(warmup):
         cb.build_device(ue_dev[i % 64])
     torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
-    with torch.cuda.stream(stream):
-        for i in range(steps):
-            ev[i][0].record(stream)
-            cb.build_device(ue_dev[i % 64])
-            ev[i][1].record(stream)
+    start.record(stream)
+    for i in range(steps):
+        cb.build_device(ue_dev[i % 64])
+    end.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    avg_us = start.elapsed_time(end) * 1e3 / steps
+
+    # per-build device time (an event pair around each build, so each sample
+    # also holds that build's dispatch latency)
+    n_ev = min(steps, 500)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_ev)]
+    for i in range(n_ev):
+        ev[i][0].record(stream)
+        cb.build_device(ue_dev[i % 64])
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
     dev_us = np.array([a.elapsed_time(b) * 1e3 for a, b in ev])
 
     # latency: one build at a time, host clock around enqueue + completion
@@ -111,17 +129,17 @@ def run_leg(precision: str, steps: int, warmup: int, latency_builds: int, stream
     cb.close()
 
     flops = cfg.flops_per_codebook
-    avg_us = float(dev_us.mean())
     achieved = flops / (avg_us * 1e-6) / 1e12
     return {
+        "workload": workload,
         "precision": precision,
         "kernel": f"{path}",
         "nodes_per_s": cfg.num_nodes * steps / wall,
         "evals_per_s": cfg.num_evals * steps / wall,
         "ms_per_step": wall / steps * 1e3,
         "device_us_mean": avg_us,
-        "device_us_p50": pct(dev_us, 50),
-        "device_us_p99": pct(dev_us, 99),
+        "device_us_per_build_event_p50": pct(dev_us, 50),
+        "device_us_per_build_event_p99": pct(dev_us, 99),
         "latency_device_resident_us": {"p50": pct(lat_dev, 50), "p99": pct(lat_dev, 99),
                                        "p99.9": pct(lat_dev, 99.9), "max": float(np.max(lat_dev)),
                                        "misses_over_125us": int(np.sum(np.asarray(lat_dev) > SLOT_US)),
@@ -163,6 +181,8 @@ def main():
     ap.add_argument("--latency-builds", type=int, default=2000)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--legs", default="fp32,bf16,fp8")
+    ap.add_argument("--context-legs", default="tiny-e4k2/fp32,paper-depth1/fp32",
+                    help="other workloads timed the same way (WORKLOAD/PRECISION, comma separated), reported as context")
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -180,6 +200,13 @@ def main():
         legs[prec] = run_leg(prec, args.steps, args.warmup, args.latency_builds, stream)
         print(f"[bench] {prec}: {legs[prec]['nodes_per_s']:.4g} nodes/s, device {legs[prec]['device_us_mean']:.1f} us, "
               f"p99 host {legs[prec]['latency_host_inclusive_us']['p99']:.1f} us", file=sys.stderr, flush=True)
+    context = {}
+    for item in filter(None, args.context_legs.split(",")):
+        name, prec = item.split("/")
+        context[item] = run_leg(prec, args.steps, args.warmup, args.latency_builds, stream, workload=name)
+        print(f"[bench] context {item}: {context[item]['nodes_per_s']:.4g} nodes/s, device "
+              f"{context[item]['device_us_mean']:.1f} us, p99 host "
+              f"{context[item]['latency_host_inclusive_us']['p99']:.1f} us", file=sys.stderr, flush=True)
     head = legs["fp32"]
     cfg = wl.WORKLOADS[WORKLOAD]
     out = {
@@ -213,6 +240,7 @@ def main():
             "avg_launch_us": head["device_us_mean"],
         },
         "legs": legs,
+        "context_legs": context,
     }
     if "bf16" in legs:
         out["bf16_vs_fp32_speedup"] = legs["bf16"]["nodes_per_s"] / head["nodes_per_s"]

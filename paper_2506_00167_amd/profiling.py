@@ -12,7 +12,7 @@
       reads rocprofv3 CSV output (kernel_stats / kernel_trace / counter
       collection) and prints a short text summary.
   python -m paper_2506_00167_amd.profiling traffic --fetch DIR --write DIR --copy-fetch DIR --copy-write DIR
-         --kernel SUBSTR --key KERNEL/WORKLOAD/PRECISION [--copy-mib N]
+         --kernel SUBSTR --key KERNEL/WORKLOAD/PRECISION [--copy-mib N] [--out FILE]
       HBM bytes per launch of the kernel from a FETCH_SIZE run and a
       WRITE_SIZE run, each scaled by what the same counter reports for the
       plain copy of known size; stored in profiles/traffic.json with the hash
@@ -88,6 +88,10 @@ def _counter_per_dispatch(d, kernel):
 
 def _summarize(args):
     lines = [f"# rocprofv3 summary: kernels matching '{args.kernel}'", ""]
+    for c in args.command or []:
+        lines.append(f"command: {c}")
+    if args.command:
+        lines.append("")
     stats = _rows(args.dir, "*kernel_stats.csv")
     for r in stats:
         if args.kernel in r.get("Name", ""):
@@ -133,8 +137,9 @@ def _traffic(args):
     entry = {"fetch_kib": fetch * f_factor, "write_kib": write * w_factor,
              "bytes_per_launch": (fetch * f_factor + write * w_factor) * 1024.0,
              "fetch_factor": f_factor, "write_factor": w_factor,
-             "raw_fetch_size": fetch, "raw_write_size": write, "source_hash": kernel_source_hash()}
-    path = os.path.join(root, "profiles", "traffic.json")
+             "raw_fetch_size": fetch, "raw_write_size": write,
+             "source_hash": kernel_source_hash(args.key.split("/")[0])}
+    path = args.out or os.path.join(root, "profiles", "traffic.json")
     data = json.load(open(path)) if os.path.exists(path) else {}
     data[args.key] = entry
     os.makedirs(os.path.dirname(path), exist_ok=True)
@@ -162,6 +167,7 @@ def main(argv=None):
     m.add_argument("--copy-dir")
     m.add_argument("--copy-kernel", default="copy")
     m.add_argument("--copy-mib", type=int, default=256)
+    m.add_argument("--command", action="append", help="command line that produced DIR (repeatable)")
     t = sub.add_parser("traffic")
     for k in ("fetch", "write", "copy_fetch", "copy_write"):
         t.add_argument("--" + k.replace("_", "-"), dest=k, required=True)
@@ -169,6 +175,7 @@ def main(argv=None):
     t.add_argument("--key", required=True)
     t.add_argument("--copy-kernel", default="copy")
     t.add_argument("--copy-mib", type=int, default=256)
+    t.add_argument("--out", help="traffic file to update (default profiles/traffic.json)")
     args = ap.parse_args(argv)
     {"build": _build, "stress": _stress, "copy": _copy, "summarize": _summarize, "traffic": _traffic}[args.cmd](args)
 
