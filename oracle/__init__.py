@@ -35,9 +35,15 @@ _f64p = ctypes.POINTER(ctypes.c_double)
 _u8p = ctypes.POINTER(ctypes.c_uint8)
 
 
+LARGEST_REMAINDER, HUNTINGTON_HILL = 0, 1
+_ROUNDING = {"lr": LARGEST_REMAINDER, "largest_remainder": LARGEST_REMAINDER, "hh": HUNTINGTON_HILL,
+             "huntington_hill": HUNTINGTON_HILL}
+
+
 class _Tree(ctypes.Structure):
     _fields_ = [("num_ue", ctypes.c_int32), ("max_arrival", ctypes.c_int32),
-                ("num_minislots", ctypes.c_int32), ("rb_per_unit", ctypes.c_int32)]
+                ("num_minislots", ctypes.c_int32), ("rb_per_unit", ctypes.c_int32),
+                ("rounding", ctypes.c_int32)]
 
 
 class _Actor(ctypes.Structure):
@@ -85,6 +91,13 @@ def _load(path: str = _LIB_PATH):
     lib.oracle_allocate.restype = ctypes.c_double
     lib.oracle_allocate.argtypes = [ctypes.c_int32, _f64p, _i32p, ctypes.c_int32, ctypes.c_int32,
                                     _i32p, _f64p]
+    lib.oracle_allocate_rounding.restype = ctypes.c_double
+    lib.oracle_allocate_rounding.argtypes = [ctypes.c_int32, _f64p, _i32p, ctypes.c_int32, ctypes.c_int32,
+                                             ctypes.c_int32, _i32p, _f64p]
+    lib.oracle_huntington_hill.restype = None
+    lib.oracle_huntington_hill.argtypes = [ctypes.c_int32, _f64p, _i32p, ctypes.c_int64, _i32p]
+    lib.oracle_margin_hh.restype = ctypes.c_double
+    lib.oracle_margin_hh.argtypes = [ctypes.c_int32, _f64p, _f64p, ctypes.c_double, _i32p, ctypes.c_int64, _i32p]
     lib.oracle_build_tree.restype = ctypes.c_int
     lib.oracle_build_tree.argtypes = [ctypes.POINTER(_Tree), ctypes.POINTER(_Actor), _i32p, _i32p,
                                       _f32p, _u8p, _f64p, _f64p]
@@ -151,7 +164,8 @@ class Actor:
 
 
 def _tree(cfg) -> _Tree:
-    return _Tree(cfg.num_ue, cfg.max_arrival, cfg.num_minislots, cfg.rb_per_unit)
+    return _Tree(cfg.num_ue, cfg.max_arrival, cfg.num_minislots, cfg.rb_per_unit,
+                 _ROUNDING[getattr(cfg, "rounding", "lr")])
 
 
 def _ue_arrays(ue):
@@ -234,6 +248,23 @@ def largest_remainder(x, R, T: int) -> np.ndarray:
     return a
 
 
+def huntington_hill(x, R, T: int) -> np.ndarray:
+    x = _c(x, np.float64)
+    R = _c(R, np.int32)
+    a = np.empty(x.size, dtype=np.int32)
+    lib().oracle_huntington_hill(x.size, _p(x, _f64p), _p(R, _i32p), int(T), _p(a, _i32p))
+    return a
+
+
+def margin_hh(x, p, s: float, R, T: int, a) -> float:
+    x = _c(x, np.float64)
+    p = _c(p, np.float64)
+    R = _c(R, np.int32)
+    a = _c(a, np.int32)
+    return float(lib().oracle_margin_hh(x.size, _p(x, _f64p), _p(p, _f64p), float(s), _p(R, _i32p), int(T),
+                                        _p(a, _i32p)))
+
+
 def margin(x, p, s: float, R, T: int) -> float:
     x = _c(x, np.float64)
     p = _c(p, np.float64)
@@ -241,13 +272,14 @@ def margin(x, p, s: float, R, T: int) -> float:
     return float(lib().oracle_margin(x.size, _p(x, _f64p), _p(p, _f64p), float(s), _p(R, _i32p), int(T)))
 
 
-def allocate(z, R, U: int, k: int):
+def allocate(z, R, U: int, k: int, rounding: str = "lr"):
     """Returns (a, margin, x) for one node's logits."""
     z = _c(z, np.float64)
     R = _c(R, np.int32)
     a = np.empty(z.size, dtype=np.int32)
     x = np.empty(z.size, dtype=np.float64)
-    m = lib().oracle_allocate(z.size, _p(z, _f64p), _p(R, _i32p), U, k, _p(a, _i32p), _p(x, _f64p))
+    m = lib().oracle_allocate_rounding(z.size, _p(z, _f64p), _p(R, _i32p), U, k, _ROUNDING[rounding],
+                                       _p(a, _i32p), _p(x, _f64p))
     return a, float(m), x
 
 

@@ -35,8 +35,11 @@
  *   - T = min(U*k, sum_e R_e): demand is capped by the RBs scheduled in the
  *     TTI (Eq. (7) has no solution above that). Caps are per mini-slot.
  *   - The integer step is largest remainder (Hamilton) rounding with ties
- *     broken towards the lower UE index; the paper names Huntington-Hill,
- *     which cannot place fewer units than there are positive quotas.
+ *     broken towards the lower UE index by default; the paper names
+ *     Huntington-Hill, which cannot place fewer units than there are positive
+ *     quotas. Huntington-Hill is the other rounding mode (priority form, ties
+ *     to the larger share then the lower index; below one unit per positive
+ *     share the T largest shares get one unit each).
  *   - Features (dim 4E+2, blocks of E): R_e/32, MCS_e/32, SINR_e/32, c_e/64,
  *     then tau/8 and k/8. All scales are powers of two.
  *   - BFS node order, level by level; within a level k_1 is the most
@@ -65,7 +68,11 @@ typedef struct {
     int32_t max_arrival;   /* K */
     int32_t num_minislots; /* M */
     int32_t rb_per_unit;   /* U */
+    int32_t rounding;      /* ORACLE_LARGEST_REMAINDER or ORACLE_HUNTINGTON_HILL */
 } oracle_tree;
+
+#define ORACLE_LARGEST_REMAINDER 0
+#define ORACLE_HUNTINGTON_HILL 1
 
 typedef struct {
     int32_t num_layers;      /* weight layers: hidden layers + output layer */
@@ -361,6 +368,87 @@ void oracle_largest_remainder(int32_t E, const double* x, const int32_t* R, int6
     }
 }
 
+/* Huntington-Hill apportionment of T units (the paper's rounding, Sec. IV-B,
+ * after Balinski and Young), in its priority form: units are handed out one at
+ * a time, each to the UE with the largest priority x_e / sqrt(n_e (n_e + 1)),
+ * n_e being the units it already holds; a UE's first unit has infinite
+ * priority, a UE at its cap R_e takes no more, and a UE with x_e = 0 takes
+ * none. Equal priorities go to the larger share, then to the lower index. When
+ * T is smaller than the number of positive shares (no Huntington-Hill
+ * allocation exists then, as every positive share is owed a unit), the same
+ * rule gives one unit to each of the T largest shares. */
+void oracle_huntington_hill(int32_t E, const double* x, const int32_t* R, int64_t T, int32_t* a)
+{
+    for (int32_t e = 0; e < E; ++e)
+        a[e] = 0;
+    for (int64_t n = 0; n < T; ++n) {
+        int32_t best = -1;
+        double best_pr = 0.0;
+        for (int32_t e = 0; e < E; ++e) {
+            if (!(x[e] > 0.0) || a[e] >= R[e])
+                continue;
+            const double pr = a[e] == 0 ? INFINITY : x[e] / sqrt((double)a[e] * (double)(a[e] + 1));
+            /* strict comparisons keep the lower index among full ties */
+            if (best < 0 || pr > best_pr || (pr == best_pr && x[e] > x[best])) {
+                best = e;
+                best_pr = pr;
+            }
+        }
+        if (best < 0)
+            break;
+        a[best] += 1;
+    }
+}
+
+/* Float64 distance (in units of the shares x) from the nearest change of the
+ * shares that would flip a Huntington-Hill decision: a share crossing its cap,
+ * or a held unit and a withheld one of two UEs swapping priority. For the pair
+ * (i holds its n_i-th unit, j withholds its (n_j+1)-th), the priorities move by
+ * at most |dx| / sqrt(n (n+1)), so the pair flips only once |dx| reaches
+ * (pr_i - pr_j) / (1/g_i + 1/g_j); two first units (both infinite) are
+ * ordered by the shares and flip at |dx| = (x_i - x_j) / 2; a held first unit
+ * is lost only when its share reaches zero. */
+double oracle_margin_hh(int32_t E, const double* x, const double* p, double s, const int32_t* R, int64_t T,
+                        const int32_t* a)
+{
+    int64_t rsum = 0;
+    for (int32_t e = 0; e < E; ++e)
+        rsum += R[e];
+    if (T <= 0 || T >= rsum)
+        return INFINITY;
+    double m = INFINITY;
+    for (int32_t e = 0; e < E; ++e)
+        if (R[e] > 0) { /* cap switch */
+            double d = fabs(s * p[e] - (double)R[e]);
+            if (d < m)
+                m = d;
+        }
+    for (int32_t i = 0; i < E; ++i) {
+        if (a[i] < 1)
+            continue;
+        if (x[i] < m) /* a first unit is owed only to a positive share */
+            m = x[i];
+        const double gi = sqrt((double)(a[i] - 1) * (double)a[i]); /* last held unit */
+        for (int32_t j = 0; j < E; ++j) {
+            if (j == i || !(x[j] > 0.0) || a[j] >= R[j])
+                continue;
+            const double gj = sqrt((double)a[j] * (double)(a[j] + 1)); /* next withheld unit */
+            double d;
+            if (gi == 0.0 && gj == 0.0)
+                d = fabs(x[i] - x[j]) / 2.0;
+            else if (gi == 0.0)
+                continue; /* an infinite priority never loses to a finite one */
+            else if (gj == 0.0)
+                d = 0.0; /* cannot happen for a Huntington-Hill result */
+            else
+                d = (x[i] / gi - x[j] / gj) / (1.0 / gi + 1.0 / gj);
+            if (d < m)
+                m = d;
+        }
+    }
+    return m < 0.0 ? 0.0 : m;
+}
+
 /* Distance in float64 from the nearest input change that would flip a
  * decision of the integer step: a share crossing an integer (floor), or the
  * r-th and (r+1)-th largest eligible remainders swapping order, or a share
@@ -419,10 +507,22 @@ double oracle_margin(int32_t E, const double* x, const double* p, double s, cons
     return m;
 }
 
-/* From logits to the integer puncturing vector of one node: softmax, capped
- * split of T = min(U*k, sum R) and largest remainder. Returns the margin. */
+/* From logits to the integer puncturing vector of one node with largest
+ * remainder rounding (see oracle_allocate_rounding). Returns the margin. */
+double oracle_allocate_rounding(int32_t E, const double* z, const int32_t* R, int32_t U, int32_t k, int32_t rounding,
+                                int32_t* a, double* x_out);
+
 double oracle_allocate(int32_t E, const double* z, const int32_t* R, int32_t U, int32_t k, int32_t* a,
                        double* x_out)
+{
+    return oracle_allocate_rounding(E, z, R, U, k, ORACLE_LARGEST_REMAINDER, a, x_out);
+}
+
+/* The enforcer of one node (Sec. IV-B): softmax, the capped proportional split
+ * of T = min(U k, sum R) (Eq. (7)), then the integer step (largest remainder,
+ * or Huntington-Hill). Returns the decision margin. */
+double oracle_allocate_rounding(int32_t E, const double* z, const int32_t* R, int32_t U, int32_t k, int32_t rounding,
+                                int32_t* a, double* x_out)
 {
     double p[MAX_UE], x[MAX_UE];
     int64_t rsum = 0;
@@ -432,10 +532,15 @@ double oracle_allocate(int32_t E, const double* z, const int32_t* R, int32_t U, 
     int64_t T = demand < rsum ? demand : rsum;
     oracle_softmax(E, z, p);
     double s = oracle_capped_scale(E, p, R, T, x);
-    oracle_largest_remainder(E, x, R, T, a);
+    if (rounding == ORACLE_HUNTINGTON_HILL)
+        oracle_huntington_hill(E, x, R, T, a);
+    else
+        oracle_largest_remainder(E, x, R, T, a);
     if (x_out)
         for (int32_t e = 0; e < E; ++e)
             x_out[e] = x[e];
+    if (rounding == ORACLE_HUNTINGTON_HILL)
+        return oracle_margin_hh(E, x, p, s, R, T, a);
     return oracle_margin(E, x, p, s, R, T);
 }
 
@@ -446,7 +551,7 @@ static int check_inputs(const oracle_tree* t, const oracle_actor* f)
     if (!t || !f)
         return ORACLE_EINVAL;
     if (t->num_ue < 1 || t->num_ue > MAX_UE || t->max_arrival < 1 || t->num_minislots < 1 ||
-        t->rb_per_unit < 0)
+        t->rb_per_unit < 0 || t->rounding < ORACLE_LARGEST_REMAINDER || t->rounding > ORACLE_HUNTINGTON_HILL)
         return ORACLE_EINVAL;
     if (f->dims[0] != 4 * t->num_ue + 2 || f->dims[f->num_layers] != t->num_ue)
         return ORACLE_EINVAL;
@@ -463,7 +568,7 @@ static int eval_node(const oracle_tree* t, const oracle_actor* f, const int32_t*
     int rc = oracle_mlp(f, x, z, NULL);
     if (rc)
         return rc;
-    double m = oracle_allocate(t->num_ue, z, rb, t->rb_per_unit, k, a, NULL);
+    double m = oracle_allocate_rounding(t->num_ue, z, rb, t->rb_per_unit, k, t->rounding, a, NULL);
     if (margin)
         *margin = m;
     return ORACLE_OK;
@@ -593,7 +698,7 @@ int oracle_rollout(const oracle_tree* t, const oracle_actor* f, const int32_t* r
             rc = oracle_mlp(f, x, z, amax);
             if (rc)
                 return rc;
-            oracle_allocate(E, z, rb, t->rb_per_unit, k, a, NULL);
+            oracle_allocate_rounding(E, z, rb, t->rb_per_unit, k, t->rounding, a, NULL);
         }
         for (int32_t e = 0; e < E; ++e) {
             out[(tau - 1) * E + e] = a[e];

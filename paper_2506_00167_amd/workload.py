@@ -35,6 +35,8 @@ class TreeConfig:
     rb_per_unit   U, RBs one URLLC arrival punctures.
     hidden        hidden widths of the actor MLP.
     precision     arithmetic of the layer GEMMs: fp32, bf16 or fp8 (e4m3).
+    rounding      integer step of the enforcer: "lr" (largest remainder) or
+                  "hh" (Huntington-Hill).
     """
 
     num_ue: int
@@ -43,6 +45,7 @@ class TreeConfig:
     rb_per_unit: int = 2
     hidden: Tuple[int, ...] = (256, 256)
     precision: str = "fp32"
+    rounding: str = "lr"
 
     @property
     def d_in(self) -> int:
@@ -72,6 +75,9 @@ class TreeConfig:
 
     def with_precision(self, precision: str) -> "TreeConfig":
         return dataclasses.replace(self, precision=precision)
+
+    def with_rounding(self, rounding: str) -> "TreeConfig":
+        return dataclasses.replace(self, rounding=rounding)
 
 
 # Named workloads. The first is small enough for the oracle to finish in well

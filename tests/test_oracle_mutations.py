@@ -13,6 +13,7 @@ import pytest
 
 import oracle
 from tests import test_oracle_alloc as ta
+from tests import test_oracle_hh as th
 from tests import test_oracle_mlp as tm
 from tests import test_oracle_tree as tt
 
@@ -43,6 +44,14 @@ MUTANTS = {
     "bf16 mantissa": ("return round_sig(v, 8, -126 - 7);", "return round_sig(v, 7, -126 - 7);"),
     "e4m3 saturation": ("if (r > 448.0)\n        r = 448.0;", "if (r > 480.0)\n        r = 480.0;"),
     "rollout state": ("            c[e] += a[e];", "            c[e] += 0;"),
+    "hh arithmetic-mean divisor": ("x[e] / sqrt((double)a[e] * (double)(a[e] + 1));",
+                                   "x[e] / ((double)a[e] + 0.5);"),
+    "hh first unit not guaranteed": ("a[e] == 0 ? INFINITY :", "a[e] == 0 ? x[e] :"),
+    "hh tie to smaller share": ("(pr == best_pr && x[e] > x[best])", "(pr == best_pr && x[e] < x[best])"),
+    "hh cap ignored": ("if (!(x[e] > 0.0) || a[e] >= R[e])\n                continue;\n            const double pr",
+                       "if (!(x[e] > 0.0))\n                continue;\n            const double pr"),
+    "hh margin one-sided": ("d = (x[i] / gi - x[j] / gj) / (1.0 / gi + 1.0 / gj);",
+                            "d = (x[i] / gi - x[j] / gj) * gi;"),
 }
 
 PINS = [
@@ -62,6 +71,12 @@ PINS = [
     lambda: tt.test_tree_equals_brute_force_rollouts(False),
     lambda: tt.test_invariants_tiny_workload(True),
     tt.test_depth_one_is_the_papers_codebook,
+    th.test_matches_divisor_form_random,
+    th.test_hand_case_differs_from_largest_remainder,
+    th.test_hand_case_cap_and_ties,
+    th.test_tie_goes_to_larger_share_then_lower_index,
+    th.test_zero_share_and_cap_never_receive,
+    th.test_margin_is_a_safe_distance,
 ]
 
 
