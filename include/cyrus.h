@@ -55,6 +55,13 @@ extern "C" {
 /* ------------------------------------------------------------ flags */
 #define CYRUS_FLAG_EXPORT_LOGITS 1u      /* keep the FP32 logits of every node */
 #define CYRUS_FLAG_LEVEL_KERNEL 2u       /* force the one-launch-per-level path */
+/* Integer step of the enforcer: Huntington-Hill apportionment (the rounding
+ * the paper names, Sec. IV-B) instead of the default largest remainder. Units
+ * go by priority x_e / sqrt(n (n+1)) within the caps, ties to the larger share
+ * then the lower UE index; when T is below the number of UEs with a positive
+ * share (no Huntington-Hill allocation exists then) the T largest shares get
+ * one unit each. */
+#define CYRUS_FLAG_HUNTINGTON_HILL 4u
 
 #define CYRUS_MAX_HIDDEN 4
 #define CYRUS_MAX_LAYERS (CYRUS_MAX_HIDDEN + 1)

@@ -77,7 +77,7 @@ int validate_config(const cyrus_config* cfg)
             return fail(CYRUS_ERANGE, "hidden[%d] = %d is not a multiple of 128 in [128, 512]", i, cfg->hidden[i]);
     if (cfg->precision != CYRUS_FP32 && cfg->precision != CYRUS_BF16 && cfg->precision != CYRUS_FP8_E4M3)
         return fail(CYRUS_EINVAL, "unknown precision %d", cfg->precision);
-    if (cfg->flags & ~(CYRUS_FLAG_EXPORT_LOGITS | CYRUS_FLAG_LEVEL_KERNEL))
+    if (cfg->flags & ~(CYRUS_FLAG_EXPORT_LOGITS | CYRUS_FLAG_LEVEL_KERNEL | CYRUS_FLAG_HUNTINGTON_HILL))
         return fail(CYRUS_EINVAL, "unknown flags 0x%x", cfg->flags);
     return CYRUS_OK;
 }
@@ -203,6 +203,7 @@ DevTree make_devtree(const cyrus_codebook* cb, const int32_t* ue_dev)
     t.K = s.K;
     t.M = s.M;
     t.U = cb->cfg.rb_per_unit;
+    t.rounding = (cb->cfg.flags & CYRUS_FLAG_HUNTINGTON_HILL) ? kHuntingtonHill : kLargestRemainder;
     t.n_layers = s.n_layers;
     t.in_dim0 = s.dims[0];
     const uint8_t* wb = cb->ws + s.off_w[cb->active];

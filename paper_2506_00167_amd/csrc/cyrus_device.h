@@ -242,94 +242,6 @@ __device__ __forceinline__ void store1<kFP8>(uint8_t* dst, float v, float inv_sc
 }
 
 // ---------------------------------------------------------------------------
-// Feasibility enforcer for one node, FP32 (softmax, capped proportional split
-// of T = min(U k, sum R) as the KL projection, largest-remainder rounding with
-// ties to the lower UE index). EMAX bounds E so the per-UE arrays stay in
-// registers. z: logits (LDS, stride 1). Writes a[e] for e < E.
-template <int EMAX>
-__device__ __forceinline__ void enforce(int E, const float* z, const int* R, int rsum, int demand, int* a)
-{
-    float p[EMAX], x[EMAX];
-    float zmax = -3.0e38f;
-#pragma unroll
-    for (int e = 0; e < EMAX; ++e)
-        if (e < E)
-            zmax = fmaxf(zmax, z[e]);
-    float sum = 0.f;
-#pragma unroll
-    for (int e = 0; e < EMAX; ++e) {
-        p[e] = 0.f;
-        if (e < E) {
-            p[e] = expf(fmaxf(z[e] - zmax, -80.f));
-            sum += p[e];
-        }
-    }
-#pragma unroll
-    for (int e = 0; e < EMAX; ++e)
-        p[e] = p[e] / sum;
-
-    const int T = demand < rsum ? demand : rsum;
-    if (T >= rsum) {
-#pragma unroll
-        for (int e = 0; e < EMAX; ++e)
-            if (e < E)
-                a[e] = R[e];
-        return;
-    }
-    // capped proportional split: grow the capped set until stable
-    uint32_t capped = 0;
-    float s = 0.f;
-    for (int pass = 0; pass <= EMAX; ++pass) {
-        float rem = (float)T, psum = 0.f;
-#pragma unroll
-        for (int e = 0; e < EMAX; ++e) {
-            if (e < E) {
-                if (capped & (1u << e))
-                    rem -= (float)R[e];
-                else
-                    psum += p[e];
-            }
-        }
-        s = rem / psum;
-        uint32_t grow = 0;
-#pragma unroll
-        for (int e = 0; e < EMAX; ++e)
-            if (e < E && !(capped & (1u << e)) && s * p[e] >= (float)R[e])
-                grow |= 1u << e;
-        if (!grow)
-            break;
-        capped |= grow;
-    }
-    int fsum = 0;
-    float frac[EMAX];
-    int fl[EMAX];
-#pragma unroll
-    for (int e = 0; e < EMAX; ++e) {
-        x[e] = (capped & (1u << e)) ? (float)R[e] : s * p[e];
-        float f = floorf(x[e]);
-        fl[e] = (int)f;
-        frac[e] = x[e] - f;
-        if (e < E)
-            fsum += fl[e];
-    }
-    const int r = T - fsum;
-    // rank of every eligible UE in (fraction desc, index asc); the top r get
-    // one more unit
-#pragma unroll
-    for (int e = 0; e < EMAX; ++e) {
-        if (e >= E)
-            continue;
-        const bool elig = fl[e] < R[e];
-        int rank = 0;
-#pragma unroll
-        for (int q = 0; q < EMAX; ++q) {
-            if (q < E && q != e && fl[q] < R[q] && (frac[q] > frac[e] || (frac[q] == frac[e] && q < e)))
-                ++rank;
-        }
-        a[e] = fl[e] + ((elig && rank < r) ? 1 : 0);
-    }
-}
-
 // Lane-parallel enforcer: a group of G lanes (G a power of two >= E, G <= 64)
 // handles one node, lane e of the group UE e. Softmax, the capped split and
 // largest remainder use butterfly reductions inside the group; the extra unit
@@ -364,7 +276,79 @@ __device__ __forceinline__ int group_isum(int v)
 }
 
 template <int G>
-__device__ __forceinline__ int enforce_group(int E, int e, float z, int R, int rsum, int demand)
+__device__ __forceinline__ float group_min(float v)
+{
+#pragma unroll
+    for (int m = G / 2; m >= 1; m >>= 1)
+        v = fminf(v, __shfl_xor(v, m, G));
+    return v;
+}
+
+template <int G>
+__device__ __forceinline__ int group_imax(int v)
+{
+#pragma unroll
+    for (int m = G / 2; m >= 1; m >>= 1)
+        v = max(v, __shfl_xor(v, m, G));
+    return v;
+}
+
+template <int G>
+__device__ __forceinline__ int group_imin(int v)
+{
+#pragma unroll
+    for (int m = G / 2; m >= 1; m >>= 1)
+        v = min(v, __shfl_xor(v, m, G));
+    return v;
+}
+
+// Huntington-Hill integer step (Sec. IV-B, after Balinski and Young) for the
+// shares x of one node, lane e of a G-lane group holding UE e. A unit's
+// priority is x_e / sqrt(n (n+1)) for the n units UE e already holds (the
+// first unit: infinite); the allocation is the T units of highest priority
+// within the caps, equal priorities going to the larger share and then the
+// lower index, and a UE with no share receiving nothing. Computed from the
+// rounding at divisor 1 (every unit of priority >= 1), then the units of
+// highest priority are added one by one, or those of lowest priority removed
+// (the reverse order: smaller share, then higher index), until the sum is T.
+// Below one unit per positive share this gives one unit to each of the T
+// largest shares. The loops are uniform over the group.
+template <int G>
+__device__ __forceinline__ int hh_round(int e, bool live, float x, int R, int T)
+{
+    const float kInf = __builtin_huge_valf();
+    const bool pos = live && R > 0 && x > 0.f;
+    int a = 0;
+    if (pos) {
+        const float f = floorf(x);
+        a = min((int)f + (x >= sqrtf(f * (f + 1.f)) ? 1 : 0), R);
+    }
+    int S = group_isum<G>(a);
+    while (S < T) {
+        const bool cand = pos && a < R;
+        const float pr = cand ? (a == 0 ? kInf : x / sqrtf((float)a * (float)(a + 1))) : -1.f;
+        const float top = group_max<G>(pr);
+        const bool at = cand && pr == top;
+        const float xm = group_max<G>(at ? x : -1.f);
+        const int w = group_imin<G>(at && x == xm ? e : G);
+        a += e == w ? 1 : 0;
+        ++S;
+    }
+    while (S > T) {
+        const bool cand = pos && a > 0;
+        const float pr = cand ? (a == 1 ? kInf : x / sqrtf((float)(a - 1) * (float)a)) : kInf;
+        const float low = group_min<G>(pr);
+        const bool at = cand && pr == low;
+        const float xm = group_min<G>(at ? x : kInf);
+        const int w = group_imax<G>(at && x == xm ? e : -1);
+        a -= e == w ? 1 : 0;
+        --S;
+    }
+    return a;
+}
+
+template <int G>
+__device__ __forceinline__ int enforce_group(int E, int e, float z, int R, int rsum, int demand, int rounding)
 {
     const bool live = e < E;
     const float zmax = group_max<G>(live ? z : -3.0e38f);
@@ -386,6 +370,8 @@ __device__ __forceinline__ int enforce_group(int E, int e, float z, int R, int r
         capped = capped || grow;
     }
     const float x = !live ? 0.f : (capped ? (float)R : s * p);
+    if (rounding == kHuntingtonHill)
+        return hh_round<G>(e, live, x, R, T);
     const float fl = floorf(x);
     const int f = (int)fl;
     const float frac = x - fl;
@@ -461,7 +447,8 @@ __device__ __forceinline__ int disum(int v)
 // 8/16-lane boundaries, with DPP reductions; the remainder ranks go through
 // `rank_row` (G floats of LDS private to this group).
 template <int G>
-__device__ __forceinline__ int enforce_dpp(int E, int e, float z, int R, int rsum, int demand, float* rank_row)
+__device__ __forceinline__ int enforce_dpp(int E, int e, float z, int R, int rsum, int demand, float* rank_row,
+                                           int rounding)
 {
     const bool live = e < E;
     const int T = demand < rsum ? demand : rsum;
@@ -483,6 +470,8 @@ __device__ __forceinline__ int enforce_dpp(int E, int e, float z, int R, int rsu
         capped = capped || grow;
     }
     const float x = !live ? 0.f : (capped ? (float)R : s * p);
+    if (rounding == kHuntingtonHill)
+        return hh_round<G>(e, live, x, R, T);
     const float fl = floorf(x);
     const int f = (int)fl;
     const float frac = x - fl;
@@ -501,16 +490,6 @@ __device__ __forceinline__ int enforce_dpp(int E, int e, float z, int R, int rsu
     for (int q = 0; q < G; ++q)
         rank += (fq[q] > frac || (fq[q] == frac && q < e)) ? 1 : 0;
     return f + ((elig && rank < r) ? 1 : 0);
-}
-
-__device__ __forceinline__ void enforce_any(int E, const float* z, const int* R, int rsum, int demand, int* a)
-{
-    if (E <= 8)
-        enforce<8>(E, z, R, rsum, demand, a);
-    else if (E <= 16)
-        enforce<16>(E, z, R, rsum, demand, a);
-    else
-        enforce<32>(E, z, R, rsum, demand, a);
 }
 
 }  // namespace cyrus

@@ -14,6 +14,7 @@ constexpr int kLogitStride = kMaxUE + 1;  // LDS row stride of the logits (bank-
 constexpr int kMaxEntries = 128;          // (codebook, level) entries per batched level launch
 
 enum Prec { kFP32 = 0, kBF16 = 1, kFP8 = 2 };
+enum Rounding { kLargestRemainder = 0, kHuntingtonHill = 1 };  // integer step of the enforcer
 
 inline constexpr int prec_esize(int p) { return p == kFP32 ? 4 : (p == kBF16 ? 2 : 1); }
 inline constexpr int prec_chunk(int p) { return p == kFP32 ? 16 : (p == kBF16 ? 32 : 64); }
@@ -22,6 +23,7 @@ inline constexpr int prec_chunk(int p) { return p == kFP32 ? 16 : (p == kBF16 ? 
 // from a device array in batched launches.
 struct DevTree {
     int32_t E, K, M, U;
+    int32_t rounding;                 // Rounding
     int32_t n_layers;                 // hidden layers + output layer
     int32_t in_dim0;                  // 4E + 2
     int32_t in_pad[kMaxLayers];       // layer input width padded to the k-chunk

@@ -36,7 +36,7 @@ __device__ __forceinline__ void finish_rows_level(const DevTree& t, const float*
     // Every field of t is read once, before the first store: the output
     // pointers could alias the tree descriptor in global memory, so a field
     // read after a store would be fetched again from memory.
-    const int E = t.E, K = t.K, U = t.U;
+    const int E = t.E, K = t.K, U = t.U, rounding = t.rounding;
     gu8* const alloc = as_global_mut(t.alloc);
     gu8* const state = as_global_mut(t.state);
     gf32* const logits = as_global_mut(t.logits);
@@ -49,9 +49,9 @@ __device__ __forceinline__ void finish_rows_level(const DevTree& t, const float*
             const float z = e < E ? zrow[e] : 0.f;
             int a;
             if constexpr (G <= 16)
-                a = enforce_dpp<G>(E, e, z, e < E ? R[e] : 0, rsum, U * k, zrow);  // row reused for ranks
+                a = enforce_dpp<G>(E, e, z, e < E ? R[e] : 0, rsum, U * k, zrow, rounding);  // row reused for ranks
             else
-                a = enforce_group<G>(E, e, z, e < E ? R[e] : 0, rsum, U * k);
+                a = enforce_group<G>(E, e, z, e < E ? R[e] : 0, rsum, U * k, rounding);
             if (e < E) {
                 const int64_t node = off + (int64_t)p * (K + 1) + k;
                 const uint8_t c = pst[(p - p_lo) * E + e];

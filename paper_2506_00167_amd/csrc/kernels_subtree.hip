@@ -359,7 +359,7 @@ __device__ __forceinline__ void finish_rows(const DevTree& t, const SubtreeSmem&
             }
             const int k = k_of(row);
             const int R = e < E ? sm.R[e] : 0;
-            const int a = enforce_dpp<G>(E, e, z, R, sm.misc[0], t.U * k, sm.zl + row * kLogitStride);
+            const int a = enforce_dpp<G>(E, e, z, R, sm.misc[0], t.U * k, sm.zl + row * kLogitStride, t.rounding);
             if (e < E) {
                 const uint8_t c = cin_of(row)[e];
                 const uint8_t st = (uint8_t)(c + a);

@@ -25,6 +25,7 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "ERANGE", -3: "EWORKSPACE", -4: "EDEVICE", 
 PRECISION = {"fp32": 0, "bf16": 1, "fp8": 2}
 FLAG_EXPORT_LOGITS = 1
 FLAG_LEVEL_KERNEL = 2
+FLAG_HUNTINGTON_HILL = 4
 MAX_HIDDEN = 4
 MAX_LAYERS = 5
 
@@ -148,7 +149,10 @@ def make_config(cfg: TreeConfig, export_logits: bool = False, force_level: bool 
     for i, h in enumerate(cfg.hidden):
         c.hidden[i] = h
     c.precision = PRECISION[cfg.precision]
-    c.flags = (FLAG_EXPORT_LOGITS if export_logits else 0) | (FLAG_LEVEL_KERNEL if force_level else 0)
+    if cfg.rounding not in ("lr", "hh"):
+        raise ValueError(f"rounding must be 'lr' or 'hh', not {cfg.rounding!r}")
+    c.flags = ((FLAG_EXPORT_LOGITS if export_logits else 0) | (FLAG_LEVEL_KERNEL if force_level else 0)
+               | (FLAG_HUNTINGTON_HILL if cfg.rounding == "hh" else 0))
     return c
 
 

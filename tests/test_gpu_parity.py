@@ -198,3 +198,33 @@ def test_oru_assemble_matches_oracle():
             node = oracle.node_index(cfg.max_arrival, served[:tau])
             assert y[tau - 1].tolist() == alloc[node].tolist()
     cb.close()
+
+
+def _skewed(weights, E, seed):
+    """Uneven output biases, so that shares are uneven and the two roundings
+    part ways at many nodes."""
+    rng = np.random.default_rng(seed)
+    w = list(weights)
+    w[-1] = (w[-1][0], rng.uniform(-3.0, 3.0, size=E).astype(np.float32))
+    return w
+
+
+@pytest.mark.parametrize("shape", [
+    dict(num_ue=8, max_arrival=3, rb_per_unit=5, hidden=(256, 256)),
+    dict(num_ue=4, max_arrival=2, rb_per_unit=9, hidden=(256, 256)),
+    dict(num_ue=24, max_arrival=2, num_minislots=4, rb_per_unit=6, hidden=(256, 128)),  # 32-lane groups
+])
+@pytest.mark.parametrize("force_level", [True, False])
+def test_huntington_hill_fp32(shape, force_level):
+    cfg = wl.TreeConfig(rounding="hh", **shape)
+    weights = _skewed(wl.make_weights(cfg, 41), cfg.num_ue, 42)
+    ue = wl.make_ue_state(cfg.num_ue, 43)
+    cb, alloc, logits = _build(cfg, weights, ue, force_level=force_level)
+    parity.check_invariants(cfg, ue, alloc)
+    rep = parity.compare(cfg, weights, ue, alloc, logits, logit_tol=FP32_LOGIT_TOL)
+    _report(f"hh {shape} level={force_level} path={cb.kernel_path}", rep)
+    # the flag reaches the kernels: largest remainder gives another codebook
+    cb_lr, alloc_lr, _ = _build(cfg.with_rounding("lr"), weights, ue, force_level=force_level)
+    assert not np.array_equal(alloc, alloc_lr)
+    cb_lr.close()
+    cb.close()
