@@ -33,9 +33,12 @@ _i64p = ctypes.POINTER(ctypes.c_int64)
 _f32p = ctypes.POINTER(ctypes.c_float)
 _f64p = ctypes.POINTER(ctypes.c_double)
 _u8p = ctypes.POINTER(ctypes.c_uint8)
+_u32p = ctypes.POINTER(ctypes.c_uint32)
 
 
 LARGEST_REMAINDER, HUNTINGTON_HILL = 0, 1
+SOFTMAX_HEAD, GAUSSIAN_HEAD = 0, 1
+_HEAD = {"softmax": SOFTMAX_HEAD, "gaussian": GAUSSIAN_HEAD}
 _ROUNDING = {"lr": LARGEST_REMAINDER, "largest_remainder": LARGEST_REMAINDER, "hh": HUNTINGTON_HILL,
              "huntington_hill": HUNTINGTON_HILL}
 
@@ -43,7 +46,8 @@ _ROUNDING = {"lr": LARGEST_REMAINDER, "largest_remainder": LARGEST_REMAINDER, "h
 class _Tree(ctypes.Structure):
     _fields_ = [("num_ue", ctypes.c_int32), ("max_arrival", ctypes.c_int32),
                 ("num_minislots", ctypes.c_int32), ("rb_per_unit", ctypes.c_int32),
-                ("rounding", ctypes.c_int32)]
+                ("rounding", ctypes.c_int32), ("head", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("tti", ctypes.c_uint64)]
 
 
 class _Actor(ctypes.Structure):
@@ -98,6 +102,13 @@ def _load(path: str = _LIB_PATH):
     lib.oracle_huntington_hill.argtypes = [ctypes.c_int32, _f64p, _i32p, ctypes.c_int64, _i32p]
     lib.oracle_margin_hh.restype = ctypes.c_double
     lib.oracle_margin_hh.argtypes = [ctypes.c_int32, _f64p, _f64p, ctypes.c_double, _i32p, ctypes.c_int64, _i32p]
+    lib.oracle_philox4x32_10.restype = None
+    lib.oracle_philox4x32_10.argtypes = [_u32p, _u32p, _u32p]
+    lib.oracle_normal.restype = ctypes.c_double
+    lib.oracle_normal.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int64, ctypes.c_int32]
+    lib.oracle_gaussian_head.restype = None
+    lib.oracle_gaussian_head.argtypes = [ctypes.c_int32, _f64p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int64,
+                                         _f64p]
     lib.oracle_build_tree.restype = ctypes.c_int
     lib.oracle_build_tree.argtypes = [ctypes.POINTER(_Tree), ctypes.POINTER(_Actor), _i32p, _i32p,
                                       _f32p, _u8p, _f64p, _f64p]
@@ -163,9 +174,10 @@ class Actor:
                              self._wqp)
 
 
-def _tree(cfg) -> _Tree:
+def _tree(cfg, seed: int = 0, tti: int = 0) -> _Tree:
     return _Tree(cfg.num_ue, cfg.max_arrival, cfg.num_minislots, cfg.rb_per_unit,
-                 _ROUNDING[getattr(cfg, "rounding", "lr")])
+                 _ROUNDING[getattr(cfg, "rounding", "lr")], _HEAD[getattr(cfg, "head", "softmax")],
+                 int(seed) & 0xFFFFFFFFFFFFFFFF, int(tti) & 0xFFFFFFFFFFFFFFFF)
 
 
 def _ue_arrays(ue):
@@ -283,9 +295,34 @@ def allocate(z, R, U: int, k: int, rounding: str = "lr"):
     return a, float(m), x
 
 
+# ---------------------------------------------------------------- Gaussian head
+
+def philox4x32_10(ctr, key) -> np.ndarray:
+    c = _c(ctr, np.uint32)
+    k = _c(key, np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().oracle_philox4x32_10(c.ctypes.data_as(_u32p), k.ctypes.data_as(_u32p), out.ctypes.data_as(_u32p))
+    return out
+
+
+def normal(seed: int, tti: int, node: int, e: int) -> float:
+    return float(lib().oracle_normal(int(seed) & 0xFFFFFFFFFFFFFFFF, int(tti) & 0xFFFFFFFFFFFFFFFF, int(node), int(e)))
+
+
+def gaussian_head(out, seed: int, tti: int, node: int) -> np.ndarray:
+    """Log-shares z (E) of one node from the actor's 2E outputs (mu, log sigma)."""
+    out = _c(out, np.float64)
+    E = out.size // 2
+    z = np.zeros(E, dtype=np.float64)
+    lib().oracle_gaussian_head(E, _p(out, _f64p), int(seed) & 0xFFFFFFFFFFFFFFFF, int(tti) & 0xFFFFFFFFFFFFFFFF,
+                               int(node), _p(z, _f64p))
+    return z
+
+
 # ---------------------------------------------------------------------- trees
 
-def build_tree(cfg, weights, ue, precision: str = "exact", act_scale=None, actor: Actor | None = None):
+def build_tree(cfg, weights, ue, precision: str = "exact", act_scale=None, actor: Actor | None = None,
+               seed: int = 0, tti: int = 0):
     """Free-running FP64 codebook. Returns (alloc [nodes,E] u8, logits [nodes,E]
     f64, margin [nodes] f64)."""
     f = actor or Actor(weights, precision, act_scale)
@@ -294,7 +331,7 @@ def build_tree(cfg, weights, ue, precision: str = "exact", act_scale=None, actor
     alloc = np.zeros((n, E), dtype=np.uint8)
     logits = np.zeros((n, E), dtype=np.float64)
     marg = np.zeros(n, dtype=np.float64)
-    t = _tree(cfg)
+    t = _tree(cfg, seed, tti)
     _check(f.lib.oracle_build_tree(ctypes.byref(t), ctypes.byref(f.struct), _p(rb, _i32p), _p(mcs, _i32p),
                                    _p(sinr, _f32p), _p(alloc, _u8p), _p(logits, _f64p), _p(marg, _f64p)),
            "build_tree")
@@ -302,7 +339,7 @@ def build_tree(cfg, weights, ue, precision: str = "exact", act_scale=None, actor
 
 
 def eval_conditioned(cfg, weights, ue, given_alloc, nodes=None, precision: str = "exact",
-                     act_scale=None, actor: Actor | None = None):
+                     act_scale=None, actor: Actor | None = None, seed: int = 0, tti: int = 0):
     """Recompute the listed nodes (all if None) from the state their ancestors
     reach under `given_alloc`. Returns (alloc [n,E] i32, logits [n,E], margin [n])."""
     f = actor or Actor(weights, precision, act_scale)
@@ -316,7 +353,7 @@ def eval_conditioned(cfg, weights, ue, given_alloc, nodes=None, precision: str =
     alloc = np.zeros((n, E), dtype=np.int32)
     logits = np.zeros((n, E), dtype=np.float64)
     marg = np.zeros(n, dtype=np.float64)
-    t = _tree(cfg)
+    t = _tree(cfg, seed, tti)
     _check(f.lib.oracle_eval_conditioned(ctypes.byref(t), ctypes.byref(f.struct), _p(rb, _i32p),
                                          _p(mcs, _i32p), _p(sinr, _f32p), _p(given, _u8p), _p(ids, _i64p),
                                          n, _p(alloc, _i32p), _p(logits, _f64p), _p(marg, _f64p)),
@@ -325,12 +362,12 @@ def eval_conditioned(cfg, weights, ue, given_alloc, nodes=None, precision: str =
 
 
 def rollout(cfg, weights, ue, seq, precision: str = "exact", act_scale=None,
-            actor: Actor | None = None, amax: np.ndarray | None = None) -> np.ndarray:
+            actor: Actor | None = None, amax: np.ndarray | None = None, seed: int = 0, tti: int = 0) -> np.ndarray:
     f = actor or Actor(weights, precision, act_scale)
     rb, mcs, sinr = _ue_arrays(ue)
     seq = _c(seq, np.int32)
     out = np.zeros((seq.size, cfg.num_ue), dtype=np.int32)
-    t = _tree(cfg)
+    t = _tree(cfg, seed, tti)
     _check(f.lib.oracle_rollout(ctypes.byref(t), ctypes.byref(f.struct), _p(rb, _i32p), _p(mcs, _i32p),
                                 _p(sinr, _f32p), _p(seq, _i32p), seq.size, _p(out, _i32p),
                                 None if amax is None else _p(amax, _f64p)), "rollout")
@@ -346,7 +383,8 @@ def node_index(K: int, seq) -> int:
     return level_offset(K, tau) + i
 
 
-def oru_assemble(cfg, weights, ue, raw, carry_in: int = 0, actor: Actor | None = None):
+def oru_assemble(cfg, weights, ue, raw, carry_in: int = 0, actor: Actor | None = None, seed: int = 0,
+                 tti: int = 0):
     """Controller capping/buffering plus Alg. 3: returns (served [len], Y [len,E], carry_out)."""
     f = actor or Actor(weights)
     rb, mcs, sinr = _ue_arrays(ue)
@@ -354,7 +392,7 @@ def oru_assemble(cfg, weights, ue, raw, carry_in: int = 0, actor: Actor | None =
     served = np.zeros(raw.size, dtype=np.int32)
     y = np.zeros((raw.size, cfg.num_ue), dtype=np.int32)
     co = ctypes.c_int32()
-    t = _tree(cfg)
+    t = _tree(cfg, seed, tti)
     _check(f.lib.oracle_oru_assemble(ctypes.byref(t), ctypes.byref(f.struct), _p(rb, _i32p), _p(mcs, _i32p),
                                      _p(sinr, _f32p), _p(raw, _i32p), raw.size, int(carry_in), _p(served, _i32p),
                                      _p(y, _i32p), ctypes.byref(co)), "oru_assemble")

@@ -69,10 +69,15 @@ typedef struct {
     int32_t num_minislots; /* M */
     int32_t rb_per_unit;   /* U */
     int32_t rounding;      /* ORACLE_LARGEST_REMAINDER or ORACLE_HUNTINGTON_HILL */
+    int32_t head;          /* ORACLE_SOFTMAX_HEAD (E logits) or ORACLE_GAUSSIAN_HEAD (2E: mu, log sigma) */
+    uint64_t seed;         /* Gaussian head: Philox key */
+    uint64_t tti;          /* Gaussian head: TTI number, part of the Philox counter */
 } oracle_tree;
 
 #define ORACLE_LARGEST_REMAINDER 0
 #define ORACLE_HUNTINGTON_HILL 1
+#define ORACLE_SOFTMAX_HEAD 0
+#define ORACLE_GAUSSIAN_HEAD 1
 
 typedef struct {
     int32_t num_layers;      /* weight layers: hidden layers + output layer */
@@ -333,6 +338,69 @@ double oracle_capped_scale(int32_t E, const double* p, const int32_t* R, int64_t
     return s;
 }
 
+/* ------------------------------------------------------- Gaussian head */
+
+/* Philox4x32-10, the counter-based generator of Salmon, Moraes, Dror and Shaw
+ * (SC'11), written from its definition: ten rounds, each multiplying counter
+ * words 0 and 2 by the two round constants into 64-bit products, then
+ * recombining (hi(R1 c2) ^ c1 ^ k0, lo(R1 c2), hi(R0 c0) ^ c3 ^ k1, lo(R0 c0));
+ * the key is bumped by the two Weyl constants between rounds. */
+void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3], k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n1 = (uint32_t)p1;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        const uint32_t n3 = (uint32_t)p0;
+        c0 = n0;
+        c1 = n1;
+        c2 = n2;
+        c3 = n3;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = c0;
+    out[1] = c1;
+    out[2] = c2;
+    out[3] = c3;
+}
+
+/* The standard normal draw of UE e at tree node `node` in TTI `tti`: Philox
+ * with key = seed and counter = (node, e, tti low, tti high), then Box-Muller
+ * on the first two words, each mapped to (0, 1) as (w + 1/2) / 2^32. */
+double oracle_normal(uint64_t seed, uint64_t tti, int64_t node, int32_t e)
+{
+    const uint32_t ctr[4] = {(uint32_t)node, (uint32_t)e, (uint32_t)tti, (uint32_t)(tti >> 32)};
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t w[4];
+    oracle_philox4x32_10(ctr, key, w);
+    const double u1 = ((double)w[0] + 0.5) / 4294967296.0;
+    const double u2 = ((double)w[1] + 0.5) / 4294967296.0;
+    const double two_pi = 6.283185307179586476925286766559;
+    return sqrt(-2.0 * log(u1)) * cos(two_pi * u2);
+}
+
+/* The paper's stochastic policy head (Sec. IV-B and its GPU implementation):
+ * the actor's 2E outputs are means mu_e and, in the usual SAC form, log
+ * standard deviations clamped to [-20, 2]; u_e = mu_e + sigma_e eps_e with the
+ * reparameterisation trick; tanh maps the sample to b_e = (1 + tanh u_e) / 2 in
+ * (0, 1). The KL projection only needs b up to its scale, so the node's
+ * logits are z_e = log b_e, evaluated as -log(1 + exp(-2 u_e)) (the same
+ * number: (1 + tanh u) / 2 is the logistic function of 2u), and softmax(z) =
+ * b / sum b. */
+void oracle_gaussian_head(int32_t E, const double* out, uint64_t seed, uint64_t tti, int64_t node, double* z)
+{
+    for (int32_t e = 0; e < E; ++e) {
+        double ls = out[E + e];
+        ls = ls < -20.0 ? -20.0 : (ls > 2.0 ? 2.0 : ls);
+        const double u = out[e] + exp(ls) * oracle_normal(seed, tti, node, e);
+        z[e] = u >= 0.0 ? -log1p(exp(-2.0 * u)) : 2.0 * u - log1p(exp(2.0 * u));
+    }
+}
+
 /* Infeasibility (ii): integer rounding that keeps sum = T. Largest remainder:
  * floor every share, then give one more unit to each of the r = T - sum floor
  * UEs with the largest fractional parts among those still below their cap,
@@ -550,24 +618,31 @@ static int check_inputs(const oracle_tree* t, const oracle_actor* f)
 {
     if (!t || !f)
         return ORACLE_EINVAL;
-    if (t->num_ue < 1 || t->num_ue > MAX_UE || t->max_arrival < 1 || t->num_minislots < 1 ||
-        t->rb_per_unit < 0 || t->rounding < ORACLE_LARGEST_REMAINDER || t->rounding > ORACLE_HUNTINGTON_HILL)
+    if (t->num_ue < 1 || t->num_ue > MAX_UE / 2 || t->max_arrival < 1 || t->num_minislots < 1 ||
+        t->rb_per_unit < 0 || t->rounding < ORACLE_LARGEST_REMAINDER || t->rounding > ORACLE_HUNTINGTON_HILL ||
+        t->head < ORACLE_SOFTMAX_HEAD || t->head > ORACLE_GAUSSIAN_HEAD)
         return ORACLE_EINVAL;
-    if (f->dims[0] != 4 * t->num_ue + 2 || f->dims[f->num_layers] != t->num_ue)
+    const int32_t n_out = t->head == ORACLE_GAUSSIAN_HEAD ? 2 * t->num_ue : t->num_ue;
+    if (f->dims[0] != 4 * t->num_ue + 2 || f->dims[f->num_layers] != n_out)
         return ORACLE_EINVAL;
     return ORACLE_OK;
 }
 
 /* One evaluated node: features, actor, enforcer. */
 static int eval_node(const oracle_tree* t, const oracle_actor* f, const int32_t* rb, const int32_t* mcs,
-                     const float* sinr, const int32_t* c_in, int32_t tau, int32_t k, int32_t* a,
-                     double* z, double* margin)
+                     const float* sinr, const int32_t* c_in, int64_t node, int32_t tau, int32_t k, int32_t* a,
+                     double* z, double* margin, double* amax)
 {
-    double x[4 * MAX_UE + 2];
+    double x[4 * MAX_UE + 2], out[MAX_UE];
     oracle_features(t->num_ue, rb, mcs, sinr, c_in, tau, k, x);
-    int rc = oracle_mlp(f, x, z, NULL);
+    int rc = oracle_mlp(f, x, out, amax);
     if (rc)
         return rc;
+    if (t->head == ORACLE_GAUSSIAN_HEAD)
+        oracle_gaussian_head(t->num_ue, out, t->seed, t->tti, node, z);
+    else
+        for (int32_t e = 0; e < t->num_ue; ++e)
+            z[e] = out[e];
     double m = oracle_allocate_rounding(t->num_ue, z, rb, t->rb_per_unit, k, t->rounding, a, NULL);
     if (margin)
         *margin = m;
@@ -604,7 +679,7 @@ int oracle_build_tree(const oracle_tree* t, const oracle_actor* f, const int32_t
             int32_t a[MAX_UE] = {0};
             double z[MAX_UE] = {0}, m = INFINITY;
             if (k > 0) {
-                rc = eval_node(t, f, rb, mcs, sinr, c_in, tau, k, a, z, &m);
+                rc = eval_node(t, f, rb, mcs, sinr, c_in, node, tau, k, a, z, &m, NULL);
                 if (rc)
                     break;
             }
@@ -659,7 +734,7 @@ int oracle_eval_conditioned(const oracle_tree* t, const oracle_actor* f, const i
                 anc_i /= (K + 1);
             }
             if (k > 0) {
-                rc = eval_node(t, f, rb, mcs, sinr, c_in, tau, k, a, z, &m);
+                rc = eval_node(t, f, rb, mcs, sinr, c_in, node, tau, k, a, z, &m, NULL);
                 if (rc)
                     return rc;
             }
@@ -685,20 +760,20 @@ int oracle_rollout(const oracle_tree* t, const oracle_actor* f, const int32_t* r
     int rc = check_inputs(t, f);
     if (rc)
         return rc;
-    const int32_t E = t->num_ue;
+    const int32_t E = t->num_ue, K = t->max_arrival;
     int32_t c[MAX_UE] = {0};
+    int64_t i = 0; /* index of the current node within its level */
     for (int32_t tau = 1; tau <= len; ++tau) {
         int32_t k = seq[tau - 1];
-        if (k < 0 || k > t->max_arrival)
+        if (k < 0 || k > K)
             return ORACLE_EINVAL;
+        i = i * (K + 1) + k;
         int32_t a[MAX_UE] = {0};
         if (k > 0) {
-            double x[4 * MAX_UE + 2], z[MAX_UE];
-            oracle_features(E, rb, mcs, sinr, c, tau, k, x);
-            rc = oracle_mlp(f, x, z, amax);
+            double z[MAX_UE];
+            rc = eval_node(t, f, rb, mcs, sinr, c, oracle_level_offset(K, tau) + i, tau, k, a, z, NULL, amax);
             if (rc)
                 return rc;
-            oracle_allocate_rounding(E, z, rb, t->rb_per_unit, k, t->rounding, a, NULL);
         }
         for (int32_t e = 0; e < E; ++e) {
             out[(tau - 1) * E + e] = a[e];

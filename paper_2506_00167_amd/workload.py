@@ -37,6 +37,8 @@ class TreeConfig:
     precision     arithmetic of the layer GEMMs: fp32, bf16 or fp8 (e4m3).
     rounding      integer step of the enforcer: "lr" (largest remainder) or
                   "hh" (Huntington-Hill).
+    head          policy head: "softmax" (E logits) or "gaussian" (2E outputs,
+                  means and log standard deviations, sampled per node).
     """
 
     num_ue: int
@@ -46,6 +48,7 @@ class TreeConfig:
     hidden: Tuple[int, ...] = (256, 256)
     precision: str = "fp32"
     rounding: str = "lr"
+    head: str = "softmax"
 
     @property
     def d_in(self) -> int:
@@ -53,7 +56,7 @@ class TreeConfig:
 
     @property
     def dims(self) -> Tuple[int, ...]:
-        return (self.d_in,) + tuple(self.hidden) + (self.num_ue,)
+        return (self.d_in,) + tuple(self.hidden) + (self.num_ue * (2 if self.head == "gaussian" else 1),)
 
     @property
     def num_nodes(self) -> int:
@@ -78,6 +81,9 @@ class TreeConfig:
 
     def with_rounding(self, rounding: str) -> "TreeConfig":
         return dataclasses.replace(self, rounding=rounding)
+
+    def with_head(self, head: str) -> "TreeConfig":
+        return dataclasses.replace(self, head=head)
 
 
 # Named workloads. The first is small enough for the oracle to finish in well

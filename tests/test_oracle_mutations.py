@@ -13,6 +13,7 @@ import pytest
 
 import oracle
 from tests import test_oracle_alloc as ta
+from tests import test_oracle_gaussian as tg
 from tests import test_oracle_hh as th
 from tests import test_oracle_mlp as tm
 from tests import test_oracle_tree as tt
@@ -50,6 +51,16 @@ MUTANTS = {
     "hh tie to smaller share": ("(pr == best_pr && x[e] > x[best])", "(pr == best_pr && x[e] < x[best])"),
     "hh cap ignored": ("if (!(x[e] > 0.0) || a[e] >= R[e])\n                continue;\n            const double pr",
                        "if (!(x[e] > 0.0))\n                continue;\n            const double pr"),
+    "philox round constant": ("(uint64_t)0xCD9E8D57u * c2;", "(uint64_t)0xCD9E8D55u * c2;"),
+    "philox key schedule": ("k1 += 0xBB67AE85u;", "k1 += 0x9E3779B9u;"),
+    "box-muller radius": ("return sqrt(-2.0 * log(u1)) * cos(two_pi * u2);", "return sqrt(-log(u1)) * cos(two_pi * u2);"),
+    "normal counter ignores the UE": ("const uint32_t ctr[4] = {(uint32_t)node, (uint32_t)e,",
+                                      "const uint32_t ctr[4] = {(uint32_t)node, (uint32_t)0,"),
+    "log-sigma clamp": ("ls = ls < -20.0 ? -20.0 : (ls > 2.0 ? 2.0 : ls);", "ls = ls < -20.0 ? -20.0 : ls;"),
+    "share map without the half": ("z[e] = u >= 0.0 ? -log1p(exp(-2.0 * u)) : 2.0 * u - log1p(exp(2.0 * u));",
+                                   "z[e] = u >= 0.0 ? -log1p(exp(-u)) : u - log1p(exp(u));"),
+    "rollout node counter": ("oracle_level_offset(K, tau) + i, tau, k, a, z, NULL, amax);",
+                             "oracle_level_offset(K, tau) + i / (K + 1), tau, k, a, z, NULL, amax);"),
     "hh margin one-sided": ("d = (x[i] / gi - x[j] / gj) / (1.0 / gi + 1.0 / gj);",
                             "d = (x[i] / gi - x[j] / gj) * gi;"),
 }
@@ -77,6 +88,12 @@ PINS = [
     th.test_tie_goes_to_larger_share_then_lower_index,
     th.test_zero_share_and_cap_never_receive,
     th.test_margin_is_a_safe_distance,
+    tg.test_philox_known_answers,
+    tg.test_normal_is_standard,
+    tg.test_normal_depends_on_every_key_part,
+    tg.test_head_matches_tanh_on_the_same_draws,
+    tg.test_head_clamps_log_sigma,
+    lambda: tg.test_gaussian_tree_equals_rollouts("lr"),
 ]
 
 
