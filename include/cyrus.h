@@ -62,6 +62,14 @@ extern "C" {
  * share (no Huntington-Hill allocation exists then) the T largest shares get
  * one unit each. */
 #define CYRUS_FLAG_HUNTINGTON_HILL 4u
+/* The paper's stochastic policy head (Sec. IV-B): the actor has 2E outputs,
+ * means mu_e then log standard deviations (clamped to [-20, 2]); every
+ * evaluated node draws eps_e ~ N(0, 1) (Philox4x32-10, key = seed, counter =
+ * (node, e, tti); Box-Muller on the first two words), samples u = mu + sigma
+ * eps, maps it through tanh to b_e = (1 + tanh u_e) / 2 and hands the
+ * enforcer the log-shares log b_e in place of logits. Seed and TTI come from
+ * cyrus_codebook_set_rng. Without it the actor has E outputs (logits). */
+#define CYRUS_FLAG_GAUSSIAN_HEAD 8u
 
 #define CYRUS_MAX_HIDDEN 4
 #define CYRUS_MAX_LAYERS (CYRUS_MAX_HIDDEN + 1)
@@ -192,6 +200,12 @@ int64_t cyrus_codebook_num_nodes(const cyrus_codebook* cb);
  * workgroup per subtree, actor weights held in registers) or "level" (one
  * launch per mini-slot level). */
 const char* cyrus_codebook_kernel_path(const cyrus_codebook* cb);
+
+/* Gaussian head only: the Philox key (`seed`) and the TTI number that the
+ * following builds of this handle use (engine requests take them at submit).
+ * Builds with the same seed, TTI, weights and UE state are identical. Default
+ * 0, 0. CYRUS_EINVAL if cb is NULL. */
+int cyrus_codebook_set_rng(cyrus_codebook* cb, uint64_t seed, uint64_t tti);
 
 /* Release the handle (not the caller-owned buffers). Waits for pending work. */
 void cyrus_codebook_destroy(cyrus_codebook* cb);

@@ -77,7 +77,8 @@ int validate_config(const cyrus_config* cfg)
             return fail(CYRUS_ERANGE, "hidden[%d] = %d is not a multiple of 128 in [128, 512]", i, cfg->hidden[i]);
     if (cfg->precision != CYRUS_FP32 && cfg->precision != CYRUS_BF16 && cfg->precision != CYRUS_FP8_E4M3)
         return fail(CYRUS_EINVAL, "unknown precision %d", cfg->precision);
-    if (cfg->flags & ~(CYRUS_FLAG_EXPORT_LOGITS | CYRUS_FLAG_LEVEL_KERNEL | CYRUS_FLAG_HUNTINGTON_HILL))
+    if (cfg->flags &
+        ~(CYRUS_FLAG_EXPORT_LOGITS | CYRUS_FLAG_LEVEL_KERNEL | CYRUS_FLAG_HUNTINGTON_HILL | CYRUS_FLAG_GAUSSIAN_HEAD))
         return fail(CYRUS_EINVAL, "unknown flags 0x%x", cfg->flags);
     return CYRUS_OK;
 }
@@ -93,7 +94,7 @@ Shape make_shape(const cyrus_config* cfg)
     s.dims[0] = 4 * s.E + 2;
     for (int i = 0; i < cfg->num_hidden; ++i)
         s.dims[i + 1] = cfg->hidden[i];
-    s.dims[s.n_layers] = s.E;
+    s.dims[s.n_layers] = (cfg->flags & CYRUS_FLAG_GAUSSIAN_HEAD) ? 2 * s.E : s.E;
     const int kc = prec_chunk(s.prec);
     s.w_bytes = 0;
     s.staging_floats = 0;
@@ -204,6 +205,9 @@ DevTree make_devtree(const cyrus_codebook* cb, const int32_t* ue_dev)
     t.M = s.M;
     t.U = cb->cfg.rb_per_unit;
     t.rounding = (cb->cfg.flags & CYRUS_FLAG_HUNTINGTON_HILL) ? kHuntingtonHill : kLargestRemainder;
+    t.head = (cb->cfg.flags & CYRUS_FLAG_GAUSSIAN_HEAD) ? kGaussianHead : kSoftmaxHead;
+    t.seed = cb->rng_seed;
+    t.tti = cb->rng_tti;
     t.n_layers = s.n_layers;
     t.in_dim0 = s.dims[0];
     const uint8_t* wb = cb->ws + s.off_w[cb->active];
@@ -576,6 +580,15 @@ const char* cyrus_codebook_kernel_path(const cyrus_codebook* cb)
     if (!cb)
         return "none";
     return cb->path == 1 ? "subtree" : "level";
+}
+
+int cyrus_codebook_set_rng(cyrus_codebook* cb, uint64_t seed, uint64_t tti)
+{
+    if (!cb)
+        return fail(CYRUS_EINVAL, "handle is NULL");
+    cb->rng_seed = seed;
+    cb->rng_tti = tti;
+    return CYRUS_OK;
 }
 
 void cyrus_codebook_destroy(cyrus_codebook* cb)

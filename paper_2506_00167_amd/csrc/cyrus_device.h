@@ -129,6 +129,48 @@ __device__ __forceinline__ void mma_pair<kFP8>(const uint4& a0, const uint4& a1,
     acc = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b, acc, 0, 0, 0, 127, 0, 127);
 }
 
+// ---------------------------------------------------------------------------
+// Gaussian policy head (Sec. IV-B). Philox4x32-10 (Salmon, Moraes, Dror and
+// Shaw, SC'11), from its definition: ten rounds of two 32x32->64 products of
+// counter words 0 and 2 by the round constants, recombined as
+// (hi(R1 c2) ^ c1 ^ k0, lo(R1 c2), hi(R0 c0) ^ c3 ^ k1, lo(R0 c0)), the key
+// bumped by the Weyl constants between rounds.
+__device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32_t& c2, uint32_t& c3, uint32_t k0,
+                                              uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+        c0 = hi1 ^ c1 ^ k0;
+        c1 = lo1;
+        c2 = hi0 ^ c3 ^ k1;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+// The log-share log b_e of UE e at tree node `node`: eps ~ N(0, 1) from Philox
+// (key = seed, counter = (node, e, tti)) by Box-Muller on the first two words
+// mapped to (0, 1) as (w + 1/2) 2^-32, u = mu + sigma eps with sigma =
+// exp(clamp(log sigma, -20, 2)), b = (1 + tanh u) / 2, evaluated as
+// -log(1 + exp(-2u)). -ln(w-uniform) is taken from whichever end of (0, 1) is
+// exact in FP32: ln(u1) for u1 < 1/2, log1p(-(1 - u1)) above, where 1 - u1 is
+// formed from the complemented word.
+__device__ __forceinline__ float gaussian_log_share(float mu, float log_sigma, uint64_t seed, uint64_t tti,
+                                                   int64_t node, int e)
+{
+    uint32_t w0 = (uint32_t)node, w1 = (uint32_t)e, w2 = (uint32_t)tti, w3 = (uint32_t)(tti >> 32);
+    philox4x32_10(w0, w1, w2, w3, (uint32_t)seed, (uint32_t)(seed >> 32));
+    const float kTwoM32 = 2.3283064365386963e-10f;  // 2^-32
+    const float nlog_u1 = w0 < 0x80000000u ? -logf(((float)w0 + 0.5f) * kTwoM32)
+                                           : -log1pf(-((float)(~w0) + 0.5f) * kTwoM32);
+    const float eps = sqrtf(2.f * nlog_u1) * cospif(2.f * (((float)w1 + 0.5f) * kTwoM32));
+    const float u = mu + expf(fminf(fmaxf(log_sigma, -20.f), 2.f)) * eps;
+    return u >= 0.f ? -log1pf(expf(-2.f * u)) : 2.f * u - log1pf(expf(2.f * u));
+}
+
 // Workgroup barrier that orders LDS only: waits for this wave's LDS operations
 // (lgkmcnt = 0) and meets the other waves, but leaves global loads and stores in
 // flight (vmcnt and expcnt at their maximum in the gfx9 s_waitcnt encoding).

@@ -105,6 +105,7 @@ struct Request {
     int drain_slot = -1;
     double t_submit = 0, t_done = 0;
     std::vector<int32_t> ue;  // rb[E], mcs[E], sinr bits[E]
+    uint64_t seed = 0, tti = 0;  // Gaussian head: the cell's Philox key and TTI at submit
     size_t dev_off = 0, dev_bytes = 0, host_off = 0, host_bytes = 0;
     bool has_dev = false, has_host = false;
 };
@@ -231,6 +232,8 @@ int launch_step(cyrus_engine* e)
         trees[i].alloc = dbase;
         trees[i].state = dbase + tree;
         trees[i].logits = nullptr;
+        trees[i].seed = r->seed;
+        trees[i].tti = r->tti;
     }
     int rtt = 0, buf = 0;
     size_t lds = 0;
@@ -349,6 +352,8 @@ int cyrus_engine_submit(cyrus_engine* e, cyrus_codebook* cell, const cyrus_ue_st
         return set_error(CYRUS_EINVAL, "out of host memory");
     r->ticket = e->next_ticket++;
     r->cell = cell;
+    r->seed = cell->rng_seed;
+    r->tti = cell->rng_tti;
     r->t_submit = now_us();
     r->ue.resize(3 * s.E);
     for (int i = 0; i < s.E; ++i) {

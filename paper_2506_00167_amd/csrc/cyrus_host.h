@@ -70,6 +70,7 @@ struct cyrus_codebook {
     bool mirror_valid = false;
     int path = 0;  // 0 level, 1 subtree
     int rtt = 1;
+    uint64_t rng_seed = 0, rng_tti = 0;  // Gaussian head: Philox key and TTI of the next builds
     std::vector<float> pack;  // host FP32 fragment staging
 };
 

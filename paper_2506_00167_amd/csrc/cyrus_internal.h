@@ -15,6 +15,7 @@ constexpr int kMaxEntries = 128;          // (codebook, level) entries per batch
 
 enum Prec { kFP32 = 0, kBF16 = 1, kFP8 = 2 };
 enum Rounding { kLargestRemainder = 0, kHuntingtonHill = 1 };  // integer step of the enforcer
+enum Head { kSoftmaxHead = 0, kGaussianHead = 1 };              // policy head: E logits, or 2E (mu, log sigma)
 
 inline constexpr int prec_esize(int p) { return p == kFP32 ? 4 : (p == kBF16 ? 2 : 1); }
 inline constexpr int prec_chunk(int p) { return p == kFP32 ? 16 : (p == kBF16 ? 32 : 64); }
@@ -36,6 +37,8 @@ struct DevTree {
     uint8_t* alloc;                   // [nodes][E]
     uint8_t* state;                   // [nodes][E] punctured RBs so far, after the node
     float* logits;                    // [nodes][E] or null
+    int32_t head;                     // Head
+    uint64_t seed, tti;               // Gaussian head: Philox key and TTI
 };
 
 inline int64_t ipow(int64_t b, int e)

@@ -174,9 +174,11 @@ __device__ __forceinline__ void hidden_layer(const DevTree& t, int l, const uint
 // the biases of all layers staged in LDS (layer after layer, out_pad each;
 // a hidden layer's already in the next layer's input scale).
 // Leaves the FP32 logits in zl[row * kLogitStride + e].
+// Row `row` of the tile is evaluated node off + p (K+1) + k of its level (r =
+// row0 + row = p K + k - 1); the Gaussian head keys its draws by that node.
 template <int P, int RTT>
 __device__ __forceinline__ void run_mlp(const DevTree& t, int nrows, uint8_t* bufA, uint8_t* bufB, float* zl,
-                                        const float* bias)
+                                        const float* bias, int64_t off, int row0)
 {
     constexpr int kc = Traits<P>::kChunk, es = Traits<P>::kEsize, RT = 16 * RTT;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, c16 = lane & 15;
@@ -250,14 +252,23 @@ __device__ __forceinline__ void run_mlp(const DevTree& t, int nrows, uint8_t* bu
                         acc[rt];
         }
         lds_barrier();
-        const int E = t.E;
+        const int E = t.E, K = t.K;
         const float deq = t.deq[l];
+        const bool gaussian = t.head == kGaussianHead;
         for (int idx = threadIdx.x; idx < nrows * E; idx += kThreads) {
             const int row = idx / E, e = idx - row * E;
             float s = 0.f;
             for (int w = 0; w < kWaves; ++w)
                 s += part[(size_t)(w * RT + row) * opad + e];
-            zl[row * kLogitStride + e] = s * deq + bias[e];
+            float z = s * deq + bias[e];
+            if (gaussian) {  // outputs E..2E-1 are the log standard deviations
+                float s2 = 0.f;
+                for (int w = 0; w < kWaves; ++w)
+                    s2 += part[(size_t)(w * RT + row) * opad + E + e];
+                const int r = row0 + row, p = r / K, k = r - p * K + 1;
+                z = gaussian_log_share(z, s2 * deq + bias[E + e], t.seed, t.tti, off + (int64_t)p * (K + 1) + k, e);
+            }
+            zl[row * kLogitStride + e] = z;
         }
         lds_barrier();
     }
@@ -426,7 +437,7 @@ __device__ __forceinline__ void level_tile(const DevTree& t, int tau, int row0, 
         }
     }
     lds_barrier();
-    run_mlp<P, RTT>(t, nrows, m.bufA, m.bufB, m.zl, m.bias);
+    run_mlp<P, RTT>(t, nrows, m.bufA, m.bufB, m.zl, m.bias, off, row0);
 
     const int rsum = *m.rsum;
     if (E <= 8)

@@ -340,10 +340,11 @@ __device__ __forceinline__ void write_features(const DevTree& t, const SubtreeSm
 // that node to global memory; when sib_of(r) >= 0 (the first child of a
 // parent) it also writes that k = 0 sibling: nothing punctured, parent state
 // passed on, into sib_st_of(r).
-template <int G, int RT, class KOf, class CinOf, class SoutOf, class NodeOf, class SibOf, class SibStOf>
+template <int G, int RT, bool EXT, class KOf, class CinOf, class SoutOf, class IdOf, class NodeOf, class SibOf,
+          class SibStOf>
 __device__ __forceinline__ void finish_rows(const DevTree& t, const SubtreeSmem& sm, const float* part, float deq,
                                             const float* bo, int nrows, KOf k_of, CinOf cin_of, SoutOf sout_of,
-                                            NodeOf node_of, SibOf sib_of, SibStOf sib_st_of)
+                                            IdOf id_of, NodeOf node_of, SibOf sib_of, SibStOf sib_st_of)
 {
     const int E = t.E;
     for (int base = 0; base < nrows; base += kThreads / G) {
@@ -356,10 +357,18 @@ __device__ __forceinline__ void finish_rows(const DevTree& t, const SubtreeSmem&
                 for (int w = 0; w < kWaves; ++w)
                     acc += part[(size_t)(w * RT + row) * 16 + e];
                 z = acc * deq + bo[e];
+                if (EXT && t.head == kGaussianHead) {  // one output tile: mu (0..E-1), log sigma (E..2E-1)
+                    float acc2 = 0.f;
+#pragma unroll
+                    for (int w = 0; w < kWaves; ++w)
+                        acc2 += part[(size_t)(w * RT + row) * 16 + E + e];
+                    z = gaussian_log_share(z, acc2 * deq + bo[E + e], t.seed, t.tti, id_of(row), e);
+                }
             }
             const int k = k_of(row);
             const int R = e < E ? sm.R[e] : 0;
-            const int a = enforce_dpp<G>(E, e, z, R, sm.misc[0], t.U * k, sm.zl + row * kLogitStride, t.rounding);
+            const int a = enforce_dpp<G>(E, e, z, R, sm.misc[0], t.U * k, sm.zl + row * kLogitStride,
+                                         EXT ? t.rounding : (int)kLargestRemainder);
             if (e < E) {
                 const uint8_t c = cin_of(row)[e];
                 const uint8_t st = (uint8_t)(c + a);
@@ -384,7 +393,7 @@ __device__ __forceinline__ void finish_rows(const DevTree& t, const SubtreeSmem&
     }
 }
 
-template <int P, int T, int CH1, int CHH, int NHH, int G>
+template <int P, int T, int CH1, int CHH, int NHH, int G, bool EXT>
 __device__ __forceinline__ void subtree_body(const DevTree& t, int split, int bufsize, int stbytes, uint8_t* smem)
 {
     SubtreeSmem sm;
@@ -456,9 +465,9 @@ __device__ __forceinline__ void subtree_body(const DevTree& t, int split, int bu
             write_features<P>(t, sm, 1, tau, [&](int) { return sm.st0; }, [&](int) { return k; });
             lds_barrier();
             const float* part = mlp_regs<P, T, CH1, CHH, NHH>(t, W, 1, sm.bufA, sm.bufB, sm.bias, bias_off);
-            finish_rows<G, kRT>(
+            finish_rows<G, kRT, EXT>(
                 t, sm, part, deq_out, bias_out, 1, [&](int) { return k; }, [&](int) { return sm.st0; },
-                [&](int) { return sm.st1; }, [&](int) { return owner ? node : (int64_t)-1; },
+                [&](int) { return sm.st1; }, [&](int) { return node; }, [&](int) { return owner ? node : (int64_t)-1; },
                 [&](int) { return (int64_t)-1; }, [&](int) { return sm.st1; });
             lds_barrier();
             uint8_t* tmp = sm.st0;
@@ -490,9 +499,10 @@ __device__ __forceinline__ void subtree_body(const DevTree& t, int split, int bu
                 t, sm, nrows, tau, [&](int row) { return prev + parent_of(row) * E; }, k_of);
             lds_barrier();
             const float* part = mlp_regs<P, T, CH1, CHH, NHH>(t, W, nrows, sm.bufA, sm.bufB, sm.bias, bias_off);
-            finish_rows<G, kRT>(
+            finish_rows<G, kRT, EXT>(
                 t, sm, part, deq_out, bias_out, nrows, k_of, [&](int row) { return prev + parent_of(row) * E; },
                 [&](int row) { return cur + (parent_of(row) * K1 + k_of(row)) * E; },
+                [&](int row) { return base + parent_of(row) * K1 + k_of(row); },
                 [&](int row) { return base + parent_of(row) * K1 + k_of(row); },
                 [&](int row) { return k_of(row) == 1 ? base + parent_of(row) * K1 : (int64_t)-1; },
                 [&](int row) { return cur + parent_of(row) * K1 * E; });
@@ -504,15 +514,19 @@ __device__ __forceinline__ void subtree_body(const DevTree& t, int split, int bu
     }
 }
 
-template <int P, int T, int CH1, int CHH, int NHH>
+// EXT: the options beyond softmax logits and largest remainder (the Gaussian
+// head, whose 2E outputs fit the one output tile for E <= 8, and
+// Huntington-Hill rounding) are compiled into a separate kernel, so the
+// default kernel carries none of their code or registers.
+template <int P, int T, int CH1, int CHH, int NHH, bool EXT>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 2))) void subtree_kernel(
     DevTree t, int split, int bufsize, int stbytes)
 {
     extern __shared__ __align__(16) uint8_t smem[];
     if (t.E <= 8)
-        subtree_body<P, T, CH1, CHH, NHH, 8>(t, split, bufsize, stbytes, smem);
+        subtree_body<P, T, CH1, CHH, NHH, 8, EXT>(t, split, bufsize, stbytes, smem);
     else
-        subtree_body<P, T, CH1, CHH, NHH, 16>(t, split, bufsize, stbytes, smem);
+        subtree_body<P, T, CH1, CHH, NHH, 16, EXT>(t, split, bufsize, stbytes, smem);
 }
 
 struct SubtreePlan {
@@ -540,8 +554,8 @@ int num_cus()
 
 bool plan_subtree(const DevTree& t, int prec, SubtreePlan& pl)
 {
-    if (t.E > 16 || t.n_layers < 2 || t.n_layers > 3)
-        return false;
+    if (t.E > 16 || t.n_layers < 2 || t.n_layers > 3 || t.out_pad[t.n_layers - 1] > 16)
+        return false;  // one 16-wide output tile (E logits, or mu and log sigma for E <= 8)
     const int H = t.out_pad[0];
     if (H != 128 && H != 256)
         return false;
@@ -583,12 +597,18 @@ hipError_t launch_t(const DevTree& t, const SubtreePlan& pl, hipStream_t s)
 {
     static bool attr = false;
     if (!attr) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&subtree_kernel<P, T, CH1, CHH, NHH>),
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&subtree_kernel<P, T, CH1, CHH, NHH, false>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&subtree_kernel<P, T, CH1, CHH, NHH, true>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         attr = true;
     }
-    hipLaunchKernelGGL((subtree_kernel<P, T, CH1, CHH, NHH>), dim3(pl.grid), dim3(kThreads), pl.lds, s, t, pl.split,
-                       pl.bufsize, pl.stbytes);
+    if (t.head == kGaussianHead || t.rounding == kHuntingtonHill)
+        hipLaunchKernelGGL((subtree_kernel<P, T, CH1, CHH, NHH, true>), dim3(pl.grid), dim3(kThreads), pl.lds, s, t,
+                           pl.split, pl.bufsize, pl.stbytes);
+    else
+        hipLaunchKernelGGL((subtree_kernel<P, T, CH1, CHH, NHH, false>), dim3(pl.grid), dim3(kThreads), pl.lds, s, t,
+                           pl.split, pl.bufsize, pl.stbytes);
     return hipGetLastError();
 }
 

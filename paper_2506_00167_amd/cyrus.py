@@ -26,6 +26,7 @@ PRECISION = {"fp32": 0, "bf16": 1, "fp8": 2}
 FLAG_EXPORT_LOGITS = 1
 FLAG_LEVEL_KERNEL = 2
 FLAG_HUNTINGTON_HILL = 4
+FLAG_GAUSSIAN_HEAD = 8
 MAX_HIDDEN = 4
 MAX_LAYERS = 5
 
@@ -33,7 +34,7 @@ SYMBOLS = (
     "cyrus_codebook_workspace_size", "cyrus_codebook_create", "cyrus_codebook_set_weights",
     "cyrus_codebook_build", "cyrus_codebook_build_device", "cyrus_codebook_build_batch",
     "cyrus_codebook_wait", "cyrus_codebook_lookup", "cyrus_codebook_assemble", "cyrus_codebook_export", "cyrus_codebook_device_alloc",
-    "cyrus_codebook_num_nodes", "cyrus_codebook_kernel_path", "cyrus_codebook_destroy",
+    "cyrus_codebook_num_nodes", "cyrus_codebook_kernel_path", "cyrus_codebook_set_rng", "cyrus_codebook_destroy",
     "cyrus_status_string", "cyrus_last_error",
     "cyrus_engine_create", "cyrus_engine_submit", "cyrus_engine_step", "cyrus_engine_poll",
     "cyrus_engine_completed", "cyrus_engine_result", "cyrus_engine_stats", "cyrus_engine_destroy",
@@ -99,6 +100,7 @@ def lib():
         L.cyrus_codebook_num_nodes.restype = ctypes.c_int64
         L.cyrus_codebook_kernel_path.argtypes = [vp]
         L.cyrus_codebook_kernel_path.restype = ctypes.c_char_p
+        L.cyrus_codebook_set_rng.argtypes = [vp, ctypes.c_uint64, ctypes.c_uint64]
         L.cyrus_codebook_destroy.argtypes = [vp]
         L.cyrus_codebook_destroy.restype = None
         L.cyrus_status_string.argtypes = [ctypes.c_int]
@@ -151,8 +153,11 @@ def make_config(cfg: TreeConfig, export_logits: bool = False, force_level: bool 
     c.precision = PRECISION[cfg.precision]
     if cfg.rounding not in ("lr", "hh"):
         raise ValueError(f"rounding must be 'lr' or 'hh', not {cfg.rounding!r}")
+    if cfg.head not in ("softmax", "gaussian"):
+        raise ValueError(f"head must be 'softmax' or 'gaussian', not {cfg.head!r}")
     c.flags = ((FLAG_EXPORT_LOGITS if export_logits else 0) | (FLAG_LEVEL_KERNEL if force_level else 0)
-               | (FLAG_HUNTINGTON_HILL if cfg.rounding == "hh" else 0))
+               | (FLAG_HUNTINGTON_HILL if cfg.rounding == "hh" else 0)
+               | (FLAG_GAUSSIAN_HEAD if cfg.head == "gaussian" else 0))
     return c
 
 
@@ -308,6 +313,12 @@ class Codebook:
     @property
     def kernel_path(self) -> str:
         return cyrus_codebook_kernel_path(self.handle)
+
+    def set_rng(self, seed: int, tti: int):
+        """Gaussian head: Philox key and TTI number of the following builds."""
+        _check(lib().cyrus_codebook_set_rng(self.handle, int(seed) & 0xFFFFFFFFFFFFFFFF,
+                                            int(tti) & 0xFFFFFFFFFFFFFFFF), "cyrus_codebook_set_rng")
+        return self
 
     def set_weights(self, weights, act_scale=None):
         self._w = _WeightsView(weights, act_scale)

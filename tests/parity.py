@@ -73,14 +73,16 @@ def demand(cfg, ue, node: int) -> int:
 
 
 def compare(cfg, weights, ue, gpu_alloc, gpu_logits=None, nodes=None, actor=None, precision="exact",
-            act_scale=None, logit_tol=None, free_running=True, margin_slack=1.0, dz_floor=0.0) -> ParityReport:
+            act_scale=None, logit_tol=None, free_running=True, margin_slack=1.0, dz_floor=0.0, seed=0,
+            tti=0) -> ParityReport:
     """Compare a GPU codebook with the oracle. `nodes` restricts the
     conditioned check to a sample (free-running is then skipped). Without GPU
     logits, `dz_floor` stands in for the per-node logit error (a tolerance
     established by the tests that do export logits)."""
     actor = actor or oracle.Actor(weights, precision, act_scale)
     ids = np.arange(cfg.num_nodes) if nodes is None else np.asarray(nodes, dtype=np.int64)
-    c_alloc, c_logits, c_margin = oracle.eval_conditioned(cfg, weights, ue, gpu_alloc, ids, actor=actor)
+    c_alloc, c_logits, c_margin = oracle.eval_conditioned(cfg, weights, ue, gpu_alloc, ids, actor=actor, seed=seed,
+                                                          tti=tti)
     g = np.asarray(gpu_alloc)[ids].astype(np.int32)
     mism = np.nonzero((c_alloc != g).any(axis=1))[0]
     if gpu_logits is not None:
@@ -112,7 +114,7 @@ def compare(cfg, weights, ue, gpu_alloc, gpu_logits=None, nodes=None, actor=None
     n_evals = int(evals_mask.sum()) if evals_mask is not None else cfg.num_evals
     free_m, free_bad = 0, 0
     if free_running and nodes is None:
-        f_alloc, _, _ = oracle.build_tree(cfg, weights, ue, actor=actor)
+        f_alloc, _, _ = oracle.build_tree(cfg, weights, ue, actor=actor, seed=seed, tti=tti)
         diff = np.nonzero((f_alloc != np.asarray(gpu_alloc)).any(axis=1))[0]
         free_m = int(diff.size)
         cond_set = set(int(ids[j]) for j in mism)

@@ -228,3 +228,65 @@ def test_huntington_hill_fp32(shape, force_level):
     assert not np.array_equal(alloc, alloc_lr)
     cb_lr.close()
     cb.close()
+
+
+@pytest.mark.parametrize("shape", [
+    dict(num_ue=8, max_arrival=3, rb_per_unit=3, hidden=(256, 256)),
+    dict(num_ue=4, max_arrival=2, rb_per_unit=5, hidden=(128,)),
+    dict(num_ue=16, max_arrival=4, num_minislots=3, hidden=(256, 256)),   # 2E = 32: two output tiles
+])
+@pytest.mark.parametrize("rounding", ["lr", "hh"])
+def test_gaussian_head_fp32(shape, rounding):
+    cfg = wl.TreeConfig(head="gaussian", rounding=rounding, **shape)
+    weights = wl.make_weights(cfg, 51)
+    ue = wl.make_ue_state(cfg.num_ue, 52)
+    seed, tti = 0x1234_5678_9ABC, 77_000_001
+    for force_level in (True, False):
+        cb = cyrus.Codebook(cfg, weights, export_logits=True, force_level=force_level)
+        cb.set_rng(seed, tti)
+        print(f"[build] gaussian {shape} {rounding} level={force_level} path={cb.kernel_path}", flush=True)
+        cb.build(ue)
+        cb.wait()
+        alloc, logits = cb.export()
+        parity.check_invariants(cfg, ue, alloc)
+        rep = parity.compare(cfg, weights, ue, alloc, logits, logit_tol=FP32_LOGIT_TOL, seed=seed, tti=tti)
+        _report(f"gaussian {shape} {rounding} level={force_level} path={cb.kernel_path}", rep)
+        # the same key and TTI repeat the codebook; the next TTI draws anew
+        cb.build(ue)
+        cb.wait()
+        again, logits2 = cb.export()
+        assert np.array_equal(again, alloc) and np.array_equal(logits2, logits)
+        cb.set_rng(seed, tti + 1)
+        cb.build(ue)
+        cb.wait()
+        assert not np.array_equal(cb.export()[1], logits)
+        cb.close()
+
+
+def test_gaussian_head_bf16_and_batch():
+    import torch
+    cfg = wl.TreeConfig(num_ue=8, max_arrival=3, hidden=(256, 256), precision="bf16", head="gaussian")
+    weights = wl.make_weights(cfg, 53)
+    ues = [wl.make_ue_state(cfg.num_ue, 54 + j) for j in range(3)]
+    cells = []
+    for j in range(3):
+        c = cyrus.Codebook(cfg, weights, export_logits=True, force_level=True)
+        c.set_rng(99, 1000 + j)
+        cells.append(c)
+    dev = [cyrus.ue_device_tensor(u) for u in ues]
+    cyrus.build_batch(cells, dev)
+    torch.cuda.synchronize()
+    for j, c in enumerate(cells):
+        alloc, logits = c.export()
+        # A hidden activation that the FP32 and FP64 sums place on either side
+        # of a BF16 rounding boundary differs by one BF16 unit (2^-8 relative);
+        # the head multiplies an error in log sigma by up to 2 sigma |eps|
+        # (sigma <= e^2), so the same-precision logit bound of 2e-3 for
+        # softmax logits becomes 2e-2 here.
+        rep = parity.compare(cfg, weights, ues[j], alloc, logits, precision="bf16", logit_tol=2e-2, seed=99,
+                             tti=1000 + j)
+        _report(f"gaussian bf16 batch cell {j}", rep)
+        c.build(ues[j])
+        c.wait()
+        assert np.array_equal(c.export()[0], alloc)
+        c.close()
