@@ -73,15 +73,22 @@ def pct(a, q):
     return float(np.percentile(np.asarray(a), q))
 
 
-def run_leg(precision: str, steps: int, warmup: int, latency_builds: int, stream, workload: str = WORKLOAD):
+def run_leg(precision: str, steps: int, warmup: int, latency_builds: int, stream, workload: str = WORKLOAD,
+            options=()):
+    """options: "hh" (Huntington-Hill rounding), "gaussian" (the Gaussian policy head)."""
     import torch
     from paper_2506_00167_amd import cyrus
 
     cfg = wl.WORKLOADS[workload].with_precision(precision)
+    if "hh" in options:
+        cfg = cfg.with_rounding("hh")
+    if "gaussian" in options:
+        cfg = cfg.with_head("gaussian")
     seed = wl.WEIGHT_SEEDS[workload]
     weights = wl.make_weights(cfg, seed)
     act = fp8_act_scales(workload, seed) if precision == "fp8" else None
     cb = cyrus.Codebook(cfg, weights, act_scale=act, stream=stream)
+    cb.set_rng(0x5EED, 1)
     ues = [wl.make_ue_state(cfg.num_ue, wl.ue_seed(i)) for i in range(64)]
     ue_dev = [cyrus.ue_device_tensor(u) for u in ues]
     torch.cuda.synchronize()
@@ -132,6 +139,7 @@ def run_leg(precision: str, steps: int, warmup: int, latency_builds: int, stream
     achieved = flops / (avg_us * 1e-6) / 1e12
     return {
         "workload": workload,
+        "options": list(options),
         "precision": precision,
         "kernel": f"{path}",
         "nodes_per_s": cfg.num_nodes * steps / wall,
@@ -181,8 +189,10 @@ def main():
     ap.add_argument("--latency-builds", type=int, default=2000)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--legs", default="fp32,bf16,fp8")
-    ap.add_argument("--context-legs", default="tiny-e4k2/fp32,paper-depth1/fp32",
-                    help="other workloads timed the same way (WORKLOAD/PRECISION, comma separated), reported as context")
+    ap.add_argument("--context-legs",
+                    default="tiny-e4k2/fp32,paper-depth1/fp32,tree-e8k3/fp32+hh,tree-e8k3/fp32+gaussian",
+                    help="other workloads timed the same way (WORKLOAD/PRECISION[+OPTION...], comma separated: "
+                         "options hh, gaussian), reported as context")
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -202,8 +212,10 @@ def main():
               f"p99 host {legs[prec]['latency_host_inclusive_us']['p99']:.1f} us", file=sys.stderr, flush=True)
     context = {}
     for item in filter(None, args.context_legs.split(",")):
-        name, prec = item.split("/")
-        context[item] = run_leg(prec, args.steps, args.warmup, args.latency_builds, stream, workload=name)
+        name, rest = item.split("/")
+        prec, *opts = rest.split("+")
+        context[item] = run_leg(prec, args.steps, args.warmup, args.latency_builds, stream, workload=name,
+                                options=tuple(opts))
         print(f"[bench] context {item}: {context[item]['nodes_per_s']:.4g} nodes/s, device "
               f"{context[item]['device_us_mean']:.1f} us, p99 host "
               f"{context[item]['latency_host_inclusive_us']['p99']:.1f} us", file=sys.stderr, flush=True)

@@ -50,6 +50,11 @@ class _Tree(ctypes.Structure):
                 ("tti", ctypes.c_uint64)]
 
 
+class _CriticCfg(ctypes.Structure):
+    _fields_ = [("num_ue", ctypes.c_int32), ("num_minislots", ctypes.c_int32), ("num_samples", ctypes.c_int32),
+                ("discount", ctypes.c_double), ("entropy_coef", ctypes.c_double)]
+
+
 class _Actor(ctypes.Structure):
     _fields_ = [("num_layers", ctypes.c_int32), ("dims", _i32p),
                 ("w", ctypes.POINTER(_f32p)), ("b", ctypes.POINTER(_f32p)),
@@ -109,6 +114,14 @@ def _load(path: str = _LIB_PATH):
     lib.oracle_gaussian_head.restype = None
     lib.oracle_gaussian_head.argtypes = [ctypes.c_int32, _f64p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int64,
                                          _f64p]
+    lib.oracle_log_prob_tanh_gaussian.restype = ctypes.c_double
+    lib.oracle_log_prob_tanh_gaussian.argtypes = [ctypes.c_int32, _f64p, _f64p]
+    lib.oracle_sample_tanh_gaussian.restype = ctypes.c_double
+    lib.oracle_sample_tanh_gaussian.argtypes = [ctypes.c_int32, _f64p, ctypes.c_uint64, ctypes.c_uint64,
+                                                ctypes.c_int64, _f64p]
+    lib.oracle_critic_evaluate.restype = ctypes.c_int
+    lib.oracle_critic_evaluate.argtypes = [ctypes.POINTER(_CriticCfg)] + [ctypes.POINTER(_Actor)] * 5 + [
+        _i32p, _i32p, _u8p, _f32p, _f32p, ctypes.c_uint64, ctypes.c_uint64, _f64p, _f64p, _f64p, _f64p]
     lib.oracle_build_tree.restype = ctypes.c_int
     lib.oracle_build_tree.argtypes = [ctypes.POINTER(_Tree), ctypes.POINTER(_Actor), _i32p, _i32p,
                                       _f32p, _u8p, _f64p, _f64p]
@@ -317,6 +330,49 @@ def gaussian_head(out, seed: int, tti: int, node: int) -> np.ndarray:
     lib().oracle_gaussian_head(E, _p(out, _f64p), int(seed) & 0xFFFFFFFFFFFFFFFF, int(tti) & 0xFFFFFFFFFFFFFFFF,
                                int(node), _p(z, _f64p))
     return z
+
+
+def log_prob_tanh_gaussian(out, u) -> float:
+    """log pi of the action (1 + tanh u) / 2 under the actor outputs (mu, log sigma)."""
+    out = _c(out, np.float64)
+    u = _c(u, np.float64)
+    return float(lib().oracle_log_prob_tanh_gaussian(u.size, _p(out, _f64p), _p(u, _f64p)))
+
+
+def sample_tanh_gaussian(out, seed: int, tti: int, node: int):
+    """(y, log pi(y)): the policy's action for actor outputs (mu, log sigma)."""
+    out = _c(out, np.float64)
+    E = out.size // 2
+    y = np.zeros(E, dtype=np.float64)
+    lp = lib().oracle_sample_tanh_gaussian(E, _p(out, _f64p), int(seed) & 0xFFFFFFFFFFFFFFFF,
+                                           int(tti) & 0xFFFFFFFFFFFFFFFF, int(node), _p(y, _f64p))
+    return y, float(lp)
+
+
+def critic_evaluate(E: int, M: int, actor_w, q_w, qt_w, ue, k, c, y, r, seed: int, episode: int,
+                    discount: float, entropy_coef: float):
+    """Critic pass over H buffer samples (Eqs. (3), (4)). ue [H,3E] i32 (rb, mcs,
+    sinr bits), k [H,M], c [H,M,E] u8, y [H,M,E] f32, r [H] f32; q_w and qt_w are
+    pairs of critic weight lists. Returns (q [2,H,M], qhat [H,M], logpi [H,M],
+    loss [2])."""
+    ue = _c(ue, np.int32)
+    H = ue.shape[0]
+    k = _c(k, np.int32)
+    c = _c(c, np.uint8)
+    y = _c(y, np.float32)
+    r = _c(r, np.float32)
+    nets = [Actor(actor_w)] + [Actor(w) for w in q_w] + [Actor(w) for w in qt_w]
+    cfg = _CriticCfg(E, M, H, float(discount), float(entropy_coef))
+    q = np.zeros((2, H, M), dtype=np.float64)
+    qhat = np.zeros((H, M), dtype=np.float64)
+    lp = np.zeros((H, M), dtype=np.float64)
+    loss = np.zeros(2, dtype=np.float64)
+    _check(lib().oracle_critic_evaluate(ctypes.byref(cfg), *[ctypes.byref(n.struct) for n in nets], _p(ue, _i32p),
+                                        _p(k, _i32p), _p(c, _u8p), _p(y, _f32p), _p(r, _f32p),
+                                        int(seed) & 0xFFFFFFFFFFFFFFFF, int(episode) & 0xFFFFFFFFFFFFFFFF,
+                                        _p(q, _f64p), _p(qhat, _f64p), _p(lp, _f64p), _p(loss, _f64p)),
+           "critic_evaluate")
+    return q, qhat, lp, loss
 
 
 # ---------------------------------------------------------------------- trees

@@ -383,6 +383,12 @@ double oracle_normal(uint64_t seed, uint64_t tti, int64_t node, int32_t e)
     return sqrt(-2.0 * log(u1)) * cos(two_pi * u2);
 }
 
+/* Log standard deviations are clamped to [-20, 2] (the usual SAC bounds). */
+static double clamp_log_sigma(double ls)
+{
+    return ls < -20.0 ? -20.0 : (ls > 2.0 ? 2.0 : ls);
+}
+
 /* The paper's stochastic policy head (Sec. IV-B and its GPU implementation):
  * the actor's 2E outputs are means mu_e and, in the usual SAC form, log
  * standard deviations clamped to [-20, 2]; u_e = mu_e + sigma_e eps_e with the
@@ -394,11 +400,42 @@ double oracle_normal(uint64_t seed, uint64_t tti, int64_t node, int32_t e)
 void oracle_gaussian_head(int32_t E, const double* out, uint64_t seed, uint64_t tti, int64_t node, double* z)
 {
     for (int32_t e = 0; e < E; ++e) {
-        double ls = out[E + e];
-        ls = ls < -20.0 ? -20.0 : (ls > 2.0 ? 2.0 : ls);
+        const double ls = clamp_log_sigma(out[E + e]);
         const double u = out[e] + exp(ls) * oracle_normal(seed, tti, node, e);
         z[e] = u >= 0.0 ? -log1p(exp(-2.0 * u)) : 2.0 * u - log1p(exp(2.0 * u));
     }
+}
+
+/* log of the density of the policy's action y = (1 + tanh u) / 2 at the
+ * pre-tanh point u, for the actor outputs (mu, log sigma): the Gaussian log
+ * density of u minus the log of |dy/du| = (1 - tanh(u)^2) / 2 (change of
+ * variables), summed over the E independent UEs. log((1 - tanh^2 u) / 2) is
+ * log(2 y (1 - y)), evaluated as log 2 - log(1 + e^-2u) - log(1 + e^2u). */
+double oracle_log_prob_tanh_gaussian(int32_t E, const double* out, const double* u)
+{
+    const double half_log_two_pi = 0.91893853320467274178032973640562;
+    double lp = 0.0;
+    for (int32_t e = 0; e < E; ++e) {
+        const double ls = clamp_log_sigma(out[E + e]);
+        const double d = (u[e] - out[e]) / exp(ls);
+        const double log_jac = log(2.0) - log1p(exp(-2.0 * u[e])) - log1p(exp(2.0 * u[e]));
+        lp += -0.5 * d * d - ls - half_log_two_pi - log_jac;
+    }
+    return lp;
+}
+
+/* One action of the policy for the critic's target (Eq. (4)): the same draws
+ * as the Gaussian head, y_e = (1 + tanh u_e) / 2 with u = mu + sigma eps; returns
+ * log pi(y). */
+double oracle_sample_tanh_gaussian(int32_t E, const double* out, uint64_t seed, uint64_t tti, int64_t node, double* y)
+{
+    double u[MAX_UE];
+    for (int32_t e = 0; e < E; ++e) {
+        const double ls = clamp_log_sigma(out[E + e]);
+        u[e] = out[e] + exp(ls) * oracle_normal(seed, tti, node, e);
+        y[e] = (1.0 + tanh(u[e])) / 2.0;
+    }
+    return oracle_log_prob_tanh_gaussian(E, out, u);
 }
 
 /* Infeasibility (ii): integer rounding that keeps sum = T. Largest remainder:
@@ -806,4 +843,118 @@ int oracle_oru_assemble(const oracle_tree* t, const oracle_actor* f, const int32
     }
     *carry_out = q;
     return oracle_rollout(t, f, rb, mcs, sinr, served, len, y, NULL);
+}
+
+/* ------------------------------------------------------------ critic (RIC) */
+
+typedef struct {
+    int32_t num_ue;        /* E */
+    int32_t num_minislots; /* M, steps per sample */
+    int32_t num_samples;   /* H */
+    double discount;       /* lambda of Eq. (4) */
+    double entropy_coef;   /* zeta of Eq. (4) */
+} oracle_critic_cfg;
+
+/* Critic input at step tau of sample h: the actor's state features
+ * (oracle_features with the carried state c and arrivals k of that step)
+ * followed by the action y, dimension 5E+2. */
+static void critic_input(int32_t E, const int32_t* ue_h, const uint8_t* c_step, int32_t tau, int32_t k,
+                         const double* y, double* x)
+{
+    int32_t rb[MAX_UE] = {0}, mcs[MAX_UE] = {0}, c[MAX_UE] = {0};
+    float sinr[MAX_UE] = {0};
+    for (int32_t e = 0; e < E; ++e) {
+        rb[e] = ue_h[e];
+        mcs[e] = ue_h[E + e];
+        memcpy(&sinr[e], &ue_h[2 * E + e], 4);
+        c[e] = c_step[e];
+    }
+    oracle_features(E, rb, mcs, sinr, c, tau, k, x);
+    for (int32_t e = 0; e < E; ++e)
+        x[4 * E + 2 + e] = y[e];
+}
+
+/* The Near-RT RIC's critic pass over H buffer samples of M steps (Sec. IV-B):
+ *   q[i][h][tau]  = Q_i([s, c, tau, k], y) for the stored action y (Eq. (3));
+ *   qhat[h][tau]  = Eq. (4): for tau < M, lambda (min_i Qtarg_i(state of step
+ *                   tau+1, y~) - zeta log pi(y~)), y~ a fresh action of the
+ *                   actor at step tau+1 (the Gaussian head's draws, counter
+ *                   node = h M + tau, TTI = episode); when no packet arrives
+ *                   at tau+1 the policy does not act (y~ = 0, log pi = 0);
+ *                   at tau = M the slot's reward r_h;
+ *   loss[i]       = (1 / (H M)) sum_h sum_tau (q[i][h][tau] - qhat[h][tau])^2.
+ * Layouts: ue [H][3E] (rb, mcs, sinr bits), k [H][M], c [H][M][E] (punctured
+ * RBs carried into the step), y [H][M][E], r [H]; q [2][H][M]; qhat and
+ * logpi (optional) [H][M]. */
+int oracle_critic_evaluate(const oracle_critic_cfg* cfg, const oracle_actor* actor, const oracle_actor* q1,
+                           const oracle_actor* q2, const oracle_actor* qt1, const oracle_actor* qt2,
+                           const int32_t* ue, const int32_t* k, const uint8_t* c, const float* y, const float* r,
+                           uint64_t seed, uint64_t episode, double* q, double* qhat, double* logpi, double* loss)
+{
+    if (!cfg || cfg->num_ue < 1 || cfg->num_ue > MAX_UE / 2 || cfg->num_minislots < 1 || cfg->num_samples < 1)
+        return ORACLE_EINVAL;
+    const int32_t E = cfg->num_ue, M = cfg->num_minislots, H = cfg->num_samples;
+    const oracle_actor* crit[2] = {q1, q2};
+    const oracle_actor* targ[2] = {qt1, qt2};
+    for (int i = 0; i < 2; ++i)
+        if (crit[i]->dims[0] != 5 * E + 2 || crit[i]->dims[crit[i]->num_layers] != 1 ||
+            targ[i]->dims[0] != 5 * E + 2 || targ[i]->dims[targ[i]->num_layers] != 1)
+            return ORACLE_EINVAL;
+    if (actor->dims[0] != 4 * E + 2 || actor->dims[actor->num_layers] != 2 * E)
+        return ORACLE_EINVAL;
+    double sq[2] = {0.0, 0.0};
+    for (int32_t h = 0; h < H; ++h) {
+        const int32_t* ue_h = ue + (int64_t)h * 3 * E;
+        for (int32_t tau = 1; tau <= M; ++tau) {
+            const int64_t row = (int64_t)h * M + (tau - 1);
+            double x[5 * MAX_UE + 2], yv[MAX_UE], out[MAX_UE], qv;
+            for (int32_t e = 0; e < E; ++e)
+                yv[e] = y[row * E + e];
+            critic_input(E, ue_h, c + row * E, tau, k[row], yv, x);
+            for (int i = 0; i < 2; ++i) {
+                int rc = oracle_mlp(crit[i], x, &qv, NULL);
+                if (rc)
+                    return rc;
+                q[(int64_t)i * H * M + row] = qv;
+            }
+            double target, lp = 0.0;
+            if (tau == M) {
+                target = r[h];
+            } else {
+                const int64_t nrow = row + 1; /* step tau + 1 of the same sample */
+                const int32_t kn = k[nrow];
+                double yt[MAX_UE];
+                for (int32_t e = 0; e < E; ++e)
+                    yt[e] = 0.0;
+                if (kn > 0) {
+                    double xa[4 * MAX_UE + 2];
+                    critic_input(E, ue_h, c + nrow * E, tau + 1, kn, yt, x); /* features only, y unused */
+                    for (int32_t j = 0; j < 4 * E + 2; ++j)
+                        xa[j] = x[j];
+                    int rc = oracle_mlp(actor, xa, out, NULL);
+                    if (rc)
+                        return rc;
+                    lp = oracle_sample_tanh_gaussian(E, out, seed, episode, nrow, yt);
+                }
+                critic_input(E, ue_h, c + nrow * E, tau + 1, kn, yt, x);
+                double qt[2];
+                for (int i = 0; i < 2; ++i) {
+                    int rc = oracle_mlp(targ[i], x, &qt[i], NULL);
+                    if (rc)
+                        return rc;
+                }
+                target = cfg->discount * ((qt[0] < qt[1] ? qt[0] : qt[1]) - cfg->entropy_coef * lp);
+            }
+            qhat[row] = target;
+            if (logpi)
+                logpi[row] = lp;
+            for (int i = 0; i < 2; ++i) {
+                const double d = q[(int64_t)i * H * M + row] - target;
+                sq[i] += d * d;
+            }
+        }
+    }
+    for (int i = 0; i < 2; ++i)
+        loss[i] = sq[i] / ((double)H * M);
+    return ORACLE_OK;
 }

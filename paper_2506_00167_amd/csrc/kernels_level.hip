@@ -12,10 +12,9 @@
 
 #include "cyrus_device.h"
 #include "cyrus_kernels.h"
+#include "cyrus_mlp.h"
 
 namespace cyrus {
-
-constexpr int kPF = 4;  // output-layer weight chunks loaded per group
 
 __device__ __forceinline__ int64_t dev_level_offset(int K, int tau)
 {
@@ -68,209 +67,6 @@ __device__ __forceinline__ void finish_rows_level(const DevTree& t, const float*
                 }
             }
         }
-    }
-}
-
-// One hidden layer, out = ReLU(W in + b), for the T neuron tiles this wave
-// owns (tiles wave, wave + 8, ...). The reduction runs over chunk pairs; the
-// weight fragments of the next pair are requested before the MFMAs of the
-// current one, and the loop body has no branches (clamped addresses, whole
-// row tiles; rows past the tile's live rows are computed and discarded), so
-// the loads stay in flight behind the matrix work.
-template <int P, int RTT, int T>
-__device__ __forceinline__ void hidden_layer(const DevTree& t, int l, const uint8_t* in, uint8_t* out,
-                                             const float* bias_l, int art)
-{
-    constexpr int kc = Traits<P>::kChunk, es = Traits<P>::kEsize;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, c16 = lane & 15;
-    const int nch = t.in_pad[l] / kc;
-    const int sin = t.in_pad[l] * es + 16;
-    const int sout = t.out_pad[l] * es + 16;
-    const guint4* wl = as_global(t.w[l]);
-    floatx4 acc[T][RTT];
-#pragma unroll
-    for (int tt = 0; tt < T; ++tt)
-#pragma unroll
-        for (int rt = 0; rt < RTT; ++rt)
-            acc[tt][rt] = floatx4{0.f, 0.f, 0.f, 0.f};
-    const guint4* wp[T];
-#pragma unroll
-    for (int tt = 0; tt < T; ++tt)
-        wp[tt] = wl + (size_t)(wave + kWaves * tt) * nch * 64 + lane;
-    const uint8_t* bp = in + c16 * sin + g * (kc / 4) * es;
-    const int npair = nch >> 1;
-    // two register sets in ping-pong: while one pair's fragments feed the
-    // MFMAs, the other set is being loaded, so each wait only covers loads
-    // issued one step earlier
-    uint4 x0[T], x1[T], y0[T], y1[T];
-#define CYRUS_LOAD_PAIR(D0, D1, Q)                                                                                     \
-    {                                                                                                                  \
-        const int c_ = min((Q), max(npair - 1, 0)) * 2; /* clamped: past the end reloads the last pair */             \
-        _Pragma("unroll") for (int tt = 0; tt < T; ++tt)                                                              \
-        {                                                                                                              \
-            D0[tt] = gld(wp[tt] + (size_t)c_ * 64);                                                                          \
-            D1[tt] = gld(wp[tt] + (size_t)(c_ + 1) * 64);                                                                    \
-        }                                                                                                              \
-    }
-#define CYRUS_MMA_PAIRS(S0, S1, Q)                                                                                     \
-    {                                                                                                                  \
-        const uint8_t* bq_ = bp + 2 * (Q) * kc * es;                                                                   \
-        _Pragma("unroll") for (int rt = 0; rt < RTT; ++rt)                                                            \
-        {                                                                                                              \
-            const uint4 b0_ = *reinterpret_cast<const uint4*>(bq_ + rt * 16 * sin);                                    \
-            const uint4 b1_ = *reinterpret_cast<const uint4*>(bq_ + rt * 16 * sin + kc * es);                          \
-            _Pragma("unroll") for (int tt = 0; tt < T; ++tt) mma_pair<P>(S0[tt], S1[tt], b0_, b1_, acc[tt][rt]);      \
-        }                                                                                                              \
-    }
-    if (npair > 0)
-        CYRUS_LOAD_PAIR(x0, x1, 0)
-    int q = 0;
-    for (; q + 1 < npair; q += 2) {
-        CYRUS_LOAD_PAIR(y0, y1, q + 1)
-        __builtin_amdgcn_sched_barrier(0);  // the next pair's loads go out before this pair's MFMAs
-        CYRUS_MMA_PAIRS(x0, x1, q)
-        CYRUS_LOAD_PAIR(x0, x1, q + 2)
-        __builtin_amdgcn_sched_barrier(0);
-        CYRUS_MMA_PAIRS(y0, y1, q + 1)
-    }
-    if (q < npair)
-        CYRUS_MMA_PAIRS(x0, x1, q)
-#undef CYRUS_LOAD_PAIR
-#undef CYRUS_MMA_PAIRS
-    if (nch & 1) {  // odd chunk count (FP32/BF16 first layer): one last chunk
-        const int c = nch - 1;
-        const uint8_t* bq = bp + c * kc * es;
-        uint4 a0[T];
-#pragma unroll
-        for (int tt = 0; tt < T; ++tt)
-            a0[tt] = gld(wp[tt] + (size_t)c * 64);
-#pragma unroll
-        for (int rt = 0; rt < RTT; ++rt) {
-            const uint4 b0 = *reinterpret_cast<const uint4*>(bq + rt * 16 * sin);
-#pragma unroll
-            for (int tt = 0; tt < T; ++tt)
-                mma_chunk<P>(a0[tt], b0, acc[tt][rt]);
-        }
-    }
-    // Epilogue in the next layer's input scale: the staged bias is already
-    // multiplied by it, and deq times it is exact (both are powers of two;
-    // 1 outside FP8), so fma(acc, c1, bias) equals the scaled (deq acc + b).
-    const float c1 = t.deq[l] * t.inv_in_scale[l + 1];
-#pragma unroll
-    for (int tt = 0; tt < T; ++tt) {
-        const int nt = wave + kWaves * tt;
-        const floatx4 bias = *reinterpret_cast<const floatx4*>(bias_l + nt * 16 + g * 4);
-#pragma unroll
-        for (int rt = 0; rt < RTT; ++rt) {
-            if (rt < art)
-                store_act4<P>(out + (rt * 16 + c16) * sout + (nt * 16 + g * 4) * es,
-                              fmaf(acc[tt][rt][0], c1, bias[0]), fmaf(acc[tt][rt][1], c1, bias[1]),
-                              fmaf(acc[tt][rt][2], c1, bias[2]), fmaf(acc[tt][rt][3], c1, bias[3]));
-        }
-    }
-}
-
-// Actor forward pass over `nrows` node rows whose features are in bufA, with
-// the biases of all layers staged in LDS (layer after layer, out_pad each;
-// a hidden layer's already in the next layer's input scale).
-// Leaves the FP32 logits in zl[row * kLogitStride + e].
-// Row `row` of the tile is evaluated node off + p (K+1) + k of its level (r =
-// row0 + row = p K + k - 1); the Gaussian head keys its draws by that node.
-template <int P, int RTT>
-__device__ __forceinline__ void run_mlp(const DevTree& t, int nrows, uint8_t* bufA, uint8_t* bufB, float* zl,
-                                        const float* bias, int64_t off, int row0)
-{
-    constexpr int kc = Traits<P>::kChunk, es = Traits<P>::kEsize, RT = 16 * RTT;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, c16 = lane & 15;
-    const int art = (nrows + 15) >> 4;
-    uint8_t* in = bufA;
-    uint8_t* out = bufB;
-    for (int l = 0; l + 1 < t.n_layers; ++l) {
-        const int T = (t.out_pad[l] >> 4) / kWaves;  // neuron tiles per wave (hidden widths are multiples of 128)
-        switch (T) {
-        case 1:
-            hidden_layer<P, RTT, 1>(t, l, in, out, bias, art);
-            break;
-        case 2:
-            hidden_layer<P, RTT, 2>(t, l, in, out, bias, art);
-            break;
-        case 3:
-            hidden_layer<P, RTT, 3>(t, l, in, out, bias, art);
-            break;
-        default:
-            hidden_layer<P, RTT, 4>(t, l, in, out, bias, art);
-            break;
-        }
-        lds_barrier();
-        bias += t.out_pad[l];
-        uint8_t* tmp = in;
-        in = out;
-        out = tmp;
-    }
-    // Output layer: the reduction dimension is split across the waves; each
-    // wave leaves a partial logit tile, summed in wave order below.
-    {
-        const int l = t.n_layers - 1;
-        const int nch = t.in_pad[l] / kc;
-        const int sin = t.in_pad[l] * es + 16;
-        const int opad = t.out_pad[l];
-        const int ntile = opad >> 4;
-        const int cpw = (nch + kWaves - 1) / kWaves;
-        const int c0 = wave * cpw, c1 = min(nch, c0 + cpw);
-        float* part = reinterpret_cast<float*>(out);
-        const guint4* wl = as_global(t.w[l]);
-        for (int nt = 0; nt < ntile; ++nt) {
-            floatx4 acc[RTT];
-#pragma unroll
-            for (int rt = 0; rt < RTT; ++rt)
-                acc[rt] = floatx4{0.f, 0.f, 0.f, 0.f};
-            const guint4* wp = wl + (size_t)nt * nch * 64 + lane;
-            const uint8_t* bp = in + c16 * sin + g * (kc / 4) * es;
-            for (int cb = c0; cb < c1; cb += kPF) {
-                uint4 a[kPF];
-#pragma unroll
-                for (int j = 0; j < kPF; ++j)
-                    a[j] = (cb + j < c1) ? gld(wp + (size_t)(cb + j) * 64) : uint4{0, 0, 0, 0};
-#pragma unroll
-                for (int j = 0; j < kPF; ++j) {
-                    if (cb + j < c1) {
-#pragma unroll
-                        for (int rt = 0; rt < RTT; ++rt) {
-                            if (rt < art) {
-                                const uint4 b =
-                                    *reinterpret_cast<const uint4*>(bp + rt * 16 * sin + (cb + j) * kc * es);
-                                mma_chunk<P>(a[j], b, acc[rt]);
-                            }
-                        }
-                    }
-                }
-            }
-#pragma unroll
-            for (int rt = 0; rt < RTT; ++rt)
-                if (rt < art)
-                    *reinterpret_cast<floatx4*>(part + (size_t)(wave * RT + rt * 16 + c16) * opad + nt * 16 + g * 4) =
-                        acc[rt];
-        }
-        lds_barrier();
-        const int E = t.E, K = t.K;
-        const float deq = t.deq[l];
-        const bool gaussian = t.head == kGaussianHead;
-        for (int idx = threadIdx.x; idx < nrows * E; idx += kThreads) {
-            const int row = idx / E, e = idx - row * E;
-            float s = 0.f;
-            for (int w = 0; w < kWaves; ++w)
-                s += part[(size_t)(w * RT + row) * opad + e];
-            float z = s * deq + bias[e];
-            if (gaussian) {  // outputs E..2E-1 are the log standard deviations
-                float s2 = 0.f;
-                for (int w = 0; w < kWaves; ++w)
-                    s2 += part[(size_t)(w * RT + row) * opad + E + e];
-                const int r = row0 + row, p = r / K, k = r - p * K + 1;
-                z = gaussian_log_share(z, s2 * deq + bias[E + e], t.seed, t.tti, off + (int64_t)p * (K + 1) + k, e);
-            }
-            zl[row * kLogitStride + e] = z;
-        }
-        lds_barrier();
     }
 }
 

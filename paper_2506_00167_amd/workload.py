@@ -18,7 +18,7 @@ seeded draws stand in for them):
 from __future__ import annotations
 
 import dataclasses
-from typing import List, Tuple
+from typing import Sequence, List, Tuple
 
 import numpy as np
 
@@ -109,9 +109,13 @@ UE_SEED_BASE = 1_000_000
 
 def make_weights(cfg: TreeConfig, seed: int) -> List[Tuple[np.ndarray, np.ndarray]]:
     """Xavier-uniform float32 weights [out][in] and uniform biases per layer."""
+    return make_net_weights(cfg.dims, seed)
+
+
+def make_net_weights(d: Sequence[int], seed: int) -> List[Tuple[np.ndarray, np.ndarray]]:
+    """The same recipe for any layer widths d[0] -> d[1] -> ... -> d[-1]."""
     rng = np.random.Generator(np.random.PCG64(seed))
     layers = []
-    d = cfg.dims
     for i in range(len(d) - 1):
         fan_in, fan_out = d[i], d[i + 1]
         lim_w = np.sqrt(6.0 / (fan_in + fan_out))
@@ -155,6 +159,78 @@ def make_ue_state_edge(num_ue: int, seed: int, max_rb: int = 4) -> UEState:
 
 def ue_seed(i: int) -> int:
     return UE_SEED_BASE + i
+
+
+@dataclasses.dataclass(frozen=True)
+class CriticConfig:
+    """The Near-RT RIC's critic pass (Sec. IV-B): H buffer samples of M steps
+    for E UEs; an actor with the Gaussian head (2E outputs) and four critics
+    (Q1, Q2 and their targets) of the given hidden widths on [state, y]."""
+
+    num_ue: int = 8
+    max_arrival: int = 3
+    num_minislots: int = 7
+    num_samples: int = 256
+    rb_per_unit: int = 2
+    actor_hidden: Tuple[int, ...] = (256, 256)
+    critic_hidden: Tuple[int, ...] = (256, 256)
+    discount: float = 0.99
+    entropy_coef: float = 0.2
+
+    @property
+    def actor_dims(self) -> Tuple[int, ...]:
+        return (4 * self.num_ue + 2,) + tuple(self.actor_hidden) + (2 * self.num_ue,)
+
+    @property
+    def critic_dims(self) -> Tuple[int, ...]:
+        return (5 * self.num_ue + 2,) + tuple(self.critic_hidden) + (1,)
+
+    @property
+    def rows(self) -> int:
+        return self.num_samples * self.num_minislots
+
+    @property
+    def flops(self) -> int:
+        """Algorithmic FLOPs of one pass: two critics on every row; the actor
+        and two target critics on every row but the last step of a sample."""
+        mac = lambda d: sum(d[i] * d[i + 1] for i in range(len(d) - 1))  # noqa: E731
+        H, M = self.num_samples, self.num_minislots
+        return 2 * (2 * H * M * mac(self.critic_dims) + H * (M - 1) * (mac(self.actor_dims) + 2 * mac(self.critic_dims)))
+
+
+CRITIC_RIC = CriticConfig()
+
+
+def make_critic_weights(cfg: CriticConfig, seed: int):
+    """(actor, [Q1, Q2], [Qtarg1, Qtarg2]) weight lists."""
+    actor = make_net_weights(cfg.actor_dims, seed)
+    q = [make_net_weights(cfg.critic_dims, seed + 1 + i) for i in range(2)]
+    qt = [make_net_weights(cfg.critic_dims, seed + 3 + i) for i in range(2)]
+    return actor, q, qt
+
+
+def make_critic_batch(cfg: CriticConfig, seed: int):
+    """H synthetic buffer samples: UE state per sample (ue [H,3E] int32: rb,
+    mcs, sinr bits), arrivals k [H,M] in 0..K, stored actions y [H,M,E] in
+    (0,1), carried punctured RBs c [H,M,E] (0 at step 1, then the running sum of
+    floor(y * min(R, U k)) of the earlier steps, within 8 bits) and rewards r [H]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    H, M, E = cfg.num_samples, cfg.num_minislots, cfg.num_ue
+    ue = np.zeros((H, 3 * E), dtype=np.int32)
+    for h in range(H):
+        st = make_ue_state(E, int(rng.integers(0, 2**31)))
+        ue[h, :E] = st.rb
+        ue[h, E:2 * E] = st.mcs
+        ue[h, 2 * E:] = st.sinr_db.view(np.int32)
+    k = rng.integers(0, cfg.max_arrival + 1, size=(H, M)).astype(np.int32)
+    y = rng.uniform(0.01, 0.99, size=(H, M, E)).astype(np.float32)
+    c = np.zeros((H, M, E), dtype=np.uint8)
+    for tau in range(1, M):
+        cap = np.minimum(ue[:, None, :E], (cfg.rb_per_unit * k[:, tau - 1])[:, None, None])[:, 0, :]
+        step = np.floor(y[:, tau - 1, :] * cap).astype(np.int64)
+        c[:, tau, :] = np.minimum(c[:, tau - 1, :].astype(np.int64) + step, 255).astype(np.uint8)
+    r = rng.normal(0.0, 1.0, size=H).astype(np.float32)
+    return ue, k, c, y, r
 
 
 def serving_cell_configs(num_cells: int = 64, seed: int = 424242) -> List[Tuple[TreeConfig, int]]:

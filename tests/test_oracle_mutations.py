@@ -13,6 +13,7 @@ import pytest
 
 import oracle
 from tests import test_oracle_alloc as ta
+from tests import test_oracle_critic as tc
 from tests import test_oracle_gaussian as tg
 from tests import test_oracle_hh as th
 from tests import test_oracle_mlp as tm
@@ -56,11 +57,19 @@ MUTANTS = {
     "box-muller radius": ("return sqrt(-2.0 * log(u1)) * cos(two_pi * u2);", "return sqrt(-log(u1)) * cos(two_pi * u2);"),
     "normal counter ignores the UE": ("const uint32_t ctr[4] = {(uint32_t)node, (uint32_t)e,",
                                       "const uint32_t ctr[4] = {(uint32_t)node, (uint32_t)0,"),
-    "log-sigma clamp": ("ls = ls < -20.0 ? -20.0 : (ls > 2.0 ? 2.0 : ls);", "ls = ls < -20.0 ? -20.0 : ls;"),
+    "log-sigma clamp": ("return ls < -20.0 ? -20.0 : (ls > 2.0 ? 2.0 : ls);", "return ls < -20.0 ? -20.0 : ls;"),
     "share map without the half": ("z[e] = u >= 0.0 ? -log1p(exp(-2.0 * u)) : 2.0 * u - log1p(exp(2.0 * u));",
                                    "z[e] = u >= 0.0 ? -log1p(exp(-u)) : u - log1p(exp(u));"),
     "rollout node counter": ("oracle_level_offset(K, tau) + i, tau, k, a, z, NULL, amax);",
                              "oracle_level_offset(K, tau) + i / (K + 1), tau, k, a, z, NULL, amax);"),
+    "log-density Jacobian sign": ("lp += -0.5 * d * d - ls - half_log_two_pi - log_jac;",
+                                  "lp += -0.5 * d * d - ls - half_log_two_pi + log_jac;"),
+    "log-density missing log sigma": ("lp += -0.5 * d * d - ls - half_log_two_pi - log_jac;",
+                                      "lp += -0.5 * d * d - half_log_two_pi - log_jac;"),
+    "target takes the larger critic": ("(qt[0] < qt[1] ? qt[0] : qt[1])", "(qt[0] > qt[1] ? qt[0] : qt[1])"),
+    "entropy term added": ("- cfg->entropy_coef * lp);", "+ cfg->entropy_coef * lp);"),
+    "target from the same step": ("const int64_t nrow = row + 1;", "const int64_t nrow = row;"),
+    "loss not averaged": ("loss[i] = sq[i] / ((double)H * M);", "loss[i] = sq[i] / (double)H;"),
     "hh margin one-sided": ("d = (x[i] / gi - x[j] / gj) / (1.0 / gi + 1.0 / gj);",
                             "d = (x[i] / gi - x[j] / gj) * gi;"),
 }
@@ -94,6 +103,11 @@ PINS = [
     tg.test_head_matches_tanh_on_the_same_draws,
     tg.test_head_clamps_log_sigma,
     lambda: tg.test_gaussian_tree_equals_rollouts("lr"),
+    tc.test_policy_density_integrates_to_one,
+    tc.test_policy_density_matches_scipy,
+    tc.test_sample_is_the_heads_draw_through_tanh,
+    tc.test_hand_set_critics_give_the_closed_form_target_and_loss,
+    tc.test_critic_forward_matches_numpy,
 ]
 
 
