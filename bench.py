@@ -163,6 +163,35 @@ def run_leg(precision: str, steps: int, warmup: int, latency_builds: int, stream
     }
 
 
+def critic_leg(steps: int, warmup: int, stream):
+    """The Near-RT RIC critic pass (H = 256 samples x M = 7 steps, actor with the
+    Gaussian head and four 2 x 256 critics, FP32), timed with one event pair."""
+    import torch
+    from paper_2506_00167_amd import cyrus
+
+    cfg = wl.CRITIC_RIC
+    actor, q, qt = wl.make_critic_weights(cfg, 7)
+    cr = cyrus.Critic(cfg, actor, q, qt, stream=stream)
+    batch = cyrus.critic_batch_to_device(wl.make_critic_batch(cfg, 8))
+    torch.cuda.synchronize()
+    for i in range(warmup):
+        cr.evaluate(batch, 1, i)
+    torch.cuda.synchronize()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for i in range(steps):
+        cr.evaluate(batch, 1, i)
+    end.record(stream)
+    torch.cuda.synchronize()
+    us = start.elapsed_time(end) * 1e3 / steps
+    cr.close()
+    tflops = cfg.flops / (us * 1e-6) / 1e12
+    return {"workload": f"critic pass H={cfg.num_samples} M={cfg.num_minislots} E={cfg.num_ue}, "
+                        f"actor {cfg.actor_dims}, critics {cfg.critic_dims}, fp32",
+            "us_per_pass": us, "rows_per_s": cfg.rows / (us * 1e-6), "flops_per_pass": cfg.flops,
+            "achieved_tflops": tflops, "mfma_frac": tflops / PEAK_TFLOPS["fp32"]}
+
+
 def cpu_baseline(seconds: float):
     """The FP64 oracle, single-threaded, on whole codebooks of the same
     workload until `seconds` of CPU work have been spent."""
@@ -194,6 +223,7 @@ def main():
                     help="other workloads timed the same way (WORKLOAD/PRECISION[+OPTION...], comma separated: "
                          "options hh, gaussian), reported as context")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-critic", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: the codebook build of one cell fits one MI355X and this build has "
@@ -219,6 +249,10 @@ def main():
         print(f"[bench] context {item}: {context[item]['nodes_per_s']:.4g} nodes/s, device "
               f"{context[item]['device_us_mean']:.1f} us, p99 host "
               f"{context[item]['latency_host_inclusive_us']['p99']:.1f} us", file=sys.stderr, flush=True)
+    critic = critic_leg(max(10, args.steps // 10), 5, stream) if not args.no_critic else None
+    if critic:
+        print(f"[bench] critic pass: {critic['us_per_pass']:.1f} us, {critic['achieved_tflops']:.1f} TFLOP/s",
+              file=sys.stderr, flush=True)
     head = legs["fp32"]
     cfg = wl.WORKLOADS[WORKLOAD]
     out = {
@@ -253,6 +287,7 @@ def main():
         },
         "legs": legs,
         "context_legs": context,
+        "critic": critic,
     }
     if "bf16" in legs:
         out["bf16_vs_fp32_speedup"] = legs["bf16"]["nodes_per_s"] / head["nodes_per_s"]

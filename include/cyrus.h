@@ -214,6 +214,75 @@ const char* cyrus_status_string(int status);
 const char* cyrus_last_error(void);
 
 /* ------------------------------------------------------------------------
+ * Near-RT RIC critic pass (Sec. IV-B, Eqs. (3) and (4)): the batched forward
+ * evaluation that the critics' update needs, for H buffer samples of M steps
+ * (the backward pass and the optimiser are not part of this library).
+ *
+ * For sample h and step tau (1..M) the critic input is the actor's state
+ * features at that step (R/32, MCS/32, SINR/32, c/64 per UE, tau/8, k/8) followed
+ * by the action y, dimension 5E+2. The pass computes
+ *   q[i][h][tau] = Q_i(state, y),  i = 0, 1                      (Eq. (3) input)
+ *   qhat[h][tau] = discount * (min_i Qtarg_i(state at tau+1, y~)
+ *                              - entropy_coef * log pi(y~))      (Eq. (4), tau < M)
+ *                = reward[h]                                      (tau = M)
+ * where y~ is a fresh action of the actor (Gaussian head, the draws of
+ * CYRUS_FLAG_GAUSSIAN_HEAD with counter node = h M + tau and TTI = episode,
+ * y~ = (1 + tanh u) / 2) and log pi its log density; when no packet arrives at
+ * step tau+1 the policy does not act (y~ = 0, log pi = 0). Then
+ *   loss[i] = mean over h, tau of (q[i][h][tau] - qhat[h][tau])^2      (Eq. (3)).
+ * All arithmetic is FP32 with FP32 accumulation. */
+typedef struct {
+    int32_t num_ue;                         /* E in [1, 16] */
+    int32_t num_minislots;                  /* M in [1, 7]: steps per sample */
+    int32_t num_samples;                    /* H >= 1, H*M <= 2^24 */
+    int32_t actor_hidden_layers;            /* in [1, 4] */
+    int32_t actor_hidden[CYRUS_MAX_HIDDEN]; /* multiples of 128 in [128, 512] */
+    int32_t critic_hidden_layers;           /* in [1, 4] */
+    int32_t critic_hidden[CYRUS_MAX_HIDDEN];
+    float discount;                         /* lambda of Eq. (4) */
+    float entropy_coef;                     /* zeta of Eq. (4) */
+} cyrus_critic_config;
+
+/* FP32 host weights, row-major [out][in] per layer (act_scale is ignored).
+ *   actor     4E+2 -> actor_hidden -> 2E (means, then log standard deviations)
+ *   q, q_targ 5E+2 -> critic_hidden -> 1 */
+typedef struct {
+    cyrus_weights actor;
+    cyrus_weights q[2];
+    cyrus_weights q_targ[2];
+} cyrus_critic_weights;
+
+/* One batch of buffer samples, device arrays read during the pass. */
+typedef struct {
+    const int32_t* ue;    /* [H][3E]: rb, mcs, sinr_db (float bits) per UE */
+    const int32_t* k;     /* [H][M]: URLLC arrivals of each step, in [0, 255] */
+    const uint8_t* c;     /* [H][M][E]: punctured RBs carried into each step */
+    const float* y;       /* [H][M][E]: the stored actions */
+    const float* reward;  /* [H]: r(t) of each sample */
+} cyrus_critic_batch;
+
+typedef struct cyrus_critic cyrus_critic;
+
+/* Device workspace bytes (align 256) for `cfg`: the five networks' packed
+ * weights and their descriptors. */
+int cyrus_critic_workspace_size(const cyrus_critic_config* cfg, size_t* device_bytes);
+
+/* Bind a critic evaluator to the current device: validates cfg, packs the
+ * weights into the caller-owned workspace on `stream` and waits for the copy.
+ * *out receives the handle. The library allocates no device memory. */
+int cyrus_critic_create(const cyrus_critic_config* cfg, const cyrus_critic_weights* w, void* device_ws,
+                        size_t ws_bytes, void* stream, cyrus_critic** out);
+
+/* One pass over a batch, asynchronous on `stream`. Outputs are device arrays:
+ * q [2][H][M], qhat [H][M], loss [2]. Same inputs, seed and episode give the
+ * same outputs bit for bit. CYRUS_EINVAL for NULL pointers. */
+int cyrus_critic_evaluate(cyrus_critic* cr, const cyrus_critic_batch* batch, uint64_t seed, uint64_t episode,
+                          float* q, float* qhat, float* loss, void* stream);
+
+/* Release the handle (not the workspace). */
+void cyrus_critic_destroy(cyrus_critic* cr);
+
+/* ------------------------------------------------------------------------
  * Serving engine: continuous batching of codebook requests from many cells.
  *
  * Each cell is a cyrus_codebook handle (its actor weights stay resident in its

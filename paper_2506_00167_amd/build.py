@@ -18,7 +18,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcyrus.so")
 ARCH = "gfx950"
 
-SOURCES = ["cyrus_api.cpp", "cyrus_batch.cpp", "cyrus_engine.cpp", "kernels_level.hip", "kernels_subtree.hip"]
+SOURCES = ["cyrus_api.cpp", "cyrus_batch.cpp", "cyrus_engine.cpp", "cyrus_critic.cpp", "kernels_level.hip",
+           "kernels_subtree.hip", "kernels_critic.hip"]
 
 FLAGS = [
     "-x", "hip", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",

@@ -158,16 +158,22 @@ __device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32
 // -log(1 + exp(-2u)). -ln(w-uniform) is taken from whichever end of (0, 1) is
 // exact in FP32: ln(u1) for u1 < 1/2, log1p(-(1 - u1)) above, where 1 - u1 is
 // formed from the complemented word.
-__device__ __forceinline__ float gaussian_log_share(float mu, float log_sigma, uint64_t seed, uint64_t tti,
-                                                   int64_t node, int e)
+__device__ __forceinline__ float gaussian_eps(uint64_t seed, uint64_t tti, int64_t node, int e)
 {
     uint32_t w0 = (uint32_t)node, w1 = (uint32_t)e, w2 = (uint32_t)tti, w3 = (uint32_t)(tti >> 32);
     philox4x32_10(w0, w1, w2, w3, (uint32_t)seed, (uint32_t)(seed >> 32));
     const float kTwoM32 = 2.3283064365386963e-10f;  // 2^-32
     const float nlog_u1 = w0 < 0x80000000u ? -logf(((float)w0 + 0.5f) * kTwoM32)
                                            : -log1pf(-((float)(~w0) + 0.5f) * kTwoM32);
-    const float eps = sqrtf(2.f * nlog_u1) * cospif(2.f * (((float)w1 + 0.5f) * kTwoM32));
-    const float u = mu + expf(fminf(fmaxf(log_sigma, -20.f), 2.f)) * eps;
+    return sqrtf(2.f * nlog_u1) * cospif(2.f * (((float)w1 + 0.5f) * kTwoM32));
+}
+
+__device__ __forceinline__ float clamp_log_sigma(float ls) { return fminf(fmaxf(ls, -20.f), 2.f); }
+
+__device__ __forceinline__ float gaussian_log_share(float mu, float log_sigma, uint64_t seed, uint64_t tti,
+                                                   int64_t node, int e)
+{
+    const float u = mu + expf(clamp_log_sigma(log_sigma)) * gaussian_eps(seed, tti, node, e);
     return u >= 0.f ? -log1pf(expf(-2.f * u)) : 2.f * u - log1pf(expf(2.f * u));
 }
 

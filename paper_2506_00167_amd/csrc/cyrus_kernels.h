@@ -19,6 +19,28 @@ hipError_t launch_level(const DevTree& t, int prec, int rtt, int tau, hipStream_
 hipError_t launch_level_batch(const DevTree* trees, const int* ent_tree, const int* ent_tau, const int* prefix, int n,
                               int nblocks, int prec, int rtt, int buf, size_t lds, hipStream_t s);
 
+// Critic pass (kernels_critic.hip). nets: actor, Q1, Q2, Qtarg1, Qtarg2 as
+// FP32 MLP descriptors (E = number of outputs, softmax head = raw outputs).
+struct CriticArgs {
+    const DevTree* nets;
+    const int32_t* ue;
+    const int32_t* k;
+    const uint8_t* c;
+    const float* y;
+    const float* reward;
+    float* q;
+    float* qhat;
+    float* loss;
+    int E, M, H;
+    float discount, entropy_coef;
+    uint64_t seed, episode;
+    int bufsize;
+    int bias_off[5];
+    int bias_total;
+};
+size_t critic_lds_bytes(int bufsize, int bias_total, int rtt);
+hipError_t launch_critic(const CriticArgs& a, int rtt, size_t lds, hipStream_t s);
+
 // FP32 fragment-ordered weights -> packed storage of `prec`.
 hipError_t launch_convert_weights(int prec, const float* src, uint8_t* dst, int64_t n_floats, float inv_w_scale,
                                   hipStream_t s);

@@ -1,0 +1,249 @@
+// The Near-RT RIC's critic pass (Sec. IV-B, Eqs. (3) and (4)) on MFMA: one
+// workgroup per 16*RTT rows (sample h, step tau). Per tile the workgroup runs
+// five FP32 MLPs with the activations in LDS and the weight fragments read
+// from L2: the critics Q1 and Q2 on [state, y]; the actor at step tau+1, whose
+// Gaussian draws give a fresh action y~ and its log density; the target
+// critics on [state at tau+1, y~]; and the target of Eq. (4). A second,
+// one-workgroup kernel forms the mean squared errors of Eq. (3) in a fixed
+// summation order.
+#include "cyrus_device.h"
+#include "cyrus_kernels.h"
+#include "cyrus_mlp.h"
+
+namespace cyrus {
+
+namespace {
+
+constexpr float kHalfLog2Pi = 0.91893853320467274f;
+constexpr float kLog2 = 0.69314718055994531f;
+
+// The tile's inputs, staged in LDS once: the UE state of the samples it
+// touches, and k, c, y of its rows plus the row after the last (for step
+// tau+1 of the last row).
+struct CriticStage {
+    int32_t* ue;  // [(RT / M + 2) samples][3E]
+    int32_t* k;   // [RT + 1]
+    int32_t* c;   // [(RT + 1) E]
+    float* y;     // [RT E]
+    int h0;
+};
+
+// Input value f of a network for row `row`, whose step is `tau` (1-based) and
+// whose stored inputs sit at staged row `srow`: R/32, MCS/32, SINR/32, c/64
+// per UE, tau/8, k/8, then the action (critic only: y_row, else zero), zero
+// padded.
+__device__ __forceinline__ float critic_feature(const CriticArgs& a, const CriticStage& st, int f, int h, int tau,
+                                                int srow, const float* y_row)
+{
+    const int E = a.E;
+    const int32_t* ue = st.ue + (h - st.h0) * 3 * E;
+    if (f < 2 * E)
+        return (float)ue[f] * (1.f / 32.f);
+    if (f < 3 * E)
+        return __int_as_float(ue[f]) * (1.f / 32.f);
+    if (f < 4 * E)
+        return (float)st.c[srow * E + f - 3 * E] * (1.f / 64.f);
+    if (f == 4 * E)
+        return (float)tau * (1.f / 8.f);
+    if (f == 4 * E + 1)
+        return (float)st.k[srow] * (1.f / 8.f);
+    if (y_row && f < 5 * E + 2)
+        return y_row[f - 4 * E - 2];
+    return 0.f;
+}
+
+template <int RTT>
+__global__ __launch_bounds__(kThreads) void critic_kernel(CriticArgs a)
+{
+    constexpr int RT = 16 * RTT;
+    extern __shared__ __align__(16) uint8_t smem[];
+    uint8_t* bufA = smem;
+    uint8_t* bufB = smem + a.bufsize;
+    float* zl = reinterpret_cast<float*>(smem + 2 * a.bufsize);
+    float* bias = zl + RT * kLogitStride;        // every network's biases
+    float* qt = bias + a.bias_total;             // [RT] first target critic
+    float* lp = qt + RT;                         // [RT] log pi of y~
+    float* yt = lp + RT;                         // [RT][16] y~
+    float* lpe = yt + RT * 16;                   // [RT][16] per-UE log-density terms
+    CriticStage st;
+    st.ue = reinterpret_cast<int32_t*>(lpe + RT * 16);
+    st.k = st.ue + (RT + 2) * 3 * kMaxUE / 2;  // room for RT + 2 samples of E <= 16
+    st.c = st.k + RT + 4;
+    st.y = reinterpret_cast<float*>(st.c + (RT + 1) * 16);
+
+    const int E = a.E, M = a.M;
+    const int rows = a.H * M;
+    const int j0 = blockIdx.x * RT;
+    const int nrows = min(RT, rows - j0);
+    if (nrows <= 0)
+        return;
+    const int nin = min(nrows + 1, rows - j0);  // staged rows: the tile's, and the next one if it exists
+    st.h0 = j0 / M;
+    const int nsamp = (j0 + nin - 1) / M - st.h0 + 1;
+    // stage the biases of all five networks and the tile's inputs; every
+    // global load of a thread is independent of its earlier stores
+    for (int n = 0; n < 5; ++n) {
+        const DevTree& t = a.nets[n];
+        int off = a.bias_off[n];
+        for (int l = 0; l < t.n_layers; ++l) {
+            for (int i = threadIdx.x; i < t.out_pad[l]; i += kThreads)
+                bias[off + i] = gptr(t.b[l])[i];
+            off += t.out_pad[l];
+        }
+    }
+    for (int i = threadIdx.x; i < nsamp * 3 * E; i += kThreads)
+        st.ue[i] = gptr(a.ue)[(int64_t)st.h0 * 3 * E + i];
+    for (int i = threadIdx.x; i < nin; i += kThreads)
+        st.k[i] = gptr(a.k)[j0 + i];
+    for (int i = threadIdx.x; i < nin * E; i += kThreads)
+        st.c[i] = gptr(a.c)[(int64_t)j0 * E + i];
+    for (int i = threadIdx.x; i < nrows * E; i += kThreads)
+        st.y[i] = gptr(a.y)[(int64_t)j0 * E + i];
+    lds_barrier();
+
+    // network input rows: critic (5E+2, stride sc) or actor (4E+2, stride sa)
+    // floats, for the row's own step (next = false) or step tau+1 (next =
+    // true; rows whose step is the last are zero)
+    auto fill = [&](int width, int stride, bool next, bool with_y, const float* ysrc) {
+        for (int idx = threadIdx.x; idx < RT * width; idx += kThreads) {
+            const int row = idx / width, f = idx - row * width;
+            const int j = j0 + row;
+            float v = 0.f;
+            if (row < nrows && (!next || (j % M) + 1 < M)) {
+                const int srow = row + (next ? 1 : 0);
+                const float* yr = !with_y ? nullptr : (ysrc ? ysrc + row * 16 : st.y + row * E);
+                v = critic_feature(a, st, f, j / M, j % M + 1 + (next ? 1 : 0), srow, yr);
+            }
+            reinterpret_cast<float*>(bufA)[row * stride + f] = v;
+        }
+        lds_barrier();
+    };
+    const int wc = a.nets[1].in_pad[0], sc = wc + 4;
+    const int wa = a.nets[0].in_pad[0], sa = wa + 4;
+    auto net = [&](int n) { run_mlp<kFP32, RTT>(a.nets[n], nrows, bufA, bufB, zl, bias + a.bias_off[n], 0, 0); };
+
+    // Q1 and Q2 on the stored action
+    for (int i = 0; i < 2; ++i) {
+        fill(wc, sc, false, true, nullptr);
+        net(1 + i);
+        for (int row = threadIdx.x; row < nrows; row += kThreads)
+            a.q[(int64_t)i * rows + j0 + row] = zl[row * kLogitStride];
+        lds_barrier();
+    }
+
+    // the actor at step tau+1
+    fill(wa, sa, true, false, nullptr);
+    net(0);
+    // y~ = (1 + tanh u) / 2 with u = mu + sigma eps, and the terms of log pi:
+    // -eps^2/2 - log sigma - log(2 pi)/2 - log|dy/du|, where
+    // log|dy/du| = log 2 - 2|u| - 2 log(1 + e^-2|u|)
+    for (int idx = threadIdx.x; idx < nrows * 16; idx += kThreads) {
+        const int row = idx >> 4, e = idx & 15;
+        const int j = j0 + row;
+        float y = 0.f, term = 0.f;
+        if (e < E && (j % M) + 1 < M && st.k[row + 1] > 0) {
+            const float mu = zl[row * kLogitStride + e];
+            const float ls = clamp_log_sigma(zl[row * kLogitStride + E + e]);
+            const float eps = gaussian_eps(a.seed, a.episode, (int64_t)(j + 1), e);
+            const float u = mu + expf(ls) * eps;
+            y = 0.5f * (1.f + tanhf(u));
+            const float au = fabsf(u);
+            const float log_jac = kLog2 - 2.f * au - 2.f * log1pf(expf(-2.f * au));
+            term = -0.5f * eps * eps - ls - kHalfLog2Pi - log_jac;
+        }
+        yt[row * 16 + e] = y;
+        lpe[row * 16 + e] = term;
+    }
+    lds_barrier();
+    for (int row = threadIdx.x; row < nrows; row += kThreads) {
+        float s = 0.f;
+        for (int e = 0; e < E; ++e)
+            s += lpe[row * 16 + e];
+        lp[row] = s;
+    }
+    // the target critics on [state at tau+1, y~]
+    fill(wc, sc, true, true, yt);
+    net(3);
+    for (int row = threadIdx.x; row < nrows; row += kThreads)
+        qt[row] = zl[row * kLogitStride];
+    lds_barrier();
+    fill(wc, sc, true, true, yt);
+    net(4);
+    for (int row = threadIdx.x; row < nrows; row += kThreads) {
+        const int j = j0 + row;
+        float target;
+        if ((j % M) + 1 == M)
+            target = a.reward[j / M];
+        else
+            target = a.discount * (fminf(qt[row], zl[row * kLogitStride]) - a.entropy_coef * lp[row]);
+        a.qhat[j] = target;
+    }
+}
+
+// loss[i] = mean over rows of (q[i][row] - qhat[row])^2; every thread sums a
+// fixed stride of rows, then a fixed-order tree in LDS.
+__global__ __launch_bounds__(256) void critic_loss_kernel(const float* q, const float* qhat, int rows, float* loss)
+{
+    __shared__ float part[2][256];
+    for (int i = 0; i < 2; ++i) {
+        float s = 0.f;
+        for (int j = threadIdx.x; j < rows; j += 256) {
+            const float d = q[(int64_t)i * rows + j] - qhat[j];
+            s += d * d;
+        }
+        part[i][threadIdx.x] = s;
+    }
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            part[0][threadIdx.x] += part[0][threadIdx.x + w];
+            part[1][threadIdx.x] += part[1][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 2)
+        loss[threadIdx.x] = part[threadIdx.x][0] / (float)rows;
+}
+
+}  // namespace
+
+size_t critic_lds_bytes(int bufsize, int bias_total, int rtt)
+{
+    const size_t RT = 16 * (size_t)rtt;
+    const size_t stage = ((RT + 2) * 3 * kMaxUE / 2 + RT + 4 + (RT + 1) * 16) * 4 + RT * 16 * 4;
+    return 2 * (size_t)bufsize + RT * kLogitStride * 4 + (size_t)bias_total * 4 + RT * 4 * 2 + RT * 16 * 4 * 2 +
+           stage;
+}
+
+template <int RTT>
+static hipError_t launch_critic_t(const CriticArgs& a, size_t lds, hipStream_t s)
+{
+    static bool attr = false;
+    if (!attr) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&critic_kernel<RTT>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        attr = true;
+    }
+    const int rows = a.H * a.M;
+    const int grid = (rows + 16 * RTT - 1) / (16 * RTT);
+    hipLaunchKernelGGL((critic_kernel<RTT>), dim3(grid), dim3(kThreads), lds, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(critic_loss_kernel, dim3(1), dim3(256), 0, s, a.q, a.qhat, rows, a.loss);
+    return hipGetLastError();
+}
+
+hipError_t launch_critic(const CriticArgs& a, int rtt, size_t lds, hipStream_t s)
+{
+    switch (rtt) {
+    case 4:
+        return launch_critic_t<4>(a, lds, s);
+    case 2:
+        return launch_critic_t<2>(a, lds, s);
+    default:
+        return launch_critic_t<1>(a, lds, s);
+    }
+}
+
+}  // namespace cyrus

@@ -36,6 +36,7 @@ SYMBOLS = (
     "cyrus_codebook_wait", "cyrus_codebook_lookup", "cyrus_codebook_assemble", "cyrus_codebook_export", "cyrus_codebook_device_alloc",
     "cyrus_codebook_num_nodes", "cyrus_codebook_kernel_path", "cyrus_codebook_set_rng", "cyrus_codebook_destroy",
     "cyrus_status_string", "cyrus_last_error",
+    "cyrus_critic_workspace_size", "cyrus_critic_create", "cyrus_critic_evaluate", "cyrus_critic_destroy",
     "cyrus_engine_create", "cyrus_engine_submit", "cyrus_engine_step", "cyrus_engine_poll",
     "cyrus_engine_completed", "cyrus_engine_result", "cyrus_engine_stats", "cyrus_engine_destroy",
 )
@@ -61,6 +62,21 @@ _u8p = ctypes.POINTER(ctypes.c_uint8)
 
 class cyrus_weights(ctypes.Structure):
     _fields_ = [("w", _f32p * MAX_LAYERS), ("b", _f32p * MAX_LAYERS), ("act_scale", _f32p)]
+
+
+class cyrus_critic_config(ctypes.Structure):
+    _fields_ = [("num_ue", ctypes.c_int32), ("num_minislots", ctypes.c_int32), ("num_samples", ctypes.c_int32),
+                ("actor_hidden_layers", ctypes.c_int32), ("actor_hidden", ctypes.c_int32 * MAX_HIDDEN),
+                ("critic_hidden_layers", ctypes.c_int32), ("critic_hidden", ctypes.c_int32 * MAX_HIDDEN),
+                ("discount", ctypes.c_float), ("entropy_coef", ctypes.c_float)]
+
+
+class cyrus_critic_weights(ctypes.Structure):
+    _fields_ = [("actor", cyrus_weights), ("q", cyrus_weights * 2), ("q_targ", cyrus_weights * 2)]
+
+
+class cyrus_critic_batch(ctypes.Structure):
+    _fields_ = [("ue", _i32p), ("k", _i32p), ("c", _u8p), ("y", _f32p), ("reward", _f32p)]
 
 
 class cyrus_ue_state(ctypes.Structure):
@@ -101,6 +117,13 @@ def lib():
         L.cyrus_codebook_kernel_path.argtypes = [vp]
         L.cyrus_codebook_kernel_path.restype = ctypes.c_char_p
         L.cyrus_codebook_set_rng.argtypes = [vp, ctypes.c_uint64, ctypes.c_uint64]
+        L.cyrus_critic_workspace_size.argtypes = [ctypes.POINTER(cyrus_critic_config), ctypes.POINTER(sz)]
+        L.cyrus_critic_create.argtypes = [ctypes.POINTER(cyrus_critic_config), ctypes.POINTER(cyrus_critic_weights),
+                                          vp, sz, vp, ctypes.POINTER(vp)]
+        L.cyrus_critic_evaluate.argtypes = [vp, ctypes.POINTER(cyrus_critic_batch), ctypes.c_uint64, ctypes.c_uint64,
+                                            vp, vp, vp, vp]
+        L.cyrus_critic_destroy.argtypes = [vp]
+        L.cyrus_critic_destroy.restype = None
         L.cyrus_codebook_destroy.argtypes = [vp]
         L.cyrus_codebook_destroy.restype = None
         L.cyrus_status_string.argtypes = [ctypes.c_int]
@@ -468,3 +491,82 @@ class Engine:
         except Exception:
             pass
 
+
+
+# ------------------------------------------------------------------- critic
+
+def make_critic_config(cfg) -> cyrus_critic_config:
+    c = cyrus_critic_config()
+    c.num_ue = cfg.num_ue
+    c.num_minislots = cfg.num_minislots
+    c.num_samples = cfg.num_samples
+    c.actor_hidden_layers = len(cfg.actor_hidden)
+    for i, h in enumerate(cfg.actor_hidden):
+        c.actor_hidden[i] = h
+    c.critic_hidden_layers = len(cfg.critic_hidden)
+    for i, h in enumerate(cfg.critic_hidden):
+        c.critic_hidden[i] = h
+    c.discount = cfg.discount
+    c.entropy_coef = cfg.entropy_coef
+    return c
+
+
+class Critic:
+    """The Near-RT RIC critic pass (cyrus_critic_*): one actor with the Gaussian
+    head and four critics, FP32, in a caller-owned torch device workspace."""
+
+    def __init__(self, cfg, actor_w, q_w, qt_w, device: str = "cuda", stream=None):
+        import torch
+        self.cfg = cfg
+        self.device = torch.device(device)
+        self.cconf = make_critic_config(cfg)
+        d = ctypes.c_size_t()
+        _check(lib().cyrus_critic_workspace_size(ctypes.byref(self.cconf), ctypes.byref(d)),
+               "cyrus_critic_workspace_size")
+        self.ws = torch.empty(d.value, dtype=torch.uint8, device=self.device)
+        self._views = [_WeightsView(actor_w)] + [_WeightsView(w) for w in q_w] + [_WeightsView(w) for w in qt_w]
+        cw = cyrus_critic_weights()
+        cw.actor = self._views[0].struct
+        cw.q[0], cw.q[1] = self._views[1].struct, self._views[2].struct
+        cw.q_targ[0], cw.q_targ[1] = self._views[3].struct, self._views[4].struct
+        self._cw = cw
+        self.stream = stream
+        out = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib().cyrus_critic_create(ctypes.byref(self.cconf), ctypes.byref(cw), self.ws.data_ptr(), d.value,
+                                             _stream_ptr(stream), ctypes.byref(out)), "cyrus_critic_create")
+        self.handle = out.value
+        H, M = cfg.num_samples, cfg.num_minislots
+        self.q = torch.empty((2, H, M), dtype=torch.float32, device=self.device)
+        self.qhat = torch.empty((H, M), dtype=torch.float32, device=self.device)
+        self.loss = torch.empty(2, dtype=torch.float32, device=self.device)
+
+    def evaluate(self, batch, seed: int, episode: int):
+        """batch: device tensors (ue [H,3E] i32, k [H,M] i32, c [H,M,E] u8, y [H,M,E]
+        f32, r [H] f32). Returns the output tensors (q [2,H,M], qhat [H,M], loss [2]),
+        written asynchronously on the handle's stream."""
+        ue, k, c, y, r = batch
+        self._keep = batch
+        b = cyrus_critic_batch(ctypes.cast(ue.data_ptr(), _i32p), ctypes.cast(k.data_ptr(), _i32p),
+                               ctypes.cast(c.data_ptr(), _u8p), ctypes.cast(y.data_ptr(), _f32p),
+                               ctypes.cast(r.data_ptr(), _f32p))
+        _check(lib().cyrus_critic_evaluate(self.handle, ctypes.byref(b), int(seed) & 0xFFFFFFFFFFFFFFFF,
+                                           int(episode) & 0xFFFFFFFFFFFFFFFF, self.q.data_ptr(), self.qhat.data_ptr(),
+                                           self.loss.data_ptr(), _stream_ptr(self.stream)), "cyrus_critic_evaluate")
+        return self.q, self.qhat, self.loss
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().cyrus_critic_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def critic_batch_to_device(batch, device: str = "cuda"):
+    import torch
+    return tuple(torch.from_numpy(np.ascontiguousarray(a)).to(device) for a in batch)

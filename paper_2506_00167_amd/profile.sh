@@ -15,7 +15,7 @@ export PYTHONPATH=$ROOT
 export TMPDIR=/tmp
 cd /tmp || exit 1
 
-BENCH="python3 $ROOT/bench.py --steps 300 --warmup 30 --latency-builds 100 --no-cpu --legs fp32 --context-legs="
+BENCH="python3 $ROOT/bench.py --steps 300 --warmup 30 --latency-builds 100 --no-cpu --no-critic --legs fp32 --context-legs="
 BUILD="python3 -m paper_2506_00167_amd.profiling build --workload tree-e8k3 --precision fp32 --builds 50"
 STRESS="python3 -m paper_2506_00167_amd.profiling stress --iters 3"
 COPY="python3 -m paper_2506_00167_amd.profiling copy --mib 256 --reps 5"
