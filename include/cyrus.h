@@ -315,11 +315,21 @@ int cyrus_engine_create(void* device_pool, size_t device_bytes, void* host_pool,
 int cyrus_engine_submit(cyrus_engine* eng, cyrus_codebook* cell, const cyrus_ue_state* ue, int64_t* ticket);
 
 /* One engine iteration: retire requests whose codebook copy finished, admit
- * waiting requests that fit, then enqueue one batched level launch for all
- * running requests (and the host copies of the ones that reached level M).
- * Never blocks on the GPU except to reuse a descriptor slot still in flight.
- * Outputs (nullable): running and waiting request counts after the step. */
+ * waiting requests that fit, then enqueue batched level launches for all
+ * running requests, each launch advancing every running request by one level
+ * (and queueing the host copies of the ones that reached level M): one launch
+ * per step by default (iteration-level batching: requests join between
+ * levels), up to levels_per_step launches (see below). Never blocks on the GPU
+ * except to reuse a descriptor slot still in flight. Outputs (nullable):
+ * running and waiting request counts after the step. */
 int cyrus_engine_step(cyrus_engine* eng, int32_t* running, int32_t* waiting);
+
+/* Level launches per cyrus_engine_step, in [1, 7] (default 1). With 7, every
+ * request admitted in a step completes in that step's launches: one host step
+ * per request instead of one per level, so a request's latency is one step's
+ * GPU time plus its wait for the step, at the cost of new arrivals waiting for
+ * the next step. CYRUS_ERANGE outside [1, 7]. */
+int cyrus_engine_set_levels_per_step(cyrus_engine* eng, int32_t levels);
 
 /* Status of a ticket (CYRUS_REQ_*); *latency_us (nullable) receives, once
  * done, the time from submit to the step that observed completion. */

@@ -122,6 +122,7 @@ struct cyrus_engine {
     uint8_t* hpool = nullptr;
     Pool dfree, hfree;
     int max_active = 0;
+    int levels_per_step = 1;
     hipStream_t stream = nullptr;
     int device = 0;
     int prec = -1;
@@ -368,6 +369,16 @@ int cyrus_engine_submit(cyrus_engine* e, cyrus_codebook* cell, const cyrus_ue_st
     return CYRUS_OK;
 }
 
+int cyrus_engine_set_levels_per_step(cyrus_engine* e, int32_t levels)
+{
+    if (!e)
+        return set_error(CYRUS_EINVAL, "NULL engine");
+    if (levels < 1 || levels > 7)
+        return set_error(CYRUS_ERANGE, "levels per step outside [1, 7]");
+    e->levels_per_step = levels;
+    return CYRUS_OK;
+}
+
 int cyrus_engine_step(cyrus_engine* e, int32_t* running, int32_t* waiting)
 {
     if (!e)
@@ -377,7 +388,7 @@ int cyrus_engine_step(cyrus_engine* e, int32_t* running, int32_t* waiting)
     int rc = retire(e);
     if (rc == CYRUS_OK)
         rc = admit(e);
-    if (rc == CYRUS_OK)
+    for (int i = 0; rc == CYRUS_OK && i < e->levels_per_step && !e->running.empty(); ++i)
         rc = launch_step(e);
     if (running)
         *running = (int32_t)e->running.size();

@@ -37,7 +37,8 @@ SYMBOLS = (
     "cyrus_codebook_num_nodes", "cyrus_codebook_kernel_path", "cyrus_codebook_set_rng", "cyrus_codebook_destroy",
     "cyrus_status_string", "cyrus_last_error",
     "cyrus_critic_workspace_size", "cyrus_critic_create", "cyrus_critic_evaluate", "cyrus_critic_destroy",
-    "cyrus_engine_create", "cyrus_engine_submit", "cyrus_engine_step", "cyrus_engine_poll",
+    "cyrus_engine_create", "cyrus_engine_submit", "cyrus_engine_step", "cyrus_engine_set_levels_per_step",
+    "cyrus_engine_poll",
     "cyrus_engine_completed", "cyrus_engine_result", "cyrus_engine_stats", "cyrus_engine_destroy",
 )
 REQ_WAITING, REQ_RUNNING, REQ_DONE = 0, 1, 2
@@ -133,6 +134,7 @@ def lib():
         L.cyrus_engine_create.argtypes = [vp, sz, vp, sz, ctypes.c_int32, vp, ctypes.POINTER(vp)]
         L.cyrus_engine_submit.argtypes = [vp, vp, ctypes.POINTER(cyrus_ue_state), ctypes.POINTER(ctypes.c_int64)]
         L.cyrus_engine_step.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+        L.cyrus_engine_set_levels_per_step.argtypes = [vp, ctypes.c_int32]
         L.cyrus_engine_poll.argtypes = [vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32),
                                         ctypes.POINTER(ctypes.c_double)]
         L.cyrus_engine_completed.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
@@ -465,6 +467,10 @@ class Engine:
 
     def step(self):
         return cyrus_engine_step(self.handle)
+
+    def set_levels_per_step(self, levels: int):
+        _check(lib().cyrus_engine_set_levels_per_step(self.handle, int(levels)), "cyrus_engine_set_levels_per_step")
+        return self
 
     def poll(self, ticket: int):
         return cyrus_engine_poll(self.handle, ticket)

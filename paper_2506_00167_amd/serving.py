@@ -41,8 +41,9 @@ def make_requests(cells, n: int, seed: int = 7):
     return out
 
 
-def default_engine(max_active: int = 64, pool_mib: int = 256, stream=None):
-    return cyrus.Engine(pool_mib << 20, pool_mib << 20, max_active=max_active, stream=stream)
+def default_engine(max_active: int = 64, pool_mib: int = 256, stream=None, levels_per_step: int = 1):
+    eng = cyrus.Engine(pool_mib << 20, pool_mib << 20, max_active=max_active, stream=stream)
+    return eng.set_levels_per_step(levels_per_step)
 
 
 def run_stream(engine, cells, requests, arrivals_s, keep_results: bool = False):
@@ -110,29 +111,33 @@ def main():
     ap.add_argument("--loads", default="0.25,0.5,0.75,0.9")
     ap.add_argument("--max-active", type=int, default=64)
     ap.add_argument("--pool-mib", type=int, default=256)
+    ap.add_argument("--levels-per-step", default="1,7",
+                    help="comma separated: 1 = iteration-level batching, 7 = each step runs its requests to the end")
     args = ap.parse_args()
     import torch
     cyrus.lib()
     stream = torch.cuda.Stream()
     cells = make_cells(args.cells, stream=stream)
     torch.cuda.synchronize()
-    eng = default_engine(args.max_active, args.pool_mib, stream=stream)
-    warm = make_requests(cells, 200, seed=1)
-    saturation(eng, cells, warm)
-    reqs = make_requests(cells, args.requests, seed=2)
-    sat = saturation(eng, cells, reqs)
-    print(json.dumps({"mode": "saturation", **sat}), flush=True)
-    rate_sat = sat["served_req_per_s"]
-    for load in [float(x) for x in args.loads.split(",")]:
-        arr = wl.poisson_arrivals(load * rate_sat, args.requests, seed=424242)
-        arr = arr - arr[0]
-        res = run_stream(eng, cells, make_requests(cells, args.requests, seed=3), arr)
-        print(json.dumps({"mode": "poisson", "load": load, **res}), flush=True)
-    # one request per cell per slot (8000 slots/s per cell)
-    per_slot = 8000.0 * args.cells
-    print(json.dumps({"mode": "note", "one_request_per_cell_per_slot_req_per_s": per_slot,
-                      "ratio_to_saturation": per_slot / rate_sat}), flush=True)
-    eng.close()
+    for lps in [int(x) for x in args.levels_per_step.split(",")]:
+        eng = default_engine(args.max_active, args.pool_mib, stream=stream, levels_per_step=lps)
+        warm = make_requests(cells, 200, seed=1)
+        saturation(eng, cells, warm)
+        reqs = make_requests(cells, args.requests, seed=2)
+        sat = saturation(eng, cells, reqs)
+        print(json.dumps({"mode": "saturation", "levels_per_step": lps, **sat}), flush=True)
+        rate_sat = sat["served_req_per_s"]
+        for load in [float(x) for x in args.loads.split(",")]:
+            arr = wl.poisson_arrivals(load * rate_sat, args.requests, seed=424242)
+            arr = arr - arr[0]
+            res = run_stream(eng, cells, make_requests(cells, args.requests, seed=3), arr)
+            print(json.dumps({"mode": "poisson", "levels_per_step": lps, "load": load, **res}), flush=True)
+        # one request per cell per slot (8000 slots/s per cell)
+        per_slot = 8000.0 * args.cells
+        print(json.dumps({"mode": "note", "levels_per_step": lps,
+                          "one_request_per_cell_per_slot_req_per_s": per_slot,
+                          "ratio_to_saturation": per_slot / rate_sat}), flush=True)
+        eng.close()
 
 
 if __name__ == "__main__":

@@ -45,8 +45,9 @@ def _alone(engine, cell, ue):
             return engine.result(t)
 
 
-def test_mixed_equals_alone_and_single_build(cells):
-    eng = serving.default_engine(max_active=32, pool_mib=128)
+@pytest.mark.parametrize("levels_per_step", [1, 7])
+def test_mixed_equals_alone_and_single_build(cells, levels_per_step):
+    eng = serving.default_engine(max_active=32, pool_mib=128, levels_per_step=levels_per_step)
     reqs = serving.make_requests(cells, 40, seed=11)
     probe_idx = [3, 17, 29]
     alone = {i: _alone(eng, cells[reqs[i][0]], reqs[i][1]) for i in probe_idx}
