@@ -319,7 +319,10 @@ int cyrus_engine_submit(cyrus_engine* eng, cyrus_codebook* cell, const cyrus_ue_
  * running requests, each launch advancing every running request by one level
  * (and queueing the host copies of the ones that reached level M): one launch
  * per step by default (iteration-level batching: requests join between
- * levels), up to levels_per_step launches (see below). Never blocks on the GPU
+ * levels), up to levels_per_step launches (see below). Under light load (at
+ * most two new such requests in the step) a request whose cell takes the
+ * single-launch path (cyrus_codebook_kernel_path: "subtree") is built whole
+ * by one launch at its first step instead. Never blocks on the GPU
  * except to reuse a descriptor slot still in flight. Outputs (nullable):
  * running and waiting request counts after the step. */
 int cyrus_engine_step(cyrus_engine* eng, int32_t* running, int32_t* waiting);

@@ -95,7 +95,8 @@ class Pool {
     size_t align_ = 256, used_ = 0, peak_ = 0;
 };
 
-constexpr int kSlots = 4;  // descriptor slots (launches) in flight
+constexpr int kSlots = 4;      // descriptor slots (launches) in flight
+constexpr int kSingleMax = 2;  // new single-launch requests per step served one launch each
 
 struct Request {
     int64_t ticket;
@@ -222,56 +223,84 @@ int launch_step(cyrus_engine* e)
         if (err != hipSuccess)
             return hip_err(err, "hipEventSynchronize(slot)");
     }
-    const int n = (int)e->running.size();
-    DevTree trees[kMaxBatch];
-    for (int i = 0; i < n; ++i) {
-        Request* r = e->running[i];
+    auto tree_of = [&](const Request* r) {
         const Shape& s = codebook_shape(r->cell);
         const size_t tree = ((size_t)s.nodes * s.E + 255) / 256 * 256;
         uint8_t* dbase = e->dpool + r->dev_off;
-        trees[i] = make_devtree(r->cell, reinterpret_cast<const int32_t*>(dbase + 2 * tree));
-        trees[i].alloc = dbase;
-        trees[i].state = dbase + tree;
-        trees[i].logits = nullptr;
-        trees[i].seed = r->seed;
-        trees[i].tti = r->tti;
+        DevTree t = make_devtree(r->cell, reinterpret_cast<const int32_t*>(dbase + 2 * tree));
+        t.alloc = dbase;
+        t.state = dbase + tree;
+        t.logits = nullptr;
+        t.seed = r->seed;
+        t.tti = r->tti;
+        return t;
+    };
+    // Under light load, new requests on cells that take the single-launch
+    // path (the whole tree in one launch, one workgroup per subtree, all CUs)
+    // run it at their first step and are done in this step. Each such launch
+    // holds the whole GPU, so with more new arrivals than kSingleMax in one
+    // step they all join the batched level launch instead, which serves many
+    // requests for the price of one.
+    std::vector<Request*> lvl;
+    std::vector<bool> whole(e->running.size(), false);
+    int fresh = 0;
+    for (const Request* r : e->running)
+        fresh += (r->level == 1 && codebook_path(r->cell) == 1) ? 1 : 0;
+    const bool single = fresh <= kSingleMax;
+    for (size_t i = 0; i < e->running.size(); ++i) {
+        Request* r = e->running[i];
+        if (single && r->level == 1 && codebook_path(r->cell) == 1) {
+            const hipError_t err = launch_subtree(tree_of(r), e->prec, e->stream);
+            if (err != hipSuccess)
+                return hip_err(err, "single-launch build");
+            whole[i] = true;
+        } else {
+            lvl.push_back(r);
+        }
     }
-    int rtt = 0, buf = 0;
-    size_t lds = 0;
-    if (!plan_level_batch(trees, n, e->prec, &rtt, &buf, &lds))
-        return set_error(CYRUS_EUNSUPPORTED, "batch does not fit the level kernel's LDS");
-
-    uint8_t* h = e->hpool + e->slot_hoff[slot];
-    uint8_t* d = e->dpool + e->slot_doff[slot];
-    const size_t ent_off = (sizeof(DevTree) * kMaxBatch + 255) / 256 * 256;
-    std::memcpy(h, trees, sizeof(DevTree) * n);
-    int32_t* ent = reinterpret_cast<int32_t*>(h + ent_off);
-    int total = 0;
-    for (int i = 0; i < n; ++i) {
-        const Request* r = e->running[i];
-        const int64_t n_eval = trees[i].K * ipow(trees[i].K + 1, r->level - 1);
-        ent[i] = i;
-        ent[kMaxBatch + i] = r->level;
-        ent[2 * kMaxBatch + i] = total;
-        total += (int)((n_eval + 16 * rtt - 1) / (16 * rtt));
+    hipError_t err = hipSuccess;
+    if (!lvl.empty()) {
+        const int n = (int)lvl.size();
+        DevTree trees[kMaxBatch];
+        for (int i = 0; i < n; ++i)
+            trees[i] = tree_of(lvl[i]);
+        int rtt = 0, buf = 0;
+        size_t lds = 0;
+        if (!plan_level_batch(trees, n, e->prec, &rtt, &buf, &lds))
+            return set_error(CYRUS_EUNSUPPORTED, "batch does not fit the level kernel's LDS");
+        uint8_t* h = e->hpool + e->slot_hoff[slot];
+        uint8_t* d = e->dpool + e->slot_doff[slot];
+        const size_t ent_off = (sizeof(DevTree) * kMaxBatch + 255) / 256 * 256;
+        std::memcpy(h, trees, sizeof(DevTree) * n);
+        int32_t* ent = reinterpret_cast<int32_t*>(h + ent_off);
+        int total = 0;
+        for (int i = 0; i < n; ++i) {
+            const Request* r = lvl[i];
+            const int64_t n_eval = trees[i].K * ipow(trees[i].K + 1, r->level - 1);
+            ent[i] = i;
+            ent[kMaxBatch + i] = r->level;
+            ent[2 * kMaxBatch + i] = total;
+            total += (int)((n_eval + 16 * rtt - 1) / (16 * rtt));
+        }
+        ent[2 * kMaxBatch + n] = total;
+        err = hipMemcpyAsync(d, h, sizeof(DevTree) * n, hipMemcpyHostToDevice, e->stream);
+        if (err == hipSuccess)
+            err = hipMemcpyAsync(d + ent_off, h + ent_off, (size_t)(3 * kMaxBatch + 1) * 4, hipMemcpyHostToDevice,
+                                 e->stream);
+        if (err != hipSuccess)
+            return hip_err(err, "descriptor copy");
+        const int32_t* dent = reinterpret_cast<const int32_t*>(d + ent_off);
+        err = launch_level_batch(reinterpret_cast<const DevTree*>(d), dent, dent + kMaxBatch, dent + 2 * kMaxBatch, n,
+                                 total, e->prec, rtt, buf, lds, e->stream);
+        if (err != hipSuccess)
+            return hip_err(err, "batched level launch");
     }
-    ent[2 * kMaxBatch + n] = total;
-    hipError_t err = hipMemcpyAsync(d, h, sizeof(DevTree) * n, hipMemcpyHostToDevice, e->stream);
-    if (err == hipSuccess)
-        err = hipMemcpyAsync(d + ent_off, h + ent_off, (size_t)(3 * kMaxBatch + 1) * 4, hipMemcpyHostToDevice,
-                             e->stream);
-    if (err != hipSuccess)
-        return hip_err(err, "descriptor copy");
-    const int32_t* dent = reinterpret_cast<const int32_t*>(d + ent_off);
-    err = launch_level_batch(reinterpret_cast<const DevTree*>(d), dent, dent + kMaxBatch, dent + 2 * kMaxBatch, n,
-                             total, e->prec, rtt, buf, lds, e->stream);
-    if (err != hipSuccess)
-        return hip_err(err, "batched level launch");
     // requests that reached their last level: codebook to the host pool
     std::vector<Request*> still;
-    for (Request* r : e->running) {
+    for (size_t i = 0; i < e->running.size(); ++i) {
+        Request* r = e->running[i];
         const Shape& s = codebook_shape(r->cell);
-        if (r->level == s.M) {
+        if (whole[i] || r->level == s.M) {
             err = hipMemcpyAsync(e->hpool + r->host_off, e->dpool + r->dev_off, (size_t)s.nodes * s.E,
                                  hipMemcpyDeviceToHost, e->stream);
             if (err != hipSuccess)

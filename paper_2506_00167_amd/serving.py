@@ -27,7 +27,7 @@ SLOT_US = 125.0
 def make_cells(num_cells: int = 64, seed: int = 424242, device: str = "cuda", stream=None):
     cells = []
     for cfg, wseed in wl.serving_cell_configs(num_cells, seed):
-        cells.append(cyrus.Codebook(cfg, wl.make_weights(cfg, wseed), force_level=True, device=device,
+        cells.append(cyrus.Codebook(cfg, wl.make_weights(cfg, wseed), device=device,
                                     stream=stream))
     return cells
 
