@@ -177,6 +177,10 @@ __device__ __forceinline__ float gaussian_log_share(float mu, float log_sigma, u
     return u >= 0.f ? -log1pf(expf(-2.f * u)) : 2.f * u - log1pf(expf(2.f * u));
 }
 
+// Index of the calling wave in its workgroup, as a wave-uniform (scalar)
+// value, so that offsets derived from it live in SGPRs.
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
+
 // Workgroup barrier that orders LDS only: waits for this wave's LDS operations
 // (lgkmcnt = 0) and meets the other waves, but leaves global loads and stores in
 // flight (vmcnt and expcnt at their maximum in the gfx9 s_waitcnt encoding).

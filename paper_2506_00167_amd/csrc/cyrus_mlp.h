@@ -21,7 +21,7 @@ __device__ __forceinline__ void hidden_layer(const DevTree& t, int l, const uint
                                              const float* bias_l, int art)
 {
     constexpr int kc = Traits<P>::kChunk, es = Traits<P>::kEsize;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, c16 = lane & 15;
+    const int lane = threadIdx.x & 63, wave = wave_id(), g = lane >> 4, c16 = lane & 15;
     const int nch = t.in_pad[l] / kc;
     const int sin = t.in_pad[l] * es + 16;
     const int sout = t.out_pad[l] * es + 16;
@@ -120,7 +120,7 @@ __device__ __forceinline__ void run_mlp(const DevTree& t, int nrows, uint8_t* bu
                                         const float* bias, int64_t off, int row0)
 {
     constexpr int kc = Traits<P>::kChunk, es = Traits<P>::kEsize, RT = 16 * RTT;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, c16 = lane & 15;
+    const int lane = threadIdx.x & 63, wave = wave_id(), g = lane >> 4, c16 = lane & 15;
     const int art = (nrows + 15) >> 4;
     uint8_t* in = bufA;
     uint8_t* out = bufB;

@@ -209,7 +209,7 @@ __device__ __forceinline__ float* mlp_regs(const DevTree& t, const WaveWeights<P
 {
     using WW = WaveWeights<P, T, CH1, CHH, NHH>;
     constexpr int kc = Traits<P>::kChunk, es = Traits<P>::kEsize, kRTT = Rows<P>::kRTT, kRT = Rows<P>::kRT;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, c16 = lane & 15;
+    const int lane = threadIdx.x & 63, wave = wave_id(), g = lane >> 4, c16 = lane & 15;
     const int art = (nrows + 15) >> 4;
     const int s0 = t.in_pad[0] * es + 16, sh = CHH * kc * es + 16;
     const int nch1 = t.in_pad[0] / kc;
@@ -410,7 +410,7 @@ __device__ __forceinline__ void subtree_body(const DevTree& t, int split, int bu
     sm.st0 = reinterpret_cast<uint8_t*>(sm.bias + nbias);
     sm.st1 = sm.st0 + stbytes;
 
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wave = wave_id();
     const int E = t.E, K = t.K, M = t.M, K1 = K + 1;
     const int r = blockIdx.x;
 
