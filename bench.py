@@ -226,7 +226,7 @@ def main():
     ap.add_argument("--no-critic", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only: the codebook build of one cell fits one MI355X and this build has "
+        print(f"bench.py runs on one GPU only: the codebook build of one cell fits one MI355X and the library has "
               f"no multi-GPU path (asked for --gpus {args.gpus})", file=sys.stderr)
         sys.exit(2)
     import torch

@@ -3,13 +3,13 @@
 # kernel trace + stats of bench.py (the FP32 subtree kernel, C2) and of the
 # 32-cell FP8 stress batch (level kernel), then one counter per run
 # (FETCH_SIZE, WRITE_SIZE) on single-codebook builds and on a plain copy of
-# known size that calibrates the counters. Summaries go to OUT (default
-# gpurun_out/prof under the repository root).
+# known size that calibrates the counters. Summaries and raw output go to OUT
+# (default prof_out under the repository root).
 #
 #   bash paper_2506_00167_amd/profile.sh [OUT]
 set -o pipefail
 ROOT=$(cd "$(dirname "$0")/.." && pwd)
-OUT=${1:-$ROOT/gpurun_out/prof}
+OUT=${1:-$ROOT/prof_out}
 mkdir -p "$OUT"
 export PYTHONPATH=$ROOT
 export TMPDIR=/tmp

@@ -7,9 +7,9 @@ within a tolerance derived from FP32 accumulation plus the occasional
 activation that rounds to the neighbouring format value, and every
 conditioned-mode disagreement explained by the measured logit error.
 
-Report (BJ's measure): max logit error and allocation-disagreement rate of
-each variant against the exact FP64 oracle, written to
-gpurun_out/precision_report.json.
+Report: max logit error and allocation-disagreement rate of each variant
+against the exact FP64 oracle, written to precision_report.json in the
+directory named by CYRUS_REPORT_DIR (default: reports/ under the repository).
 """
 import json
 import os
@@ -24,6 +24,7 @@ from tests import parity
 pytestmark = pytest.mark.gpu
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+REPORT_DIR = os.environ.get("CYRUS_REPORT_DIR", os.path.join(ROOT, "reports"))
 SCALES = json.load(open(os.path.join(ROOT, "tests", "golden", "fp8_act_scales.json")))
 
 # Logit tolerance against the same-precision oracle: FP32 accumulation error
@@ -63,8 +64,8 @@ def test_tree_e8k3_reduced_precision(prec, force_level):
     print(f"[{prec} {path}] vs FP64 oracle: {exact.as_dict()}", flush=True)
     REPORT[f"tree-e8k3/{prec}/{path}"] = {"vs_same_precision_oracle": same.as_dict(),
                                           "vs_fp64_oracle": exact.as_dict()}
-    os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
-    with open(os.path.join(ROOT, "gpurun_out", "precision_report.json"), "w") as f:
+    os.makedirs(REPORT_DIR, exist_ok=True)
+    with open(os.path.join(REPORT_DIR, "precision_report.json"), "w") as f:
         json.dump(REPORT, f, indent=1)
 
 
@@ -77,7 +78,7 @@ def test_fp32_report_vs_fp64():
         rep = parity.compare(cfg, weights, ue, alloc, logits, logit_tol=1e-4)
         assert rep.cond_unexplained == 0 and rep.free_unexplained == 0
         REPORT[f"tree-e8k3/fp32/{path}"] = {"vs_fp64_oracle": rep.as_dict()}
-    with open(os.path.join(ROOT, "gpurun_out", "precision_report.json"), "w") as f:
+    with open(os.path.join(REPORT_DIR, "precision_report.json"), "w") as f:
         json.dump(REPORT, f, indent=1)
 
 
