@@ -135,7 +135,9 @@ def run_leg(precision: str, steps: int, warmup: int, latency_builds: int, stream
     path = cb.kernel_path
     cb.close()
 
-    flops = cfg.flops_per_codebook
+    # the subtree kernel multiplies the static inputs once per launch; the
+    # level kernel multiplies the full input row of every node
+    flops = cfg.flops_per_codebook_folded if path == "subtree" else cfg.flops_per_codebook
     achieved = flops / (avg_us * 1e-6) / 1e12
     return {
         "workload": workload,

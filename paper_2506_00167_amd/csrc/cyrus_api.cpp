@@ -106,6 +106,10 @@ Shape make_shape(const cyrus_config* cfg)
         s.w_bytes += align_up((size_t)s.in_pad[l] * s.out_pad[l] * prec_esize(s.prec), 256);
         s.staging_floats = std::max(s.staging_floats, (size_t)s.in_pad[l] * s.out_pad[l]);
     }
+    s.in_pad_d = (int)align_up(s.E + 2, s.prec == kFP8 ? 2 * kc : kc);
+    s.w1d_off = s.w_bytes;
+    s.w_bytes += align_up((size_t)s.in_pad_d * s.out_pad[0] * prec_esize(s.prec), 256);
+    s.staging_floats = std::max(s.staging_floats, (size_t)s.in_pad_d * s.out_pad[0]);
     for (int l = 0; l < s.n_layers; ++l) {
         s.b_off[l] = s.w_bytes;
         s.w_bytes += align_up((size_t)s.out_pad[l] * 4, 256);
@@ -219,6 +223,8 @@ DevTree make_devtree(const cyrus_codebook* cb, const int32_t* ue_dev)
         t.deq[l] = cb->deq[l];
         t.inv_in_scale[l] = cb->inv_in[l];
     }
+    t.in_pad_d = s.in_pad_d;
+    t.w1d = wb + s.w1d_off;
     t.ue = ue_dev;
     t.alloc = cb->ws + s.off_alloc;
     t.state = cb->ws + s.off_state;
@@ -274,6 +280,20 @@ static int load_weights(cyrus_codebook* cb, const cyrus_weights* w, hipStream_t 
         std::memcpy(bias.data(), w->b[l], sizeof(float) * s.dims[l + 1]);
         HIP_TRY(hipMemcpyAsync(wb + s.b_off[l], bias.data(), bias.size() * 4, hipMemcpyHostToDevice, stream));
         // the host staging vectors are reused by the next layer
+        HIP_TRY(hipStreamSynchronize(stream));
+    }
+    {
+        // the per-node columns of layer 1 (c, tau, k: the last E + 2), packed
+        // on their own with the layer's weight scale
+        const int nd = s.E + 2, in0 = s.dims[0], h1 = s.dims[1];
+        std::vector<float> wd((size_t)h1 * nd);
+        for (int n = 0; n < h1; ++n)
+            for (int j = 0; j < nd; ++j)
+                wd[(size_t)n * nd + j] = w->w[0][(size_t)n * in0 + 3 * s.E + j];
+        const size_t n = (size_t)s.in_pad_d * s.out_pad[0];
+        pack_fragments(wd.data(), h1, nd, s.out_pad[0], s.in_pad_d, s.prec, cb->pack.data());
+        HIP_TRY(hipMemcpyAsync(staging, cb->pack.data(), n * 4, hipMemcpyHostToDevice, stream));
+        HIP_TRY(launch_convert_weights(s.prec, staging, wb + s.w1d_off, (int64_t)n, 1.f / w_scale[0], stream));
         HIP_TRY(hipStreamSynchronize(stream));
     }
     for (int l = 0; l < s.n_layers; ++l) {

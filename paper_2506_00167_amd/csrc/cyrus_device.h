@@ -293,6 +293,42 @@ __device__ __forceinline__ void store1<kFP8>(uint8_t* dst, float v, float inv_sc
     *dst = (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(v, 0.f, 0, false) & 0xff);
 }
 
+// The value store1<P> would store for v, as a float: what an MFMA of
+// precision P reads for that input.
+template <int P>
+__device__ __forceinline__ float stored_value(float v, float inv_scale);
+template <>
+__device__ __forceinline__ float stored_value<kFP32>(float v, float)
+{
+    return v;
+}
+template <>
+__device__ __forceinline__ float stored_value<kBF16>(float v, float)
+{
+    return __uint_as_float(bf16_bits(v) << 16);
+}
+template <>
+__device__ __forceinline__ float stored_value<kFP8>(float v, float inv_scale)
+{
+    v = fminf(fmaxf(v * inv_scale, -448.f), 448.f);
+    return __builtin_amdgcn_cvt_f32_fp8(__builtin_amdgcn_cvt_pk_fp8_f32(v, 0.f, 0, false), 0);
+}
+
+// Element j (0 <= j < 16 / esize) of a 16-byte fragment of precision P, as a
+// float (exact: every storage type widens to FP32 without rounding). j is a
+// constant once the caller's loop is unrolled.
+template <int P>
+__device__ __forceinline__ float frag_value(const uint4& f, int j)
+{
+    const uint32_t w[4] = {f.x, f.y, f.z, f.w};
+    if constexpr (P == kFP32)
+        return __uint_as_float(w[j]);
+    else if constexpr (P == kBF16)
+        return __uint_as_float((j & 1) ? (w[j / 2] & 0xffff0000u) : (w[j / 2] << 16));
+    else
+        return __builtin_amdgcn_cvt_f32_fp8((int)(w[j / 4] >> (8 * (j % 4))), 0);
+}
+
 // ---------------------------------------------------------------------------
 // Lane-parallel enforcer: a group of G lanes (G a power of two >= E, G <= 64)
 // handles one node, lane e of the group UE e. Softmax, the capped split and

@@ -23,6 +23,8 @@ struct Shape {
     int dims[kMaxLayers + 1];
     int in_pad[kMaxLayers], out_pad[kMaxLayers];
     size_t w_off[kMaxLayers], b_off[kMaxLayers];
+    int in_pad_d;            // per-node inputs of layer 1 (E + 2), padded
+    size_t w1d_off;          // their fragments, within one weight buffer
     size_t w_bytes;          // one weight buffer (packed weights + biases)
     size_t staging_floats;   // FP32 staging for the largest layer
     int64_t nodes;

@@ -30,6 +30,11 @@ struct DevTree {
     int32_t in_pad[kMaxLayers];       // layer input width padded to the k-chunk
     int32_t out_pad[kMaxLayers];      // layer output width padded to 16
     const uint8_t* w[kMaxLayers];     // packed weight fragments
+    // Layer 1 split by input: the first 3E inputs (R, MCS, SINR) are the same
+    // for every node of a tree, the last E + 2 (c, tau, k) are the node's own.
+    // w1d holds the fragments of the per-node columns only, in_pad_d wide.
+    int32_t in_pad_d;
+    const uint8_t* w1d;
     const float* b[kMaxLayers];       // biases, out_pad entries (zero padded)
     float deq[kMaxLayers];            // FP8: weight scale * input scale; else 1
     float inv_in_scale[kMaxLayers];   // FP8: 1 / input scale of layer l; else 1

@@ -12,7 +12,10 @@
 // Every wave loads its share of the actor into registers once (the MFMA A
 // fragments of its output-neuron tiles, plus its slice of the output layer's
 // reduction dimension); afterwards each level step only moves node
-// activations through LDS. Waves meet at LDS-only barriers: the kernel never
+// activations through LDS. The first 3E inputs (R, MCS, SINR) are the same for
+// every node of the tree, so their part of the first layer is computed once
+// per launch and folded into that layer's bias; node rows then carry only
+// their E + 2 own inputs (c, tau, k). Waves meet at LDS-only barriers: the kernel never
 // reads back what it writes to global memory, so codebook stores (to HBM or,
 // for host builds, to pinned host memory) stay in flight across steps.
 #include "cyrus_device.h"
@@ -49,7 +52,7 @@ __device__ __forceinline__ int ipow_dev(int b, int e)
 
 // Register-resident fragments of one wave.
 //   T     output-neuron tiles of 16 per hidden layer owned by this wave
-//   CH1   chunks of the first layer's (padded) input, upper bound
+//   CH1   chunks of the first layer's per-node input (in_pad_d / chunk)
 //   CHH   chunks of a hidden layer's input (H / chunk)
 //   NHH   hidden->hidden layers (0 or 1)
 template <int P, int T, int CH1, int CHH, int NHH>
@@ -65,15 +68,13 @@ __device__ __forceinline__ void load_weights(const DevTree& t, WaveWeights<P, T,
                                              int lane)
 {
     using WW = WaveWeights<P, T, CH1, CHH, NHH>;
-    constexpr int kc = Traits<P>::kChunk;
-    const int nch1 = t.in_pad[0] / kc;
-    const uint4* g1 = reinterpret_cast<const uint4*>(t.w[0]);
+    const uint4* g1 = reinterpret_cast<const uint4*>(t.w1d);
 #pragma unroll
     for (int tt = 0; tt < T; ++tt) {
         const int nt = wave + kWaves * tt;
 #pragma unroll
         for (int c = 0; c < CH1; ++c)
-            W.w1[tt][c] = (c < nch1) ? g1[((size_t)nt * nch1 + c) * 64 + lane] : uint4{0, 0, 0, 0};
+            W.w1[tt][c] = g1[((size_t)nt * CH1 + c) * 64 + lane];
     }
     if constexpr (NHH > 0) {
         const uint4* gh = reinterpret_cast<const uint4*>(t.w[1]);
@@ -211,8 +212,8 @@ __device__ __forceinline__ float* mlp_regs(const DevTree& t, const WaveWeights<P
     constexpr int kc = Traits<P>::kChunk, es = Traits<P>::kEsize, kRTT = Rows<P>::kRTT, kRT = Rows<P>::kRT;
     const int lane = threadIdx.x & 63, wave = wave_id(), g = lane >> 4, c16 = lane & 15;
     const int art = (nrows + 15) >> 4;
-    const int s0 = t.in_pad[0] * es + 16, sh = CHH * kc * es + 16;
-    const int nch1 = t.in_pad[0] / kc;
+    const int s0 = CH1 * kc * es + 16, sh = CHH * kc * es + 16;
+    constexpr int nch1 = CH1;
     const bool valu = (P == kFP32) && nrows <= 4;
     if constexpr (P == kFP32) {
         if (valu)
@@ -299,34 +300,37 @@ struct SubtreeSmem {
     uint8_t* st1;   // states of the current level
 };
 
-// Feature rows for `nrows` nodes: state from state_of(row), level tau,
-// arrival arrival_of(row). Eight rows per pass, 64 threads per row.
-template <int P, class StateOf, class ArrivalOf>
+// Per-node input rows for `nrows` nodes: [c/64 | tau/8 | k/8], zero padded
+// to in_pad_d, with state c from state_of(row), level tau and arrival
+// arrival_of(row). One thread per input (at most 64 per row).
+template <int P, int CH1, class StateOf, class ArrivalOf>
 __device__ __forceinline__ void write_features(const DevTree& t, const SubtreeSmem& sm, int nrows, int tau,
                                                StateOf state_of, ArrivalOf arrival_of)
 {
-    constexpr int es = Traits<P>::kEsize;
-    const int E = t.E, in0 = t.in_pad[0], d_in = t.in_dim0, s0 = in0 * es + 16;
+    constexpr int es = Traits<P>::kEsize, in0 = CH1 * Traits<P>::kChunk, s0 = in0 * es + 16;
+    constexpr int tpr = in0 < 64 ? in0 : 64;  // threads per row
+    const int E = t.E;
     // MFMA passes read whole 16-row tiles: rows past nrows are zeroed so they
     // stay finite (each output row depends on its own input row only); the
     // FP32 VALU path for a few rows reads nothing past nrows
     const int nrows_pad = (P == kFP32 && nrows <= 4) ? nrows : ((nrows + 15) >> 4) << 4;
     const float inv0 = t.inv_in_scale[0], ftau = (float)tau * (1.f / 8.f);
-    const int f0 = threadIdx.x & 63;
-    for (int row = threadIdx.x >> 6; row < nrows_pad; row += kThreads / 64) {
+    const int f0 = threadIdx.x % tpr;
+    for (int row = threadIdx.x / tpr; row < nrows_pad; row += kThreads / tpr) {
         const bool live = row < nrows;
         const uint8_t* st = live ? state_of(row) : nullptr;
         const float fk = live ? (float)arrival_of(row) * (1.f / 8.f) : 0.f;
         uint8_t* dst = sm.bufA + row * s0;
-        for (int f = f0; f < in0; f += 64) {
+#pragma unroll
+        for (int f = f0; f < in0; f += tpr) {
             float v = 0.f;
-            if (live && f < d_in) {
-                if (f < 3 * E)
-                    v = sm.statf[f];
-                else if (f < 4 * E)
-                    v = (float)st[f - 3 * E] * (1.f / 64.f);
-                else
-                    v = (f == 4 * E) ? ftau : fk;
+            if (live) {
+                if (f < E)
+                    v = (float)st[f] * (1.f / 64.f);
+                else if (f == E)
+                    v = ftau;
+                else if (f == E + 1)
+                    v = fk;
             }
             store1<P>(dst + f * es, v, inv0);
         }
@@ -414,38 +418,90 @@ __device__ __forceinline__ void subtree_body(const DevTree& t, int split, int bu
     const int E = t.E, K = t.K, M = t.M, K1 = K + 1;
     const int r = blockIdx.x;
 
+    // Global loads, issued in the order they are consumed and the register-
+    // resident weights last, so that the set-up below waits for nothing
+    // behind it: the UE state, every layer's bias (tid < out_pad), and the
+    // static-input fragments of neuron tid of the first layer.
+    constexpr int NL = NHH + 2;                                   // layers
+    constexpr int kc = Traits<P>::kChunk, per = kc / 4;           // inputs per 16-byte fragment
+    constexpr int NQ = 3 * 16 / per;                              // static fragments per neuron, E <= 16
+    const int tid = threadIdx.x, n_stat = 3 * E;
+    int32_t ue_rb = 0, ue_mcs = 0, ue_sinr = 0;
+    if (tid < E) {
+        ue_rb = t.ue[tid];
+        ue_mcs = t.ue[E + tid];
+        ue_sinr = t.ue[2 * E + tid];
+    }
+    float bl[NL];
+#pragma unroll
+    for (int l = 0; l < NL; ++l)
+        bl[l] = tid < t.out_pad[l] ? t.b[l][tid] : 0.f;
+    // inputs q*per .. q*per + per - 1 of neuron n sit in chunk q / 4, lane
+    // 16 * (q % 4) + n % 16 of n's tile in the full-width layout
+    uint4 sw[NQ];
+    {
+        const int nch = t.in_pad[0] / kc;
+        const uint4* g = reinterpret_cast<const uint4*>(t.w[0]);
+        const bool mine = tid < t.out_pad[0];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+            sw[q] = (mine && q * per < n_stat) ? g[((size_t)(tid >> 4) * nch + q / 4) * 64 + 16 * (q % 4) + (tid & 15)]
+                                               : uint4{0, 0, 0, 0};
+    }
     WaveWeights<P, T, CH1, CHH, NHH> W;
     load_weights(t, W, wave, lane);
 
-    if (threadIdx.x < E) {
-        const int e = threadIdx.x;
-        sm.R[e] = t.ue[e];
-        sm.statf[e] = (float)t.ue[e] * (1.f / 32.f);
-        sm.statf[E + e] = (float)t.ue[E + e] * (1.f / 32.f);
-        sm.statf[2 * E + e] = __int_as_float(t.ue[2 * E + e]) * (1.f / 32.f);
-        sm.st0[e] = 0;  // root state
+    if (tid < E) {
+        sm.R[tid] = ue_rb;
+        sm.statf[tid] = (float)ue_rb * (1.f / 32.f);
+        sm.statf[E + tid] = (float)ue_mcs * (1.f / 32.f);
+        sm.statf[2 * E + tid] = __int_as_float(ue_sinr) * (1.f / 32.f);
+        sm.st0[tid] = 0;  // root state
     }
-    if (threadIdx.x == 0) {
-        int off = 0;
-        for (int l = 0; l < t.n_layers; ++l) {
-            sm.misc[1 + l] = off;
-            off += t.out_pad[l];
+    if (wave == 0) {
+        // total RBs (E <= 16: lanes 0..15) and the bias offsets
+        int v = lane < E ? ue_rb : 0;
+        v += __shfl_xor(v, 1);
+        v += __shfl_xor(v, 2);
+        v += __shfl_xor(v, 4);
+        v += __shfl_xor(v, 8);
+        if (lane == 0) {
+            sm.misc[0] = v;
+            int off = 0;
+#pragma unroll
+            for (int l = 0; l < NL; ++l) {
+                sm.misc[1 + l] = off;
+                off += t.out_pad[l];
+            }
         }
     }
     {
-        int off = 0;
-        for (int l = 0; l < t.n_layers; ++l) {
-            for (int i = threadIdx.x; i < t.out_pad[l]; i += kThreads)
-                sm.bias[off + i] = t.b[l][i];
+        int off = t.out_pad[0];
+#pragma unroll
+        for (int l = 1; l < NL; ++l) {
+            if (tid < t.out_pad[l])
+                sm.bias[off + tid] = bl[l];
             off += t.out_pad[l];
         }
     }
     lds_barrier();
-    if (threadIdx.x == 0) {
-        int s = 0;
-        for (int e = 0; e < E; ++e)
-            s += sm.R[e];
-        sm.misc[0] = s;
+    // first-layer bias with the static inputs folded in, from the values the
+    // MFMA would read: the stored weights and the inputs in the storage type
+    if (tid < t.out_pad[0]) {
+        const float inv0 = t.inv_in_scale[0];
+        float acc = 0.f;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            if (q * per < n_stat) {
+#pragma unroll
+                for (int j = 0; j < per; ++j) {
+                    const int f = q * per + j;
+                    if (f < n_stat)
+                        acc = fmaf(frag_value<P>(sw[q], j), stored_value<P>(sm.statf[f], inv0), acc);
+                }
+            }
+        }
+        sm.bias[tid] = bl[0] + t.deq[0] * acc;
     }
     lds_barrier();
     const int* bias_off = sm.misc + 1;
@@ -462,7 +518,7 @@ __device__ __forceinline__ void subtree_body(const DevTree& t, int split, int bu
         const int64_t node = sub_level_offset(K, tau) + idx;
         const bool owner = (r % below) == 0;
         if (k > 0) {
-            write_features<P>(t, sm, 1, tau, [&](int) { return sm.st0; }, [&](int) { return k; });
+            write_features<P, CH1>(t, sm, 1, tau, [&](int) { return sm.st0; }, [&](int) { return k; });
             lds_barrier();
             const float* part = mlp_regs<P, T, CH1, CHH, NHH>(t, W, 1, sm.bufA, sm.bufB, sm.bias, bias_off);
             finish_rows<G, kRT, EXT>(
@@ -495,7 +551,7 @@ __device__ __forceinline__ void subtree_body(const DevTree& t, int split, int bu
             // row j of the level: parent p = j / K, arrival k = j % K + 1
             auto parent_of = [&](int row) { return (int)(((float)(j0 + row) + 0.5f) * invK); };
             auto k_of = [&](int row) { return j0 + row - parent_of(row) * K + 1; };
-            write_features<P>(
+            write_features<P, CH1>(
                 t, sm, nrows, tau, [&](int row) { return prev + parent_of(row) * E; }, k_of);
             lds_barrier();
             const float* part = mlp_regs<P, T, CH1, CHH, NHH>(t, W, nrows, sm.bufA, sm.bufB, sm.bias, bias_off);
@@ -562,8 +618,11 @@ bool plan_subtree(const DevTree& t, int prec, SubtreePlan& pl)
     if (t.n_layers == 3 && t.out_pad[1] != H)
         return false;
     const int kc = prec_chunk(prec), es = prec_esize(prec);
-    const int ch1_max = prec == kFP32 ? 5 : (prec == kBF16 ? 3 : 2);
-    if (t.in_pad[0] / kc > ch1_max)
+    // per-node first-layer inputs: one chunk (BF16; FP32 with E <= 14), two
+    // (FP32 with E > 14) or one chunk pair (FP8)
+    const int nch1 = t.in_pad_d / kc;
+    if (!t.w1d || t.in_pad_d % kc != 0 || nch1 < 1 || nch1 > (prec == kFP32 ? 2 : (prec == kBF16 ? 1 : 2)) ||
+        (prec == kFP8 && nch1 != 2))
         return false;
     const int ncu = num_cus();
     int split = 0;
@@ -576,7 +635,7 @@ bool plan_subtree(const DevTree& t, int prec, SubtreePlan& pl)
     // the biggest subtree level must not serialise too many passes
     if (t.K * ipow(t.K + 1, t.M - split - 1) > 8 * kRTmax)
         return false;
-    size_t stride = (size_t)t.in_pad[0] * es + 16;
+    size_t stride = (size_t)t.in_pad_d * es + 16;
     stride = std::max(stride, (size_t)H * es + 16);
     size_t buf = std::max(stride * kRTmax, (size_t)kWaves * kRTmax * 16 * 4);
     buf = (buf + 15) & ~(size_t)15;
@@ -636,14 +695,13 @@ hipError_t launch_subtree(const DevTree& t, int prec, hipStream_t s)
     SubtreePlan pl;
     if (!plan_subtree(t, prec, pl))
         return hipErrorInvalidValue;
-    const int nch1 = t.in_pad[0] / prec_chunk(prec);
-    // register arrays are sized by the first layer's chunk count (rounded up)
+    // register arrays are sized by the exact chunk count of the per-node inputs
+    const int nch1 = t.in_pad_d / prec_chunk(prec);
     if (prec == kFP32)
-        return nch1 <= 2 ? dispatch_width<kFP32, 2>(t, pl, s)
-                         : (nch1 <= 3 ? dispatch_width<kFP32, 3>(t, pl, s) : dispatch_width<kFP32, 5>(t, pl, s));
+        return nch1 == 1 ? dispatch_width<kFP32, 1>(t, pl, s) : dispatch_width<kFP32, 2>(t, pl, s);
     if (prec == kBF16)
-        return nch1 <= 2 ? dispatch_width<kBF16, 2>(t, pl, s) : dispatch_width<kBF16, 3>(t, pl, s);
-    return nch1 <= 1 ? dispatch_width<kFP8, 1>(t, pl, s) : dispatch_width<kFP8, 2>(t, pl, s);
+        return dispatch_width<kBF16, 1>(t, pl, s);
+    return dispatch_width<kFP8, 2>(t, pl, s);
 }
 
 }  // namespace cyrus

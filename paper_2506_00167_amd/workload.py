@@ -76,6 +76,16 @@ class TreeConfig:
     def flops_per_codebook(self) -> int:
         return 2 * self.macs_per_eval * self.num_evals
 
+    @property
+    def flops_per_codebook_folded(self) -> int:
+        """FLOPs when the first layer's static inputs (R, MCS, SINR: 3E of them,
+        the same at every node) are multiplied once per codebook and each
+        evaluation multiplies only its own E + 2 inputs (c, tau, k)."""
+        d = self.dims
+        static = 3 * self.num_ue
+        per_eval = (d[0] - static) * d[1] + sum(d[i] * d[i + 1] for i in range(1, len(d) - 1))
+        return 2 * (per_eval * self.num_evals + static * d[1])
+
     def with_precision(self, precision: str) -> "TreeConfig":
         return dataclasses.replace(self, precision=precision)
 
