@@ -531,6 +531,20 @@ __device__ __forceinline__ int disum(int v)
     return v;
 }
 
+// Sum over the four 16-lane rows of a wave, column by column: lane i ends
+// with (v[c] + v[c + 16]) + (v[c + 32] + v[c + 48]), c = i % 16, the same value
+// in all four rows. gfx950's row swaps (v_permlane16_swap, v_permlane32_swap)
+// exchange rows on the vector ALU, without a round trip through LDS: a
+// 16-swap of v with itself leaves rows (0, 1) and (2, 3) with each other's
+// values in its two results, a 32-swap likewise rows (0, 1) and (2, 3).
+__device__ __forceinline__ float row_sum4(float v)
+{
+    const auto a = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    const float s = __uint_as_float(a[0]) + __uint_as_float(a[1]);
+    const auto b = __builtin_amdgcn_permlane32_swap(__float_as_uint(s), __float_as_uint(s), false, false);
+    return __uint_as_float(b[0]) + __uint_as_float(b[1]);
+}
+
 // Same enforcer as enforce_group for groups of 8 or 16 lanes aligned to
 // 8/16-lane boundaries, with DPP reductions; the remainder ranks go through
 // `rank_row` (G floats of LDS private to this group).

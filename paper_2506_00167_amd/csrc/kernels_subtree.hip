@@ -161,129 +161,178 @@ __device__ __forceinline__ void layer_regs(const uint4 (&A)[T][NCH], int nch, co
 
 // FP32, few rows: the same register-resident fragments used as a GEMV on
 // the vector ALU. Lane (g, i) holds W[n0 + i][16c + 4g + j]; it multiplies its
-// four weights of every chunk with the matching inputs (an LDS broadcast),
-// and the four lane groups are summed with two butterfly steps, so each lane
-// ends with the whole dot product of neuron n0 + i. `relu` selects the hidden
-// epilogue; the output layer leaves per-wave partial sums instead.
-template <int T, int NCH>
-__device__ __forceinline__ void layer_valu(const uint4 (&A)[T][NCH], int nch, const float* in, int sin_f, int nrows,
-                                           float* out, int sout_f, const float* bias, int wave, int g, int c16)
+// four weights of every chunk with the matching inputs, and the four lane
+// groups are summed with two butterfly steps, so each lane ends with the
+// whole dot product of neuron n0 + i (row swaps on the vector ALU, no LDS).
+// Rows go one after the other: the weights already fill most of the register
+// file.
+template <int T>
+__device__ __forceinline__ void valu_store(const float (&acc)[T], float* out, const float* bias, int wave, int g,
+                                           int c16)
 {
+#pragma unroll
+    for (int tt = 0; tt < T; ++tt) {
+        const float v = row_sum4(acc[tt]);
+        const int n = (wave + kWaves * tt) * 16 + c16;
+        if (g == 0)
+            out[n] = fmaxf(v + bias[n], 0.f);
+    }
+}
+
+template <int T, int NCH>
+__device__ __forceinline__ void valu_fma4(const uint4 (&A)[T][NCH], int c, const float (&h)[4], float (&acc)[T])
+{
+#pragma unroll
+    for (int tt = 0; tt < T; ++tt) {
+        acc[tt] = fmaf(__uint_as_float(A[tt][c].x), h[0], acc[tt]);
+        acc[tt] = fmaf(__uint_as_float(A[tt][c].y), h[1], acc[tt]);
+        acc[tt] = fmaf(__uint_as_float(A[tt][c].z), h[2], acc[tt]);
+        acc[tt] = fmaf(__uint_as_float(A[tt][c].w), h[3], acc[tt]);
+    }
+}
+
+// FP32 actor pass over nrows <= 4 rows on the vector ALU. The first layer
+// forms its inputs [c/64 | tau/8 | k/8] in registers from the state rows in
+// LDS (state_of(row), k_of(row)), so no feature rows are written and no
+// barrier precedes it. Returns the per-wave partial logit tiles, as mlp_mfma
+// does.
+template <int T, int CH1, int CHH, int NHH, class StateOf, class KOf>
+__device__ __forceinline__ float* mlp_valu(const DevTree& t, const WaveWeights<kFP32, T, CH1, CHH, NHH>& W,
+                                           int nrows, uint8_t* bufA, uint8_t* bufB, const float* bias,
+                                           const int* bias_off, int tau, StateOf state_of, KOf k_of)
+{
+    using WW = WaveWeights<kFP32, T, CH1, CHH, NHH>;
+    constexpr int kRT = Rows<kFP32>::kRT;
+    constexpr int sh = CHH * 16 + 4;  // hidden row stride in floats (16-byte pad)
+    const int lane = threadIdx.x & 63, wave = wave_id(), g = lane >> 4, c16 = lane & 15;
+    const int E = t.E;
+    float* hA = reinterpret_cast<float*>(bufA);
+    float* hB = reinterpret_cast<float*>(bufB);
+    const float ftau = (float)tau * (1.f / 8.f);
+#pragma unroll 1
     for (int r = 0; r < nrows; ++r) {
         float acc[T];
 #pragma unroll
         for (int tt = 0; tt < T; ++tt)
             acc[tt] = 0.f;
-        const float* hr = in + r * sin_f + 4 * g;
+        const uint8_t* st = state_of(r);
+        const float fk = (float)k_of(r) * (1.f / 8.f);
 #pragma unroll
-        for (int c = 0; c < NCH; ++c) {
-            if (c < nch) {
-                const floatx4 h = *reinterpret_cast<const floatx4*>(hr + 16 * c);
+        for (int c = 0; c < CH1; ++c) {
+            // every lane reads four state bytes (clamped into the row, so the
+            // reads need no branch) and keeps those that are inputs
+            uint32_t sb[4];
 #pragma unroll
-                for (int tt = 0; tt < T; ++tt) {
-                    acc[tt] = fmaf(__uint_as_float(A[tt][c].x), h[0], acc[tt]);
-                    acc[tt] = fmaf(__uint_as_float(A[tt][c].y), h[1], acc[tt]);
-                    acc[tt] = fmaf(__uint_as_float(A[tt][c].z), h[2], acc[tt]);
-                    acc[tt] = fmaf(__uint_as_float(A[tt][c].w), h[3], acc[tt]);
-                }
+            for (int j = 0; j < 4; ++j)
+                sb[j] = st[min(16 * c + 4 * g + j, E - 1)];
+            float h[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int f = 16 * c + 4 * g + j;
+                const float sv = (float)sb[j] * (1.f / 64.f);
+                const float tv = f == E ? ftau : fk;
+                const float ov = f <= E + 1 ? tv : 0.f;
+                h[j] = f < E ? sv : ov;
+            }
+            valu_fma4<T, CH1>(W.w1, c, h, acc);
+        }
+        valu_store<T>(acc, hB + r * sh, bias + bias_off[0], wave, g, c16);
+    }
+    lds_barrier();
+    float* in = hB;
+    float* out = hA;
+    if constexpr (NHH > 0) {
+#pragma unroll 1
+        for (int r = 0; r < nrows; ++r) {
+            float acc[T];
+#pragma unroll
+            for (int tt = 0; tt < T; ++tt)
+                acc[tt] = 0.f;
+#pragma unroll
+            for (int c = 0; c < CHH; ++c) {
+                const floatx4 hv = *reinterpret_cast<const floatx4*>(hB + r * sh + 4 * g + 16 * c);
+                const float h[4] = {hv[0], hv[1], hv[2], hv[3]};
+                valu_fma4<T, CHH>(W.wh, c, h, acc);
+            }
+            valu_store<T>(acc, hA + r * sh, bias + bias_off[1], wave, g, c16);
+        }
+        lds_barrier();
+        in = hA;
+        out = hB;
+    }
+    // output layer: this wave's slice of the reduction, one partial tile
+    float* part = out;
+#pragma unroll 1
+    for (int r = 0; r < nrows; ++r) {
+        float acc = 0.f;
+#pragma unroll
+        for (int j = 0; j < WW::CPW; ++j) {
+            const int c = wave * WW::CPW + j;
+            if (c < CHH) {
+                const floatx4 h = *reinterpret_cast<const floatx4*>(in + r * sh + 4 * g + 16 * c);
+                acc = fmaf(__uint_as_float(W.wo[j].x), h[0], acc);
+                acc = fmaf(__uint_as_float(W.wo[j].y), h[1], acc);
+                acc = fmaf(__uint_as_float(W.wo[j].z), h[2], acc);
+                acc = fmaf(__uint_as_float(W.wo[j].w), h[3], acc);
             }
         }
-#pragma unroll
-        for (int tt = 0; tt < T; ++tt) {
-            float v = acc[tt];
-            v += __shfl_xor(v, 16);
-            v += __shfl_xor(v, 32);
-            const int n = (wave + kWaves * tt) * 16 + c16;
-            if (g == 0)
-                out[r * sout_f + n] = fmaxf(v + bias[n], 0.f);
-        }
+        acc = row_sum4(acc);
+        if (g == 0)
+            part[(size_t)(wave * kRT + r) * 16 + c16] = acc;
     }
+    lds_barrier();
+    return part;
 }
 
-// Actor forward pass over nrows <= 64 rows whose features are in bufA. The
-// output layer's reduction is split over the waves: it leaves one partial
-// logit tile per wave, [wave][row][16] floats, in the buffer returned (the
-// enforcer adds them up). bias: LDS copy of every layer's bias.
+// Actor forward pass on the matrix cores over nrows <= 64 rows whose
+// per-node inputs are in bufA. The output layer's reduction is split over the
+// waves: it leaves one partial logit tile per wave, [wave][row][16] floats, in
+// the buffer returned (the enforcer adds them up). bias: LDS copy of every
+// layer's bias.
 template <int P, int T, int CH1, int CHH, int NHH>
-__device__ __forceinline__ float* mlp_regs(const DevTree& t, const WaveWeights<P, T, CH1, CHH, NHH>& W, int nrows,
+__device__ __forceinline__ float* mlp_mfma(const DevTree& t, const WaveWeights<P, T, CH1, CHH, NHH>& W, int nrows,
                                            uint8_t* bufA, uint8_t* bufB, const float* bias, const int* bias_off)
 {
     using WW = WaveWeights<P, T, CH1, CHH, NHH>;
     constexpr int kc = Traits<P>::kChunk, es = Traits<P>::kEsize, kRTT = Rows<P>::kRTT, kRT = Rows<P>::kRT;
     const int lane = threadIdx.x & 63, wave = wave_id(), g = lane >> 4, c16 = lane & 15;
     const int art = (nrows + 15) >> 4;
-    const int s0 = CH1 * kc * es + 16, sh = CHH * kc * es + 16;
-    constexpr int nch1 = CH1;
-    const bool valu = (P == kFP32) && nrows <= 4;
-    if constexpr (P == kFP32) {
-        if (valu)
-            layer_valu<T, CH1>(W.w1, nch1, reinterpret_cast<const float*>(bufA), s0 / 4, nrows,
-                               reinterpret_cast<float*>(bufB), sh / 4, bias + bias_off[0], wave, g, c16);
-    }
-    if (!valu)
-        layer_regs<P, T, CH1>(W.w1, nch1, bufA, s0, bufB, sh, bias + bias_off[0], t.deq[0], t.inv_in_scale[1], art,
-                              wave, g, c16);
+    constexpr int s0 = CH1 * kc * es + 16, sh = CHH * kc * es + 16;
+    layer_regs<P, T, CH1>(W.w1, CH1, bufA, s0, bufB, sh, bias + bias_off[0], t.deq[0], t.inv_in_scale[1], art, wave,
+                          g, c16);
     lds_barrier();
     uint8_t* in = bufB;
     uint8_t* out = bufA;
     if constexpr (NHH > 0) {
-        if constexpr (P == kFP32) {
-            if (valu)
-                layer_valu<T, CHH>(W.wh, CHH, reinterpret_cast<const float*>(bufB), sh / 4, nrows,
-                                   reinterpret_cast<float*>(bufA), sh / 4, bias + bias_off[1], wave, g, c16);
-        }
-        if (!valu)
-            layer_regs<P, T, CHH>(W.wh, CHH, bufB, sh, bufA, sh, bias + bias_off[1], t.deq[1], t.inv_in_scale[2],
-                                  art, wave, g, c16);
+        layer_regs<P, T, CHH>(W.wh, CHH, bufB, sh, bufA, sh, bias + bias_off[1], t.deq[1], t.inv_in_scale[2], art,
+                              wave, g, c16);
         lds_barrier();
         in = bufA;
         out = bufB;
     }
     // output layer: this wave's slice of the reduction, partial tile to LDS
     float* part = reinterpret_cast<float*>(out);
-    if (valu) {
-        for (int r = 0; r < nrows; ++r) {
-            float acc = 0.f;
-            const float* hr = reinterpret_cast<const float*>(in) + r * (sh / 4) + 4 * g;
+    floatx4 acc[kRTT];
 #pragma unroll
-            for (int j = 0; j < WW::CPW; ++j) {
-                const int c = wave * WW::CPW + j;
-                if (c < CHH) {
-                    const floatx4 h = *reinterpret_cast<const floatx4*>(hr + 16 * c);
-                    acc = fmaf(__uint_as_float(W.wo[j].x), h[0], acc);
-                    acc = fmaf(__uint_as_float(W.wo[j].y), h[1], acc);
-                    acc = fmaf(__uint_as_float(W.wo[j].z), h[2], acc);
-                    acc = fmaf(__uint_as_float(W.wo[j].w), h[3], acc);
+    for (int rt = 0; rt < kRTT; ++rt)
+        acc[rt] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const uint8_t* bp = in + c16 * sh + g * (kc / 4) * es;
+#pragma unroll
+    for (int j = 0; j < WW::CPW; ++j) {
+        const int c = wave * WW::CPW + j;
+        if (c < CHH) {
+#pragma unroll
+            for (int rt = 0; rt < kRTT; ++rt)
+                if (rt < art) {
+                    const uint4 b = *reinterpret_cast<const uint4*>(bp + rt * 16 * sh + c * kc * es);
+                    mma_chunk<P>(W.wo[j], b, acc[rt]);
                 }
-            }
-            acc += __shfl_xor(acc, 16);
-            acc += __shfl_xor(acc, 32);
-            if (g == 0)
-                part[(size_t)(wave * kRT + r) * 16 + c16] = acc;
         }
-    } else {
-        floatx4 acc[kRTT];
-#pragma unroll
-        for (int rt = 0; rt < kRTT; ++rt)
-            acc[rt] = floatx4{0.f, 0.f, 0.f, 0.f};
-        const uint8_t* bp = in + c16 * sh + g * (kc / 4) * es;
-#pragma unroll
-        for (int j = 0; j < WW::CPW; ++j) {
-            const int c = wave * WW::CPW + j;
-            if (c < CHH) {
-#pragma unroll
-                for (int rt = 0; rt < kRTT; ++rt)
-                    if (rt < art) {
-                        const uint4 b = *reinterpret_cast<const uint4*>(bp + rt * 16 * sh + c * kc * es);
-                        mma_chunk<P>(W.wo[j], b, acc[rt]);
-                    }
-            }
-        }
-#pragma unroll
-        for (int rt = 0; rt < kRTT; ++rt)
-            if (rt < art)
-                *reinterpret_cast<floatx4*>(part + (size_t)(wave * kRT + rt * 16 + c16) * 16 + g * 4) = acc[rt];
     }
+#pragma unroll
+    for (int rt = 0; rt < kRTT; ++rt)
+        if (rt < art)
+            *reinterpret_cast<floatx4*>(part + (size_t)(wave * kRT + rt * 16 + c16) * 16 + g * 4) = acc[rt];
     lds_barrier();
     return part;
 }
@@ -311,9 +360,8 @@ __device__ __forceinline__ void write_features(const DevTree& t, const SubtreeSm
     constexpr int tpr = in0 < 64 ? in0 : 64;  // threads per row
     const int E = t.E;
     // MFMA passes read whole 16-row tiles: rows past nrows are zeroed so they
-    // stay finite (each output row depends on its own input row only); the
-    // FP32 VALU path for a few rows reads nothing past nrows
-    const int nrows_pad = (P == kFP32 && nrows <= 4) ? nrows : ((nrows + 15) >> 4) << 4;
+    // stay finite (each output row depends on its own input row only)
+    const int nrows_pad = ((nrows + 15) >> 4) << 4;
     const float inv0 = t.inv_in_scale[0], ftau = (float)tau * (1.f / 8.f);
     const int f0 = threadIdx.x % tpr;
     for (int row = threadIdx.x / tpr; row < nrows_pad; row += kThreads / tpr) {
@@ -335,6 +383,22 @@ __device__ __forceinline__ void write_features(const DevTree& t, const SubtreeSm
             store1<P>(dst + f * es, v, inv0);
         }
     }
+}
+
+// One actor pass over the nrows nodes of a step: the FP32 vector-ALU path for
+// up to four rows, else the per-node input rows and the matrix-core path.
+template <int P, int T, int CH1, int CHH, int NHH, class StateOf, class KOf>
+__device__ __forceinline__ const float* eval_rows(const DevTree& t, const SubtreeSmem& sm,
+                                                  const WaveWeights<P, T, CH1, CHH, NHH>& W, int nrows, int tau,
+                                                  const int* bias_off, StateOf state_of, KOf k_of)
+{
+    if constexpr (P == kFP32) {
+        if (nrows <= 4)
+            return mlp_valu<T, CH1, CHH, NHH>(t, W, nrows, sm.bufA, sm.bufB, sm.bias, bias_off, tau, state_of, k_of);
+    }
+    write_features<P, CH1>(t, sm, nrows, tau, state_of, k_of);
+    lds_barrier();
+    return mlp_mfma<P, T, CH1, CHH, NHH>(t, W, nrows, sm.bufA, sm.bufB, sm.bias, bias_off);
 }
 
 // Enforcer over `nrows` rows, G lanes per row (lane e = UE e). Each lane first
@@ -518,9 +582,8 @@ __device__ __forceinline__ void subtree_body(const DevTree& t, int split, int bu
         const int64_t node = sub_level_offset(K, tau) + idx;
         const bool owner = (r % below) == 0;
         if (k > 0) {
-            write_features<P, CH1>(t, sm, 1, tau, [&](int) { return sm.st0; }, [&](int) { return k; });
-            lds_barrier();
-            const float* part = mlp_regs<P, T, CH1, CHH, NHH>(t, W, 1, sm.bufA, sm.bufB, sm.bias, bias_off);
+            const float* part = eval_rows<P, T, CH1, CHH, NHH>(
+                t, sm, W, 1, tau, bias_off, [&](int) { return sm.st0; }, [&](int) { return k; });
             finish_rows<G, kRT, EXT>(
                 t, sm, part, deq_out, bias_out, 1, [&](int) { return k; }, [&](int) { return sm.st0; },
                 [&](int) { return sm.st1; }, [&](int) { return node; }, [&](int) { return owner ? node : (int64_t)-1; },
@@ -551,10 +614,8 @@ __device__ __forceinline__ void subtree_body(const DevTree& t, int split, int bu
             // row j of the level: parent p = j / K, arrival k = j % K + 1
             auto parent_of = [&](int row) { return (int)(((float)(j0 + row) + 0.5f) * invK); };
             auto k_of = [&](int row) { return j0 + row - parent_of(row) * K + 1; };
-            write_features<P, CH1>(
-                t, sm, nrows, tau, [&](int row) { return prev + parent_of(row) * E; }, k_of);
-            lds_barrier();
-            const float* part = mlp_regs<P, T, CH1, CHH, NHH>(t, W, nrows, sm.bufA, sm.bufB, sm.bias, bias_off);
+            const float* part = eval_rows<P, T, CH1, CHH, NHH>(
+                t, sm, W, nrows, tau, bias_off, [&](int row) { return prev + parent_of(row) * E; }, k_of);
             finish_rows<G, kRT, EXT>(
                 t, sm, part, deq_out, bias_out, nrows, k_of, [&](int row) { return prev + parent_of(row) * E; },
                 [&](int row) { return cur + (parent_of(row) * K1 + k_of(row)) * E; },
