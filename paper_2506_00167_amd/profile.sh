@@ -3,7 +3,8 @@
 # kernel trace + stats of bench.py (the FP32 subtree kernel, C2) and of the
 # 32-cell FP8 stress batch (level kernel), then one counter per run
 # (FETCH_SIZE, WRITE_SIZE) on single-codebook builds and on a plain copy of
-# known size that calibrates the counters. Summaries and raw output go to OUT
+# known size that calibrates the counters, then the subtree kernel's executed
+# matrix-core and vector FMA operations. Summaries and raw output go to OUT
 # (default prof_out under the repository root).
 #
 #   bash paper_2506_00167_amd/profile.sh [OUT]
@@ -69,5 +70,17 @@ python3 -m paper_2506_00167_amd.profiling summarize "$OUT/write_stress" --kernel
     > "$OUT/level_kernel_batch_stress-e16k4_fp8_write.txt" &&
 python3 -m paper_2506_00167_amd.profiling traffic --fetch "$OUT/fetch_subtree" --write "$OUT/write_subtree" \
     --copy-fetch "$OUT/fetch_copy" --copy-write "$OUT/write_copy" --copy-kernel copyBuffer \
-    --kernel subtree_kernel --key subtree/tree-e8k3/fp32 --out "$OUT/traffic.json" &&
+    --kernel subtree_kernel --key subtree/tree-e8k3/fp32 --out "$OUT/traffic.json" || exit 1
+
+# work the FP32 subtree kernel executes: FP32 matrix-core operations (in units
+# of 512) and vector FMA instructions (one per wave), to set beside the
+# algorithmic FLOP count of a build
+counter mfma_subtree SQ_INSTS_VALU_MFMA_MOPS_F32 $BUILD &&
+counter vfma_subtree SQ_INSTS_VALU_FMA_F32 $BUILD &&
+python3 -m paper_2506_00167_amd.profiling summarize "$OUT/mfma_subtree" --kernel subtree_kernel \
+    --command "rocprofv3 --pmc SQ_INSTS_VALU_MFMA_MOPS_F32 --output-format csv -d OUT/mfma_subtree -o run -- $BUILD" \
+    > "$OUT/subtree_kernel_tree-e8k3_fp32_mfma_ops.txt" &&
+python3 -m paper_2506_00167_amd.profiling summarize "$OUT/vfma_subtree" --kernel subtree_kernel \
+    --command "rocprofv3 --pmc SQ_INSTS_VALU_FMA_F32 --output-format csv -d OUT/vfma_subtree -o run -- $BUILD" \
+    > "$OUT/subtree_kernel_tree-e8k3_fp32_valu_fma.txt" &&
 echo "[prof] done: $OUT" >&2
