@@ -17,6 +17,14 @@ pytestmark = pytest.mark.gpu
 
 FP32_LOGIT_TOL = 1e-4
 
+# Subtree-kernel shapes at the edges of the first layer's per-node inputs
+# (c, tau, k: E + 2 of them): exactly one 16-wide FP32 chunk at E = 14, two
+# chunks at E = 16.
+SUBTREE_WIDE = [
+    dict(num_ue=14, max_arrival=3, num_minislots=4, hidden=(128, 128)),
+    dict(num_ue=16, max_arrival=2, num_minislots=4, hidden=(256, 256)),
+]
+
 
 def _build(cfg, weights, ue, **kw):
     cb = cyrus.Codebook(cfg, weights, export_logits=True, **kw)
@@ -65,6 +73,7 @@ def test_tree_e8k3_fp32(force_level, seed):
     dict(num_ue=16, max_arrival=4, num_minislots=3, hidden=(512, 512)),
     dict(num_ue=32, max_arrival=2, num_minislots=4, hidden=(256, 384, 128)),  # 32 UEs: two output tiles
     dict(num_ue=5, max_arrival=7, num_minislots=2, rb_per_unit=3, hidden=(256, 256, 256, 256)),
+    *SUBTREE_WIDE,
 ])
 def test_shapes_fp32(shape):
     cfg = wl.TreeConfig(**shape)
@@ -79,12 +88,25 @@ def test_shapes_fp32(shape):
 
 
 def test_latency_path_is_selected():
-    for cfg in (wl.TINY, wl.TREE_E8K3, wl.PAPER_DEPTH1, wl.TREE_E8K3.with_precision("bf16")):
+    wide = [wl.TreeConfig(**s) for s in SUBTREE_WIDE]
+    for cfg in (wl.TINY, wl.TREE_E8K3, wl.PAPER_DEPTH1, wl.TREE_E8K3.with_precision("bf16"), *wide):
         cb = cyrus.Codebook(cfg, wl.make_weights(cfg, 1), act_scale=None)
         assert cb.kernel_path == "subtree", cfg
         cb.close()
     cb = cyrus.Codebook(wl.TREE_E8K3, wl.make_weights(wl.TREE_E8K3, 1), force_level=True)
     assert cb.kernel_path == "level"
+    cb.close()
+
+
+def test_subtree_bf16_wide():
+    cfg = wl.TreeConfig(precision="bf16", **SUBTREE_WIDE[1])
+    weights = wl.make_weights(cfg, 33)
+    ue = wl.make_ue_state(cfg.num_ue, 34)
+    cb, alloc, logits = _build(cfg, weights, ue)
+    assert cb.kernel_path == "subtree"
+    parity.check_invariants(cfg, ue, alloc)
+    rep = parity.compare(cfg, weights, ue, alloc, logits, precision="bf16", logit_tol=2e-3)
+    _report("bf16 e16k2 subtree", rep)
     cb.close()
 
 
