@@ -264,7 +264,8 @@ typedef struct {
 typedef struct cyrus_critic cyrus_critic;
 
 /* Device workspace bytes (align 256) for `cfg`: the five networks' packed
- * weights and their descriptors. */
+ * weights, their descriptors, and 12 bytes per row (H M rows) of scratch for
+ * the per-row targets, which cyrus_critic_evaluate overwrites. */
 int cyrus_critic_workspace_size(const cyrus_critic_config* cfg, size_t* device_bytes);
 
 /* Bind a critic evaluator to the current device: validates cfg, packs the
@@ -275,7 +276,9 @@ int cyrus_critic_create(const cyrus_critic_config* cfg, const cyrus_critic_weigh
 
 /* One pass over a batch, asynchronous on `stream`. Outputs are device arrays:
  * q [2][H][M], qhat [H][M], loss [2]. Same inputs, seed and episode give the
- * same outputs bit for bit. CYRUS_EINVAL for NULL pointers. */
+ * same outputs bit for bit. Passes on one handle share its workspace scratch,
+ * so passes that overlap in time (other streams) race; order them on one
+ * stream. CYRUS_EINVAL for NULL pointers. */
 int cyrus_critic_evaluate(cyrus_critic* cr, const cyrus_critic_batch* batch, uint64_t seed, uint64_t episode,
                           float* q, float* qhat, float* loss, void* stream);
 

@@ -19,6 +19,7 @@ struct cyrus_critic {
     int device = 0;
     uint8_t* ws = nullptr;
     const DevTree* nets = nullptr;  // in the workspace
+    float* tgt = nullptr;           // per-row target scratch in the workspace: [3][H M]
     int rtt = 1;
     size_t lds = 0;
     int bufsize = 0;
@@ -50,6 +51,7 @@ struct NetShape {
 struct CriticLayout {
     NetShape net[5];
     size_t nets_off;  // DevTree[5]
+    size_t tgt_off;   // float[3][H M]: both target critics and log pi, per row
     size_t bytes;
 };
 
@@ -110,7 +112,8 @@ CriticLayout layout(const cyrus_critic_config* c)
         }
     }
     L.nets_off = off;
-    L.bytes = align_up(off + sizeof(DevTree) * 5, 256);
+    L.tgt_off = align_up(off + sizeof(DevTree) * 5, 256);
+    L.bytes = align_up(L.tgt_off + (size_t)3 * c->num_samples * c->num_minislots * 4, 256);
     return L;
 }
 
@@ -208,6 +211,7 @@ extern "C" int cyrus_critic_create(const cyrus_critic_config* cfg, const cyrus_c
     }
     cr->bias_total = boff;
     cr->nets = reinterpret_cast<const DevTree*>(cr->ws + L.nets_off);
+    cr->tgt = reinterpret_cast<float*>(cr->ws + L.tgt_off);
     e = hipMemcpyAsync(cr->ws + L.nets_off, nets, sizeof nets, hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
         e = hipStreamSynchronize(st);
@@ -215,14 +219,15 @@ extern "C" int cyrus_critic_create(const cyrus_critic_config* cfg, const cyrus_c
         delete cr;
         return hip_fail(e, "descriptor upload");
     }
-    // row tiles per workgroup: the largest whose LDS fits and whose grid still
-    // covers every CU; the smallest that fits when the batch is too small
+    // row tiles per workgroup (four workgroups per tile, one per role): the
+    // smallest whose LDS fits and whose grid runs in one round on the CUs;
+    // the largest that fits when no tile size gives one round
     int ncu = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, cr->device) != hipSuccess || ncu < 1)
         ncu = 256;
     const int64_t rows = (int64_t)cfg->num_samples * cfg->num_minislots;
     cr->rtt = 0;
-    for (int r : {4, 2, 1}) {
+    for (int r : {1, 2, 4}) {
         const size_t rt = 16 * (size_t)r;
         const size_t buf = align_up(std::max(stride * rt, (size_t)kWaves * rt * part * 4), 16);
         const size_t lds = critic_lds_bytes((int)buf, cr->bias_total, r);
@@ -231,7 +236,7 @@ extern "C" int cyrus_critic_create(const cyrus_critic_config* cfg, const cyrus_c
         cr->rtt = r;
         cr->bufsize = (int)buf;
         cr->lds = lds;
-        if ((rows + (int64_t)rt - 1) / (int64_t)rt >= ncu)
+        if (4 * ((rows + (int64_t)rt - 1) / (int64_t)rt) <= ncu)
             break;
     }
     if (!cr->rtt) {
@@ -260,6 +265,9 @@ extern "C" int cyrus_critic_evaluate(cyrus_critic* cr, const cyrus_critic_batch*
     a.q = q;
     a.qhat = qhat;
     a.loss = loss;
+    const int64_t rows = (int64_t)cr->cfg.num_samples * cr->cfg.num_minislots;
+    a.tq = cr->tgt;
+    a.tlp = cr->tgt + 2 * rows;
     a.E = cr->cfg.num_ue;
     a.M = cr->cfg.num_minislots;
     a.H = cr->cfg.num_samples;

@@ -31,6 +31,8 @@ struct CriticArgs {
     float* q;
     float* qhat;
     float* loss;
+    float* tq;   // [2][H M] target critics at step tau+1 (workspace scratch)
+    float* tlp;  // [H M] log pi of the fresh action (workspace scratch)
     int E, M, H;
     float discount, entropy_coef;
     uint64_t seed, episode;

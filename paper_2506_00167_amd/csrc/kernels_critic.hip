@@ -1,11 +1,15 @@
-// The Near-RT RIC's critic pass (Sec. IV-B, Eqs. (3) and (4)) on MFMA: one
-// workgroup per 16*RTT rows (sample h, step tau). Per tile the workgroup runs
-// five FP32 MLPs with the activations in LDS and the weight fragments read
-// from L2: the critics Q1 and Q2 on [state, y]; the actor at step tau+1, whose
-// Gaussian draws give a fresh action y~ and its log density; the target
-// critics on [state at tau+1, y~]; and the target of Eq. (4). A second,
-// one-workgroup kernel forms the mean squared errors of Eq. (3) in a fixed
-// summation order.
+// The Near-RT RIC's critic pass (Sec. IV-B, Eqs. (3) and (4)) on MFMA. Each
+// tile of 16*RTT rows (sample h, step tau) gets four workgroups, one per role,
+// running FP32 MLPs with the activations in LDS and the weight fragments read
+// from L2:
+//   role 0, 1: critic Q1 or Q2 on [state, y];
+//   role 2, 3: the actor at step tau+1, whose Gaussian draws give a fresh
+//              action y~ and its log density, then target critic 1 or 2 on
+//              [state at tau+1, y~].
+// Roles 2 and 3 draw the same y~ (the draws are a function of the row, not of
+// the thread), so no workgroup waits for another and the longest chain is two
+// networks. A second, one-workgroup kernel forms the target of Eq. (4) and the
+// mean squared errors of Eq. (3) in a fixed summation order.
 #include "cyrus_device.h"
 #include "cyrus_kernels.h"
 #include "cyrus_mlp.h"
@@ -61,8 +65,7 @@ __global__ __launch_bounds__(kThreads) void critic_kernel(CriticArgs a)
     uint8_t* bufB = smem + a.bufsize;
     float* zl = reinterpret_cast<float*>(smem + 2 * a.bufsize);
     float* bias = zl + RT * kLogitStride;        // every network's biases
-    float* qt = bias + a.bias_total;             // [RT] first target critic
-    float* lp = qt + RT;                         // [RT] log pi of y~
+    float* lp = bias + a.bias_total;             // [RT] log pi of y~
     float* yt = lp + RT;                         // [RT][16] y~
     float* lpe = yt + RT * 16;                   // [RT][16] per-UE log-density terms
     CriticStage st;
@@ -73,7 +76,8 @@ __global__ __launch_bounds__(kThreads) void critic_kernel(CriticArgs a)
 
     const int E = a.E, M = a.M;
     const int rows = a.H * M;
-    const int j0 = blockIdx.x * RT;
+    const int role = (int)(blockIdx.x & 3u);
+    const int j0 = (int)(blockIdx.x >> 2) * RT;
     const int nrows = min(RT, rows - j0);
     if (nrows <= 0)
         return;
@@ -122,13 +126,13 @@ __global__ __launch_bounds__(kThreads) void critic_kernel(CriticArgs a)
     const int wa = a.nets[0].in_pad[0], sa = wa + 4;
     auto net = [&](int n) { run_mlp<kFP32, RTT>(a.nets[n], nrows, bufA, bufB, zl, bias + a.bias_off[n], 0, 0); };
 
-    // Q1 and Q2 on the stored action
-    for (int i = 0; i < 2; ++i) {
+    if (role < 2) {
+        // Q1 or Q2 on the stored action
         fill(wc, sc, false, true, nullptr);
-        net(1 + i);
+        net(1 + role);
         for (int row = threadIdx.x; row < nrows; row += kThreads)
-            a.q[(int64_t)i * rows + j0 + row] = zl[row * kLogitStride];
-        lds_barrier();
+            a.q[(int64_t)role * rows + j0 + row] = zl[row * kLogitStride];
+        return;
     }
 
     // the actor at step tau+1
@@ -155,44 +159,41 @@ __global__ __launch_bounds__(kThreads) void critic_kernel(CriticArgs a)
         lpe[row * 16 + e] = term;
     }
     lds_barrier();
-    for (int row = threadIdx.x; row < nrows; row += kThreads) {
-        float s = 0.f;
-        for (int e = 0; e < E; ++e)
-            s += lpe[row * 16 + e];
-        lp[row] = s;
-    }
-    // the target critics on [state at tau+1, y~]
+    if (role == 2)
+        for (int row = threadIdx.x; row < nrows; row += kThreads) {
+            float s = 0.f;
+            for (int e = 0; e < E; ++e)
+                s += lpe[row * 16 + e];
+            a.tlp[j0 + row] = s;
+        }
+    // target critic 1 or 2 on [state at tau+1, y~]
     fill(wc, sc, true, true, yt);
-    net(3);
+    net(1 + role);
     for (int row = threadIdx.x; row < nrows; row += kThreads)
-        qt[row] = zl[row * kLogitStride];
-    lds_barrier();
-    fill(wc, sc, true, true, yt);
-    net(4);
-    for (int row = threadIdx.x; row < nrows; row += kThreads) {
-        const int j = j0 + row;
-        float target;
-        if ((j % M) + 1 == M)
-            target = a.reward[j / M];
-        else
-            target = a.discount * (fminf(qt[row], zl[row * kLogitStride]) - a.entropy_coef * lp[row]);
-        a.qhat[j] = target;
-    }
+        a.tq[(int64_t)(role - 2) * rows + j0 + row] = zl[row * kLogitStride];
 }
 
-// loss[i] = mean over rows of (q[i][row] - qhat[row])^2; every thread sums a
-// fixed stride of rows, then a fixed-order tree in LDS.
-__global__ __launch_bounds__(256) void critic_loss_kernel(const float* q, const float* qhat, int rows, float* loss)
+// The target of Eq. (4) per row, then loss[i] = mean over rows of
+// (q[i][row] - qhat[row])^2; every thread handles a fixed stride of rows,
+// then a fixed-order tree in LDS.
+__global__ __launch_bounds__(256) void critic_loss_kernel(CriticArgs a)
 {
     __shared__ float part[2][256];
-    for (int i = 0; i < 2; ++i) {
-        float s = 0.f;
-        for (int j = threadIdx.x; j < rows; j += 256) {
-            const float d = q[(int64_t)i * rows + j] - qhat[j];
-            s += d * d;
-        }
-        part[i][threadIdx.x] = s;
+    const int rows = a.H * a.M;
+    float s0 = 0.f, s1 = 0.f;
+    for (int j = threadIdx.x; j < rows; j += 256) {
+        float target;
+        if ((j % a.M) + 1 == a.M)
+            target = a.reward[j / a.M];
+        else
+            target = a.discount * (fminf(a.tq[j], a.tq[rows + j]) - a.entropy_coef * a.tlp[j]);
+        a.qhat[j] = target;
+        const float d0 = a.q[j] - target, d1 = a.q[rows + j] - target;
+        s0 += d0 * d0;
+        s1 += d1 * d1;
     }
+    part[0][threadIdx.x] = s0;
+    part[1][threadIdx.x] = s1;
     __syncthreads();
     for (int w = 128; w >= 1; w >>= 1) {
         if ((int)threadIdx.x < w) {
@@ -202,7 +203,7 @@ __global__ __launch_bounds__(256) void critic_loss_kernel(const float* q, const 
         __syncthreads();
     }
     if (threadIdx.x < 2)
-        loss[threadIdx.x] = part[threadIdx.x][0] / (float)rows;
+        a.loss[threadIdx.x] = part[threadIdx.x][0] / (float)rows;
 }
 
 }  // namespace
@@ -211,8 +212,7 @@ size_t critic_lds_bytes(int bufsize, int bias_total, int rtt)
 {
     const size_t RT = 16 * (size_t)rtt;
     const size_t stage = ((RT + 2) * 3 * kMaxUE / 2 + RT + 4 + (RT + 1) * 16) * 4 + RT * 16 * 4;
-    return 2 * (size_t)bufsize + RT * kLogitStride * 4 + (size_t)bias_total * 4 + RT * 4 * 2 + RT * 16 * 4 * 2 +
-           stage;
+    return 2 * (size_t)bufsize + RT * kLogitStride * 4 + (size_t)bias_total * 4 + RT * 4 + RT * 16 * 4 * 2 + stage;
 }
 
 template <int RTT>
@@ -225,12 +225,12 @@ static hipError_t launch_critic_t(const CriticArgs& a, size_t lds, hipStream_t s
         attr = true;
     }
     const int rows = a.H * a.M;
-    const int grid = (rows + 16 * RTT - 1) / (16 * RTT);
+    const int grid = 4 * ((rows + 16 * RTT - 1) / (16 * RTT));  // four roles per row tile
     hipLaunchKernelGGL((critic_kernel<RTT>), dim3(grid), dim3(kThreads), lds, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL(critic_loss_kernel, dim3(1), dim3(256), 0, s, a.q, a.qhat, rows, a.loss);
+    hipLaunchKernelGGL(critic_loss_kernel, dim3(1), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
