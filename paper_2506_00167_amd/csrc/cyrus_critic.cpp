@@ -21,6 +21,7 @@ struct cyrus_critic {
     const DevTree* nets = nullptr;  // in the workspace
     float* tgt = nullptr;           // per-row target scratch in the workspace: [3][H M]
     int rtt = 1;
+    int regs_t = 0, regs_ch1 = 0;  // register-resident kernel: tiles per wave, first-layer chunks (0: streamed)
     size_t lds = 0;
     int bufsize = 0;
     int bias_off[5] = {0};
@@ -50,6 +51,7 @@ struct NetShape {
 
 struct CriticLayout {
     NetShape net[5];
+    int regs_t, regs_ch1;  // register-resident kernel shape, or 0
     size_t nets_off;  // DevTree[5]
     size_t tgt_off;   // float[3][H M]: both target critics and log pi, per row
     size_t bytes;
@@ -87,10 +89,26 @@ int validate(const cyrus_critic_config* c)
     return rc ? rc : check_hidden(c->critic_hidden_layers, c->critic_hidden, "critic");
 }
 
+// The register-resident critic kernel takes two hidden layers of one width H
+// in {128, 256} in all five networks and at most 16 actor outputs (E <= 8);
+// every network's first layer is then padded to the critics' 5E+2 inputs.
+bool regs_shape(const cyrus_critic_config* c, int* H)
+{
+    const int h = c->actor_hidden[0];
+    *H = h;
+    return c->actor_hidden_layers == 2 && c->critic_hidden_layers == 2 && (h == 128 || h == 256) &&
+           c->actor_hidden[1] == h && c->critic_hidden[0] == h && c->critic_hidden[1] == h && 2 * c->num_ue <= 16;
+}
+
 CriticLayout layout(const cyrus_critic_config* c)
 {
     CriticLayout L{};
     const int E = c->num_ue;
+    int H = 0;
+    const bool regs = regs_shape(c, &H);
+    const int in0 = (int)align_up(5 * E + 2, 16);
+    L.regs_t = regs ? H / 128 : 0;
+    L.regs_ch1 = regs ? in0 / 16 : 0;
     size_t off = 0;
     for (int n = 0; n < 5; ++n) {
         NetShape& s = L.net[n];
@@ -103,7 +121,7 @@ CriticLayout layout(const cyrus_critic_config* c)
             s.dims[i + 1] = hw[i];
         s.dims[nh + 1] = actor ? 2 * E : 1;
         for (int l = 0; l < s.n_layers; ++l) {
-            s.in_pad[l] = (int)align_up(s.dims[l], 16);
+            s.in_pad[l] = (l == 0 && regs) ? in0 : (int)align_up(s.dims[l], 16);
             s.out_pad[l] = (int)align_up(s.dims[l + 1], 16);
             s.w_off[l] = off;
             off = align_up(off + (size_t)s.in_pad[l] * s.out_pad[l] * 4, 256);
@@ -191,6 +209,10 @@ extern "C" int cyrus_critic_create(const cyrus_critic_config* cfg, const cyrus_c
             t.b[l] = reinterpret_cast<const float*>(cr->ws + s.b_off[l]);
             t.deq[l] = 1.f;
             t.inv_in_scale[l] = 1.f;
+            if (l == 0) {  // the register-resident kernel loads layer 1 through these
+                t.w1d = t.w[0];
+                t.in_pad_d = t.in_pad[0];
+            }
             boff += s.out_pad[l];
             stride = std::max(stride, (size_t)s.in_pad[l] * 4 + 16);
             pack.assign((size_t)s.in_pad[l] * s.out_pad[l], 0.f);
@@ -219,15 +241,30 @@ extern "C" int cyrus_critic_create(const cyrus_critic_config* cfg, const cyrus_c
         delete cr;
         return hip_fail(e, "descriptor upload");
     }
-    // row tiles per workgroup (four workgroups per tile, one per role): the
-    // smallest whose LDS fits and whose grid runs in one round on the CUs;
-    // the largest that fits when no tile size gives one round
     int ncu = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, cr->device) != hipSuccess || ncu < 1)
         ncu = 256;
     const int64_t rows = (int64_t)cfg->num_samples * cfg->num_minislots;
     cr->rtt = 0;
+    if (L.regs_t) {
+        // register-resident kernel: 32-row tiles; the output partials of a
+        // pass take 8 waves x 48 rows x 16 floats of one activation buffer
+        const size_t buf = align_up(std::max(stride * 32, (size_t)kWaves * 48 * 16 * 4), 16);
+        const size_t lds = critic_lds_bytes((int)buf, cr->bias_total, 2);
+        if (lds <= 160 * 1024) {
+            cr->rtt = 2;
+            cr->bufsize = (int)buf;
+            cr->lds = lds;
+            cr->regs_t = L.regs_t;
+            cr->regs_ch1 = L.regs_ch1;
+        }
+    }
+    // streamed-weight kernel: row tiles per workgroup (four workgroups per
+    // tile, one per role): the smallest whose LDS fits and whose grid runs in
+    // one round on the CUs; the largest that fits when none gives one round
     for (int r : {1, 2, 4}) {
+        if (cr->regs_t)
+            break;
         const size_t rt = 16 * (size_t)r;
         const size_t buf = align_up(std::max(stride * rt, (size_t)kWaves * rt * part * 4), 16);
         const size_t lds = critic_lds_bytes((int)buf, cr->bias_total, r);
@@ -279,7 +316,7 @@ extern "C" int cyrus_critic_evaluate(cyrus_critic* cr, const cyrus_critic_batch*
     for (int n = 0; n < 5; ++n)
         a.bias_off[n] = cr->bias_off[n];
     a.bias_total = cr->bias_total;
-    e = launch_critic(a, cr->rtt, cr->lds, static_cast<hipStream_t>(stream));
+    e = launch_critic(a, cr->rtt, cr->regs_t, cr->regs_ch1, cr->lds, static_cast<hipStream_t>(stream));
     if (e != hipSuccess)
         return hip_fail(e, "critic launch");
     return CYRUS_OK;

@@ -41,7 +41,9 @@ struct CriticArgs {
     int bias_total;
 };
 size_t critic_lds_bytes(int bufsize, int bias_total, int rtt);
-hipError_t launch_critic(const CriticArgs& a, int rtt, size_t lds, hipStream_t s);
+// regs_t > 0: the register-resident kernel (regs_t neuron tiles per wave,
+// regs_ch1 first-layer chunks, rtt = 2); else the streamed-weight kernel.
+hipError_t launch_critic(const CriticArgs& a, int rtt, int regs_t, int regs_ch1, size_t lds, hipStream_t s);
 
 // FP32 fragment-ordered weights -> packed storage of `prec`.
 hipError_t launch_convert_weights(int prec, const float* src, uint8_t* dst, int64_t n_floats, float inv_w_scale,

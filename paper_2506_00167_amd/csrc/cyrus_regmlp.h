@@ -1,0 +1,187 @@
+// Actor-style MLP with its weights resident in registers, on MFMA: each wave
+// holds the A fragments of its output-neuron tiles (hidden layers) and its
+// slice of the output layer's reduction, loaded once; activations move
+// through LDS in the transposed layer form (weights as the A operand, node
+// rows as the B operand). Shared by the subtree kernel and the critic pass.
+#pragma once
+
+#include "cyrus_device.h"
+
+namespace cyrus {
+
+namespace {
+
+// Row tiles per pass: 64 rows for BF16/FP8; 48 for FP32, whose register-
+// resident weights leave room for fewer accumulators.
+template <int P>
+struct Rows {
+    static constexpr int kRTT = (P == kFP32) ? 3 : 4;
+    static constexpr int kRT = 16 * kRTT;
+};
+constexpr int kRTmax = 64;
+
+// Register-resident fragments of one wave.
+//   T     output-neuron tiles of 16 per hidden layer owned by this wave
+//   CH1   chunks of the first layer's per-node input (in_pad_d / chunk)
+//   CHH   chunks of a hidden layer's input (H / chunk)
+//   NHH   hidden->hidden layers (0 or 1)
+template <int P, int T, int CH1, int CHH, int NHH>
+struct WaveWeights {
+    static constexpr int CPW = (CHH + kWaves - 1) / kWaves;  // output-layer chunks per wave
+    uint4 w1[T][CH1];
+    uint4 wh[NHH > 0 ? T : 1][NHH > 0 ? CHH : 1];
+    uint4 wo[CPW];
+};
+
+template <int P, int T, int CH1, int CHH, int NHH>
+__device__ __forceinline__ void load_weights(const DevTree& t, WaveWeights<P, T, CH1, CHH, NHH>& W, int wave,
+                                             int lane)
+{
+    using WW = WaveWeights<P, T, CH1, CHH, NHH>;
+    const uint4* g1 = reinterpret_cast<const uint4*>(t.w1d);
+#pragma unroll
+    for (int tt = 0; tt < T; ++tt) {
+        const int nt = wave + kWaves * tt;
+#pragma unroll
+        for (int c = 0; c < CH1; ++c)
+            W.w1[tt][c] = g1[((size_t)nt * CH1 + c) * 64 + lane];
+    }
+    if constexpr (NHH > 0) {
+        const uint4* gh = reinterpret_cast<const uint4*>(t.w[1]);
+#pragma unroll
+        for (int tt = 0; tt < T; ++tt) {
+            const int nt = wave + kWaves * tt;
+#pragma unroll
+            for (int c = 0; c < CHH; ++c)
+                W.wh[tt][c] = gh[((size_t)nt * CHH + c) * 64 + lane];
+        }
+    }
+    const uint4* go = reinterpret_cast<const uint4*>(t.w[NHH + 1]);
+#pragma unroll
+    for (int j = 0; j < WW::CPW; ++j) {
+        const int c = wave * WW::CPW + j;
+        W.wo[j] = (c < CHH) ? go[(size_t)c * 64 + lane] : uint4{0, 0, 0, 0};
+    }
+}
+
+// One layer with register-resident A fragments: out = act(A * in) for the
+// wave's T neuron tiles over `art` row tiles.
+template <int P, int T, int NCH>
+__device__ __forceinline__ void layer_regs(const uint4 (&A)[T][NCH], int nch, const uint8_t* in, int sin,
+                                           uint8_t* out, int sout, const float* bias, float deq, float inv_next,
+                                           int art, int wave, int g, int c16)
+{
+    constexpr int kc = Traits<P>::kChunk, es = Traits<P>::kEsize, kRTT = Rows<P>::kRTT;
+    floatx4 acc[T][kRTT];
+#pragma unroll
+    for (int tt = 0; tt < T; ++tt)
+#pragma unroll
+        for (int rt = 0; rt < kRTT; ++rt)
+            acc[tt][rt] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const uint8_t* bp = in + c16 * sin + g * (kc / 4) * es;
+    if constexpr (P == kFP8 && NCH % 2 == 0) {
+        // chunk pairs: one 16x16x128 MFMA per pair (nch is even for FP8)
+#pragma unroll
+        for (int c = 0; c < NCH; c += 2) {
+            if (c < nch) {
+#pragma unroll
+                for (int rt = 0; rt < kRTT; ++rt) {
+                    if (rt < art) {
+                        const uint8_t* brow = bp + rt * 16 * sin + c * kc * es;
+                        const uint4 b0 = *reinterpret_cast<const uint4*>(brow);
+                        const uint4 b1 = *reinterpret_cast<const uint4*>(brow + kc * es);
+#pragma unroll
+                        for (int tt = 0; tt < T; ++tt)
+                            mma_pair<P>(A[tt][c], A[tt][c + 1], b0, b1, acc[tt][rt]);
+                    }
+                }
+            }
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            if (c < nch) {
+#pragma unroll
+                for (int rt = 0; rt < kRTT; ++rt) {
+                    if (rt < art) {
+                        const uint4 b = *reinterpret_cast<const uint4*>(bp + rt * 16 * sin + c * kc * es);
+#pragma unroll
+                        for (int tt = 0; tt < T; ++tt)
+                            mma_chunk<P>(A[tt][c], b, acc[tt][rt]);
+                    }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int tt = 0; tt < T; ++tt) {
+        const int nt = wave + kWaves * tt;
+        const float* bb = bias + nt * 16 + g * 4;
+        const float b0 = bb[0], b1 = bb[1], b2 = bb[2], b3 = bb[3];
+#pragma unroll
+        for (int rt = 0; rt < kRTT; ++rt) {
+            if (rt < art) {
+                store4<P>(out + (rt * 16 + c16) * sout + (nt * 16 + g * 4) * es,
+                          fmaxf(acc[tt][rt][0] * deq + b0, 0.f), fmaxf(acc[tt][rt][1] * deq + b1, 0.f),
+                          fmaxf(acc[tt][rt][2] * deq + b2, 0.f), fmaxf(acc[tt][rt][3] * deq + b3, 0.f), inv_next);
+            }
+        }
+    }
+}
+
+// Actor forward pass on the matrix cores over nrows <= 64 rows whose
+// per-node inputs are in bufA. The output layer's reduction is split over the
+// waves: it leaves one partial logit tile per wave, [wave][row][16] floats, in
+// the buffer returned (the enforcer adds them up). bias: LDS copy of every
+// layer's bias.
+template <int P, int T, int CH1, int CHH, int NHH>
+__device__ __forceinline__ float* mlp_mfma(const DevTree& t, const WaveWeights<P, T, CH1, CHH, NHH>& W, int nrows,
+                                           uint8_t* bufA, uint8_t* bufB, const float* bias, const int* bias_off)
+{
+    using WW = WaveWeights<P, T, CH1, CHH, NHH>;
+    constexpr int kc = Traits<P>::kChunk, es = Traits<P>::kEsize, kRTT = Rows<P>::kRTT, kRT = Rows<P>::kRT;
+    const int lane = threadIdx.x & 63, wave = wave_id(), g = lane >> 4, c16 = lane & 15;
+    const int art = (nrows + 15) >> 4;
+    constexpr int s0 = CH1 * kc * es + 16, sh = CHH * kc * es + 16;
+    layer_regs<P, T, CH1>(W.w1, CH1, bufA, s0, bufB, sh, bias + bias_off[0], t.deq[0], t.inv_in_scale[1], art, wave,
+                          g, c16);
+    lds_barrier();
+    uint8_t* in = bufB;
+    uint8_t* out = bufA;
+    if constexpr (NHH > 0) {
+        layer_regs<P, T, CHH>(W.wh, CHH, bufB, sh, bufA, sh, bias + bias_off[1], t.deq[1], t.inv_in_scale[2], art,
+                              wave, g, c16);
+        lds_barrier();
+        in = bufA;
+        out = bufB;
+    }
+    // output layer: this wave's slice of the reduction, partial tile to LDS
+    float* part = reinterpret_cast<float*>(out);
+    floatx4 acc[kRTT];
+#pragma unroll
+    for (int rt = 0; rt < kRTT; ++rt)
+        acc[rt] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const uint8_t* bp = in + c16 * sh + g * (kc / 4) * es;
+#pragma unroll
+    for (int j = 0; j < WW::CPW; ++j) {
+        const int c = wave * WW::CPW + j;
+        if (c < CHH) {
+#pragma unroll
+            for (int rt = 0; rt < kRTT; ++rt)
+                if (rt < art) {
+                    const uint4 b = *reinterpret_cast<const uint4*>(bp + rt * 16 * sh + c * kc * es);
+                    mma_chunk<P>(W.wo[j], b, acc[rt]);
+                }
+        }
+    }
+#pragma unroll
+    for (int rt = 0; rt < kRTT; ++rt)
+        if (rt < art)
+            *reinterpret_cast<floatx4*>(part + (size_t)(wave * kRT + rt * 16 + c16) * 16 + g * 4) = acc[rt];
+    lds_barrier();
+    return part;
+}
+
+}  // namespace
+
+}  // namespace cyrus

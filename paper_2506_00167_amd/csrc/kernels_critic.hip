@@ -13,6 +13,7 @@
 #include "cyrus_device.h"
 #include "cyrus_kernels.h"
 #include "cyrus_mlp.h"
+#include "cyrus_regmlp.h"
 
 namespace cyrus {
 
@@ -56,11 +57,13 @@ __device__ __forceinline__ float critic_feature(const CriticArgs& a, const Criti
     return 0.f;
 }
 
-template <int RTT>
-__global__ __launch_bounds__(kThreads) void critic_kernel(CriticArgs a)
+// One workgroup's share of a tile: staging, then the networks of its role.
+// run_net(n, nrows, bufA, bufB, zl, bias) evaluates network n over the
+// tile's rows, whose inputs are in bufA (row stride in_pad[0] + 4 floats),
+// and leaves its outputs, bias included, in zl[row * kLogitStride + e].
+template <int RT, class RunNet>
+__device__ __forceinline__ void critic_tile(const CriticArgs& a, uint8_t* smem, RunNet run_net)
 {
-    constexpr int RT = 16 * RTT;
-    extern __shared__ __align__(16) uint8_t smem[];
     uint8_t* bufA = smem;
     uint8_t* bufB = smem + a.bufsize;
     float* zl = reinterpret_cast<float*>(smem + 2 * a.bufsize);
@@ -84,25 +87,73 @@ __global__ __launch_bounds__(kThreads) void critic_kernel(CriticArgs a)
     const int nin = min(nrows + 1, rows - j0);  // staged rows: the tile's, and the next one if it exists
     st.h0 = j0 / M;
     const int nsamp = (j0 + nin - 1) / M - st.h0 + 1;
-    // stage the biases of all five networks and the tile's inputs; every
-    // global load of a thread is independent of its earlier stores
+    // stage the biases of all five networks and the tile's inputs: every
+    // thread issues all its global loads (fixed, unrolled counts) before its
+    // first LDS store, so the staging costs one memory latency. A layer has at
+    // most kThreads outputs, so a thread copies at most one bias per layer.
+    const int tid = threadIdx.x;
+    float bv[5][kMaxLayers];
+#pragma unroll
+    for (int n = 0; n < 5; ++n)
+#pragma unroll
+        for (int l = 0; l < kMaxLayers; ++l) {
+            const DevTree& t = a.nets[n];
+            bv[n][l] = (l < t.n_layers && tid < t.out_pad[l]) ? gptr(t.b[l])[tid] : 0.f;
+        }
+    constexpr int nUe = ((RT + 2) * 3 * 16 + kThreads - 1) / kThreads;  // samples touched <= RT + 2, E <= 16
+    constexpr int nC = ((RT + 1) * 16 + kThreads - 1) / kThreads;
+    constexpr int nY = (RT * 16 + kThreads - 1) / kThreads;
+    int32_t uev[nUe], cv[nC];
+    float yv[nY];
+#pragma unroll
+    for (int q = 0; q < nUe; ++q) {
+        const int i = tid + q * kThreads;
+        uev[q] = i < nsamp * 3 * E ? gptr(a.ue)[(int64_t)st.h0 * 3 * E + i] : 0;
+    }
+    const int32_t kv = tid < nin ? gptr(a.k)[j0 + tid] : 0;
+#pragma unroll
+    for (int q = 0; q < nC; ++q) {
+        const int i = tid + q * kThreads;
+        cv[q] = i < nin * E ? (int32_t)gptr(a.c)[(int64_t)j0 * E + i] : 0;
+    }
+#pragma unroll
+    for (int q = 0; q < nY; ++q) {
+        const int i = tid + q * kThreads;
+        yv[q] = i < nrows * E ? gptr(a.y)[(int64_t)j0 * E + i] : 0.f;
+    }
+#pragma unroll
     for (int n = 0; n < 5; ++n) {
         const DevTree& t = a.nets[n];
         int off = a.bias_off[n];
-        for (int l = 0; l < t.n_layers; ++l) {
-            for (int i = threadIdx.x; i < t.out_pad[l]; i += kThreads)
-                bias[off + i] = gptr(t.b[l])[i];
-            off += t.out_pad[l];
+#pragma unroll
+        for (int l = 0; l < kMaxLayers; ++l) {
+            if (l < t.n_layers) {
+                if (tid < t.out_pad[l])
+                    bias[off + tid] = bv[n][l];
+                off += t.out_pad[l];
+            }
         }
     }
-    for (int i = threadIdx.x; i < nsamp * 3 * E; i += kThreads)
-        st.ue[i] = gptr(a.ue)[(int64_t)st.h0 * 3 * E + i];
-    for (int i = threadIdx.x; i < nin; i += kThreads)
-        st.k[i] = gptr(a.k)[j0 + i];
-    for (int i = threadIdx.x; i < nin * E; i += kThreads)
-        st.c[i] = gptr(a.c)[(int64_t)j0 * E + i];
-    for (int i = threadIdx.x; i < nrows * E; i += kThreads)
-        st.y[i] = gptr(a.y)[(int64_t)j0 * E + i];
+#pragma unroll
+    for (int q = 0; q < nUe; ++q) {
+        const int i = tid + q * kThreads;
+        if (i < nsamp * 3 * E)
+            st.ue[i] = uev[q];
+    }
+    if (tid < nin)
+        st.k[tid] = kv;
+#pragma unroll
+    for (int q = 0; q < nC; ++q) {
+        const int i = tid + q * kThreads;
+        if (i < nin * E)
+            st.c[i] = cv[q];
+    }
+#pragma unroll
+    for (int q = 0; q < nY; ++q) {
+        const int i = tid + q * kThreads;
+        if (i < nrows * E)
+            st.y[i] = yv[q];
+    }
     lds_barrier();
 
     // network input rows: critic (5E+2, stride sc) or actor (4E+2, stride sa)
@@ -124,7 +175,7 @@ __global__ __launch_bounds__(kThreads) void critic_kernel(CriticArgs a)
     };
     const int wc = a.nets[1].in_pad[0], sc = wc + 4;
     const int wa = a.nets[0].in_pad[0], sa = wa + 4;
-    auto net = [&](int n) { run_mlp<kFP32, RTT>(a.nets[n], nrows, bufA, bufB, zl, bias + a.bias_off[n], 0, 0); };
+    auto net = [&](int n) { run_net(n, nrows, bufA, bufB, zl, bias); };
 
     if (role < 2) {
         // Q1 or Q2 on the stored action
@@ -173,37 +224,98 @@ __global__ __launch_bounds__(kThreads) void critic_kernel(CriticArgs a)
         a.tq[(int64_t)(role - 2) * rows + j0 + row] = zl[row * kLogitStride];
 }
 
-// The target of Eq. (4) per row, then loss[i] = mean over rows of
-// (q[i][row] - qhat[row])^2; every thread handles a fixed stride of rows,
-// then a fixed-order tree in LDS.
-__global__ __launch_bounds__(256) void critic_loss_kernel(CriticArgs a)
+template <int RTT>
+__global__ __launch_bounds__(kThreads) void critic_kernel(CriticArgs a)
 {
-    __shared__ float part[2][256];
-    const int rows = a.H * a.M;
+    extern __shared__ __align__(16) uint8_t smem[];
+    critic_tile<16 * RTT>(a, smem, [&](int n, int nrows, uint8_t* bufA, uint8_t* bufB, float* zl, const float* bias) {
+        run_mlp<kFP32, RTT>(a.nets[n], nrows, bufA, bufB, zl, bias + a.bias_off[n], 0, 0);
+    });
+}
+
+// Register-resident variant for networks of two hidden layers of 128 T
+// neurons, CH1 first-layer chunks (all five networks padded alike) and at
+// most 16 outputs. For each network a workgroup runs, every wave loads its
+// fragments into registers in one burst (the target critic of roles 2 and 3
+// reuses the registers of the actor), and the layers run from registers as in
+// the subtree kernel. The waves' partial outputs are added in wave order.
+template <int T, int CH1, int RTT>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 2))) void critic_regs_kernel(
+    CriticArgs a)
+{
+    constexpr int CHH = 8 * T, kRT = Rows<kFP32>::kRT;
+    static_assert(16 * RTT <= kRT, "row tiles of one pass");
+    extern __shared__ __align__(16) uint8_t smem[];
+    WaveWeights<kFP32, T, CH1, CHH, 1> W;
+    const int lane = threadIdx.x & 63, wave = wave_id();
+    critic_tile<16 * RTT>(a, smem, [&](int n, int nrows, uint8_t* bufA, uint8_t* bufB, float* zl, const float* bias) {
+        const DevTree& t = a.nets[n];
+        load_weights(t, W, wave, lane);
+        const int boff[3] = {0, t.out_pad[0], t.out_pad[0] + t.out_pad[1]};
+        const float* b = bias + a.bias_off[n];
+        const float* part = mlp_mfma<kFP32, T, CH1, CHH, 1>(t, W, nrows, bufA, bufB, b, boff);
+        for (int idx = threadIdx.x; idx < nrows * 16; idx += kThreads) {
+            const int row = idx >> 4, e = idx & 15;
+            float s = 0.f;
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w)
+                s += part[(size_t)(w * kRT + row) * 16 + e];
+            zl[row * kLogitStride + e] = s + b[boff[2] + e];
+        }
+        lds_barrier();
+    });
+}
+
+// The target of Eq. (4) per row, then loss[i] = mean over rows of
+// (q[i][row] - qhat[row])^2. Thread t takes rows t, t + 512, ... in batches of
+// four per thread whose loads are all issued before the arithmetic; the
+// thread sums then meet in a fixed-order tree in LDS.
+__global__ __launch_bounds__(kThreads) void critic_loss_kernel(CriticArgs a)
+{
+    constexpr int kB = 4;
+    __shared__ float part[2][kThreads];
+    const int rows = a.H * a.M, tid = threadIdx.x;
     float s0 = 0.f, s1 = 0.f;
-    for (int j = threadIdx.x; j < rows; j += 256) {
-        float target;
-        if ((j % a.M) + 1 == a.M)
-            target = a.reward[j / a.M];
-        else
-            target = a.discount * (fminf(a.tq[j], a.tq[rows + j]) - a.entropy_coef * a.tlp[j]);
-        a.qhat[j] = target;
-        const float d0 = a.q[j] - target, d1 = a.q[rows + j] - target;
-        s0 += d0 * d0;
-        s1 += d1 * d1;
+    for (int base = 0; base < rows; base += kB * kThreads) {
+        float q0[kB], q1[kB], t1[kB], t2[kB], lp[kB], rw[kB];
+#pragma unroll
+        for (int b = 0; b < kB; ++b) {
+            const int j = base + b * kThreads + tid;
+            const bool in = j < rows;
+            const int jj = in ? j : 0;
+            q0[b] = a.q[jj];
+            q1[b] = a.q[rows + jj];
+            t1[b] = a.tq[jj];
+            t2[b] = a.tq[rows + jj];
+            lp[b] = a.tlp[jj];
+            rw[b] = a.reward[jj / a.M];
+        }
+#pragma unroll
+        for (int b = 0; b < kB; ++b) {
+            const int j = base + b * kThreads + tid;
+            if (j < rows) {
+                const float target = (j % a.M) + 1 == a.M
+                                         ? rw[b]
+                                         : a.discount * (fminf(t1[b], t2[b]) - a.entropy_coef * lp[b]);
+                a.qhat[j] = target;
+                const float d0 = q0[b] - target, d1 = q1[b] - target;
+                s0 += d0 * d0;
+                s1 += d1 * d1;
+            }
+        }
     }
-    part[0][threadIdx.x] = s0;
-    part[1][threadIdx.x] = s1;
+    part[0][tid] = s0;
+    part[1][tid] = s1;
     __syncthreads();
-    for (int w = 128; w >= 1; w >>= 1) {
-        if ((int)threadIdx.x < w) {
-            part[0][threadIdx.x] += part[0][threadIdx.x + w];
-            part[1][threadIdx.x] += part[1][threadIdx.x + w];
+    for (int w = kThreads / 2; w >= 1; w >>= 1) {
+        if (tid < w) {
+            part[0][tid] += part[0][tid + w];
+            part[1][tid] += part[1][tid + w];
         }
         __syncthreads();
     }
-    if (threadIdx.x < 2)
-        a.loss[threadIdx.x] = part[threadIdx.x][0] / (float)rows;
+    if (tid < 2)
+        a.loss[tid] = part[tid][0] / (float)rows;
 }
 
 }  // namespace
@@ -215,34 +327,48 @@ size_t critic_lds_bytes(int bufsize, int bias_total, int rtt)
     return 2 * (size_t)bufsize + RT * kLogitStride * 4 + (size_t)bias_total * 4 + RT * 4 + RT * 16 * 4 * 2 + stage;
 }
 
-template <int RTT>
-static hipError_t launch_critic_t(const CriticArgs& a, size_t lds, hipStream_t s)
+template <void (*K)(CriticArgs)>
+static hipError_t launch_critic_k(int tile_rows, const CriticArgs& a, size_t lds, hipStream_t s)
 {
     static bool attr = false;
     if (!attr) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&critic_kernel<RTT>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(K), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  160 * 1024);
         attr = true;
     }
     const int rows = a.H * a.M;
-    const int grid = 4 * ((rows + 16 * RTT - 1) / (16 * RTT));  // four roles per row tile
-    hipLaunchKernelGGL((critic_kernel<RTT>), dim3(grid), dim3(kThreads), lds, s, a);
+    const int grid = 4 * ((rows + tile_rows - 1) / tile_rows);  // four roles per row tile
+    hipLaunchKernelGGL(K, dim3(grid), dim3(kThreads), lds, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL(critic_loss_kernel, dim3(1), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(critic_loss_kernel, dim3(1), dim3(kThreads), 0, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_critic(const CriticArgs& a, int rtt, size_t lds, hipStream_t s)
+hipError_t launch_critic(const CriticArgs& a, int rtt, int regs_t, int regs_ch1, size_t lds, hipStream_t s)
 {
+    if (regs_t == 2) {
+        if (regs_ch1 == 1)
+            return launch_critic_k<critic_regs_kernel<2, 1, 2>>(32, a, lds, s);
+        if (regs_ch1 == 2)
+            return launch_critic_k<critic_regs_kernel<2, 2, 2>>(32, a, lds, s);
+        return launch_critic_k<critic_regs_kernel<2, 3, 2>>(32, a, lds, s);
+    }
+    if (regs_t == 1) {
+        if (regs_ch1 == 1)
+            return launch_critic_k<critic_regs_kernel<1, 1, 2>>(32, a, lds, s);
+        if (regs_ch1 == 2)
+            return launch_critic_k<critic_regs_kernel<1, 2, 2>>(32, a, lds, s);
+        return launch_critic_k<critic_regs_kernel<1, 3, 2>>(32, a, lds, s);
+    }
     switch (rtt) {
     case 4:
-        return launch_critic_t<4>(a, lds, s);
+        return launch_critic_k<critic_kernel<4>>(64, a, lds, s);
     case 2:
-        return launch_critic_t<2>(a, lds, s);
+        return launch_critic_k<critic_kernel<2>>(32, a, lds, s);
     default:
-        return launch_critic_t<1>(a, lds, s);
+        return launch_critic_k<critic_kernel<1>>(16, a, lds, s);
     }
 }
 
