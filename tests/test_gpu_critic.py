@@ -50,10 +50,22 @@ def _check(cfg, wseed, bseed, seed, episode):
 
 
 def test_critic_small_ragged():
-    # 37 samples x 7 steps = 259 rows: four 64-row tiles and a ragged tail
+    # 37 samples x 7 steps = 259 rows: whole row tiles and a ragged tail; a
+    # single 128-wide actor layer takes the streamed-weight kernel
     cfg = wl.CriticConfig(num_ue=4, max_arrival=2, num_minislots=7, num_samples=37, actor_hidden=(128,),
                           critic_hidden=(256, 128), discount=0.95, entropy_coef=0.1)
     _check(cfg, 61, 62, 5, 9)
+
+
+@pytest.mark.parametrize("shape", [
+    # register-resident kernel with 128-wide layers (one neuron tile per
+    # wave), 5E+2 = 17 inputs in two chunks, 41 x 5 = 205 rows (ragged tile)
+    dict(num_ue=3, num_minislots=5, num_samples=41, actor_hidden=(128, 128), critic_hidden=(128, 128)),
+    # 256-wide layers, 5E+2 = 12 inputs in one chunk, 23 x 7 = 161 rows
+    dict(num_ue=2, num_minislots=7, num_samples=23),
+])
+def test_critic_register_shapes(shape):
+    _check(wl.CriticConfig(**shape), 67, 68, 11, 3)
 
 
 def test_critic_ric_shape():
