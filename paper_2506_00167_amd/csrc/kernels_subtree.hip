@@ -249,13 +249,25 @@ __device__ __forceinline__ void finish_rows(const DevTree& t, const SubtreeSmem&
     for (int base = 0; base < nrows; base += kThreads / G) {
         const int row = base + (int)threadIdx.x / G, e = (int)threadIdx.x % G;
         if (row < nrows) {
+            // every LDS value of the row is requested before the first add:
+            // the UE's caps and parent state, then the partial logits
+            const int k = k_of(row);
+            const int R = e < E ? sm.R[e] : 0;
+            const int rsum = sm.misc[0];
+            const uint8_t c = e < E ? cin_of(row)[e] : (uint8_t)0;
             float z = 0.f;
             if (e < E) {
+                // (the adds keep the wave order)
+                float pw[kWaves];
+#pragma unroll
+                for (int w = 0; w < kWaves; ++w)
+                    pw[w] = part[(size_t)(w * RT + row) * 16 + e];
+                const float be = bo[e];
                 float acc = 0.f;
 #pragma unroll
                 for (int w = 0; w < kWaves; ++w)
-                    acc += part[(size_t)(w * RT + row) * 16 + e];
-                z = acc * deq + bo[e];
+                    acc += pw[w];
+                z = acc * deq + be;
                 if (EXT && t.head == kGaussianHead) {  // one output tile: mu (0..E-1), log sigma (E..2E-1)
                     float acc2 = 0.f;
 #pragma unroll
@@ -264,13 +276,10 @@ __device__ __forceinline__ void finish_rows(const DevTree& t, const SubtreeSmem&
                     z = gaussian_log_share(z, acc2 * deq + bo[E + e], t.seed, t.tti, id_of(row), e);
                 }
             }
-            const int k = k_of(row);
-            const int R = e < E ? sm.R[e] : 0;
-            const int a = enforce_dpp<G>(E, e, z, R, sm.misc[0], t.U * k, sm.zl + row * kLogitStride,
+            const int a = enforce_dpp<G>(E, e, z, R, rsum, t.U * k, sm.zl + row * kLogitStride,
                                          EXT ? t.rounding : (int)kLargestRemainder);
+            const uint8_t st = (uint8_t)(c + a);
             if (e < E) {
-                const uint8_t c = cin_of(row)[e];
-                const uint8_t st = (uint8_t)(c + a);
                 sout_of(row)[e] = st;
                 const int64_t node = node_of(row);
                 if (node >= 0) {
