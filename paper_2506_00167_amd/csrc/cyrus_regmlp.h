@@ -56,23 +56,23 @@ __device__ __forceinline__ void load_weights(const DevTree& t, WaveWeights<P, T,
                 W.wh[tt][c] = gh[((size_t)nt * CHH + c) * 64 + lane];
         }
     }
+    // output-layer chunks wave, wave + kWaves, ...: for FP32 (chunk = one
+    // neuron tile) these are the wave's own tiles of the last hidden layer
     const uint4* go = reinterpret_cast<const uint4*>(t.w[NHH + 1]);
 #pragma unroll
     for (int j = 0; j < WW::CPW; ++j) {
-        const int c = wave * WW::CPW + j;
+        const int c = wave + kWaves * j;
         W.wo[j] = (c < CHH) ? go[(size_t)c * 64 + lane] : uint4{0, 0, 0, 0};
     }
 }
 
-// One layer with register-resident A fragments: out = act(A * in) for the
-// wave's T neuron tiles over `art` row tiles.
+// acc = A * in for the wave's T neuron tiles over `art` row tiles (inputs
+// from LDS, row stride sin bytes).
 template <int P, int T, int NCH>
-__device__ __forceinline__ void layer_regs(const uint4 (&A)[T][NCH], int nch, const uint8_t* in, int sin,
-                                           uint8_t* out, int sout, const float* bias, float deq, float inv_next,
-                                           int art, int wave, int g, int c16)
+__device__ __forceinline__ void layer_acc(const uint4 (&A)[T][NCH], int nch, const uint8_t* in, int sin, int art,
+                                          int g, int c16, floatx4 (&acc)[T][Rows<P>::kRTT])
 {
     constexpr int kc = Traits<P>::kChunk, es = Traits<P>::kEsize, kRTT = Rows<P>::kRTT;
-    floatx4 acc[T][kRTT];
 #pragma unroll
     for (int tt = 0; tt < T; ++tt)
 #pragma unroll
@@ -113,6 +113,18 @@ __device__ __forceinline__ void layer_regs(const uint4 (&A)[T][NCH], int nch, co
             }
         }
     }
+}
+
+// One layer with register-resident A fragments: out = act(A * in) for the
+// wave's T neuron tiles over `art` row tiles.
+template <int P, int T, int NCH>
+__device__ __forceinline__ void layer_regs(const uint4 (&A)[T][NCH], int nch, const uint8_t* in, int sin,
+                                           uint8_t* out, int sout, const float* bias, float deq, float inv_next,
+                                           int art, int wave, int g, int c16)
+{
+    constexpr int es = Traits<P>::kEsize, kRTT = Rows<P>::kRTT;
+    floatx4 acc[T][kRTT];
+    layer_acc<P, T, NCH>(A, nch, in, sin, art, g, c16, acc);
 #pragma unroll
     for (int tt = 0; tt < T; ++tt) {
         const int nt = wave + kWaves * tt;
@@ -146,6 +158,42 @@ __device__ __forceinline__ float* mlp_mfma(const DevTree& t, const WaveWeights<P
     layer_regs<P, T, CH1>(W.w1, CH1, bufA, s0, bufB, sh, bias + bias_off[0], t.deq[0], t.inv_in_scale[1], art, wave,
                           g, c16);
     lds_barrier();
+    if constexpr (P == kFP32 && NHH > 0) {
+        // FP32: the last hidden layer feeds the output layer from registers.
+        // Lane (g, c16)'s accumulator of tile tt holds neurons 16 nt + 4g ..
+        // 16 nt + 4g + 3 of row rt*16 + c16: the B fragment of output chunk
+        // nt, which is this wave's W.wo[tt]. Its activations never go to LDS.
+        static_assert(WW::CPW == T, "output-layer chunks are the wave's own tiles");
+        floatx4 hacc[T][kRTT];
+        layer_acc<P, T, CHH>(W.wh, CHH, bufB, sh, art, g, c16, hacc);
+        floatx4 acc[kRTT];
+#pragma unroll
+        for (int rt = 0; rt < kRTT; ++rt)
+            acc[rt] = floatx4{0.f, 0.f, 0.f, 0.f};
+        const float deq = t.deq[1];
+#pragma unroll
+        for (int tt = 0; tt < T; ++tt) {
+            const float* bb = bias + bias_off[1] + (wave + kWaves * tt) * 16 + g * 4;
+            const float b0 = bb[0], b1 = bb[1], b2 = bb[2], b3 = bb[3];
+#pragma unroll
+            for (int rt = 0; rt < kRTT; ++rt)
+                if (rt < art) {
+                    const uint4 h = {__float_as_uint(fmaxf(hacc[tt][rt][0] * deq + b0, 0.f)),
+                                     __float_as_uint(fmaxf(hacc[tt][rt][1] * deq + b1, 0.f)),
+                                     __float_as_uint(fmaxf(hacc[tt][rt][2] * deq + b2, 0.f)),
+                                     __float_as_uint(fmaxf(hacc[tt][rt][3] * deq + b3, 0.f))};
+                    mma_chunk<P>(W.wo[tt], h, acc[rt]);
+                }
+        }
+        // bufA (the inputs, consumed before the last barrier) takes the partials
+        float* part = reinterpret_cast<float*>(bufA);
+#pragma unroll
+        for (int rt = 0; rt < kRTT; ++rt)
+            if (rt < art)
+                *reinterpret_cast<floatx4*>(part + (size_t)(wave * kRT + rt * 16 + c16) * 16 + g * 4) = acc[rt];
+        lds_barrier();
+        return part;
+    }
     uint8_t* in = bufB;
     uint8_t* out = bufA;
     if constexpr (NHH > 0) {
@@ -164,7 +212,7 @@ __device__ __forceinline__ float* mlp_mfma(const DevTree& t, const WaveWeights<P
     const uint8_t* bp = in + c16 * sh + g * (kc / 4) * es;
 #pragma unroll
     for (int j = 0; j < WW::CPW; ++j) {
-        const int c = wave * WW::CPW + j;
+        const int c = wave + kWaves * j;
         if (c < CHH) {
 #pragma unroll
             for (int rt = 0; rt < kRTT; ++rt)

@@ -151,7 +151,7 @@ __device__ __forceinline__ float* mlp_valu(const DevTree& t, const WaveWeights<k
         float acc = 0.f;
 #pragma unroll
         for (int j = 0; j < WW::CPW; ++j) {
-            const int c = wave * WW::CPW + j;
+            const int c = wave + kWaves * j;
             if (c < CHH) {
                 const floatx4 h = *reinterpret_cast<const floatx4*>(in + r * sh + 4 * g + 16 * c);
                 acc = fmaf(__uint_as_float(W.wo[j].x), h[0], acc);
