@@ -330,6 +330,26 @@ __device__ __forceinline__ float frag_value(const uint4& f, int j)
 }
 
 // ---------------------------------------------------------------------------
+// Groups of 8 or 16 lanes on the DPP fabric: butterfly all-reductions with
+// quad permutations (xor 1, xor 2), the half-row mirror (lane i <-> 7-i) and
+// the row mirror (lane i <-> 15-i). Every lane of the group ends with the same
+// value (each step adds two partial sums in either order).
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+constexpr int kDppXor1 = 0xB1;        // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;        // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141;  // row_half_mirror
+constexpr int kDppMirror = 0x140;      // row_mirror
+
+// ---------------------------------------------------------------------------
 // Lane-parallel enforcer: a group of G lanes (G a power of two >= E, G <= 64)
 // handles one node, lane e of the group UE e. Softmax, the capped split and
 // largest remainder use butterfly reductions inside the group; the extra unit
@@ -345,9 +365,19 @@ __device__ __forceinline__ float group_sum(float v)
     return v;
 }
 
+// The exact group reductions (integer sums, minima, maxima) of 8- and
+// 16-lane groups run on the DPP fabric, wider groups through lane shuffles.
 template <int G>
 __device__ __forceinline__ float group_max(float v)
 {
+    if constexpr (G == 8 || G == 16) {
+        v = fmaxf(v, dpp_f<kDppXor1>(v));
+        v = fmaxf(v, dpp_f<kDppXor2>(v));
+        v = fmaxf(v, dpp_f<kDppHalfMirror>(v));
+        if constexpr (G == 16)
+            v = fmaxf(v, dpp_f<kDppMirror>(v));
+        return v;
+    }
 #pragma unroll
     for (int m = G / 2; m >= 1; m >>= 1)
         v = fmaxf(v, __shfl_xor(v, m, G));
@@ -357,6 +387,14 @@ __device__ __forceinline__ float group_max(float v)
 template <int G>
 __device__ __forceinline__ int group_isum(int v)
 {
+    if constexpr (G == 8 || G == 16) {
+        v += dpp_i<kDppXor1>(v);
+        v += dpp_i<kDppXor2>(v);
+        v += dpp_i<kDppHalfMirror>(v);
+        if constexpr (G == 16)
+            v += dpp_i<kDppMirror>(v);
+        return v;
+    }
 #pragma unroll
     for (int m = G / 2; m >= 1; m >>= 1)
         v += __shfl_xor(v, m, G);
@@ -366,6 +404,14 @@ __device__ __forceinline__ int group_isum(int v)
 template <int G>
 __device__ __forceinline__ float group_min(float v)
 {
+    if constexpr (G == 8 || G == 16) {
+        v = fminf(v, dpp_f<kDppXor1>(v));
+        v = fminf(v, dpp_f<kDppXor2>(v));
+        v = fminf(v, dpp_f<kDppHalfMirror>(v));
+        if constexpr (G == 16)
+            v = fminf(v, dpp_f<kDppMirror>(v));
+        return v;
+    }
 #pragma unroll
     for (int m = G / 2; m >= 1; m >>= 1)
         v = fminf(v, __shfl_xor(v, m, G));
@@ -375,6 +421,14 @@ __device__ __forceinline__ float group_min(float v)
 template <int G>
 __device__ __forceinline__ int group_imax(int v)
 {
+    if constexpr (G == 8 || G == 16) {
+        v = max(v, dpp_i<kDppXor1>(v));
+        v = max(v, dpp_i<kDppXor2>(v));
+        v = max(v, dpp_i<kDppHalfMirror>(v));
+        if constexpr (G == 16)
+            v = max(v, dpp_i<kDppMirror>(v));
+        return v;
+    }
 #pragma unroll
     for (int m = G / 2; m >= 1; m >>= 1)
         v = max(v, __shfl_xor(v, m, G));
@@ -384,6 +438,14 @@ __device__ __forceinline__ int group_imax(int v)
 template <int G>
 __device__ __forceinline__ int group_imin(int v)
 {
+    if constexpr (G == 8 || G == 16) {
+        v = min(v, dpp_i<kDppXor1>(v));
+        v = min(v, dpp_i<kDppXor2>(v));
+        v = min(v, dpp_i<kDppHalfMirror>(v));
+        if constexpr (G == 16)
+            v = min(v, dpp_i<kDppMirror>(v));
+        return v;
+    }
 #pragma unroll
     for (int m = G / 2; m >= 1; m >>= 1)
         v = min(v, __shfl_xor(v, m, G));
@@ -478,26 +540,6 @@ __device__ __forceinline__ int enforce_group(int E, int e, float z, int R, int r
         rank += (fq[q] > frac || (fq[q] == frac && q < e)) ? 1 : 0;
     return f + ((elig && rank < r) ? 1 : 0);
 }
-
-// ---------------------------------------------------------------------------
-// Groups of 8 or 16 lanes on the DPP fabric: butterfly all-reductions with
-// quad permutations (xor 1, xor 2), the half-row mirror (lane i <-> 7-i) and
-// the row mirror (lane i <-> 15-i). Every lane of the group ends with the same
-// value (each step adds two partial sums in either order).
-template <int CTRL>
-__device__ __forceinline__ float dpp_f(float v)
-{
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
-}
-template <int CTRL>
-__device__ __forceinline__ int dpp_i(int v)
-{
-    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
-}
-constexpr int kDppXor1 = 0xB1;        // quad_perm [1,0,3,2]
-constexpr int kDppXor2 = 0x4E;        // quad_perm [2,3,0,1]
-constexpr int kDppHalfMirror = 0x141;  // row_half_mirror
-constexpr int kDppMirror = 0x140;      // row_mirror
 
 template <int G>
 __device__ __forceinline__ float dsum(float v)
