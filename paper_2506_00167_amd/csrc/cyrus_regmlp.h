@@ -11,6 +11,8 @@ namespace cyrus {
 
 namespace {
 
+typedef short short4v __attribute__((ext_vector_type(4)));
+
 // Row tiles per pass: 64 rows for BF16/FP8; 48 for FP32, whose register-
 // resident weights leave room for fewer accumulators.
 template <int P>
@@ -31,6 +33,10 @@ struct WaveWeights {
     uint4 w1[T][CH1];
     uint4 wh[NHH > 0 ? T : 1][NHH > 0 ? CHH : 1];
     uint4 wo[CPW];
+    // BF16 with a hidden->hidden layer: the output-layer weights of the
+    // wave's own last-hidden-layer tiles in the 16x16x16 MFMA layout (lane
+    // (g, i): W_o[i][16 nt + 4g .. 16 nt + 4g + 3]), fed from registers
+    uint2 wo16[(P == kBF16 && NHH > 0) ? T : 1];
 };
 
 template <int P, int T, int CH1, int CHH, int NHH>
@@ -63,6 +69,18 @@ __device__ __forceinline__ void load_weights(const DevTree& t, WaveWeights<P, T,
     for (int j = 0; j < WW::CPW; ++j) {
         const int c = wave + kWaves * j;
         W.wo[j] = (c < CHH) ? go[(size_t)c * 64 + lane] : uint4{0, 0, 0, 0};
+    }
+    if constexpr (P == kBF16 && NHH > 0) {
+        // W_o[i][k], k = 16 nt + 4g + j, sits in 32-wide chunk k / 32 at lane
+        // i + 16 ((k % 32) / 8), elements (k % 8): four consecutive BF16
+        const uint8_t* gob = t.w[NHH + 1];
+        const int g = lane >> 4, i = lane & 15;
+#pragma unroll
+        for (int tt = 0; tt < T; ++tt) {
+            const int nt = wave + kWaves * tt;
+            const int src = i + 16 * (2 * (nt & 1) + (g >> 1));
+            W.wo16[tt] = *reinterpret_cast<const uint2*>(gob + ((size_t)(nt >> 1) * 64 + src) * 16 + 8 * (g & 1));
+        }
     }
 }
 
@@ -158,12 +176,15 @@ __device__ __forceinline__ float* mlp_mfma(const DevTree& t, const WaveWeights<P
     layer_regs<P, T, CH1>(W.w1, CH1, bufA, s0, bufB, sh, bias + bias_off[0], t.deq[0], t.inv_in_scale[1], art, wave,
                           g, c16);
     lds_barrier();
-    if constexpr (P == kFP32 && NHH > 0) {
-        // FP32: the last hidden layer feeds the output layer from registers.
-        // Lane (g, c16)'s accumulator of tile tt holds neurons 16 nt + 4g ..
-        // 16 nt + 4g + 3 of row rt*16 + c16: the B fragment of output chunk
-        // nt, which is this wave's W.wo[tt]. Its activations never go to LDS.
-        static_assert(WW::CPW == T, "output-layer chunks are the wave's own tiles");
+    if constexpr ((P == kFP32 || P == kBF16) && NHH > 0) {
+        // The last hidden layer feeds the output layer from registers. Lane
+        // (g, c16)'s accumulator of tile tt holds neurons 16 nt + 4g ..
+        // 16 nt + 4g + 3 of row rt*16 + c16: the B fragment of a 16-deep step
+        // of the output layer over tile nt (FP32: the 16x16x4 chunk nt, this
+        // wave's W.wo[tt]; BF16: one 16x16x16 MFMA with W.wo16[tt], the
+        // activations rounded to BF16 as an LDS store would). Its activations
+        // never go to LDS.
+        static_assert(P != kFP32 || WW::CPW == T, "output-layer chunks are the wave's own tiles");
         floatx4 hacc[T][kRTT];
         layer_acc<P, T, CHH>(W.wh, CHH, bufB, sh, art, g, c16, hacc);
         floatx4 acc[kRTT];
@@ -178,11 +199,19 @@ __device__ __forceinline__ float* mlp_mfma(const DevTree& t, const WaveWeights<P
 #pragma unroll
             for (int rt = 0; rt < kRTT; ++rt)
                 if (rt < art) {
-                    const uint4 h = {__float_as_uint(fmaxf(hacc[tt][rt][0] * deq + b0, 0.f)),
-                                     __float_as_uint(fmaxf(hacc[tt][rt][1] * deq + b1, 0.f)),
-                                     __float_as_uint(fmaxf(hacc[tt][rt][2] * deq + b2, 0.f)),
-                                     __float_as_uint(fmaxf(hacc[tt][rt][3] * deq + b3, 0.f))};
-                    mma_chunk<P>(W.wo[tt], h, acc[rt]);
+                    const float h0 = fmaxf(hacc[tt][rt][0] * deq + b0, 0.f);
+                    const float h1 = fmaxf(hacc[tt][rt][1] * deq + b1, 0.f);
+                    const float h2 = fmaxf(hacc[tt][rt][2] * deq + b2, 0.f);
+                    const float h3 = fmaxf(hacc[tt][rt][3] * deq + b3, 0.f);
+                    if constexpr (P == kFP32) {
+                        const uint4 h = {__float_as_uint(h0), __float_as_uint(h1), __float_as_uint(h2),
+                                         __float_as_uint(h3)};
+                        mma_chunk<P>(W.wo[tt], h, acc[rt]);
+                    } else {
+                        const uint2 h = {bf16x2_bits(h0, h1), bf16x2_bits(h2, h3)};
+                        acc[rt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(
+                            __builtin_bit_cast(short4v, W.wo16[tt]), __builtin_bit_cast(short4v, h), acc[rt], 0, 0, 0);
+                    }
                 }
         }
         // bufA (the inputs, consumed before the last barrier) takes the partials
