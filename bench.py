@@ -194,6 +194,28 @@ def critic_leg(steps: int, warmup: int, stream):
             "achieved_tflops": tflops, "mfma_frac": tflops / PEAK_TFLOPS["fp32"]}
 
 
+def gemm_peak(dtype: str, n: int = 8192, reps: int = 10) -> float:
+    """Dense TFLOP/s of one large n x n x n torch matmul (the ROCm GEMM
+    library) in `dtype` on this GPU: a measured ceiling beside the datasheet
+    peak, as context for the roofline fractions."""
+    import torch
+
+    dt = {"fp32": torch.float32, "bf16": torch.bfloat16}[dtype]
+    g = torch.Generator(device="cuda").manual_seed(1)
+    a = torch.randn(n, n, device="cuda", dtype=dt, generator=g)
+    b = torch.randn(n, n, device="cuda", dtype=dt, generator=g)
+    for _ in range(2):
+        torch.matmul(a, b)
+    torch.cuda.synchronize()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(reps):
+        torch.matmul(a, b)
+    end.record()
+    torch.cuda.synchronize()
+    return 2.0 * n ** 3 * reps / (start.elapsed_time(end) * 1e-3) / 1e12
+
+
 def cpu_baseline(seconds: float):
     """The FP64 oracle, single-threaded, on whole codebooks of the same
     workload until `seconds` of CPU work have been spent."""
@@ -226,6 +248,7 @@ def main():
                          "options hh, gaussian), reported as context")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-critic", action="store_true")
+    ap.add_argument("--no-gemm-peak", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: the codebook build of one cell fits one MI355X and the library has "
@@ -254,6 +277,12 @@ def main():
     critic = critic_leg(max(10, args.steps // 10), 5, stream) if not args.no_critic else None
     if critic:
         print(f"[bench] critic pass: {critic['us_per_pass']:.1f} us, {critic['achieved_tflops']:.1f} TFLOP/s",
+              file=sys.stderr, flush=True)
+    measured = {}
+    if not args.no_gemm_peak:
+        for dt in ("fp32", "bf16"):
+            measured[dt] = gemm_peak(dt)
+        print(f"[bench] 8192^3 torch matmul: fp32 {measured['fp32']:.1f}, bf16 {measured['bf16']:.1f} TFLOP/s",
               file=sys.stderr, flush=True)
     head = legs["fp32"]
     cfg = wl.WORKLOADS[WORKLOAD]
@@ -286,7 +315,10 @@ def main():
             "traffic": load_traffic(head["kernel"], "fp32"),
             "flops_per_launch": head["flops_per_launch"],
             "avg_launch_us": head["device_us_mean"],
+            "measured_peak": measured.get("fp32"),
+            "frac_of_measured_peak": head["achieved_tflops"] / measured["fp32"] if measured else None,
         },
+        "gemm_tflops_measured": measured or None,
         "legs": legs,
         "context_legs": context,
         "critic": critic,
