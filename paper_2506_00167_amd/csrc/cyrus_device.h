@@ -170,11 +170,18 @@ __device__ __forceinline__ float gaussian_eps(uint64_t seed, uint64_t tti, int64
 
 __device__ __forceinline__ float clamp_log_sigma(float ls) { return fminf(fmaxf(ls, -20.f), 2.f); }
 
+// The log-share for a given draw eps (the same number as gaussian_log_share
+// with that node's eps).
+__device__ __forceinline__ float gaussian_log_share_eps(float mu, float log_sigma, float eps)
+{
+    const float u = mu + expf(clamp_log_sigma(log_sigma)) * eps;
+    return u >= 0.f ? -log1pf(expf(-2.f * u)) : 2.f * u - log1pf(expf(2.f * u));
+}
+
 __device__ __forceinline__ float gaussian_log_share(float mu, float log_sigma, uint64_t seed, uint64_t tti,
                                                    int64_t node, int e)
 {
-    const float u = mu + expf(clamp_log_sigma(log_sigma)) * gaussian_eps(seed, tti, node, e);
-    return u >= 0.f ? -log1pf(expf(-2.f * u)) : 2.f * u - log1pf(expf(2.f * u));
+    return gaussian_log_share_eps(mu, log_sigma, gaussian_eps(seed, tti, node, e));
 }
 
 // Index of the calling wave in its workgroup, as a wave-uniform (scalar)

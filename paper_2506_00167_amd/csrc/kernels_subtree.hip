@@ -35,6 +35,17 @@ __device__ __forceinline__ int64_t sub_level_offset(int K, int tau)
     return (p - 1) / K;
 }
 
+// Gaussian-head draw slots of one subtree workgroup: one row per ancestor
+// level, then every evaluated row of the subtree levels, sum over d of
+// K (K+1)^(d-1) = (K+1)^(M-split) - 1.
+__host__ __device__ inline int eps_slots(int K, int M, int split)
+{
+    int w = 1;
+    for (int i = 0; i < M - split; ++i)
+        w *= K + 1;
+    return split + w - 1;
+}
+
 __device__ __forceinline__ int ipow_dev(int b, int e)
 {
     int r = 1;
@@ -178,6 +189,7 @@ struct SubtreeSmem {
     float* bias;    // every layer's bias, out_pad each
     uint8_t* st0;   // states of the previous level (local nodes), E bytes each
     uint8_t* st1;   // states of the current level
+    float* eps;     // Gaussian head: the draws of every evaluated node, E each
 };
 
 // Per-node input rows for `nrows` nodes: [c/64 | tau/8 | k/8], zero padded
@@ -239,11 +251,11 @@ __device__ __forceinline__ const float* eval_rows(const DevTree& t, const Subtre
 // that node to global memory; when sib_of(r) >= 0 (the first child of a
 // parent) it also writes that k = 0 sibling: nothing punctured, parent state
 // passed on, into sib_st_of(r).
-template <int G, int RT, bool EXT, class KOf, class CinOf, class SoutOf, class IdOf, class NodeOf, class SibOf,
+template <int G, int RT, bool EXT, class KOf, class CinOf, class SoutOf, class EpsOf, class NodeOf, class SibOf,
           class SibStOf>
 __device__ __forceinline__ void finish_rows(const DevTree& t, const SubtreeSmem& sm, const float* part, float deq,
                                             const float* bo, int nrows, KOf k_of, CinOf cin_of, SoutOf sout_of,
-                                            IdOf id_of, NodeOf node_of, SibOf sib_of, SibStOf sib_st_of)
+                                            EpsOf eps_of, NodeOf node_of, SibOf sib_of, SibStOf sib_st_of)
 {
     const int E = t.E;
     for (int base = 0; base < nrows; base += kThreads / G) {
@@ -273,7 +285,7 @@ __device__ __forceinline__ void finish_rows(const DevTree& t, const SubtreeSmem&
 #pragma unroll
                     for (int w = 0; w < kWaves; ++w)
                         acc2 += part[(size_t)(w * RT + row) * 16 + E + e];
-                    z = gaussian_log_share(z, acc2 * deq + bo[E + e], t.seed, t.tti, id_of(row), e);
+                    z = gaussian_log_share_eps(z, acc2 * deq + bo[E + e], eps_of(row)[e]);
                 }
             }
             const int a = enforce_dpp<G>(E, e, z, R, rsum, t.U * k, sm.zl + row * kLogitStride,
@@ -317,6 +329,8 @@ __device__ __forceinline__ void subtree_body(const DevTree& t, int split, int bu
         nbias += t.out_pad[l];
     sm.st0 = reinterpret_cast<uint8_t*>(sm.bias + nbias);
     sm.st1 = sm.st0 + stbytes;
+    sm.eps = reinterpret_cast<float*>(
+        (reinterpret_cast<uintptr_t>(sm.st1 + stbytes) + 15) & ~static_cast<uintptr_t>(15));
 
     const int lane = threadIdx.x & 63, wave = wave_id();
     const int E = t.E, K = t.K, M = t.M, K1 = K + 1;
@@ -388,6 +402,34 @@ __device__ __forceinline__ void subtree_body(const DevTree& t, int split, int bu
             off += t.out_pad[l];
         }
     }
+    if constexpr (EXT) {
+        if (t.head == kGaussianHead) {
+            // The draws depend on (node, UE, seed, TTI) only, so every node
+            // this workgroup evaluates gets its E draws here, all threads at
+            // once, while the register weights stream in. Slot tau - 1 holds
+            // ancestor level tau; the subtree levels follow, row j of level
+            // split + d at its level's offset + j.
+            const int nsub = eps_slots(K, M, split) - split;
+            for (int f = tid; f < (split + nsub) * E; f += kThreads) {
+                const int slot = f / E, e = f - slot * E;
+                int64_t node;
+                if (slot < split) {
+                    const int tau = slot + 1;
+                    node = sub_level_offset(K, tau) + r / ipow_dev(K1, split - tau);
+                } else {
+                    int j = slot - split, d = 1, n = K;
+                    while (j >= n) {
+                        j -= n;
+                        n *= K1;
+                        ++d;
+                    }
+                    const int p = j / K, k = j - p * K + 1;
+                    node = sub_level_offset(K, split + d) + (int64_t)r * ipow_dev(K1, d) + p * K1 + k;
+                }
+                sm.eps[f] = gaussian_eps(t.seed, t.tti, node, e);
+            }
+        }
+    }
     lds_barrier();
     // first-layer bias with the static inputs folded in, from the values the
     // MFMA would read: the stored weights and the inputs in the storage type
@@ -426,7 +468,8 @@ __device__ __forceinline__ void subtree_body(const DevTree& t, int split, int bu
                 t, sm, W, 1, tau, bias_off, [&](int) { return sm.st0; }, [&](int) { return k; });
             finish_rows<G, kRT, EXT>(
                 t, sm, part, deq_out, bias_out, 1, [&](int) { return k; }, [&](int) { return sm.st0; },
-                [&](int) { return sm.st1; }, [&](int) { return node; }, [&](int) { return owner ? node : (int64_t)-1; },
+                [&](int) { return sm.st1; }, [&](int) { return sm.eps + (tau - 1) * E; },
+                [&](int) { return owner ? node : (int64_t)-1; },
                 [&](int) { return (int64_t)-1; }, [&](int) { return sm.st1; });
             lds_barrier();
             uint8_t* tmp = sm.st0;
@@ -442,6 +485,7 @@ __device__ __forceinline__ void subtree_body(const DevTree& t, int split, int bu
 
     // ---- subtree levels split+1..M; st0 holds the previous level's states
     const float invK = 1.0f / (float)K;
+    int eps_row = split;  // first slot of this level's draws
     for (int tau = split + 1; tau <= M; ++tau) {
         const int d = tau - split;
         const int width = ipow_dev(K1, d);
@@ -459,12 +503,13 @@ __device__ __forceinline__ void subtree_body(const DevTree& t, int split, int bu
             finish_rows<G, kRT, EXT>(
                 t, sm, part, deq_out, bias_out, nrows, k_of, [&](int row) { return prev + parent_of(row) * E; },
                 [&](int row) { return cur + (parent_of(row) * K1 + k_of(row)) * E; },
-                [&](int row) { return base + parent_of(row) * K1 + k_of(row); },
+                [&](int row) { return sm.eps + (eps_row + j0 + row) * E; },
                 [&](int row) { return base + parent_of(row) * K1 + k_of(row); },
                 [&](int row) { return k_of(row) == 1 ? base + parent_of(row) * K1 : (int64_t)-1; },
                 [&](int row) { return cur + parent_of(row) * K1 * E; });
             lds_barrier();
         }
+        eps_row += n_eval;
         uint8_t* tmp = sm.st0;
         sm.st0 = sm.st1;
         sm.st1 = tmp;
@@ -549,6 +594,8 @@ bool plan_subtree(const DevTree& t, int prec, SubtreePlan& pl)
         nbias += t.out_pad[l];
     pl.lds = 2 * buf + (size_t)kRTmax * kLogitStride * 4 + (kMaxUE + 8) * 4 + 3 * kMaxUE * 4 + nbias * 4 +
              2 * (size_t)pl.stbytes;
+    if (t.head == kGaussianHead)  // the precomputed draws, 16-byte aligned
+        pl.lds += 16 + (size_t)eps_slots(t.K, t.M, split) * t.E * 4;
     return pl.lds <= 160 * 1024;
 }
 
