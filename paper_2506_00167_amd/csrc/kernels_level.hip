@@ -116,7 +116,7 @@ __device__ __forceinline__ void level_tile(const DevTree& t, int tau, int row0, 
     constexpr int kPstIters = (pst_bytes(RTT) + kThreads - 1) / kThreads;
     constexpr int kBiasBatch = 4;  // float4 bias loads in flight per thread
     const int E = t.E, K = t.K, nl = t.n_layers;
-    const int in0 = t.in_pad[0], d_in = t.in_dim0;
+    const int in0 = t.in_pad[0];
     const int64_t off = dev_level_offset(K, tau), poff = dev_level_offset(K, tau - 1);
 
     // Stage the tile's inputs in LDS, every global load issued before the
