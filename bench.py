@@ -18,6 +18,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -43,10 +44,19 @@ KERNEL_SOURCES = {
 }
 
 
+def code_tokens(src: str) -> str:
+    """C++/HIP source with comments removed and whitespace collapsed: what the
+    compiler sees, so that comment edits keep a measurement valid."""
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", " ", src)
+    return " ".join(src.split())
+
+
 def kernel_source_hash(kernel: str = "subtree") -> str:
+    """Hash of the code (comments and whitespace aside) of a kernel's sources."""
     h = hashlib.sha256()
     for name in KERNEL_SOURCES[kernel]:
-        h.update(open(os.path.join(ROOT, "paper_2506_00167_amd", "csrc", name), "rb").read())
+        h.update(code_tokens(open(os.path.join(ROOT, "paper_2506_00167_amd", "csrc", name)).read()).encode())
     return h.hexdigest()[:16]
 
 

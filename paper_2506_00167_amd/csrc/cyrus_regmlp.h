@@ -2,7 +2,9 @@
 // holds the A fragments of its output-neuron tiles (hidden layers) and its
 // slice of the output layer's reduction, loaded once; activations move
 // through LDS in the transposed layer form (weights as the A operand, node
-// rows as the B operand). Shared by the subtree kernel and the critic pass.
+// rows as the B operand), except that in FP32 and BF16 the last hidden
+// layer's accumulators feed the output layer straight from registers.
+// Shared by the subtree kernel and the critic pass.
 #pragma once
 
 #include "cyrus_device.h"
@@ -24,7 +26,8 @@ constexpr int kRTmax = 64;
 
 // Register-resident fragments of one wave.
 //   T     output-neuron tiles of 16 per hidden layer owned by this wave
-//   CH1   chunks of the first layer's per-node input (in_pad_d / chunk)
+//   CH1   chunks of the first layer's input as held in registers
+//         (DevTree::in_pad_d / chunk; DevTree::w1d holds those fragments)
 //   CHH   chunks of a hidden layer's input (H / chunk)
 //   NHH   hidden->hidden layers (0 or 1)
 template <int P, int T, int CH1, int CHH, int NHH>
