@@ -137,6 +137,17 @@ __device__ __forceinline__ float* mlp_valu(const DevTree& t, const WaveWeights<k
     float* in = hB;
     float* out = hA;
     if constexpr (NHH > 0) {
+        // The hidden layer feeds the output layer without LDS: after the
+        // row sums every lane holds neuron 16 nt + c16 of each of its tiles,
+        // and lane (g, i) takes neurons 16 nt + 4g .. 16 nt + 4g + 3 (its
+        // output weights W.wo[tt] of chunk nt) from lanes 4g .. 4g + 3 of its
+        // own row. The partial logits go to bufA, which no wave reads now.
+        static_assert(WW::CPW == T, "output-layer chunks are the wave's own tiles");
+        float b2[T];
+#pragma unroll
+        for (int tt = 0; tt < T; ++tt)
+            b2[tt] = bias[bias_off[1] + (wave + kWaves * tt) * 16 + c16];
+        float* part = hA;
 #pragma unroll 1
         for (int r = 0; r < nrows; ++r) {
             float acc[T];
@@ -149,11 +160,22 @@ __device__ __forceinline__ float* mlp_valu(const DevTree& t, const WaveWeights<k
                 const float h[4] = {hv[0], hv[1], hv[2], hv[3]};
                 valu_fma4<T, CHH>(W.wh, c, h, acc);
             }
-            valu_store<T>(acc, hA + r * sh, bias + bias_off[1], wave, g, c16);
+            float z = 0.f;
+#pragma unroll
+            for (int tt = 0; tt < T; ++tt) {
+                const float h = fmaxf(row_sum4(acc[tt]) + b2[tt], 0.f);
+                const int src = (lane & 48) | (4 * g);
+                z = fmaf(__uint_as_float(W.wo[tt].x), __shfl(h, src), z);
+                z = fmaf(__uint_as_float(W.wo[tt].y), __shfl(h, src + 1), z);
+                z = fmaf(__uint_as_float(W.wo[tt].z), __shfl(h, src + 2), z);
+                z = fmaf(__uint_as_float(W.wo[tt].w), __shfl(h, src + 3), z);
+            }
+            z = row_sum4(z);
+            if (g == 0)
+                part[(size_t)(wave * kRT + r) * 16 + c16] = z;
         }
         lds_barrier();
-        in = hA;
-        out = hB;
+        return part;
     }
     // output layer: this wave's slice of the reduction, one partial tile
     float* part = out;
