@@ -25,6 +25,20 @@ SUBTREE_WIDE = [
     dict(num_ue=16, max_arrival=2, num_minislots=4, hidden=(256, 256)),
 ]
 
+# Subtree-kernel shapes whose levels hold more rows than one pass (48 rows in
+# FP32, 64 in BF16/FP8): K = 7, M = 5 has subtree levels of 7, 56 and 448
+# rows (FP32: nine full passes and a 16-row tail); K = 4, M = 6 has 100 rows
+# (FP32: 48 + 48 + a 4-row tail on the vector ALU).
+SUBTREE_MULTIPASS = [
+    dict(num_ue=8, max_arrival=7, num_minislots=5, hidden=(256, 256)),
+    dict(num_ue=16, max_arrival=4, num_minislots=6, hidden=(128, 128)),
+]
+
+# The largest tree and actor the configuration accepts: E = 32, K = 7, M = 7,
+# U = 5 (M K U = 245; the carried state is 8-bit), four 512-wide hidden
+# layers. 2,396,745 nodes, 2,097,151 evaluations.
+MAX_TREE = dict(num_ue=32, max_arrival=7, num_minislots=7, rb_per_unit=5, hidden=(512, 512, 512, 512))
+
 
 def _build(cfg, weights, ue, **kw):
     cb = cyrus.Codebook(cfg, weights, export_logits=True, **kw)
@@ -74,6 +88,7 @@ def test_tree_e8k3_fp32(force_level, seed):
     dict(num_ue=32, max_arrival=2, num_minislots=4, hidden=(256, 384, 128)),  # 32 UEs: two output tiles
     dict(num_ue=5, max_arrival=7, num_minislots=2, rb_per_unit=3, hidden=(256, 256, 256, 256)),
     *SUBTREE_WIDE,
+    *SUBTREE_MULTIPASS,
 ])
 def test_shapes_fp32(shape):
     cfg = wl.TreeConfig(**shape)
@@ -88,7 +103,7 @@ def test_shapes_fp32(shape):
 
 
 def test_latency_path_is_selected():
-    wide = [wl.TreeConfig(**s) for s in SUBTREE_WIDE]
+    wide = [wl.TreeConfig(**s) for s in SUBTREE_WIDE + SUBTREE_MULTIPASS]
     for cfg in (wl.TINY, wl.TREE_E8K3, wl.PAPER_DEPTH1, wl.TREE_E8K3.with_precision("bf16"), *wide):
         cb = cyrus.Codebook(cfg, wl.make_weights(cfg, 1), act_scale=None)
         assert cb.kernel_path == "subtree", cfg
@@ -107,6 +122,36 @@ def test_subtree_bf16_wide():
     parity.check_invariants(cfg, ue, alloc)
     rep = parity.compare(cfg, weights, ue, alloc, logits, precision="bf16", logit_tol=2e-3)
     _report("bf16 e16k2 subtree", rep)
+    cb.close()
+
+
+def test_subtree_bf16_multipass():
+    cfg = wl.TreeConfig(precision="bf16", **SUBTREE_MULTIPASS[0])
+    weights = wl.make_weights(cfg, 35)
+    ue = wl.make_ue_state(cfg.num_ue, 36)
+    cb, alloc, logits = _build(cfg, weights, ue)
+    assert cb.kernel_path == "subtree"
+    parity.check_invariants(cfg, ue, alloc)
+    rep = parity.compare(cfg, weights, ue, alloc, logits, precision="bf16", logit_tol=2e-3)
+    _report("bf16 e8k7m5 subtree", rep)
+    cb.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", FP32_LOGIT_TOL), ("bf16", 2e-3)])
+def test_maximum_tree_sampled(prec, tol):
+    """Every node against the invariants; a sample of nodes, with the path
+    of all-K arrivals, recomputed by the oracle from the GPU's parent states."""
+    cfg = wl.TreeConfig(precision=prec, **MAX_TREE)
+    weights = wl.make_weights(cfg, 41)
+    ue = wl.make_ue_state(cfg.num_ue, wl.ue_seed(41))
+    cb, alloc, logits = _build(cfg, weights, ue)
+    assert cb.kernel_path == "level"
+    parity.check_invariants(cfg, ue, alloc)
+    last = cfg.num_nodes - 1
+    nodes = np.union1d(wl.sample_nodes(cfg, 400, seed=43), [last, *parity.ancestors(cfg, last)])
+    rep = parity.compare(cfg, weights, ue, alloc, logits, nodes=nodes,
+                         precision="exact" if prec == "fp32" else prec, logit_tol=tol)
+    _report(f"{prec} maximum tree sampled", rep)
     cb.close()
 
 
@@ -235,6 +280,7 @@ def _skewed(weights, E, seed):
     dict(num_ue=8, max_arrival=3, rb_per_unit=5, hidden=(256, 256)),
     dict(num_ue=4, max_arrival=2, rb_per_unit=9, hidden=(256, 256)),
     dict(num_ue=24, max_arrival=2, num_minislots=4, rb_per_unit=6, hidden=(256, 128)),  # 32-lane groups
+    dict(num_ue=8, max_arrival=4, num_minislots=6, rb_per_unit=5, hidden=(128, 128)),    # 100-row levels
 ])
 @pytest.mark.parametrize("force_level", [True, False])
 def test_huntington_hill_fp32(shape, force_level):
@@ -256,6 +302,7 @@ def test_huntington_hill_fp32(shape, force_level):
     dict(num_ue=8, max_arrival=3, rb_per_unit=3, hidden=(256, 256)),
     dict(num_ue=4, max_arrival=2, rb_per_unit=5, hidden=(128,)),
     dict(num_ue=16, max_arrival=4, num_minislots=3, hidden=(256, 256)),   # 2E = 32: two output tiles
+    dict(num_ue=8, max_arrival=4, num_minislots=6, rb_per_unit=3, hidden=(128, 128)),  # 100-row levels
 ])
 @pytest.mark.parametrize("rounding", ["lr", "hh"])
 def test_gaussian_head_fp32(shape, rounding):
