@@ -62,17 +62,26 @@ __device__ __forceinline__ int ipow_dev(int b, int e)
 // Rows go one after the other: the weights already fill most of the register
 // file.
 template <int T>
-__device__ __forceinline__ void valu_store(const float (&acc)[T], float* out, const float* bias, int wave, int g,
-                                           int c16)
+__device__ __forceinline__ void valu_store(const float (&acc)[T], float* out, const float (&bias)[T], int wave,
+                                           int g, int c16)
 {
 #pragma unroll
     for (int tt = 0; tt < T; ++tt) {
         const float v = row_sum4(acc[tt]);
         const int n = (wave + kWaves * tt) * 16 + c16;
         if (g == 0)
-            out[n] = fmaxf(v + bias[n], 0.f);
+            out[n] = fmaxf(v + bias[tt], 0.f);
     }
 }
+
+// Biases of the first two layers for the neurons a lane sums in the
+// vector-ALU steps (neuron 16 (wave + kWaves tt) + c16 of each of its tiles),
+// read from LDS once per launch.
+template <int T>
+struct ValuBias {
+    float b1[T];
+    float b2[T];
+};
 
 template <int T, int NCH>
 __device__ __forceinline__ void valu_fma4(const uint4 (&A)[T][NCH], int c, const float (&h)[4], float (&acc)[T])
@@ -93,8 +102,8 @@ __device__ __forceinline__ void valu_fma4(const uint4 (&A)[T][NCH], int c, const
 // does.
 template <int T, int CH1, int CHH, int NHH, class StateOf, class KOf>
 __device__ __forceinline__ float* mlp_valu(const DevTree& t, const WaveWeights<kFP32, T, CH1, CHH, NHH>& W,
-                                           int nrows, uint8_t* bufA, uint8_t* bufB, const float* bias,
-                                           const int* bias_off, int tau, StateOf state_of, KOf k_of)
+                                           int nrows, uint8_t* bufA, uint8_t* bufB, const ValuBias<T>& vb, int tau,
+                                           StateOf state_of, KOf k_of)
 {
     using WW = WaveWeights<kFP32, T, CH1, CHH, NHH>;
     constexpr int kRT = Rows<kFP32>::kRT;
@@ -131,7 +140,7 @@ __device__ __forceinline__ float* mlp_valu(const DevTree& t, const WaveWeights<k
             }
             valu_fma4<T, CH1>(W.w1, c, h, acc);
         }
-        valu_store<T>(acc, hB + r * sh, bias + bias_off[0], wave, g, c16);
+        valu_store<T>(acc, hB + r * sh, vb.b1, wave, g, c16);
     }
     lds_barrier();
     float* in = hB;
@@ -143,32 +152,60 @@ __device__ __forceinline__ float* mlp_valu(const DevTree& t, const WaveWeights<k
         // output weights W.wo[tt] of chunk nt) from lanes 4g .. 4g + 3 of its
         // own row. The partial logits go to bufA, which no wave reads now.
         static_assert(WW::CPW == T, "output-layer chunks are the wave's own tiles");
-        float b2[T];
-#pragma unroll
-        for (int tt = 0; tt < T; ++tt)
-            b2[tt] = bias[bias_off[1] + (wave + kWaves * tt) * 16 + c16];
         float* part = hA;
+        // The hidden row is read four chunks per batch: the scheduling
+        // barrier keeps a batch's loads together, so one LDS latency is paid
+        // per batch rather than per chunk (the compiler otherwise issues one
+        // 16-byte load per chunk and waits for it, to save registers).
+        constexpr int kBatch = 4;
+        static_assert(CHH % kBatch == 0, "hidden chunks come in batches of four");
+        const int src = (lane & 48) | (4 * g);
 #pragma unroll 1
         for (int r = 0; r < nrows; ++r) {
             float acc[T];
 #pragma unroll
             for (int tt = 0; tt < T; ++tt)
                 acc[tt] = 0.f;
+            const float* hr = hB + r * sh + 4 * g;
+            floatx4 hv[kBatch], hn4[kBatch];
 #pragma unroll
-            for (int c = 0; c < CHH; ++c) {
-                const floatx4 hv = *reinterpret_cast<const floatx4*>(hB + r * sh + 4 * g + 16 * c);
-                const float h[4] = {hv[0], hv[1], hv[2], hv[3]};
-                valu_fma4<T, CHH>(W.wh, c, h, acc);
+            for (int j = 0; j < kBatch; ++j)
+                hv[j] = *reinterpret_cast<const floatx4*>(hr + 16 * j);
+#pragma unroll
+            for (int c0 = 0; c0 < CHH; c0 += kBatch) {
+                if (c0 + kBatch < CHH) {
+#pragma unroll
+                    for (int j = 0; j < kBatch; ++j)
+                        hn4[j] = *reinterpret_cast<const floatx4*>(hr + 16 * (c0 + kBatch + j));
+                }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int j = 0; j < kBatch; ++j) {
+                    const float h[4] = {hv[j][0], hv[j][1], hv[j][2], hv[j][3]};
+                    valu_fma4<T, CHH>(W.wh, c0 + j, h, acc);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int j = 0; j < kBatch; ++j)
+                    hv[j] = hn4[j];
             }
+            // every tile's four permutes are issued before the first is used
+            float hn[T][4];
+#pragma unroll
+            for (int tt = 0; tt < T; ++tt) {
+                const float h = fmaxf(row_sum4(acc[tt]) + vb.b2[tt], 0.f);
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    hn[tt][j] = __shfl(h, src + j);
+            }
+            __builtin_amdgcn_sched_barrier(0);
             float z = 0.f;
 #pragma unroll
             for (int tt = 0; tt < T; ++tt) {
-                const float h = fmaxf(row_sum4(acc[tt]) + b2[tt], 0.f);
-                const int src = (lane & 48) | (4 * g);
-                z = fmaf(__uint_as_float(W.wo[tt].x), __shfl(h, src), z);
-                z = fmaf(__uint_as_float(W.wo[tt].y), __shfl(h, src + 1), z);
-                z = fmaf(__uint_as_float(W.wo[tt].z), __shfl(h, src + 2), z);
-                z = fmaf(__uint_as_float(W.wo[tt].w), __shfl(h, src + 3), z);
+                z = fmaf(__uint_as_float(W.wo[tt].x), hn[tt][0], z);
+                z = fmaf(__uint_as_float(W.wo[tt].y), hn[tt][1], z);
+                z = fmaf(__uint_as_float(W.wo[tt].z), hn[tt][2], z);
+                z = fmaf(__uint_as_float(W.wo[tt].w), hn[tt][3], z);
             }
             z = row_sum4(z);
             if (g == 0)
@@ -254,12 +291,13 @@ __device__ __forceinline__ void write_features(const DevTree& t, const SubtreeSm
 // up to four rows, else the per-node input rows and the matrix-core path.
 template <int P, int T, int CH1, int CHH, int NHH, class StateOf, class KOf>
 __device__ __forceinline__ const float* eval_rows(const DevTree& t, const SubtreeSmem& sm,
-                                                  const WaveWeights<P, T, CH1, CHH, NHH>& W, int nrows, int tau,
-                                                  const int* bias_off, StateOf state_of, KOf k_of)
+                                                  const WaveWeights<P, T, CH1, CHH, NHH>& W,
+                                                  const ValuBias<T>& vb, int nrows, int tau, const int* bias_off,
+                                                  StateOf state_of, KOf k_of)
 {
     if constexpr (P == kFP32) {
         if (nrows <= 4)
-            return mlp_valu<T, CH1, CHH, NHH>(t, W, nrows, sm.bufA, sm.bufB, sm.bias, bias_off, tau, state_of, k_of);
+            return mlp_valu<T, CH1, CHH, NHH>(t, W, nrows, sm.bufA, sm.bufB, vb, tau, state_of, k_of);
     }
     write_features<P, CH1>(t, sm, nrows, tau, state_of, k_of);
     lds_barrier();
@@ -473,6 +511,15 @@ __device__ __forceinline__ void subtree_body(const DevTree& t, int split, int bu
     }
     lds_barrier();
     const int* bias_off = sm.misc + 1;
+    ValuBias<T> vb;
+    if constexpr (P == kFP32) {
+#pragma unroll
+        for (int tt = 0; tt < T; ++tt) {
+            const int n = (wave + kWaves * tt) * 16 + (lane & 15);
+            vb.b1[tt] = sm.bias[bias_off[0] + n];
+            vb.b2[tt] = NHH > 0 ? sm.bias[bias_off[1] + n] : 0.f;
+        }
+    }
     const float deq_out = t.deq[NHH + 1];
     const float* bias_out = sm.bias + bias_off[NHH + 1];
     constexpr int kRT = Rows<P>::kRT;
@@ -487,7 +534,7 @@ __device__ __forceinline__ void subtree_body(const DevTree& t, int split, int bu
         const bool owner = (r % below) == 0;
         if (k > 0) {
             const float* part = eval_rows<P, T, CH1, CHH, NHH>(
-                t, sm, W, 1, tau, bias_off, [&](int) { return sm.st0; }, [&](int) { return k; });
+                t, sm, W, vb, 1, tau, bias_off, [&](int) { return sm.st0; }, [&](int) { return k; });
             finish_rows<G, kRT, EXT>(
                 t, sm, part, deq_out, bias_out, 1, [&](int) { return k; }, [&](int) { return sm.st0; },
                 [&](int) { return sm.st1; }, [&](int) { return sm.eps + (tau - 1) * E; },
@@ -521,7 +568,7 @@ __device__ __forceinline__ void subtree_body(const DevTree& t, int split, int bu
             auto parent_of = [&](int row) { return (int)(((float)(j0 + row) + 0.5f) * invK); };
             auto k_of = [&](int row) { return j0 + row - parent_of(row) * K + 1; };
             const float* part = eval_rows<P, T, CH1, CHH, NHH>(
-                t, sm, W, nrows, tau, bias_off, [&](int row) { return prev + parent_of(row) * E; }, k_of);
+                t, sm, W, vb, nrows, tau, bias_off, [&](int row) { return prev + parent_of(row) * E; }, k_of);
             finish_rows<G, kRT, EXT>(
                 t, sm, part, deq_out, bias_out, nrows, k_of, [&](int row) { return prev + parent_of(row) * E; },
                 [&](int row) { return cur + (parent_of(row) * K1 + k_of(row)) * E; },
