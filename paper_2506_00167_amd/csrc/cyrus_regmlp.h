@@ -118,6 +118,34 @@ __device__ __forceinline__ void layer_acc(const uint4 (&A)[T][NCH], int nch, con
                 }
             }
         }
+    } else if (art == kRTT) {
+        // every row tile live: the B fragments of chunk c + 1 are loaded
+        // while chunk c's MFMAs run (the scheduling barrier keeps them
+        // ahead), so the LDS latency hides behind the matrix core
+        uint4 b[kRTT], bn[kRTT];
+#pragma unroll
+        for (int rt = 0; rt < kRTT; ++rt)
+            b[rt] = *reinterpret_cast<const uint4*>(bp + rt * 16 * sin);
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            if (c < nch) {
+                if (c + 1 < nch) {
+#pragma unroll
+                    for (int rt = 0; rt < kRTT; ++rt)
+                        bn[rt] = *reinterpret_cast<const uint4*>(bp + rt * 16 * sin + (c + 1) * kc * es);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int rt = 0; rt < kRTT; ++rt)
+#pragma unroll
+                    for (int tt = 0; tt < T; ++tt)
+                        mma_chunk<P>(A[tt][c], b[rt], acc[tt][rt]);
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int rt = 0; rt < kRTT; ++rt)
+                    b[rt] = bn[rt];
+            }
+        }
     } else {
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
