@@ -89,6 +89,59 @@ __device__ __forceinline__ void load_weights(const DevTree& t, WaveWeights<P, T,
 
 // acc = A * in for the wave's T neuron tiles over `art` row tiles (inputs
 // from LDS, row stride sin bytes).
+// One layer's MFMAs over NT live row tiles (chunks of 16/32 reduction
+// values). The B fragments of a chunk are loaded D chunks ahead of its
+// MFMAs, and scheduling barriers keep the loads ahead, so LDS latency hides
+// behind the matrix core: one chunk ahead in FP32 (each load feeds four MFMAs
+// per output tile), about four 16-byte loads ahead in BF16 (one MFMA per
+// output tile).
+// Fully unrolled, so only the D + 1 chunks in flight hold registers.
+template <int P, int T, int NCH, int NT>
+__device__ __forceinline__ void layer_acc_tiles(const uint4 (&A)[T][NCH], int nch, const uint8_t* bp, int sin,
+                                                floatx4 (&acc)[T][Rows<P>::kRTT])
+{
+    constexpr int kc = Traits<P>::kChunk, es = Traits<P>::kEsize;
+    constexpr int D = (P == kFP32 || NT >= 4) ? 1 : 4 / NT;
+    uint4 b[NCH][NT];
+#pragma unroll
+    for (int c = 0; c < D && c < NCH; ++c) {
+        if (c < nch) {
+#pragma unroll
+            for (int rt = 0; rt < NT; ++rt)
+                b[c][rt] = *reinterpret_cast<const uint4*>(bp + rt * 16 * sin + c * kc * es);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+        if (c < nch) {
+            if (c + D < NCH && c + D < nch) {
+#pragma unroll
+                for (int rt = 0; rt < NT; ++rt)
+                    b[c + D][rt] = *reinterpret_cast<const uint4*>(bp + rt * 16 * sin + (c + D) * kc * es);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int rt = 0; rt < NT; ++rt)
+#pragma unroll
+                for (int tt = 0; tt < T; ++tt)
+                    mma_chunk<P>(A[tt][c], b[c][rt], acc[tt][rt]);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+}
+
+// Picks the instantiation for the number of live row tiles, art in [1, NT]
+// (art = 0 does nothing).
+template <int P, int T, int NCH, int NT>
+__device__ __forceinline__ void layer_acc_dispatch(const uint4 (&A)[T][NCH], int nch, const uint8_t* bp, int sin,
+                                                   int art, floatx4 (&acc)[T][Rows<P>::kRTT])
+{
+    if (art == NT)
+        layer_acc_tiles<P, T, NCH, NT>(A, nch, bp, sin, acc);
+    else if constexpr (NT > 1)
+        layer_acc_dispatch<P, T, NCH, NT - 1>(A, nch, bp, sin, art, acc);
+}
+
 template <int P, int T, int NCH>
 __device__ __forceinline__ void layer_acc(const uint4 (&A)[T][NCH], int nch, const uint8_t* in, int sin, int art,
                                           int g, int c16, floatx4 (&acc)[T][Rows<P>::kRTT])
@@ -118,49 +171,8 @@ __device__ __forceinline__ void layer_acc(const uint4 (&A)[T][NCH], int nch, con
                 }
             }
         }
-    } else if (art == kRTT) {
-        // every row tile live: the B fragments of chunk c + 1 are loaded
-        // while chunk c's MFMAs run (the scheduling barrier keeps them
-        // ahead), so the LDS latency hides behind the matrix core
-        uint4 b[kRTT], bn[kRTT];
-#pragma unroll
-        for (int rt = 0; rt < kRTT; ++rt)
-            b[rt] = *reinterpret_cast<const uint4*>(bp + rt * 16 * sin);
-#pragma unroll
-        for (int c = 0; c < NCH; ++c) {
-            if (c < nch) {
-                if (c + 1 < nch) {
-#pragma unroll
-                    for (int rt = 0; rt < kRTT; ++rt)
-                        bn[rt] = *reinterpret_cast<const uint4*>(bp + rt * 16 * sin + (c + 1) * kc * es);
-                }
-                __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                for (int rt = 0; rt < kRTT; ++rt)
-#pragma unroll
-                    for (int tt = 0; tt < T; ++tt)
-                        mma_chunk<P>(A[tt][c], b[rt], acc[tt][rt]);
-                __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                for (int rt = 0; rt < kRTT; ++rt)
-                    b[rt] = bn[rt];
-            }
-        }
     } else {
-#pragma unroll
-        for (int c = 0; c < NCH; ++c) {
-            if (c < nch) {
-#pragma unroll
-                for (int rt = 0; rt < kRTT; ++rt) {
-                    if (rt < art) {
-                        const uint4 b = *reinterpret_cast<const uint4*>(bp + rt * 16 * sin + c * kc * es);
-#pragma unroll
-                        for (int tt = 0; tt < T; ++tt)
-                            mma_chunk<P>(A[tt][c], b, acc[tt][rt]);
-                    }
-                }
-            }
-        }
+        layer_acc_dispatch<P, T, NCH, kRTT>(A, nch, bp, sin, art, acc);
     }
 }
 
