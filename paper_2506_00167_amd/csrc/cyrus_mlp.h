@@ -51,14 +51,23 @@ __device__ __forceinline__ void hidden_layer(const DevTree& t, int l, const uint
             D1[tt] = gld(wp[tt] + (size_t)(c_ + 1) * 64);                                                                    \
         }                                                                                                              \
     }
+    // B fragments: row tile rt + 1's pair is read from LDS while row tile
+    // rt's MFMAs run, so each wait covers a load issued one tile earlier
 #define CYRUS_MMA_PAIRS(S0, S1, Q)                                                                                     \
     {                                                                                                                  \
         const uint8_t* bq_ = bp + 2 * (Q) * kc * es;                                                                   \
+        uint4 n0_ = *reinterpret_cast<const uint4*>(bq_);                                                              \
+        uint4 n1_ = *reinterpret_cast<const uint4*>(bq_ + kc * es);                                                    \
         _Pragma("unroll") for (int rt = 0; rt < RTT; ++rt)                                                            \
         {                                                                                                              \
-            const uint4 b0_ = *reinterpret_cast<const uint4*>(bq_ + rt * 16 * sin);                                    \
-            const uint4 b1_ = *reinterpret_cast<const uint4*>(bq_ + rt * 16 * sin + kc * es);                          \
+            const uint4 b0_ = n0_, b1_ = n1_;                                                                          \
+            if (rt + 1 < RTT) {                                                                                        \
+                n0_ = *reinterpret_cast<const uint4*>(bq_ + (rt + 1) * 16 * sin);                                      \
+                n1_ = *reinterpret_cast<const uint4*>(bq_ + (rt + 1) * 16 * sin + kc * es);                            \
+            }                                                                                                          \
+            __builtin_amdgcn_sched_barrier(0);                                                                         \
             _Pragma("unroll") for (int tt = 0; tt < T; ++tt) mma_pair<P>(S0[tt], S1[tt], b0_, b1_, acc[tt][rt]);      \
+            __builtin_amdgcn_sched_barrier(0);                                                                         \
         }                                                                                                              \
     }
     if (npair > 0)
