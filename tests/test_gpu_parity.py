@@ -26,12 +26,14 @@ SUBTREE_WIDE = [
 ]
 
 # Subtree-kernel shapes whose levels hold more rows than one pass (48 rows in
-# FP32, 64 in BF16/FP8): K = 7, M = 5 has subtree levels of 7, 56 and 448
-# rows (FP32: nine full passes and a 16-row tail); K = 4, M = 6 has 100 rows
-# (FP32: 48 + 48 + a 4-row tail on the vector ALU).
+# FP32, 64 in BF16/FP8), or a partly filled pass: K = 7, M = 5 has subtree
+# levels of 7, 56 and 448 rows (FP32: nine full passes and a 16-row tail);
+# K = 4, M = 6 has 100 rows (FP32: 48 + 48 + a 4-row tail on the vector ALU);
+# K = 5, M = 5 has a 30-row level (two of the pass's 16-row tiles live).
 SUBTREE_MULTIPASS = [
     dict(num_ue=8, max_arrival=7, num_minislots=5, hidden=(256, 256)),
     dict(num_ue=16, max_arrival=4, num_minislots=6, hidden=(128, 128)),
+    dict(num_ue=8, max_arrival=5, num_minislots=5, hidden=(256, 256)),
 ]
 
 # The largest tree and actor the configuration accepts: E = 32, K = 7, M = 7,
@@ -125,15 +127,16 @@ def test_subtree_bf16_wide():
     cb.close()
 
 
-def test_subtree_bf16_multipass():
-    cfg = wl.TreeConfig(precision="bf16", **SUBTREE_MULTIPASS[0])
+@pytest.mark.parametrize("shape", [SUBTREE_MULTIPASS[0], SUBTREE_MULTIPASS[2]])
+def test_subtree_bf16_multipass(shape):
+    cfg = wl.TreeConfig(precision="bf16", **shape)
     weights = wl.make_weights(cfg, 35)
     ue = wl.make_ue_state(cfg.num_ue, 36)
     cb, alloc, logits = _build(cfg, weights, ue)
     assert cb.kernel_path == "subtree"
     parity.check_invariants(cfg, ue, alloc)
     rep = parity.compare(cfg, weights, ue, alloc, logits, precision="bf16", logit_tol=2e-3)
-    _report("bf16 e8k7m5 subtree", rep)
+    _report(f"bf16 {shape} subtree", rep)
     cb.close()
 
 
