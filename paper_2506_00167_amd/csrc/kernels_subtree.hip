@@ -153,10 +153,10 @@ __device__ __forceinline__ float* mlp_valu(const DevTree& t, const WaveWeights<k
         // own row. The partial logits go to bufA, which no wave reads now.
         static_assert(WW::CPW == T, "output-layer chunks are the wave's own tiles");
         float* part = hA;
-        // The hidden row is read four chunks per batch: the scheduling
-        // barrier keeps a batch's loads together, so one LDS latency is paid
-        // per batch rather than per chunk (the compiler otherwise issues one
-        // 16-byte load per chunk and waits for it, to save registers).
+        // The hidden row is read in batches of four chunks, each batch loaded
+        // while the previous one's FMAs run; the scheduling barriers keep the
+        // loads ahead (the compiler otherwise issues one 16-byte load per
+        // chunk and waits for it, to save registers).
         constexpr int kBatch = 4;
         static_assert(CHH % kBatch == 0, "hidden chunks come in batches of four");
         const int src = (lane & 48) | (4 * g);
@@ -185,9 +185,11 @@ __device__ __forceinline__ float* mlp_valu(const DevTree& t, const WaveWeights<k
                     valu_fma4<T, CHH>(W.wh, c0 + j, h, acc);
                 }
                 __builtin_amdgcn_sched_barrier(0);
+                if (c0 + kBatch < CHH) {
 #pragma unroll
-                for (int j = 0; j < kBatch; ++j)
-                    hv[j] = hn4[j];
+                    for (int j = 0; j < kBatch; ++j)
+                        hv[j] = hn4[j];
+                }
             }
             // every tile's four permutes are issued before the first is used
             float hn[T][4];
