@@ -96,7 +96,7 @@ def _load(path: str = _LIB_PATH):
     lib.oracle_largest_remainder.restype = None
     lib.oracle_largest_remainder.argtypes = [ctypes.c_int32, _f64p, _i32p, ctypes.c_int64, _i32p]
     lib.oracle_margin.restype = ctypes.c_double
-    lib.oracle_margin.argtypes = [ctypes.c_int32, _f64p, _f64p, ctypes.c_double, _i32p, ctypes.c_int64]
+    lib.oracle_margin.argtypes = [ctypes.c_int32, _f64p, _i32p, ctypes.c_int64]
     lib.oracle_allocate.restype = ctypes.c_double
     lib.oracle_allocate.argtypes = [ctypes.c_int32, _f64p, _i32p, ctypes.c_int32, ctypes.c_int32,
                                     _i32p, _f64p]
@@ -106,7 +106,7 @@ def _load(path: str = _LIB_PATH):
     lib.oracle_huntington_hill.restype = None
     lib.oracle_huntington_hill.argtypes = [ctypes.c_int32, _f64p, _i32p, ctypes.c_int64, _i32p]
     lib.oracle_margin_hh.restype = ctypes.c_double
-    lib.oracle_margin_hh.argtypes = [ctypes.c_int32, _f64p, _f64p, ctypes.c_double, _i32p, ctypes.c_int64, _i32p]
+    lib.oracle_margin_hh.argtypes = [ctypes.c_int32, _f64p, _i32p, ctypes.c_int64, _i32p]
     lib.oracle_philox4x32_10.restype = None
     lib.oracle_philox4x32_10.argtypes = [_u32p, _u32p, _u32p]
     lib.oracle_normal.restype = ctypes.c_double
@@ -281,20 +281,21 @@ def huntington_hill(x, R, T: int) -> np.ndarray:
     return a
 
 
-def margin_hh(x, p, s: float, R, T: int, a) -> float:
+def margin_hh(x, R, T: int, a) -> float:
+    """Max-norm distance of the shares x from the nearest change of the
+    Huntington-Hill allocation a."""
     x = _c(x, np.float64)
-    p = _c(p, np.float64)
     R = _c(R, np.int32)
     a = _c(a, np.int32)
-    return float(lib().oracle_margin_hh(x.size, _p(x, _f64p), _p(p, _f64p), float(s), _p(R, _i32p), int(T),
-                                        _p(a, _i32p)))
+    return float(lib().oracle_margin_hh(x.size, _p(x, _f64p), _p(R, _i32p), int(T), _p(a, _i32p)))
 
 
-def margin(x, p, s: float, R, T: int) -> float:
+def margin(x, R, T: int) -> float:
+    """Max-norm distance of the shares x from the nearest change of their
+    largest-remainder allocation."""
     x = _c(x, np.float64)
-    p = _c(p, np.float64)
     R = _c(R, np.int32)
-    return float(lib().oracle_margin(x.size, _p(x, _f64p), _p(p, _f64p), float(s), _p(R, _i32p), int(T)))
+    return float(lib().oracle_margin(x.size, _p(x, _f64p), _p(R, _i32p), int(T)))
 
 
 def allocate(z, R, U: int, k: int, rounding: str = "lr"):

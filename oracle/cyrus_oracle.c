@@ -505,16 +505,23 @@ void oracle_huntington_hill(int32_t E, const double* x, const int32_t* R, int64_
     }
 }
 
-/* Float64 distance (in units of the shares x) from the nearest change of the
- * shares that would flip a Huntington-Hill decision: a share crossing its cap,
- * or a held unit and a withheld one of two UEs swapping priority. For the pair
- * (i holds its n_i-th unit, j withholds its (n_j+1)-th), the priorities move by
- * at most |dx| / sqrt(n (n+1)), so the pair flips only once |dx| reaches
- * (pr_i - pr_j) / (1/g_i + 1/g_j); two first units (both infinite) are
- * ordered by the shares and flip at |dx| = (x_i - x_j) / 2; a held first unit
- * is lost only when its share reaches zero. */
-double oracle_margin_hh(int32_t E, const double* x, const double* p, double s, const int32_t* R, int64_t T,
-                        const int32_t* a)
+/* Float64 decision margin of Huntington-Hill, in the max norm over the shares
+ * (each kept in [0, R_e], the range of the capped split): no share vector
+ * closer to x than this in every component yields another allocation, and
+ * some move of two shares by a little more does. Every decision compares unit
+ * priorities x_e / g(n) with g(n) = sqrt(n (n+1)); they move with x
+ * continuously, and a UE at its cap is excluded whatever the shares, so the
+ * capped split switching a UE between capped and uncapped changes nothing.
+ * What can flip:
+ * - a held unit (the a_i-th of UE i) and a withheld one (the (a_j+1)-th of
+ *   UE j) swapping priority. Moving x_i down and x_j up by d, the priorities
+ *   meet at d = (pr_i - pr_j) / (1/g_i + 1/g_j); if x_j would pass its cap
+ *   first, x_j stops at R_j and x_i alone closes the rest, d = x_i - g_i R_j / g_j;
+ * - two first units (infinite priorities, ordered by the shares), the same
+ *   with g = 1 on both sides;
+ * - a held unit lost when its share reaches zero (a positive share is owed
+ *   its first unit, a zero share none). */
+double oracle_margin_hh(int32_t E, const double* x, const int32_t* R, int64_t T, const int32_t* a)
 {
     int64_t rsum = 0;
     for (int32_t e = 0; e < E; ++e)
@@ -522,12 +529,6 @@ double oracle_margin_hh(int32_t E, const double* x, const double* p, double s, c
     if (T <= 0 || T >= rsum)
         return INFINITY;
     double m = INFINITY;
-    for (int32_t e = 0; e < E; ++e)
-        if (R[e] > 0) { /* cap switch */
-            double d = fabs(s * p[e] - (double)R[e]);
-            if (d < m)
-                m = d;
-        }
     for (int32_t i = 0; i < E; ++i) {
         if (a[i] < 1)
             continue;
@@ -538,15 +539,18 @@ double oracle_margin_hh(int32_t E, const double* x, const double* p, double s, c
             if (j == i || !(x[j] > 0.0) || a[j] >= R[j])
                 continue;
             const double gj = sqrt((double)a[j] * (double)(a[j] + 1)); /* next withheld unit */
-            double d;
-            if (gi == 0.0 && gj == 0.0)
-                d = fabs(x[i] - x[j]) / 2.0;
-            else if (gi == 0.0)
+            double hi = gi, hj = gj;
+            if (gi == 0.0 && gj == 0.0) {
+                hi = hj = 1.0; /* two first units: ordered by the shares */
+            } else if (gi == 0.0) {
                 continue; /* an infinite priority never loses to a finite one */
-            else if (gj == 0.0)
-                d = 0.0; /* cannot happen for a Huntington-Hill result */
-            else
-                d = (x[i] / gi - x[j] / gj) / (1.0 / gi + 1.0 / gj);
+            } else if (gj == 0.0) {
+                m = 0.0; /* a withheld first unit behind a held later one: not a Huntington-Hill result */
+                continue;
+            }
+            double d = (x[i] / hi - x[j] / hj) / (1.0 / hi + 1.0 / hj);
+            if (x[j] + d > (double)R[j])
+                d = x[i] - hi * (double)R[j] / hj;
             if (d < m)
                 m = d;
         }
@@ -554,62 +558,55 @@ double oracle_margin_hh(int32_t E, const double* x, const double* p, double s, c
     return m < 0.0 ? 0.0 : m;
 }
 
-/* Distance in float64 from the nearest input change that would flip a
- * decision of the integer step: a share crossing an integer (floor), or the
- * r-th and (r+1)-th largest eligible remainders swapping order, or a share
- * crossing its cap. INFINITY when nothing can flip. */
-double oracle_margin(int32_t E, const double* x, const double* p, double s, const int32_t* R, int64_t T)
+/* Float64 decision margin of largest remainder, in the max norm over the
+ * shares: no share vector (each share kept in [0, R_e]) closer to x than this
+ * in every component rounds to another allocation.
+ * Largest remainder gives floor(x_e) plus one unit to the r = T - sum floor(x)
+ * eligible UEs (floor below the cap) with the largest remainders. That is
+ * the same as rounding every x_e - theta up (and capping at R_e) for any
+ * threshold theta strictly between the r-th and (r+1)-th largest eligible
+ * remainders, at which the rounded values sum to T. At the midpoint threshold
+ * every x_e - theta, including a capped R_e - theta, lies at least half that
+ * gap from an integer, so a shift of each share by less than half the gap
+ * rounds the same way; moving the r-th UE down and the (r+1)-th up by a
+ * little more swaps them. A share crossing an integer or reaching its cap
+ * flips nothing by itself: its remainder wraps between the top and the bottom
+ * of the order while r changes by one, and the same units are handed out.
+ * With r = 0 every share is an integer and any threshold in [0, 1) works: the
+ * margin is 1/2, exact when one share can give up a unit and another can take
+ * one (a lower bound otherwise). INFINITY when nothing can flip (T = 0, or T >= sum R: every
+ * UE at its cap). */
+double oracle_margin(int32_t E, const double* x, const int32_t* R, int64_t T)
 {
     int64_t rsum = 0;
     for (int32_t e = 0; e < E; ++e)
         rsum += R[e];
     if (T <= 0 || T >= rsum)
         return INFINITY;
-    double m = INFINITY;
-    double fr[MAX_UE];
-    int elig[MAX_UE];
+    double rem[MAX_UE];
     int64_t fsum = 0;
-    int32_t n_elig = 0;
+    int32_t n = 0;
     for (int32_t e = 0; e < E; ++e) {
-        double f = floor(x[e]);
+        const double f = floor(x[e]);
         fsum += (int64_t)f;
-        fr[e] = x[e] - f;
-        elig[e] = (f < R[e]);
-        n_elig += elig[e];
-        if (R[e] > 0) { /* cap switch */
-            double d = fabs(s * p[e] - (double)R[e]);
-            if (d < m)
-                m = d;
-        }
-        if (x[e] < (double)R[e]) { /* floor ambiguity of an uncapped share */
-            if (f >= 1.0 && fr[e] < m)
-                m = fr[e];
-            if (f + 1.0 <= (double)R[e] && 1.0 - fr[e] < m)
-                m = 1.0 - fr[e];
-        }
+        if (f < (double)R[e]) /* eligible for one more unit */
+            rem[n++] = x[e] - f;
     }
-    int64_t r = T - fsum;
-    if (r > 0 && r < n_elig) {
-        /* r-th and (r+1)-th largest remainders among eligible UEs */
-        double sorted[MAX_UE];
-        int32_t n = 0;
-        for (int32_t e = 0; e < E; ++e)
-            if (elig[e])
-                sorted[n++] = fr[e];
-        for (int32_t i = 1; i < n; ++i) { /* insertion sort, descending */
-            double v = sorted[i];
-            int32_t j = i - 1;
-            while (j >= 0 && sorted[j] < v) {
-                sorted[j + 1] = sorted[j];
-                --j;
-            }
-            sorted[j + 1] = v;
+    const int64_t r = T - fsum;
+    if (r == 0)
+        return 0.5;
+    if (r < 0 || r >= n)
+        return 0.0; /* cannot happen for shares that sum to T within their caps */
+    for (int32_t i = 1; i < n; ++i) { /* insertion sort, descending */
+        const double v = rem[i];
+        int32_t j = i - 1;
+        while (j >= 0 && rem[j] < v) {
+            rem[j + 1] = rem[j];
+            --j;
         }
-        double gap = sorted[r - 1] - sorted[r];
-        if (gap < m)
-            m = gap;
+        rem[j + 1] = v;
     }
-    return m;
+    return 0.5 * (rem[r - 1] - rem[r]);
 }
 
 /* From logits to the integer puncturing vector of one node with largest
@@ -636,7 +633,7 @@ double oracle_allocate_rounding(int32_t E, const double* z, const int32_t* R, in
     int64_t demand = (int64_t)U * k;
     int64_t T = demand < rsum ? demand : rsum;
     oracle_softmax(E, z, p);
-    double s = oracle_capped_scale(E, p, R, T, x);
+    oracle_capped_scale(E, p, R, T, x);
     if (rounding == ORACLE_HUNTINGTON_HILL)
         oracle_huntington_hill(E, x, R, T, a);
     else
@@ -645,8 +642,8 @@ double oracle_allocate_rounding(int32_t E, const double* z, const int32_t* R, in
         for (int32_t e = 0; e < E; ++e)
             x_out[e] = x[e];
     if (rounding == ORACLE_HUNTINGTON_HILL)
-        return oracle_margin_hh(E, x, p, s, R, T, a);
-    return oracle_margin(E, x, p, s, R, T);
+        return oracle_margin_hh(E, x, R, T, a);
+    return oracle_margin(E, x, R, T);
 }
 
 /* ----------------------------------------------------------- tree / Alg. 2 */

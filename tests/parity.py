@@ -2,14 +2,18 @@
 
 Conditioned mode (the gate): every node is recomputed by the oracle from the
 state its ancestors reach under the GPU's own codebook, so one disagreement
-cannot spread. A node may disagree only if the oracle's float64 decision
-margin is below the perturbation the GPU's arithmetic can cause there:
+cannot spread. The oracle's decision margin of a node is the max-norm distance
+of its float64 shares from the nearest share vector that rounds differently.
 
-  the GPU logits differ from the oracle's by dz (measured per node), which
-  moves every share x_e = T p_e / sum p by at most T (4 dz + 8 eps) to first
-  order (softmax ratio plus FP32 rounding of exp, sum and division), so a
-  remainder gap can close by twice that. The bound used is
-  B = 2 * T * (8 dz + 16 eps32), a further factor two of slack.
+- FP32 (the exact rule): a node may disagree only if that margin is below
+  1e-6. Such boundary cases are counted and reported.
+- Reduced precision (against the oracle run in the same precision): a node
+  may disagree only if the margin is below what the GPU's arithmetic can move
+  the shares there. Its logits differ from the oracle's by dz (measured per
+  node); each share x_e = s p_e then moves by at most x_e (e^(2 dz) - 1) <=
+  4 dz T for dz <= 1/2, plus the FP32 rounding of the exponentials, the E-term
+  sum, the division and the product, (E + 4) eps relative. The bound used is
+  twice that: B = T (8 dz + 4 (E + 4) eps32).
 
 Free-running mode: the oracle builds its own tree; every node where the two
 trees differ must lie in the subtree of a conditioned-mode disagreement.
@@ -23,6 +27,14 @@ import numpy as np
 import oracle
 
 EPS32 = 2.0 ** -24
+BOUNDARY = 1e-6
+
+
+def share_bound(T: int, E: int, dz: float) -> float:
+    """Twice the max-norm distance the GPU's FP32 shares can sit from the
+    oracle's at a node of demand T whose logits differ by at most dz."""
+    assert dz <= 0.5, f"logit error {dz} beyond the range of the bound"
+    return T * (8.0 * dz + 4.0 * (E + 4) * EPS32)
 
 
 @dataclasses.dataclass
@@ -42,6 +54,17 @@ class ParityReport:
 
     def as_dict(self):
         return dataclasses.asdict(self)
+
+    def check(self, tag: str, exact: bool):
+        """The gate: no unexplained disagreement in either mode; with `exact`
+        (FP32 against the FP64 oracle) every disagreement lies within 1e-6 of
+        a rounding boundary."""
+        print(f"[parity] {tag}: {self.as_dict()}", flush=True)
+        assert self.cond_unexplained == 0, f"{tag}: {self.cond_unexplained} unexplained conditioned mismatches"
+        assert self.free_unexplained == 0, f"{tag}: {self.free_unexplained} unexplained free-running mismatches"
+        if exact:
+            assert self.boundary_above_1e6 == 0, (
+                f"{tag}: {self.boundary_above_1e6} disagreements with a margin above {BOUNDARY}")
 
 
 def level_of(cfg, node: int) -> int:
@@ -72,24 +95,20 @@ def demand(cfg, ue, node: int) -> int:
     return min(cfg.rb_per_unit * k, int(np.asarray(ue.rb).sum()))
 
 
-def compare(cfg, weights, ue, gpu_alloc, gpu_logits=None, nodes=None, actor=None, precision="exact",
-            act_scale=None, logit_tol=None, free_running=True, margin_slack=1.0, dz_floor=0.0, seed=0,
-            tti=0) -> ParityReport:
-    """Compare a GPU codebook with the oracle. `nodes` restricts the
-    conditioned check to a sample (free-running is then skipped). Without GPU
-    logits, `dz_floor` stands in for the per-node logit error (a tolerance
-    established by the tests that do export logits)."""
+def compare(cfg, weights, ue, gpu_alloc, gpu_logits, nodes=None, actor=None, precision="exact",
+            act_scale=None, logit_tol=None, free_running=True, seed=0, tti=0) -> ParityReport:
+    """Compare a GPU codebook and its exported logits with the oracle.
+    `nodes` restricts the conditioned check to a sample (free-running is then
+    skipped). A disagreement is a boundary case below 1e-6, else explained if
+    its margin lies below share_bound(T, E, dz) for the node's measured logit
+    error dz, else unexplained."""
     actor = actor or oracle.Actor(weights, precision, act_scale)
     ids = np.arange(cfg.num_nodes) if nodes is None else np.asarray(nodes, dtype=np.int64)
     c_alloc, c_logits, c_margin = oracle.eval_conditioned(cfg, weights, ue, gpu_alloc, ids, actor=actor, seed=seed,
                                                           tti=tti)
     g = np.asarray(gpu_alloc)[ids].astype(np.int32)
     mism = np.nonzero((c_alloc != g).any(axis=1))[0]
-    if gpu_logits is not None:
-        dz = np.abs(np.asarray(gpu_logits, np.float64)[ids] - c_logits).max(axis=1)
-    else:
-        dz = np.zeros(ids.size)
-    dz = np.maximum(dz, dz_floor)
+    dz = np.abs(np.asarray(gpu_logits, np.float64)[ids] - c_logits).max(axis=1)
     max_dz = float(dz.max()) if dz.size else 0.0
     if logit_tol is not None:
         assert max_dz <= logit_tol, f"max logit error {max_dz:.3e} above {logit_tol:.3e}"
@@ -98,13 +117,11 @@ def compare(cfg, weights, ue, gpu_alloc, gpu_logits=None, nodes=None, actor=None
     min_m = np.inf
     for j in mism:
         node = int(ids[j])
-        T = demand(cfg, ue, node)
-        bound = margin_slack * 2.0 * T * (8.0 * dz[j] + 16.0 * EPS32)
         m = c_margin[j]
         min_m = min(min_m, m)
-        if m < 1e-6:
+        if m < BOUNDARY:
             below += 1
-        elif m < bound:
+        elif m < share_bound(demand(cfg, ue, node), cfg.num_ue, dz[j]):
             above += 1
         else:
             unexplained += 1

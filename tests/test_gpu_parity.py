@@ -1,9 +1,10 @@
 """Parity of the HIP codebook builder with the FP64 oracle, through the C ABI.
 
 FP32: conditioned-mode allocations must match the oracle at every node except
-where the oracle's float64 decision margin is below the perturbation that the
-GPU's FP32 arithmetic can cause there (see tests/parity.py); free-running
-disagreements must descend from conditioned ones. Logits within 1e-4.
+where the oracle's float64 decision margin is below 1e-6 (counted and
+reported); free-running disagreements must descend from conditioned ones.
+Logits within 1e-4. BF16: against the oracle run in BF16, every disagreement
+explained by the node's measured logit error (tests/parity.py).
 """
 import numpy as np
 import pytest
@@ -51,10 +52,8 @@ def _build(cfg, weights, ue, **kw):
     return cb, alloc, logits
 
 
-def _report(tag, rep):
-    print(f"[parity] {tag}: {rep.as_dict()}", flush=True)
-    assert rep.cond_unexplained == 0, f"{tag}: {rep.cond_unexplained} unexplained conditioned mismatches"
-    assert rep.free_unexplained == 0, f"{tag}: {rep.free_unexplained} unexplained free-running mismatches"
+def _report(tag, rep, exact=True):
+    rep.check(tag, exact)
 
 
 @pytest.mark.parametrize("force_level", [True, False])
@@ -123,7 +122,7 @@ def test_subtree_bf16_wide():
     assert cb.kernel_path == "subtree"
     parity.check_invariants(cfg, ue, alloc)
     rep = parity.compare(cfg, weights, ue, alloc, logits, precision="bf16", logit_tol=2e-3)
-    _report("bf16 e16k2 subtree", rep)
+    _report("bf16 e16k2 subtree", rep, exact=False)
     cb.close()
 
 
@@ -136,7 +135,7 @@ def test_subtree_bf16_multipass(shape):
     assert cb.kernel_path == "subtree"
     parity.check_invariants(cfg, ue, alloc)
     rep = parity.compare(cfg, weights, ue, alloc, logits, precision="bf16", logit_tol=2e-3)
-    _report(f"bf16 {shape} subtree", rep)
+    _report(f"bf16 {shape} subtree", rep, exact=False)
     cb.close()
 
 
@@ -154,7 +153,7 @@ def test_maximum_tree_sampled(prec, tol):
     nodes = np.union1d(wl.sample_nodes(cfg, 400, seed=43), [last, *parity.ancestors(cfg, last)])
     rep = parity.compare(cfg, weights, ue, alloc, logits, nodes=nodes,
                          precision="exact" if prec == "fp32" else prec, logit_tol=tol)
-    _report(f"{prec} maximum tree sampled", rep)
+    _report(f"{prec} maximum tree sampled", rep, exact=prec == "fp32")
     cb.close()
 
 
@@ -357,7 +356,7 @@ def test_gaussian_head_bf16_and_batch():
         # softmax logits becomes 2e-2 here.
         rep = parity.compare(cfg, weights, ues[j], alloc, logits, precision="bf16", logit_tol=2e-2, seed=99,
                              tti=1000 + j)
-        _report(f"gaussian bf16 batch cell {j}", rep)
+        _report(f"gaussian bf16 batch cell {j}", rep, exact=False)
         c.build(ues[j])
         c.wait()
         assert np.array_equal(c.export()[0], alloc)

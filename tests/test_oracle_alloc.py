@@ -188,7 +188,100 @@ def test_largest_remainder_tie_goes_to_lower_index():
     assert a.tolist() == [1, 1, 1]
 
 
-def test_margin_detects_flips():
+def _lr_moves(x, R, T, a, step):
+    """Every move of two shares toward each other by `step` (one down, one
+    up, kept in [0, R]): returns how many of them change the largest-remainder
+    allocation."""
+    flips = 0
+    for i in range(x.size):
+        for j in range(x.size):
+            if i == j:
+                continue
+            xp = x.copy()
+            xp[i] = max(xp[i] - step, 0.0)
+            xp[j] = min(xp[j] + step, float(R[j]))
+            flips += oracle.largest_remainder(xp, R, T).tolist() != a.tolist()
+    return flips
+
+
+def test_margin_hand_cases():
+    R = np.array([8, 8, 8], dtype=np.int32)
+    # the cut: remainders .6 | .25, .15 with one unit to hand out; the margin
+    # is half the gap between the first withheld and the last given remainder
+    x = np.array([1.6, 1.25, 0.15])
+    a = oracle.largest_remainder(x, R, 3)
+    assert a.tolist() == [2, 1, 0]
+    m = oracle.margin(x, R, 3)
+    assert m == pytest.approx(0.175, abs=1e-12)
+    assert oracle.largest_remainder(x + [-0.99 * m, 0.99 * m, 0], R, 3).tolist() == [2, 1, 0]
+    assert oracle.largest_remainder(x + [-1.01 * m, 1.01 * m, 0], R, 3).tolist() == [1, 2, 0]
+    # all shares integers: nothing to hand out, and only a move of one half
+    # (one share down, another up) creates a remainder order
+    x = np.array([2.0, 1.0, 3.0])
+    m = oracle.margin(x, R, 6)
+    assert m == 0.5
+    assert oracle.largest_remainder(x + [-0.49, 0.49, 0], R, 6).tolist() == [2, 1, 3]
+    assert oracle.largest_remainder(x + [-0.51, 0.51, 0], R, 6).tolist() == [1, 2, 3]
+    # a share at its cap is not at a decision boundary: dropping below the cap
+    # makes its remainder the largest and it takes the unit back
+    R2 = np.array([3, 8, 8], dtype=np.int32)
+    x = np.array([3.0, 1.7, 1.3])
+    a = oracle.largest_remainder(x, R2, 6)
+    assert a.tolist() == [3, 2, 1]
+    m = oracle.margin(x, R2, 6)
+    assert m == pytest.approx(0.2, abs=1e-12)
+    assert oracle.largest_remainder(x + [-0.19, 0, 0], R2, 6).tolist() == [3, 2, 1]
+    assert oracle.largest_remainder(x + [0, -1.01 * m, 1.01 * m], R2, 6).tolist() == [3, 1, 2]
+    # an exact tie at the cut is on the boundary
+    assert oracle.margin(np.array([0.5, 0.5, 1.0]), R, 2) == 0.0
+    # nothing can flip without demand, or with every UE at its cap
+    assert oracle.margin(np.zeros(3), R, 0) == np.inf
+    assert oracle.margin(R.astype(np.float64), R, int(R.sum())) == np.inf
+
+
+@pytest.mark.parametrize("kind", ["split", "integer"])
+def test_margin_is_safe_and_tight(kind):
+    """Brute force on small random nodes: no move of the shares by less than
+    the margin in every component changes the allocation (random moves and
+    every two-share move), and some two-share move by slightly more does."""
+    rng = np.random.default_rng(5 if kind == "split" else 6)
+    tight = 0
+    for _ in range(400):
+        E = int(rng.integers(2, 6))
+        R = rng.integers(0, 7, size=E).astype(np.int32)
+        if R.sum() < 2:
+            continue
+        T = int(rng.integers(1, R.sum()))
+        if kind == "split":
+            x, _ = oracle.capped_scale(rng.dirichlet(np.ones(E)), R, T)
+        else:  # integer shares within the caps that sum to T
+            x = np.zeros(E)
+            for _u in range(T):
+                free = np.nonzero(x < R)[0]
+                x[rng.choice(free)] += 1
+        a = oracle.largest_remainder(x, R, T)
+        m = oracle.margin(x, R, T)
+        assert np.isfinite(m) and m >= 0.0
+        for _r in range(30):
+            sign = rng.choice([-1.0, 1.0], size=E)
+            mag = rng.uniform(0.0, 0.999 * m, size=E)
+            mag[rng.integers(E)] = 0.999 * m
+            xp = np.clip(x + sign * mag, 0.0, R)
+            assert oracle.largest_remainder(xp, R, T).tolist() == a.tolist(), (x, R, T, m, xp)
+        assert _lr_moves(x, R, T, a, 0.999 * m) == 0, (x, R, T, m)
+        # with integer shares (nothing to hand out) the half is exact only if
+        # one share can give up a unit and another can take one
+        r = T - int(np.floor(x).sum())
+        movable = r > 0 or any(x[i] >= 1 and x[j] < R[j] for i in range(E) for j in range(E) if i != j)
+        if m > 0 and movable:
+            assert _lr_moves(x, R, T, a, 1.001 * m) > 0, (x, R, T, m)
+            tight += 1
+    assert tight > 200
+
+
+def test_margin_bounds_flips_from_logits():
+    """End to end: logits moved a little give shares within some max-norm
+    distance of the originals; below the node's margin the allocation stays."""
     rng = np.random.default_rng(4)
     flips = 0
     for _ in range(3000):
@@ -196,17 +289,12 @@ def test_margin_detects_flips():
         z = rng.normal(0, 1, size=E)
         R = rng.integers(1, 10, size=E).astype(np.int32)
         k = int(rng.integers(1, 4))
-        a, m, _ = oracle.allocate(z, R, 2, k)
-        # a perturbation of the logits moves the shares by at most T*|dz|*2;
-        # below the margin the allocation must not change
+        a, m, x = oracle.allocate(z, R, 2, k)
         dz = rng.normal(0, 1, size=E)
         dz /= np.abs(dz).max()
-        T = min(2 * k, int(R.sum()))
-        for scale in (1e-3, 1e-5):
-            step = scale
-            a2, _, _ = oracle.allocate(z + step * dz, R, 2, k)
-            moved = 2.0 * T * step
-            if moved < 0.5 * m:
+        for step in (1e-2, 1e-3, 1e-5):
+            a2, _, x2 = oracle.allocate(z + step * dz, R, 2, k)
+            if np.abs(x2 - x).max() < m:
                 assert a2.tolist() == a.tolist()
             elif a2.tolist() != a.tolist():
                 flips += 1

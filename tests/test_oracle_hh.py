@@ -128,7 +128,25 @@ def test_house_monotone_and_scale_invariant():
             prev = a
 
 
+def _hh_moves(x, R, T, a, step):
+    """Every move of two shares toward each other by `step` (one down, one
+    up, kept in [0, R]): returns how many change the Huntington-Hill result."""
+    flips = 0
+    for i in range(x.size):
+        for j in range(x.size):
+            if i == j:
+                continue
+            xp = x.copy()
+            xp[i] = max(xp[i] - step, 0.0)
+            xp[j] = min(xp[j] + step, float(R[j]))
+            flips += oracle.huntington_hill(xp, R, T).tolist() != a.tolist()
+    return flips
+
+
 def test_margin_is_a_safe_distance():
+    """No move of the shares by less than the margin in every component
+    changes the result (random moves and every two-share move), and some
+    two-share move by slightly more does."""
     rng = np.random.default_rng(17)
     tested = 0
     for _ in range(300):
@@ -136,9 +154,9 @@ def test_margin_is_a_safe_distance():
         R = rng.integers(1, 7, size=E).astype(np.int32)
         T = int(rng.integers(1, R.sum()))
         p = rng.dirichlet(np.ones(E))
-        x, s = oracle.capped_scale(p, R, T)
+        x, _ = oracle.capped_scale(p, R, T)
         a = oracle.huntington_hill(x, R, T)
-        m = oracle.margin_hh(x, p, s, R, T, a)
+        m = oracle.margin_hh(x, R, T, a)
         if not np.isfinite(m) or m <= 1e-9:
             continue
         for _ in range(10):
@@ -146,6 +164,8 @@ def test_margin_is_a_safe_distance():
             xp = np.minimum(np.maximum(x + dx, 0.0), R)
             xp[x == 0] = 0.0
             assert oracle.huntington_hill(xp, R, T).tolist() == a.tolist(), (x, dx, m)
+        assert _hh_moves(x, R, T, a, 0.999 * m) == 0, (x, R, T, m)
+        assert _hh_moves(x, R, T, a, 1.001 * m) > 0, (x, R, T, m)
         tested += 1
     assert tested > 100
 
@@ -155,12 +175,31 @@ def test_margin_is_tight_on_a_swap():
     # the margin (in the right direction) flips the decision
     x = np.array([2.0, 1.9])
     R = np.array([8, 8], dtype=np.int32)
-    p = x / x.sum()
     a = oracle.huntington_hill(x, R, 3)
     assert a.tolist() == [2, 1]
-    m = oracle.margin_hh(x, p, 1.0, R, 3, a)
+    m = oracle.margin_hh(x, R, 3, a)
     assert 0 < m < 0.1
     assert oracle.huntington_hill(x + np.array([-1.01 * m, 1.01 * m]), R, 3).tolist() == [1, 2]
+
+
+def test_margin_first_units():
+    R = np.array([8, 8, 8], dtype=np.int32)
+    # fewer units than positive shares: first units go to the larger shares,
+    # and the two at the cut swap once each has moved half their difference
+    x = np.array([0.9, 0.5, 0.6])
+    a = oracle.huntington_hill(x, R, 2)
+    assert a.tolist() == [1, 0, 1]
+    m = oracle.margin_hh(x, R, 2, a)
+    assert m == pytest.approx(0.05, abs=1e-12)
+    assert oracle.huntington_hill(x + [0, 1.01 * m, -1.01 * m], R, 2).tolist() == [1, 1, 0]
+    # a held first unit is lost only when its share reaches zero
+    x = np.array([0.05, 2.95])
+    a = oracle.huntington_hill(x, R[:2], 2)
+    assert a.tolist() == [1, 1]
+    m = oracle.margin_hh(x, R[:2], 2, a)
+    assert m == pytest.approx(0.05, abs=1e-12)
+    assert oracle.huntington_hill(x + [-0.99 * m, 0.99 * m], R[:2], 2).tolist() == [1, 1]
+    assert oracle.huntington_hill(np.array([0.0, 3.0]), R[:2], 2).tolist() == [0, 2]
 
 
 def test_allocate_hh_invariants():

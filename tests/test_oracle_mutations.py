@@ -70,8 +70,18 @@ MUTANTS = {
     "entropy term added": ("- cfg->entropy_coef * lp);", "+ cfg->entropy_coef * lp);"),
     "target from the same step": ("const int64_t nrow = row + 1;", "const int64_t nrow = row;"),
     "loss not averaged": ("loss[i] = sq[i] / ((double)H * M);", "loss[i] = sq[i] / (double)H;"),
-    "hh margin one-sided": ("d = (x[i] / gi - x[j] / gj) / (1.0 / gi + 1.0 / gj);",
-                            "d = (x[i] / gi - x[j] / gj) * gi;"),
+    "lr margin always zero": ("return 0.5 * (rem[r - 1] - rem[r]);", "return 0.0;"),
+    "lr margin the whole gap": ("return 0.5 * (rem[r - 1] - rem[r]);", "return rem[r - 1] - rem[r];"),
+    "lr margin counts floor crossings": ("return 0.5 * (rem[r - 1] - rem[r]);",
+                                         "return fmin(0.5 * (rem[r - 1] - rem[r]), fmin(rem[r - 1], 1.0 - rem[0]));"),
+    "lr margin infinite on integer shares": ("    if (r == 0)\n        return 0.5;",
+                                             "    if (r == 0)\n        return INFINITY;"),
+    "lr margin remainders ascending": ("while (j >= 0 && rem[j] < v)", "while (j >= 0 && rem[j] > v)"),
+    "hh margin without the first-unit term": (
+        "        if (x[i] < m) /* a first unit is owed only to a positive share */\n            m = x[i];\n", ""),
+    "hh margin one-sided": ("double d = (x[i] / hi - x[j] / hj) / (1.0 / hi + 1.0 / hj);",
+                            "double d = (x[i] / hi - x[j] / hj) * hi;"),
+    "hh margin ignores the cap of the rising share": ("            if (x[j] + d > (double)R[j])\n", "            if (0)\n"),
 }
 
 PINS = [
@@ -82,6 +92,9 @@ PINS = [
     ta.test_softmax_properties,
     ta.test_capped_scale_kkt,
     ta.test_largest_remainder_tie_goes_to_lower_index,
+    ta.test_margin_hand_cases,
+    lambda: ta.test_margin_is_safe_and_tight("split"),
+    lambda: ta.test_margin_is_safe_and_tight("integer"),
     tm.test_features_layout_by_hand,
     lambda: tm.test_mlp_matches_numpy((32, 48, 16)),
     tm.test_relu_only_on_hidden_layers,
@@ -97,6 +110,8 @@ PINS = [
     th.test_tie_goes_to_larger_share_then_lower_index,
     th.test_zero_share_and_cap_never_receive,
     th.test_margin_is_a_safe_distance,
+    th.test_margin_is_tight_on_a_swap,
+    th.test_margin_first_units,
     tg.test_philox_known_answers,
     tg.test_normal_is_standard,
     tg.test_normal_depends_on_every_key_part,
