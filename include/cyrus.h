@@ -83,7 +83,9 @@ extern "C" {
  *   rb_per_unit   U >= 1: RBs one URLLC packet needs (L in RB units).
  *                 M*K*U must not exceed 255 (the carried state is 8-bit).
  *   num_hidden    hidden layers of f_a, in [1, 4]; hidden[i] their widths,
- *                 each a multiple of 128 and at most 512.
+ *                 each a multiple of 32 in [32, 512] (the kernels compute
+ *                 128 neurons at a time; other widths are zero-padded to the
+ *                 next multiple of 128, which leaves the results unchanged).
  *   precision     CYRUS_FP32, CYRUS_BF16 or CYRUS_FP8_E4M3.
  *   flags         CYRUS_FLAG_*.
  * The actor's input width is 4E+2 and its output width is E. */
@@ -138,7 +140,10 @@ int cyrus_codebook_create(const cyrus_config* cfg, const cyrus_weights* w, void*
 /* Policy refresh from the Near-RT RIC (Alg. 1 pushes the updated f_a to the
  * O-DU): loads new weights into the idle half of a double buffer on `stream`,
  * waits for the copy, then makes them current. Builds enqueued before the call
- * keep the old weights. */
+ * keep the old weights: before overwriting a half, the call blocks until every
+ * build, batch and engine request enqueued earlier that reads that half has
+ * finished (on whatever stream it runs). Engine requests keep the weights
+ * that were current when they were admitted. */
 int cyrus_codebook_set_weights(cyrus_codebook* cb, const cyrus_weights* w, void* stream);
 
 /* Alg. 2 for one TTI: s(t) in, codebook B*(t) out. Asynchronous on `stream`:
@@ -157,11 +162,24 @@ int cyrus_codebook_build(cyrus_codebook* cb, const cyrus_ue_state* ue, void* str
 int cyrus_codebook_build_device(cyrus_codebook* cb, const void* ue_device, void* stream);
 
 /* Build n codebooks in shared launches on one stream (cells batched per
- * launch). All handles must share a precision. ue_device: n pointers to
- * device UE states laid out as for cyrus_codebook_build_device. Results stay
- * on the device; each handle's event is recorded after the last launch. */
-int cyrus_codebook_build_batch(cyrus_codebook* const* cbs, const void* const* ue_device, int32_t n,
-                               void* stream);
+ * launch: one batched level launch per mini-slot level covers every member's
+ * nodes at that level); the serving and stress extension of Alg. 2. All
+ * handles must share a precision and a device, and no handle may appear
+ * twice. ue: n host UE states (as for cyrus_codebook_build), validated and
+ * copied into each handle's pinned buffer before the call returns; the calls
+ * enqueue the UE copies, the level launches, then each codebook's (and
+ * logits') copy into its pinned mirror, and record each handle's event, so
+ * lookup/export read the new codebooks after it. CYRUS_ERANGE for n outside
+ * [1, 128]; CYRUS_EUNSUPPORTED (nothing enqueued) when the batch does not fit
+ * the level kernel's LDS. */
+int cyrus_codebook_build_batch(cyrus_codebook* const* cbs, const cyrus_ue_state* ue, int32_t n, void* stream);
+
+/* Device-resident batch: ue_device holds n pointers to device UE states laid
+ * out as for cyrus_codebook_build_device (4-byte aligned). Results stay in
+ * each handle's workspace (cyrus_codebook_device_alloc); each handle's event is
+ * recorded after the last launch. Same checks as cyrus_codebook_build_batch. */
+int cyrus_codebook_build_batch_device(cyrus_codebook* const* cbs, const void* const* ue_device, int32_t n,
+                                      void* stream);
 
 /* Block until the last build of this handle has finished. */
 int cyrus_codebook_wait(cyrus_codebook* cb);
@@ -170,7 +188,7 @@ int cyrus_codebook_wait(cyrus_codebook* cb);
  * mini-slot tau in [1, M] after arrivals k_1..k_tau (arrivals[0..tau-1], each
  * in [0, K], already capped by the O-RU controller). Waits for the last host
  * build once, then reads the pinned mirror. */
-int cyrus_codebook_lookup(cyrus_codebook* cb, const uint8_t* arrivals, int32_t tau, uint8_t* alloc_out);
+int cyrus_codebook_lookup(const cyrus_codebook* cb, const uint8_t* arrivals, int32_t tau, uint8_t* alloc_out);
 
 /* O-RU side of one slot: the controller caps the URLLC packets punctured in
  * a mini-slot at K and carries the rest to the next one (Sec. III-A:
@@ -182,13 +200,13 @@ int cyrus_codebook_lookup(cyrus_codebook* cb, const uint8_t* arrivals, int32_t t
  *   y             [num_minislots][E] out: the puncturing matrix Y(t)
  *   carry_out     out: packets still buffered after the slot
  * Waits for the last build like lookup. */
-int cyrus_codebook_assemble(cyrus_codebook* cb, const int32_t* raw_arrivals, int32_t carry_in, uint8_t* served,
+int cyrus_codebook_assemble(const cyrus_codebook* cb, const int32_t* raw_arrivals, int32_t carry_in, uint8_t* served,
                             uint8_t* y, int32_t* carry_out);
 
 /* Copy the whole codebook to host memory: alloc [nodes][E] bytes; logits
  * [nodes][E] FP32 or NULL (needs CYRUS_FLAG_EXPORT_LOGITS). Waits for the
  * last build; after a device build it copies from the workspace. */
-int cyrus_codebook_export(cyrus_codebook* cb, uint8_t* alloc, float* logits);
+int cyrus_codebook_export(const cyrus_codebook* cb, uint8_t* alloc, float* logits);
 
 /* Device address of the codebook array [nodes][E] inside the workspace. */
 const uint8_t* cyrus_codebook_device_alloc(const cyrus_codebook* cb);
@@ -212,6 +230,11 @@ void cyrus_codebook_destroy(cyrus_codebook* cb);
 
 const char* cyrus_status_string(int status);
 const char* cyrus_last_error(void);
+
+/* Hash (16 hex digits) of the source files this library was compiled from,
+ * fixed at build time, so a binding can refuse a library older than the
+ * sources beside it. A static string; never NULL. */
+const char* cyrus_build_source_hash(void);
 
 /* ------------------------------------------------------------------------
  * Near-RT RIC critic pass (Sec. IV-B, Eqs. (3) and (4)): the batched forward
@@ -314,7 +337,9 @@ int cyrus_engine_create(void* device_pool, size_t device_bytes, void* host_pool,
                         int32_t max_active, void* stream, cyrus_engine** out);
 
 /* Queue one request for `cell`; the UE arrays are copied before returning.
- * *ticket receives an id (increasing from 0). */
+ * *ticket receives an id (increasing from 0). CYRUS_EWORKSPACE (nothing
+ * queued) when the request's tree could never fit the engine's pools, so an
+ * oversize request cannot block the FIFO. */
 int cyrus_engine_submit(cyrus_engine* eng, cyrus_codebook* cell, const cyrus_ue_state* ue, int64_t* ticket);
 
 /* One engine iteration: retire requests whose codebook copy finished, admit

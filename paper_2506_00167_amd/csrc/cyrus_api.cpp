@@ -73,8 +73,8 @@ int validate_config(const cyrus_config* cfg)
     if (cfg->num_hidden < 1 || cfg->num_hidden > CYRUS_MAX_HIDDEN)
         return fail(CYRUS_ERANGE, "num_hidden %d outside [1, %d]", cfg->num_hidden, CYRUS_MAX_HIDDEN);
     for (int i = 0; i < cfg->num_hidden; ++i)
-        if (cfg->hidden[i] < 128 || cfg->hidden[i] > 512 || cfg->hidden[i] % 128 != 0)
-            return fail(CYRUS_ERANGE, "hidden[%d] = %d is not a multiple of 128 in [128, 512]", i, cfg->hidden[i]);
+        if (cfg->hidden[i] < 32 || cfg->hidden[i] > 512 || cfg->hidden[i] % 32 != 0)
+            return fail(CYRUS_ERANGE, "hidden[%d] = %d is not a multiple of 32 in [32, 512]", i, cfg->hidden[i]);
     if (cfg->precision != CYRUS_FP32 && cfg->precision != CYRUS_BF16 && cfg->precision != CYRUS_FP8_E4M3)
         return fail(CYRUS_EINVAL, "unknown precision %d", cfg->precision);
     if (cfg->flags &
@@ -99,9 +99,13 @@ Shape make_shape(const cyrus_config* cfg)
     s.w_bytes = 0;
     s.staging_floats = 0;
     for (int l = 0; l < s.n_layers; ++l) {
-        // FP8 reads its input in pairs of chunks (one 16x16x128 MFMA step)
-        s.in_pad[l] = (int)align_up(s.dims[l], s.prec == kFP8 ? 2 * kc : kc);
-        s.out_pad[l] = (int)align_up(s.dims[l + 1], 16);
+        // FP8 reads its input in pairs of chunks (one 16x16x128 MFMA step).
+        // Hidden layers are computed 128 neurons at a time (8 waves x 16): a
+        // width that is a multiple of 32 is zero-padded to the next multiple
+        // of 128 (zero weights and bias, so the padded neurons are ReLU(0) = 0
+        // and add nothing to the next layer).
+        s.in_pad[l] = (int)(l == 0 ? align_up(s.dims[l], s.prec == kFP8 ? 2 * kc : kc) : align_up(s.dims[l], 128));
+        s.out_pad[l] = (int)align_up(s.dims[l + 1], l + 1 < s.n_layers ? 128 : 16);
         s.w_off[l] = s.w_bytes;
         s.w_bytes += align_up((size_t)s.in_pad[l] * s.out_pad[l] * prec_esize(s.prec), 256);
         s.staging_floats = std::max(s.staging_floats, (size_t)s.in_pad[l] * s.out_pad[l]);
@@ -200,9 +204,11 @@ int choose_rtt(const DevTree& t, int prec, int max_rtt)
 
 namespace cyrus {
 
-DevTree make_devtree(const cyrus_codebook* cb, const int32_t* ue_dev)
+DevTree make_devtree(const cyrus_codebook* cb, const int32_t* ue_dev, int slot)
 {
     const Shape& s = cb->s;
+    if (slot < 0)
+        slot = cb->active;
     DevTree t{};
     t.E = s.E;
     t.K = s.K;
@@ -214,14 +220,14 @@ DevTree make_devtree(const cyrus_codebook* cb, const int32_t* ue_dev)
     t.tti = cb->rng_tti;
     t.n_layers = s.n_layers;
     t.in_dim0 = s.dims[0];
-    const uint8_t* wb = cb->ws + s.off_w[cb->active];
+    const uint8_t* wb = cb->ws + s.off_w[slot];
     for (int l = 0; l < s.n_layers; ++l) {
         t.in_pad[l] = s.in_pad[l];
         t.out_pad[l] = s.out_pad[l];
         t.w[l] = wb + s.w_off[l];
         t.b[l] = reinterpret_cast<const float*>(wb + s.b_off[l]);
-        t.deq[l] = cb->deq[l];
-        t.inv_in_scale[l] = cb->inv_in[l];
+        t.deq[l] = cb->deq[slot][l];
+        t.inv_in_scale[l] = cb->inv_in[slot][l];
     }
     t.in_pad_d = s.in_pad_d;
     t.w1d = wb + s.w1d_off;
@@ -230,6 +236,24 @@ DevTree make_devtree(const cyrus_codebook* cb, const int32_t* ue_dev)
     t.state = cb->ws + s.off_state;
     t.logits = s.export_logits ? reinterpret_cast<float*>(cb->ws + s.off_logits) : nullptr;
     return t;
+}
+
+hipError_t note_slot_use(cyrus_codebook* cb, int slot, hipStream_t stream)
+{
+    for (auto& u : cb->slot_use[slot])
+        if (u.first == stream)
+            return hipEventRecord(u.second, stream);
+    hipEvent_t ev = nullptr;
+    hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e != hipSuccess)
+        return e;
+    e = hipEventRecord(ev, stream);
+    if (e != hipSuccess) {
+        (void)hipEventDestroy(ev);
+        return e;
+    }
+    cb->slot_use[slot].emplace_back(stream, ev);
+    return hipSuccess;
 }
 
 int codebook_path(const cyrus_codebook* cb) { return cb->path; }
@@ -267,6 +291,14 @@ static int load_weights(cyrus_codebook* cb, const cyrus_weights* w, hipStream_t 
             if (!std::isfinite(w->w[l][i]))
                 return fail(CYRUS_EINVAL, "weight %zu of layer %d is not finite", i, l);
 
+    // builds, batches and engine launches enqueued earlier may still read the
+    // buffer about to be overwritten: wait for each stream's last use of it.
+    // Engine requests admitted with it may have levels still to enqueue.
+    if (cb->engine_refs[target] > 0)
+        return fail(CYRUS_ENOTREADY, "%d serving-engine requests still use the weight buffer to be replaced; step "
+                    "the engine until they finish", cb->engine_refs[target]);
+    for (auto& u : cb->slot_use[target])
+        HIP_TRY(hipEventSynchronize(u.second));
     uint8_t* wb = cb->ws + s.off_w[target];
     float* staging = reinterpret_cast<float*>(cb->ws + s.off_staging);
     cb->pack.assign(s.staging_floats, 0.f);
@@ -297,8 +329,8 @@ static int load_weights(cyrus_codebook* cb, const cyrus_weights* w, hipStream_t 
         HIP_TRY(hipStreamSynchronize(stream));
     }
     for (int l = 0; l < s.n_layers; ++l) {
-        cb->deq[l] = w_scale[l] * a_scale[l];
-        cb->inv_in[l] = 1.f / a_scale[l];
+        cb->deq[target][l] = w_scale[l] * a_scale[l];
+        cb->inv_in[target][l] = 1.f / a_scale[l];
     }
     cb->active = target;
     return CYRUS_OK;
@@ -316,7 +348,11 @@ static int enqueue_tree(cyrus_codebook* cb, const DevTree& t, hipStream_t stream
 
 static int enqueue_kernels(cyrus_codebook* cb, const int32_t* ue_dev, hipStream_t stream)
 {
-    return enqueue_tree(cb, make_devtree(cb, ue_dev), stream);
+    int rc = enqueue_tree(cb, make_devtree(cb, ue_dev), stream);
+    if (rc)
+        return rc;
+    HIP_TRY(note_slot_use(cb, cb->active, stream));
+    return CYRUS_OK;
 }
 
 extern "C" {
@@ -452,6 +488,7 @@ int cyrus_codebook_build(cyrus_codebook* cb, const cyrus_ue_state* ue, void* str
         rc = enqueue_tree(cb, t, st);
         if (rc)
             return rc;
+        HIP_TRY(note_slot_use(cb, cb->active, st));
         HIP_TRY(hipEventRecord(cb->ev_staged, st));
         cb->staged_recorded = true;
         HIP_TRY(hipEventRecord(cb->ev_done, st));
@@ -503,13 +540,16 @@ int cyrus_codebook_wait(cyrus_codebook* cb)
     return CYRUS_OK;
 }
 
-static int sync_mirror(cyrus_codebook* cb)
+// Wait for the last build, then make sure the pinned mirror holds it (a
+// device build leaves the codebook in the workspace only).
+static int sync_mirror(const cyrus_codebook* cb)
 {
     if (!cb->built)
         return fail(CYRUS_ENOTREADY, "no build has been enqueued on this handle");
-    int rc = cyrus_codebook_wait(cb);
-    if (rc)
-        return rc;
+    if (cb->pending) {
+        HIP_TRY(hipEventSynchronize(cb->ev_done));
+        cb->pending = false;
+    }
     if (!cb->mirror_valid) {
         const Shape& s = cb->s;
         HIP_TRY(hipSetDevice(cb->device));
@@ -523,7 +563,7 @@ static int sync_mirror(cyrus_codebook* cb)
     return CYRUS_OK;
 }
 
-int cyrus_codebook_lookup(cyrus_codebook* cb, const uint8_t* arrivals, int32_t tau, uint8_t* alloc_out)
+int cyrus_codebook_lookup(const cyrus_codebook* cb, const uint8_t* arrivals, int32_t tau, uint8_t* alloc_out)
 {
     if (!cb || !alloc_out || (tau > 0 && !arrivals))
         return fail(CYRUS_EINVAL, "NULL argument");
@@ -544,7 +584,7 @@ int cyrus_codebook_lookup(cyrus_codebook* cb, const uint8_t* arrivals, int32_t t
     return CYRUS_OK;
 }
 
-int cyrus_codebook_assemble(cyrus_codebook* cb, const int32_t* raw_arrivals, int32_t carry_in, uint8_t* served,
+int cyrus_codebook_assemble(const cyrus_codebook* cb, const int32_t* raw_arrivals, int32_t carry_in, uint8_t* served,
                             uint8_t* y, int32_t* carry_out)
 {
     if (!cb || !raw_arrivals || !served || !y || !carry_out)
@@ -572,7 +612,7 @@ int cyrus_codebook_assemble(cyrus_codebook* cb, const int32_t* raw_arrivals, int
     return CYRUS_OK;
 }
 
-int cyrus_codebook_export(cyrus_codebook* cb, uint8_t* alloc, float* logits)
+int cyrus_codebook_export(const cyrus_codebook* cb, uint8_t* alloc, float* logits)
 {
     if (!cb || !alloc)
         return fail(CYRUS_EINVAL, "NULL argument");
@@ -622,6 +662,11 @@ void cyrus_codebook_destroy(cyrus_codebook* cb)
         (void)hipEventSynchronize(cb->ev_staged);
     (void)hipEventDestroy(cb->ev_staged);
     (void)hipEventDestroy(cb->ev_done);
+    for (auto& uses : cb->slot_use)
+        for (auto& u : uses) {
+            (void)hipEventSynchronize(u.second);
+            (void)hipEventDestroy(u.second);
+        }
     delete cb;
 }
 
@@ -649,9 +694,15 @@ const char* cyrus_status_string(int status)
 
 const char* cyrus_last_error(void) { return g_err.c_str(); }
 
+#ifndef CYRUS_SOURCE_HASH
+#define CYRUS_SOURCE_HASH "unknown"
+#endif
+const char* cyrus_build_source_hash(void) { return CYRUS_SOURCE_HASH; }
+
 }  // extern "C"
 
 // Shared with the batch builder.
 namespace cyrus {
 int set_error(int status, const char* msg) { return fail(status, "%s", msg); }
+int stage_ue_host(cyrus_codebook* cb, const cyrus_ue_state* ue) { return stage_ue(cb, ue); }
 }  // namespace cyrus

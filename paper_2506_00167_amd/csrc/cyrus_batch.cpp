@@ -105,17 +105,18 @@ int build_batch_levels(cyrus_codebook* const* cbs, const DevTree* trees, int n, 
 
 }  // namespace cyrus
 
-extern "C" int cyrus_codebook_build_batch(cyrus_codebook* const* cbs, const void* const* ue_device, int32_t n,
-                                          void* stream)
+namespace {
+
+// Checks shared by both batch entry points.
+int check_batch(cyrus_codebook* const* cbs, int32_t n)
 {
-    if (!cbs || !ue_device)
+    if (!cbs)
         return set_error(CYRUS_EINVAL, "NULL argument");
     if (n < 1 || n > kMaxBatch)
         return set_error(CYRUS_ERANGE, "batch size outside [1, 128]");
-    DevTree trees[kMaxBatch];
     for (int i = 0; i < n; ++i) {
-        if (!cbs[i] || !ue_device[i])
-            return set_error(CYRUS_EINVAL, "NULL handle or UE pointer in the batch");
+        if (!cbs[i])
+            return set_error(CYRUS_EINVAL, "NULL handle in the batch");
         if (cbs[i]->s.prec != cbs[0]->s.prec)
             return set_error(CYRUS_EINVAL, "all codebooks of a batch must share a precision");
         if (cbs[i]->device != cbs[0]->device)
@@ -123,21 +124,102 @@ extern "C" int cyrus_codebook_build_batch(cyrus_codebook* const* cbs, const void
         for (int j = 0; j < i; ++j)
             if (cbs[j] == cbs[i])
                 return set_error(CYRUS_EINVAL, "a codebook appears twice in one batch");
+    }
+    return CYRUS_OK;
+}
+
+}  // namespace
+
+extern "C" int cyrus_codebook_build_batch_device(cyrus_codebook* const* cbs, const void* const* ue_device, int32_t n,
+                                                 void* stream)
+{
+    int rc = check_batch(cbs, n);
+    if (rc)
+        return rc;
+    if (!ue_device)
+        return set_error(CYRUS_EINVAL, "NULL argument");
+    DevTree trees[kMaxBatch];
+    for (int i = 0; i < n; ++i) {
+        if (!ue_device[i])
+            return set_error(CYRUS_EINVAL, "NULL UE pointer in the batch");
+        if (reinterpret_cast<uintptr_t>(ue_device[i]) % 4)
+            return set_error(CYRUS_EINVAL, "UE state must be 4-byte aligned");
         trees[i] = make_devtree(cbs[i], static_cast<const int32_t*>(ue_device[i]));
     }
     hipError_t e = hipSetDevice(cbs[0]->device);
     if (e != hipSuccess)
         return hip_fail(e, "hipSetDevice");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    int rc = build_batch_levels(cbs, trees, n, st);
+    rc = build_batch_levels(cbs, trees, n, st);
     if (rc)
         return rc;
     for (int i = 0; i < n; ++i) {
-        e = hipEventRecord(cbs[i]->ev_done, st);
+        e = note_slot_use(cbs[i], cbs[i]->active, st);
+        if (e == hipSuccess)
+            e = hipEventRecord(cbs[i]->ev_done, st);
         if (e != hipSuccess)
             return hip_fail(e, "hipEventRecord");
         cbs[i]->built = cbs[i]->pending = true;
         cbs[i]->mirror_valid = false;
+    }
+    return CYRUS_OK;
+}
+
+extern "C" int cyrus_codebook_build_batch(cyrus_codebook* const* cbs, const cyrus_ue_state* ue, int32_t n,
+                                          void* stream)
+{
+    int rc = check_batch(cbs, n);
+    if (rc)
+        return rc;
+    if (!ue)
+        return set_error(CYRUS_EINVAL, "NULL argument");
+    hipError_t e = hipSetDevice(cbs[0]->device);
+    if (e != hipSuccess)
+        return hip_fail(e, "hipSetDevice");
+    // every UE state is validated and staged before anything is enqueued
+    for (int i = 0; i < n; ++i) {
+        rc = stage_ue_host(cbs[i], &ue[i]);
+        if (rc)
+            return rc;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    DevTree trees[kMaxBatch];
+    for (int i = 0; i < n; ++i)
+        trees[i] = make_devtree(cbs[i], reinterpret_cast<const int32_t*>(cbs[i]->ws + cbs[i]->s.off_ue));
+    {
+        int rtt = 0, buf = 0;
+        size_t lds = 0;
+        if (!plan_level_batch(trees, n, cbs[0]->s.prec, &rtt, &buf, &lds))
+            return set_error(CYRUS_EUNSUPPORTED, "batch does not fit the level kernel's LDS");
+    }
+    for (int i = 0; i < n; ++i) {
+        const Shape& s = cbs[i]->s;
+        e = hipMemcpyAsync(cbs[i]->ws + s.off_ue, cbs[i]->host + s.hoff_ue, (size_t)3 * s.E * 4, hipMemcpyHostToDevice,
+                           st);
+        if (e != hipSuccess)
+            return hip_fail(e, "hipMemcpyAsync(UE state)");
+    }
+    rc = build_batch_levels(cbs, trees, n, st);
+    if (rc)
+        return rc;
+    for (int i = 0; i < n; ++i) {
+        cyrus_codebook* cb = cbs[i];
+        const Shape& s = cb->s;
+        e = hipEventRecord(cb->ev_staged, st);  // the UE copy out of the pinned buffer
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(cb->host + s.hoff_alloc, cb->ws + s.off_alloc, (size_t)s.nodes * s.E,
+                               hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess && s.export_logits)
+            e = hipMemcpyAsync(cb->host + s.hoff_logits, cb->ws + s.off_logits, (size_t)s.nodes * s.E * 4,
+                               hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess)
+            e = note_slot_use(cb, cb->active, st);
+        if (e == hipSuccess)
+            e = hipEventRecord(cb->ev_done, st);
+        if (e != hipSuccess)
+            return hip_fail(e, "codebook copy to the pinned mirror");
+        cb->staged_recorded = true;
+        cb->built = cb->pending = cb->mirror_valid = true;
     }
     return CYRUS_OK;
 }

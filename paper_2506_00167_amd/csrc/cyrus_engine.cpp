@@ -107,6 +107,7 @@ struct Request {
     double t_submit = 0, t_done = 0;
     std::vector<int32_t> ue;  // rb[E], mcs[E], sinr bits[E]
     uint64_t seed = 0, tti = 0;  // Gaussian head: the cell's Philox key and TTI at submit
+    int wslot = 0;               // the cell's weight buffer, fixed at admission
     size_t dev_off = 0, dev_bytes = 0, host_off = 0, host_bytes = 0;
     bool has_dev = false, has_host = false;
 };
@@ -116,12 +117,22 @@ size_t slot_bytes()
     return (sizeof(DevTree) * kMaxBatch + 255) / 256 * 256 + (size_t)(3 * kMaxBatch + 1) * 4;
 }
 
+// Pool bytes one request of `s` holds: its tree (allocations, states) and UE
+// state on the device; its codebook mirror and UE staging on the host.
+size_t request_dev_bytes(const Shape& s)
+{
+    const size_t tree = ((size_t)s.nodes * s.E + 255) / 256 * 256;
+    return 2 * tree + 3 * kMaxUE * 4;
+}
+size_t request_host_bytes(const Shape& s) { return (size_t)s.nodes * s.E + 3 * kMaxUE * 4 + 64; }
+
 }  // namespace
 
 struct cyrus_engine {
     uint8_t* dpool = nullptr;
     uint8_t* hpool = nullptr;
     Pool dfree, hfree;
+    size_t dcap = 0, hcap = 0;  // pool bytes left for requests after the descriptor slots
     int max_active = 0;
     int levels_per_step = 1;
     hipStream_t stream = nullptr;
@@ -157,6 +168,7 @@ int retire(cyrus_engine* e)
         if (q == hipSuccess) {
             r->status = CYRUS_REQ_DONE;
             r->t_done = now_us();
+            r->cell->engine_refs[r->wslot]--;
             release_request_device(e, r);
             e->newly_done.push_back(r);
             e->counters[1]++;
@@ -181,8 +193,8 @@ int admit(cyrus_engine* e)
         Request* r = e->waiting.front();
         const Shape& s = codebook_shape(r->cell);
         const size_t tree = ((size_t)s.nodes * s.E + 255) / 256 * 256;
-        r->dev_bytes = 2 * tree + 3 * kMaxUE * 4;
-        r->host_bytes = (size_t)s.nodes * s.E + 3 * kMaxUE * 4 + 64;
+        r->dev_bytes = request_dev_bytes(s);
+        r->host_bytes = request_host_bytes(s);
         if (!e->dfree.alloc(r->dev_bytes, &r->dev_off)) {
             e->counters[3]++;
             break;
@@ -207,6 +219,8 @@ int admit(cyrus_engine* e)
             return hip_err(err, "request admission copies");
         r->status = CYRUS_REQ_RUNNING;
         r->level = 1;
+        r->wslot = r->cell->active;
+        r->cell->engine_refs[r->wslot]++;
         e->running.push_back(r);
         e->waiting.pop_front();
     }
@@ -227,7 +241,7 @@ int launch_step(cyrus_engine* e)
         const Shape& s = codebook_shape(r->cell);
         const size_t tree = ((size_t)s.nodes * s.E + 255) / 256 * 256;
         uint8_t* dbase = e->dpool + r->dev_off;
-        DevTree t = make_devtree(r->cell, reinterpret_cast<const int32_t*>(dbase + 2 * tree));
+        DevTree t = make_devtree(r->cell, reinterpret_cast<const int32_t*>(dbase + 2 * tree), r->wslot);
         t.alloc = dbase;
         t.state = dbase + tree;
         t.logits = nullptr;
@@ -312,6 +326,17 @@ int launch_step(cyrus_engine* e)
             still.push_back(r);
         }
     }
+    // every weight buffer this step read: its cell's use event on the stream
+    std::vector<std::pair<cyrus_codebook*, int>> used;
+    for (const Request* r : e->running) {
+        const std::pair<cyrus_codebook*, int> u(r->cell, r->wslot);
+        if (std::find(used.begin(), used.end(), u) == used.end()) {
+            used.push_back(u);
+            err = note_slot_use(r->cell, r->wslot, e->stream);
+            if (err != hipSuccess)
+                return hip_err(err, "weight-buffer use event");
+        }
+    }
     e->running.swap(still);
     err = hipEventRecord(e->ev[slot], e->stream);
     if (err != hipSuccess)
@@ -335,7 +360,8 @@ int cyrus_engine_create(void* device_pool, size_t device_bytes, void* host_pool,
         return set_error(CYRUS_ERANGE, "max_active outside [1, 128]");
     if (reinterpret_cast<uintptr_t>(device_pool) % 256 || reinterpret_cast<uintptr_t>(host_pool) % 64)
         return set_error(CYRUS_EWORKSPACE, "pools must be 256-byte (device) and 64-byte (host) aligned");
-    if (device_bytes < kSlots * slot_bytes() || host_bytes < kSlots * slot_bytes())
+    const size_t dslots = kSlots * ((slot_bytes() + 255) / 256 * 256), hslots = kSlots * ((slot_bytes() + 63) / 64 * 64);
+    if (device_bytes < dslots || host_bytes < hslots)
         return set_error(CYRUS_EWORKSPACE, "pools smaller than the descriptor slots");
     cyrus_engine* e = new (std::nothrow) cyrus_engine();
     if (!e)
@@ -345,6 +371,8 @@ int cyrus_engine_create(void* device_pool, size_t device_bytes, void* host_pool,
     e->dfree.init(device_bytes, 256);
     e->hfree.init(host_bytes, 64);
     e->max_active = max_active;
+    e->dcap = device_bytes - dslots;
+    e->hcap = host_bytes - hslots;
     e->stream = static_cast<hipStream_t>(stream);
     if (hipGetDevice(&e->device) != hipSuccess) {
         delete e;
@@ -376,6 +404,9 @@ int cyrus_engine_submit(cyrus_engine* e, cyrus_codebook* cell, const cyrus_ue_st
     for (int i = 0; i < s.E; ++i)
         if (ue->rb[i] < 0 || ue->rb[i] > 255)
             return set_error(CYRUS_ERANGE, "rb outside [0, 255]");
+    // a request that can never fit the pools would block the FIFO forever
+    if (request_dev_bytes(s) > e->dcap || request_host_bytes(s) > e->hcap)
+        return set_error(CYRUS_EWORKSPACE, "the request's tree does not fit the engine's pools");
     e->prec = s.prec;
     Request* r = new (std::nothrow) Request();
     if (!r)
@@ -499,6 +530,10 @@ void cyrus_engine_destroy(cyrus_engine* e)
         return;
     (void)hipSetDevice(e->device);
     (void)hipStreamSynchronize(e->stream);
+    for (Request* r : e->running)
+        r->cell->engine_refs[r->wslot]--;
+    for (Request* r : e->draining)
+        r->cell->engine_refs[r->wslot]--;
     for (int i = 0; i < kSlots; ++i)
         (void)hipEventDestroy(e->ev[i]);
     for (auto& kv : e->by_ticket)

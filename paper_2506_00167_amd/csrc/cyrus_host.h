@@ -6,6 +6,7 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <utility>
 #include <vector>
 
 #include "cyrus.h"
@@ -41,11 +42,19 @@ size_t batch_area_bytes();
 void pack_fragments(const float* w, int out, int in, int out_pad, int in_pad, int prec, float* dst);
 float e4m3_weight_scale(const float* w, size_t n);
 int choose_rtt(const DevTree& t, int prec, int max_rtt);
-DevTree make_devtree(const cyrus_codebook* cb, const int32_t* ue_dev);
+// Kernel descriptor of cb with UE state ue_dev, reading weight buffer `slot`
+// (-1: the current one).
+DevTree make_devtree(const cyrus_codebook* cb, const int32_t* ue_dev, int slot = -1);
 int codebook_path(const cyrus_codebook* cb);
 int codebook_rtt(const cyrus_codebook* cb);
 const Shape& codebook_shape(const cyrus_codebook* cb);
 int set_error(int status, const char* msg);
+// Mark weight buffer `slot` of cb as read by the work enqueued so far on
+// `stream` (records that stream's use event for the slot).
+hipError_t note_slot_use(cyrus_codebook* cb, int slot, hipStream_t stream);
+// Validate one host UE state and copy it into cb's pinned staging area (after
+// the previous copy out of it has finished).
+int stage_ue_host(cyrus_codebook* cb, const cyrus_ue_state* ue);
 
 // Subtree (single-launch latency) path.
 bool subtree_supported(const DevTree& t, int prec);
@@ -62,14 +71,21 @@ struct cyrus_codebook {
     uint8_t* host = nullptr;
     uint8_t* host_dev = nullptr;  // device-side address of the pinned buffer (null: not mapped)
     int active = 0;
-    float deq[cyrus::kMaxLayers];
-    float inv_in[cyrus::kMaxLayers];
+    float deq[2][cyrus::kMaxLayers];     // per weight buffer: FP8 weight scale * input scale, else 1
+    float inv_in[2][cyrus::kMaxLayers];  // per weight buffer: FP8 1 / input scale, else 1
     hipEvent_t ev_staged = nullptr;
     hipEvent_t ev_done = nullptr;
     bool staged_recorded = false;
     bool built = false;
-    bool pending = false;
-    bool mirror_valid = false;
+    mutable bool pending = false;       // a build may still run (cleared by a wait)
+    mutable bool mirror_valid = false;  // the pinned mirror holds the last build
+    // Last use of each weight buffer: one event per stream that enqueued work
+    // reading it. set_weights waits for these before overwriting a buffer.
+    std::vector<std::pair<hipStream_t, hipEvent_t>> slot_use[2];
+    // Serving-engine requests admitted with each weight buffer and not yet
+    // retired (their next launches are not enqueued yet, so no event covers
+    // them); set_weights refuses to overwrite a buffer while this is nonzero.
+    int engine_refs[2] = {0, 0};
     int path = 0;  // 0 level, 1 subtree
     int rtt = 1;
     uint64_t rng_seed = 0, rng_tti = 0;  // Gaussian head: Philox key and TTI of the next builds

@@ -309,10 +309,11 @@ __device__ __forceinline__ const float* eval_rows(const DevTree& t, const Subtre
 // Enforcer over `nrows` rows, G lanes per row (lane e = UE e). Each lane first
 // adds up its logit from the per-wave partial tiles (fixed wave order) plus
 // the bias. Row r has arrival k_of(r), input state cin_of(r); it writes its
-// state to sout_of(r) (LDS) and, when node_of(r) >= 0, alloc/state/logits of
-// that node to global memory; when sib_of(r) >= 0 (the first child of a
+// state to sout_of(r) (LDS) and, when node_of(r) >= 0, the node's allocation
+// (and logits) to global memory; when sib_of(r) >= 0 (the first child of a
 // parent) it also writes that k = 0 sibling: nothing punctured, parent state
-// passed on, into sib_st_of(r).
+// passed on, into sib_st_of(r). Node states stay in LDS: no later launch
+// reads them on this path (the level kernels keep their own state array).
 template <int G, int RT, bool EXT, class KOf, class CinOf, class SoutOf, class EpsOf, class NodeOf, class SibOf,
           class SibStOf>
 __device__ __forceinline__ void finish_rows(const DevTree& t, const SubtreeSmem& sm, const float* part, float deq,
@@ -358,7 +359,6 @@ __device__ __forceinline__ void finish_rows(const DevTree& t, const SubtreeSmem&
                 const int64_t node = node_of(row);
                 if (node >= 0) {
                     t.alloc[node * E + e] = (uint8_t)a;
-                    t.state[node * E + e] = st;
                     if (t.logits)
                         t.logits[node * E + e] = z;
                 }
@@ -366,7 +366,6 @@ __device__ __forceinline__ void finish_rows(const DevTree& t, const SubtreeSmem&
                 if (sib >= 0) {
                     sib_st_of(row)[e] = c;
                     t.alloc[sib * E + e] = 0;
-                    t.state[sib * E + e] = c;
                     if (t.logits)
                         t.logits[sib * E + e] = 0.f;
                 }
@@ -548,7 +547,6 @@ __device__ __forceinline__ void subtree_body(const DevTree& t, int split, int bu
             sm.st1 = tmp;
         } else if (owner && threadIdx.x < E) {
             t.alloc[node * E + threadIdx.x] = 0;
-            t.state[node * E + threadIdx.x] = sm.st0[threadIdx.x];
             if (t.logits)
                 t.logits[node * E + threadIdx.x] = 0.f;
         }

@@ -33,6 +33,7 @@ MAX_LAYERS = 5
 SYMBOLS = (
     "cyrus_codebook_workspace_size", "cyrus_codebook_create", "cyrus_codebook_set_weights",
     "cyrus_codebook_build", "cyrus_codebook_build_device", "cyrus_codebook_build_batch",
+    "cyrus_codebook_build_batch_device", "cyrus_build_source_hash",
     "cyrus_codebook_wait", "cyrus_codebook_lookup", "cyrus_codebook_assemble", "cyrus_codebook_export", "cyrus_codebook_device_alloc",
     "cyrus_codebook_num_nodes", "cyrus_codebook_kernel_path", "cyrus_codebook_set_rng", "cyrus_codebook_destroy",
     "cyrus_status_string", "cyrus_last_error",
@@ -98,6 +99,13 @@ def lib():
         # allocated by torch are known to the library)
         import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
+        L.cyrus_build_source_hash.restype = ctypes.c_char_p
+        built = L.cyrus_build_source_hash().decode()
+        from . import build as _build
+        want = _build.source_hash()
+        if built != want:
+            raise RuntimeError(f"{LIB_PATH} was built from other sources (hash {built}, sources {want}): "
+                               "rebuild it with `python -m paper_2506_00167_amd.build`")
         vp, sz = ctypes.c_void_p, ctypes.c_size_t
         L.cyrus_codebook_workspace_size.argtypes = [ctypes.POINTER(cyrus_config), ctypes.POINTER(sz),
                                                     ctypes.POINTER(sz)]
@@ -106,7 +114,9 @@ def lib():
         L.cyrus_codebook_set_weights.argtypes = [vp, ctypes.POINTER(cyrus_weights), vp]
         L.cyrus_codebook_build.argtypes = [vp, ctypes.POINTER(cyrus_ue_state), vp]
         L.cyrus_codebook_build_device.argtypes = [vp, vp, vp]
-        L.cyrus_codebook_build_batch.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_int32, vp]
+        L.cyrus_codebook_build_batch.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(cyrus_ue_state), ctypes.c_int32,
+                                                 vp]
+        L.cyrus_codebook_build_batch_device.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_int32, vp]
         L.cyrus_codebook_wait.argtypes = [vp]
         L.cyrus_codebook_lookup.argtypes = [vp, _u8p, ctypes.c_int32, _u8p]
         L.cyrus_codebook_export.argtypes = [vp, _u8p, _f32p]
@@ -233,11 +243,19 @@ def cyrus_codebook_build_device(h: int, ue_dev_ptr: int, stream) -> None:
     _check(lib().cyrus_codebook_build_device(h, ue_dev_ptr, _stream_ptr(stream)), "cyrus_codebook_build_device")
 
 
-def cyrus_codebook_build_batch(handles: Sequence[int], ue_dev_ptrs: Sequence[int], stream) -> None:
+def cyrus_codebook_build_batch(handles: Sequence[int], ues: Sequence[cyrus_ue_state], stream) -> None:
+    n = len(handles)
+    hs = (ctypes.c_void_p * n)(*handles)
+    us = (cyrus_ue_state * n)(*ues)
+    _check(lib().cyrus_codebook_build_batch(hs, us, n, _stream_ptr(stream)), "cyrus_codebook_build_batch")
+
+
+def cyrus_codebook_build_batch_device(handles: Sequence[int], ue_dev_ptrs: Sequence[int], stream) -> None:
     n = len(handles)
     hs = (ctypes.c_void_p * n)(*handles)
     us = (ctypes.c_void_p * n)(*ue_dev_ptrs)
-    _check(lib().cyrus_codebook_build_batch(hs, us, n, _stream_ptr(stream)), "cyrus_codebook_build_batch")
+    _check(lib().cyrus_codebook_build_batch_device(hs, us, n, _stream_ptr(stream)),
+           "cyrus_codebook_build_batch_device")
 
 
 def cyrus_codebook_wait(h: int) -> None:
@@ -387,8 +405,15 @@ class Codebook:
             pass
 
 
-def build_batch(codebooks: Sequence[Codebook], ue_devs, stream=None):
-    cyrus_codebook_build_batch([c.handle for c in codebooks], [u.data_ptr() for u in ue_devs], stream)
+def build_batch(codebooks: Sequence[Codebook], ues: Sequence[UEState], stream=None):
+    """Host UE states in, every codebook in its pinned mirror after the wait."""
+    structs = [ue_struct(u) for u in ues]  # the arrays stay referenced for the call
+    cyrus_codebook_build_batch([c.handle for c in codebooks], [st for st, _ in structs], stream)
+
+
+def build_batch_device(codebooks: Sequence[Codebook], ue_devs, stream=None):
+    """Device UE states (ue_device_tensor) in, codebooks left on the device."""
+    cyrus_codebook_build_batch_device([c.handle for c in codebooks], [u.data_ptr() for u in ue_devs], stream)
 
 
 # ------------------------------------------------------------ serving engine

@@ -41,13 +41,13 @@ def run(iters: int = 20, warmup: int = 3, precision: str = "fp8"):
     cfg, cells, ues = make_cells(precision=precision, stream=stream)
     torch.cuda.synchronize()
     for _ in range(warmup):
-        cyrus.build_batch(cells, ues, stream)
+        cyrus.build_batch_device(cells, ues, stream)
     torch.cuda.synchronize()
     times = []
     for _ in range(iters):
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record(stream)
-        cyrus.build_batch(cells, ues, stream)
+        cyrus.build_batch_device(cells, ues, stream)
         b.record(stream)
         b.synchronize()
         times.append(a.elapsed_time(b) * 1e3)

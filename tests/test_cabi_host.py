@@ -56,10 +56,19 @@ def test_config_validation(lib, field, value, status):
 
 
 def test_hidden_width_and_state_range(lib):
-    c = cyrus.make_config(wl.TREE_E8K3)
-    c.hidden[0] = 200
-    with pytest.raises(cyrus.CyrusError):
-        cyrus.cyrus_codebook_workspace_size(c)
+    for bad in (200, 16, 544, 0):
+        c = cyrus.make_config(wl.TREE_E8K3)
+        c.hidden[0] = bad
+        with pytest.raises(cyrus.CyrusError) as ei:
+            cyrus.cyrus_codebook_workspace_size(c)
+        assert ei.value.status == -2
+    # multiples of 32 are accepted: they are computed zero-padded to 128
+    sizes = {}
+    for width in (32, 96, 128, 160, 256, 480, 512):
+        c = cyrus.make_config(wl.TREE_E8K3)
+        c.hidden[0] = c.hidden[1] = width
+        sizes[width] = cyrus.cyrus_codebook_workspace_size(c)[0]
+    assert sizes[32] == sizes[96] == sizes[128] < sizes[160] == sizes[256] < sizes[480] == sizes[512]
     c = cyrus.make_config(wl.TreeConfig(num_ue=4, max_arrival=7, num_minislots=7, rb_per_unit=6))
     with pytest.raises(cyrus.CyrusError):  # 7*7*6 > 255
         cyrus.cyrus_codebook_workspace_size(c)
@@ -85,3 +94,34 @@ def test_create_rejects_host_memory_as_workspace(lib):
                                    ctypes.byref(out))
     assert rc in (-3, -4)
     assert out.value is None
+
+
+def test_library_matches_its_sources(lib):
+    from paper_2506_00167_amd import build
+    lib.cyrus_build_source_hash.restype = ctypes.c_char_p
+    assert lib.cyrus_build_source_hash().decode() == build.source_hash()
+
+
+def test_stale_library_is_refused(monkeypatch):
+    """A library built from other sources than those beside it is refused,
+    so a stale binary cannot be tested or benchmarked silently."""
+    from paper_2506_00167_amd import build
+    if not os.path.exists(cyrus.LIB_PATH):
+        build.build()
+    monkeypatch.setattr(build, "source_hash", lambda: "0000000000000000")
+    monkeypatch.setattr(cyrus, "_lib", None)
+    with pytest.raises(RuntimeError, match="other sources"):
+        cyrus.lib()
+
+
+def test_batch_argument_checks(lib):
+    """Both batch entry points validate before enqueueing anything."""
+    vp = ctypes.c_void_p
+    hs = (vp * 1)(None)
+    ues = (cyrus.cyrus_ue_state * 1)()
+    assert lib.cyrus_codebook_build_batch(hs, ues, 0, None) == -2
+    assert lib.cyrus_codebook_build_batch(hs, ues, 129, None) == -2
+    assert lib.cyrus_codebook_build_batch(hs, ues, 1, None) == -1   # NULL handle
+    assert lib.cyrus_codebook_build_batch(None, ues, 1, None) == -1
+    assert lib.cyrus_codebook_build_batch_device(hs, (vp * 1)(None), 0, None) == -2
+    assert lib.cyrus_codebook_build_batch_device(hs, (vp * 1)(None), 1, None) == -1

@@ -202,7 +202,7 @@ def test_batch_equals_single_builds():
         single.close()
         cbs.append(cyrus.Codebook(cfg, weights, export_logits=True, force_level=True))
         ues.append(cyrus.ue_device_tensor(ue))
-    cyrus.build_batch(cbs, ues)
+    cyrus.build_batch_device(cbs, ues)
     torch.cuda.synchronize()
     for cb, (ra, rl) in zip(cbs, refs):
         a, l = cb.export()
@@ -345,7 +345,7 @@ def test_gaussian_head_bf16_and_batch():
         c.set_rng(99, 1000 + j)
         cells.append(c)
     dev = [cyrus.ue_device_tensor(u) for u in ues]
-    cyrus.build_batch(cells, dev)
+    cyrus.build_batch_device(cells, dev)
     torch.cuda.synchronize()
     for j, c in enumerate(cells):
         alloc, logits = c.export()

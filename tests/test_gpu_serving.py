@@ -74,12 +74,19 @@ def test_engine_matches_same_precision_oracle(cells):
     eng = serving.default_engine(max_active=4, pool_mib=64)
     alloc = _alone(eng, cell, ue)
     weights = wl.make_weights(cell.cfg, wl.serving_cell_configs(16, 424242)[small][1])
+    # the engine keeps no logits: the same cell built on its own by the same
+    # kernel, with logits exported, must give the engine's codebook bit for
+    # bit, and carries the per-node logit error into the oracle gate
+    ref = cyrus.Codebook(cell.cfg, weights, export_logits=True)
+    assert ref.kernel_path == cell.kernel_path
+    ref.build(ue)
+    ref_alloc, ref_logits = ref.export()
+    ref.close()
+    assert np.array_equal(ref_alloc, alloc)
     nodes = wl.sample_nodes(cell.cfg, 600, seed=3)
-    # without exported logits the per-node logit error is bounded by the BF16
-    # tolerance that the precision tests establish with exported logits
-    rep = parity.compare(cell.cfg, weights, ue, alloc, None, nodes=nodes, precision="bf16", dz_floor=2e-3)
+    rep = parity.compare(cell.cfg, weights, ue, ref_alloc, ref_logits, nodes=nodes, precision="bf16", logit_tol=2e-3)
     print(f"[serving] oracle sample {cell.cfg}: {rep.as_dict()}", flush=True)
-    assert rep.cond_unexplained == 0
+    rep.check(f"serving {cell.cfg}", exact=False)
     eng.close()
 
 
@@ -122,7 +129,7 @@ def test_stress_batch_equals_single_and_oracle():
     import torch
     from paper_2506_00167_amd import stress
     cfg, cells_, ues = stress.make_cells(n=8, export_logits=True)
-    cyrus.build_batch(cells_, ues)
+    cyrus.build_batch_device(cells_, ues)
     torch.cuda.synchronize()
     exported = [c.export() for c in cells_]
     batch = [a for a, _ in exported]
