@@ -73,17 +73,24 @@ def _rows(d, pattern):
     return out
 
 
-def _counter_per_dispatch(d, kernel):
-    """Average counter values (as recorded) per dispatch of kernels matching `kernel`."""
+def _counter_per_dispatch(d, kernel, with_duration=False):
+    """Average counter values (as recorded) per dispatch of kernels matching
+    `kernel`; with_duration: also the mean dispatch duration in ns under the
+    counter run (key "duration_ns")."""
     rows = _rows(d, "*counter_collection.csv")
-    acc = {}
+    acc, dur = {}, {}
     for r in rows:
         if kernel not in r.get("Kernel_Name", ""):
             continue
         name = r.get("Counter_Name")
         acc.setdefault(name, {}).setdefault(r.get("Dispatch_Id"), 0.0)
         acc[name][r.get("Dispatch_Id")] += float(r.get("Counter_Value", 0))
-    return {k: sum(v.values()) / len(v) for k, v in acc.items() if v}
+        if r.get("End_Timestamp") and r.get("Start_Timestamp"):
+            dur[r.get("Dispatch_Id")] = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+    out = {k: sum(v.values()) / len(v) for k, v in acc.items() if v}
+    if with_duration and dur:
+        out["duration_ns"] = sum(dur.values()) / len(dur)
+    return out
 
 
 def _summarize(args):
@@ -109,9 +116,30 @@ def _summarize(args):
                      f"lds={trace[0].get('LDS_Block_Size', trace[0].get('Lds_Size', '?'))} "
                      f"vgpr={trace[0].get('VGPR_Count', '?')} agpr={trace[0].get('Accum_VGPR_Count', '?')} "
                      f"sgpr={trace[0].get('SGPR_Count', '?')} scratch={trace[0].get('Scratch_Size', '?')}")
-    pmc = _counter_per_dispatch(args.dir, args.kernel)
+    pmc = _counter_per_dispatch(args.dir, args.kernel, with_duration=True)
+    dur_ns = pmc.pop("duration_ns", None)
     for k, v in sorted(pmc.items()):
         lines.append(f"counter {k}: {v:.1f} per dispatch")
+    if dur_ns:
+        lines.append(f"dispatch duration under counters: {dur_ns / 1e3:.2f} us average")
+    busy = pmc.get("SQ_VALU_MFMA_BUSY_CYCLES")
+    if busy and dur_ns:
+        # busy cycles are summed over every SIMD of the GPU (4 per CU)
+        simds = 4 * args.num_cu
+        lines.append(f"mfma_busy_fraction: {busy / (dur_ns * args.clock_ghz * simds):.4f} "
+                     f"(SQ_VALU_MFMA_BUSY_CYCLES / (dispatch duration x {args.clock_ghz} GHz x {simds} SIMDs))")
+        gui = pmc.get("GRBM_GUI_ACTIVE")
+        if gui:
+            # GRBM_GUI_ACTIVE is recorded summed over the 8 XCDs (about 8 x
+            # 2.4 cycles per ns of dispatch, plus the counter window)
+            lines.append(f"mfma_busy_fraction_gui: {busy / (gui / args.xcds * simds):.4f} "
+                         f"(SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE / {args.xcds} XCDs x {simds} SIMDs))")
+    if args.source_kernel:
+        root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+        sys.path.insert(0, root)
+        from bench import kernel_source_hash
+        lines.append(f"source_hash: {kernel_source_hash(args.source_kernel)} (code of the {args.source_kernel} "
+                     f"kernel sources this was taken on)")
     if args.copy_dir:
         cp = _counter_per_dispatch(args.copy_dir, args.copy_kernel)
         moved = args.copy_mib * 1024.0  # KiB each way
@@ -168,6 +196,11 @@ def main(argv=None):
     m.add_argument("--copy-kernel", default="copy")
     m.add_argument("--copy-mib", type=int, default=256)
     m.add_argument("--command", action="append", help="command line that produced DIR (repeatable)")
+    m.add_argument("--source-kernel", choices=["subtree", "level"],
+                   help="record the hash of this kernel's sources (bench.py trusts a trace only while it matches)")
+    m.add_argument("--num-cu", type=int, default=256)
+    m.add_argument("--xcds", type=int, default=8)
+    m.add_argument("--clock-ghz", type=float, default=2.4)
     t = sub.add_parser("traffic")
     for k in ("fetch", "write", "copy_fetch", "copy_write"):
         t.add_argument("--" + k.replace("_", "-"), dest=k, required=True)
