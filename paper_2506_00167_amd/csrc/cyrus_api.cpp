@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <climits>
 #include <cmath>
 #include <cstdarg>
@@ -42,6 +43,21 @@ int fail(int status, const char* fmt, ...)
     } while (0)
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Waits for a build's event by polling it for up to 2 ms, then blocks. A
+// codebook takes tens of microseconds, and a blocking wait can hand the
+// thread to the OS scheduler, whose wake-up alone may cost more than a slot.
+hipError_t wait_event(hipEvent_t ev)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    for (;;) {
+        const hipError_t e = hipEventQuery(ev);
+        if (e != hipErrorNotReady)
+            return e;
+        if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(2))
+            return hipEventSynchronize(ev);
+    }
+}
 
 bool is_pow2_float(float v)
 {
@@ -534,7 +550,7 @@ int cyrus_codebook_wait(cyrus_codebook* cb)
     if (!cb)
         return fail(CYRUS_EINVAL, "handle is NULL");
     if (cb->pending) {
-        HIP_TRY(hipEventSynchronize(cb->ev_done));
+        HIP_TRY(wait_event(cb->ev_done));
         cb->pending = false;
     }
     return CYRUS_OK;
@@ -547,7 +563,7 @@ static int sync_mirror(const cyrus_codebook* cb)
     if (!cb->built)
         return fail(CYRUS_ENOTREADY, "no build has been enqueued on this handle");
     if (cb->pending) {
-        HIP_TRY(hipEventSynchronize(cb->ev_done));
+        HIP_TRY(wait_event(cb->ev_done));
         cb->pending = false;
     }
     if (!cb->mirror_valid) {

@@ -361,3 +361,76 @@ def test_gaussian_head_bf16_and_batch():
         c.wait()
         assert np.array_equal(c.export()[0], alloc)
         c.close()
+
+
+def test_refresh_waits_for_builds_in_flight():
+    """Two weight refreshes while builds run on another stream: the second
+    one overwrites the buffer those builds read, so it must wait for them.
+    The last build before the refreshes gives the old weights' codebook; the
+    next one gives the new weights' codebook."""
+    import torch
+    cfg = wl.TREE_E8K3
+    w1, w2, w3 = (wl.make_weights(cfg, s) for s in (41, 42, 43))
+    ue = wl.make_ue_state(cfg.num_ue, wl.ue_seed(4))
+
+    def reference(w):
+        r = cyrus.Codebook(cfg, w)
+        r.build(ue)
+        a, _ = r.export()
+        r.close()
+        return a
+
+    ref1, ref3 = reference(w1), reference(w3)
+    s_build, s_refresh = torch.cuda.Stream(), torch.cuda.Stream()
+    cb = cyrus.Codebook(cfg, w1, stream=s_build)
+    ue_dev = cyrus.ue_device_tensor(ue)
+    torch.cuda.synchronize()
+    for _ in range(300):  # about 14 ms of builds in flight on s_build
+        cb.build_device(ue_dev)
+    v2, v3 = cyrus._WeightsView(w2), cyrus._WeightsView(w3)
+    cyrus.cyrus_codebook_set_weights(cb.handle, v2.struct, s_refresh)
+    cyrus.cyrus_codebook_set_weights(cb.handle, v3.struct, s_refresh)
+    cb.wait()
+    old, _ = cb.export()
+    assert np.array_equal(old, ref1), "a build enqueued before the refresh saw the new weights"
+    cb.build(ue)
+    new, _ = cb.export()
+    assert np.array_equal(new, ref3)
+    cb.close()
+
+
+def test_build_batch_host_states():
+    """The host-state batch: UE states staged by the call, codebooks in each
+    handle's pinned mirror afterwards, equal to single builds."""
+    cfgs = [wl.TINY, wl.TreeConfig(num_ue=6, max_arrival=2, num_minislots=6, hidden=(256, 256)), wl.TINY]
+    cbs = [cyrus.Codebook(c, wl.make_weights(c, 50 + i), force_level=True) for i, c in enumerate(cfgs)]
+    ues = [wl.make_ue_state(c.num_ue, 60 + i) for i, c in enumerate(cfgs)]
+    cyrus.build_batch(cbs, ues)
+    for cb, ue in zip(cbs, ues):
+        cb.wait()
+        batch, _ = cb.export()
+        assert cb.lookup([0]).tolist() == [0] * cb.cfg.num_ue
+        cb.build(ue)
+        single, _ = cb.export()
+        assert np.array_equal(batch, single)
+        parity.check_invariants(cb.cfg, ue, batch)
+        cb.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_hidden_widths_padded(precision):
+    """Hidden widths that are multiples of 32 but not of 128 (zero-padded to
+    128 inside the library) against the oracle's exact widths."""
+    cfg = wl.TreeConfig(num_ue=6, max_arrival=3, num_minislots=5, hidden=(160, 96), precision=precision)
+    weights = wl.make_weights(cfg, 71)
+    ue = wl.make_ue_state(cfg.num_ue, 72)
+    for force_level in (True, False):
+        cb, alloc, logits = _build(cfg, weights, ue, force_level=force_level)
+        parity.check_invariants(cfg, ue, alloc)
+        if precision == "fp32":
+            rep = parity.compare(cfg, weights, ue, alloc, logits, logit_tol=FP32_LOGIT_TOL)
+            _report(f"hidden 160/96 level={force_level}", rep)
+        else:
+            rep = parity.compare(cfg, weights, ue, alloc, logits, precision="bf16", logit_tol=2e-3)
+            _report(f"bf16 hidden 160/96 level={force_level}", rep, exact=False)
+        cb.close()
