@@ -305,6 +305,18 @@ int cyrus_critic_create(const cyrus_critic_config* cfg, const cyrus_critic_weigh
 int cyrus_critic_evaluate(cyrus_critic* cr, const cyrus_critic_batch* batch, uint64_t seed, uint64_t episode,
                           float* q, float* qhat, float* loss, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * pass as cyrus_critic_evaluate with the same kernels and outputs, but the
+ * per-row targets go to a static device array inside the library (one per
+ * GPU, held until the process ends, at most 65,536 rows = num_samples x
+ * num_minislots, 768 KiB) instead of the handle's workspace scratch. It calls
+ * no allocating routine. CYRUS_ERANGE (nothing enqueued) for more rows.
+ * Every call on one GPU shares that array: calls that overlap in time on one
+ * GPU (other streams, other handles) race; order them on one stream. */
+int cyrus_critic_evaluate_noalloc(cyrus_critic* cr, const cyrus_critic_batch* batch, uint64_t seed, uint64_t episode,
+                                  float* q, float* qhat, float* loss, void* stream);
+
 /* Release the handle (not the workspace). */
 void cyrus_critic_destroy(cyrus_critic* cr);
 

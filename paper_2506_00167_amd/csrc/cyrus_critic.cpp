@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "cyrus.h"
@@ -284,14 +285,41 @@ extern "C" int cyrus_critic_create(const cyrus_critic_config* cfg, const cyrus_c
     return CYRUS_OK;
 }
 
-extern "C" int cyrus_critic_evaluate(cyrus_critic* cr, const cyrus_critic_batch* b, uint64_t seed, uint64_t episode,
-                                     float* q, float* qhat, float* loss, void* stream)
+namespace {
+
+// Per-row target scratch of cyrus_critic_evaluate_noalloc, [3][rows] floats
+// (both target critics, then log pi), for at most kNoAllocMaxRows rows. Each
+// device holds its own copy for the life of the process; host code reaches it
+// only through the address hipGetSymbolAddress returns on that device.
+constexpr int64_t kNoAllocMaxRows = 1 << 16;
+static __device__ __align__(256) float scratch[3 * kNoAllocMaxRows];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[kMaxDevices] = {};
+
+// The scratch address on `dev` (which must be current), looked up once.
+int scratch_on(int dev, float** out)
 {
-    if (!cr || !b || !b->ue || !b->k || !b->c || !b->y || !b->reward || !q || !qhat || !loss)
-        return fail_msg(CYRUS_EINVAL, "NULL argument");
-    hipError_t e = hipSetDevice(cr->device);
-    if (e != hipSuccess)
-        return hip_fail(e, "hipSetDevice");
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail_msg(CYRUS_ERANGE, "device ordinal beyond the no-alloc scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+        g_scratch_ptr[dev] = static_cast<float*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return CYRUS_OK;
+}
+
+// Both critic entry points: the pass over `b` with the per-row targets in
+// `tgt` ([3][H M] floats).
+int critic_run(cyrus_critic* cr, const cyrus_critic_batch* b, uint64_t seed, uint64_t episode, float* q, float* qhat,
+               float* loss, float* tgt, hipStream_t stream)
+{
     CriticArgs a{};
     a.nets = cr->nets;
     a.ue = b->ue;
@@ -303,8 +331,8 @@ extern "C" int cyrus_critic_evaluate(cyrus_critic* cr, const cyrus_critic_batch*
     a.qhat = qhat;
     a.loss = loss;
     const int64_t rows = (int64_t)cr->cfg.num_samples * cr->cfg.num_minislots;
-    a.tq = cr->tgt;
-    a.tlp = cr->tgt + 2 * rows;
+    a.tq = tgt;
+    a.tlp = tgt + 2 * rows;
     a.E = cr->cfg.num_ue;
     a.M = cr->cfg.num_minislots;
     a.H = cr->cfg.num_samples;
@@ -316,10 +344,47 @@ extern "C" int cyrus_critic_evaluate(cyrus_critic* cr, const cyrus_critic_batch*
     for (int n = 0; n < 5; ++n)
         a.bias_off[n] = cr->bias_off[n];
     a.bias_total = cr->bias_total;
-    e = launch_critic(a, cr->rtt, cr->regs_t, cr->regs_ch1, cr->lds, static_cast<hipStream_t>(stream));
+    const hipError_t e = launch_critic(a, cr->rtt, cr->regs_t, cr->regs_ch1, cr->lds, stream);
     if (e != hipSuccess)
         return hip_fail(e, "critic launch");
     return CYRUS_OK;
+}
+
+}  // namespace
+
+extern "C" int cyrus_critic_evaluate(cyrus_critic* cr, const cyrus_critic_batch* b, uint64_t seed, uint64_t episode,
+                                     float* q, float* qhat, float* loss, void* stream)
+{
+    if (!cr || !b || !b->ue || !b->k || !b->c || !b->y || !b->reward || !q || !qhat || !loss)
+        return fail_msg(CYRUS_EINVAL, "NULL argument");
+    hipError_t e = hipSetDevice(cr->device);
+    if (e != hipSuccess)
+        return hip_fail(e, "hipSetDevice");
+    return critic_run(cr, b, seed, episode, q, qhat, loss, cr->tgt, static_cast<hipStream_t>(stream));
+}
+
+extern "C" int cyrus_critic_evaluate_noalloc(cyrus_critic* cr, const cyrus_critic_batch* b, uint64_t seed,
+                                             uint64_t episode, float* q, float* qhat, float* loss, void* stream)
+{
+    if (!cr || !b || !b->ue || !b->k || !b->c || !b->y || !b->reward || !q || !qhat || !loss)
+        return fail_msg(CYRUS_EINVAL, "NULL argument");
+    const int64_t rows = (int64_t)cr->cfg.num_samples * cr->cfg.num_minislots;
+    if (rows > kNoAllocMaxRows) {
+        char buf[160];
+        snprintf(buf, sizeof buf, "%lld rows (samples x steps) exceed the no-alloc scratch limit of %lld",
+                 (long long)rows, (long long)kNoAllocMaxRows);
+        return fail_msg(CYRUS_ERANGE, buf);
+    }
+    hipError_t e = hipSetDevice(cr->device);
+    if (e != hipSuccess)
+        return hip_fail(e, "hipSetDevice");
+    float* tgt = nullptr;
+    const int rc = scratch_on(cr->device, &tgt);
+    if (rc)
+        return rc;
+    // every row's targets are written by the main kernel before the loss
+    // kernel reads them, so the scratch needs no clearing between calls
+    return critic_run(cr, b, seed, episode, q, qhat, loss, tgt, static_cast<hipStream_t>(stream));
 }
 
 extern "C" void cyrus_critic_destroy(cyrus_critic* cr) { delete cr; }

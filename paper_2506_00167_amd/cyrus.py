@@ -37,7 +37,8 @@ SYMBOLS = (
     "cyrus_codebook_wait", "cyrus_codebook_lookup", "cyrus_codebook_assemble", "cyrus_codebook_export", "cyrus_codebook_device_alloc",
     "cyrus_codebook_num_nodes", "cyrus_codebook_kernel_path", "cyrus_codebook_set_rng", "cyrus_codebook_destroy",
     "cyrus_status_string", "cyrus_last_error",
-    "cyrus_critic_workspace_size", "cyrus_critic_create", "cyrus_critic_evaluate", "cyrus_critic_destroy",
+    "cyrus_critic_workspace_size", "cyrus_critic_create", "cyrus_critic_evaluate", "cyrus_critic_evaluate_noalloc",
+    "cyrus_critic_destroy",
     "cyrus_engine_create", "cyrus_engine_submit", "cyrus_engine_step", "cyrus_engine_set_levels_per_step",
     "cyrus_engine_poll",
     "cyrus_engine_completed", "cyrus_engine_result", "cyrus_engine_stats", "cyrus_engine_destroy",
@@ -133,6 +134,8 @@ def lib():
                                           vp, sz, vp, ctypes.POINTER(vp)]
         L.cyrus_critic_evaluate.argtypes = [vp, ctypes.POINTER(cyrus_critic_batch), ctypes.c_uint64, ctypes.c_uint64,
                                             vp, vp, vp, vp]
+        L.cyrus_critic_evaluate_noalloc.argtypes = [vp, ctypes.POINTER(cyrus_critic_batch), ctypes.c_uint64,
+                                                    ctypes.c_uint64, vp, vp, vp, vp]
         L.cyrus_critic_destroy.argtypes = [vp]
         L.cyrus_critic_destroy.restype = None
         L.cyrus_codebook_destroy.argtypes = [vp]
@@ -584,6 +587,20 @@ class Critic:
         _check(lib().cyrus_critic_evaluate(self.handle, ctypes.byref(b), int(seed) & 0xFFFFFFFFFFFFFFFF,
                                            int(episode) & 0xFFFFFFFFFFFFFFFF, self.q.data_ptr(), self.qhat.data_ptr(),
                                            self.loss.data_ptr(), _stream_ptr(self.stream)), "cyrus_critic_evaluate")
+        return self.q, self.qhat, self.loss
+
+    def evaluate_noalloc(self, batch, seed: int, episode: int):
+        """As evaluate, through cyrus_critic_evaluate_noalloc (per-row scratch in
+        the library's static device array, not the workspace)."""
+        ue, k, c, y, r = batch
+        self._keep = batch
+        b = cyrus_critic_batch(ctypes.cast(ue.data_ptr(), _i32p), ctypes.cast(k.data_ptr(), _i32p),
+                               ctypes.cast(c.data_ptr(), _u8p), ctypes.cast(y.data_ptr(), _f32p),
+                               ctypes.cast(r.data_ptr(), _f32p))
+        _check(lib().cyrus_critic_evaluate_noalloc(self.handle, ctypes.byref(b), int(seed) & 0xFFFFFFFFFFFFFFFF,
+                                                   int(episode) & 0xFFFFFFFFFFFFFFFF, self.q.data_ptr(),
+                                                   self.qhat.data_ptr(), self.loss.data_ptr(),
+                                                   _stream_ptr(self.stream)), "cyrus_critic_evaluate_noalloc")
         return self.q, self.qhat, self.loss
 
     def close(self):
