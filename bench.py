@@ -400,16 +400,17 @@ def stress_leg(iters: int, stream):
 
 def serving_leg(requests: int, stream):
     """Continuous batching of Poisson requests from 64 BF16 cells (E 4..16,
-    K 2..4, two hidden layers of 256 or 512): saturation, then a quarter of
-    it, then a pool that holds only a few trees, so admission defers."""
+    K 2..4, two hidden layers of 256 or 512) on the resident worker:
+    saturation, then a quarter of it, then a pool that holds only a few
+    trees, so admission defers."""
     import torch
     from paper_2506_00167_amd import serving
 
     cells = serving.make_cells(64, stream=stream)
     torch.cuda.synchronize()
     out = {"workload": "64 cells, E U{4..16}, K U{2,3,4}, H {256,512} x2, bf16, Poisson arrivals",
-           "requests": requests}
-    eng = serving.default_engine(64, 256, stream=stream, levels_per_step=7)
+           "engine": "resident worker", "requests": requests}
+    eng = serving.default_engine(128, 256, stream=stream, resident=True)
     serving.saturation(eng, cells, serving.make_requests(cells, 200, seed=1))
     sat = serving.saturation(eng, cells, serving.make_requests(cells, requests, seed=2))
     out["saturation"] = sat
@@ -420,9 +421,9 @@ def serving_leg(requests: int, stream):
     # device pool: the descriptor slots plus room for about two of the
     # largest trees, so that admission has to wait for memory
     biggest = max(c.num_nodes * c.cfg.num_ue for c in cells)
-    pool = 2 * 2 * biggest + (1 << 20)
+    pool = 3 * biggest + (2 << 20)
     from paper_2506_00167_amd import cyrus
-    small = cyrus.Engine(pool, pool + (8 << 20), max_active=64, stream=stream).set_levels_per_step(7)
+    small = cyrus.Engine(pool, pool + (8 << 20), max_active=128, stream=stream, resident=True)
     arr = wl.poisson_arrivals(0.5 * rate, requests // 2, seed=424243)
     out["small_pool_load_0.5"] = serving.run_stream(small, cells, serving.make_requests(cells, requests // 2, seed=4),
                                                     arr - arr[0])

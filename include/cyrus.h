@@ -374,6 +374,30 @@ int cyrus_engine_step(cyrus_engine* eng, int32_t* running, int32_t* waiting);
  * the next step. CYRUS_ERANGE outside [1, 7]. */
 int cyrus_engine_set_levels_per_step(cyrus_engine* eng, int32_t levels);
 
+/* Resident worker (on = 1), chosen before the first submit: instead of
+ * host-stepped launches, ONE resident kernel serves every request. Its
+ * workgroup 0 takes requests from a ring in the host pool (pinned memory that
+ * the device reads and writes directly); every other workgroup repeatedly
+ * claims one row tile of the oldest admitted request whose current level has
+ * tiles left, runs it (the batched level kernel's tile), and the workgroup
+ * that finishes a level's last tile opens the next level; after level M the
+ * request's completion flag is set in pinned memory. Levels of different
+ * requests overlap freely and no host step is needed between levels:
+ * cyrus_engine_step retires finished requests (it reads the flags and copies
+ * each finished codebook from the device pool into the request's block of
+ * the host pool on a copy stream of the engine's own), admits waiting ones
+ * into free slots and pool memory, and relaunches the worker when it has
+ * exited with requests waiting. The worker leaves after 20 ms with nothing to
+ * do, after 2 s without progress, after admitting 2,048 requests (the host then
+ * relaunches it), or when the engine is destroyed (requests still in flight are
+ * then abandoned). Up to 128 requests are in flight. Results are bit-identical
+ * to the same request alone (every request runs the same tile code whatever
+ * the mix). CYRUS_EINVAL after a submit or for on = 0 once resident;
+ * CYRUS_EWORKSPACE if the pools cannot hold the worker's tables (about
+ * 1.5 MiB device, 90 KiB host); CYRUS_EUNSUPPORTED if the host pool is not
+ * mapped for the device. */
+int cyrus_engine_set_resident(cyrus_engine* eng, int32_t on);
+
 /* Status of a ticket (CYRUS_REQ_*); *latency_us (nullable) receives, once
  * done, the time from submit to the step that observed completion. */
 int cyrus_engine_poll(cyrus_engine* eng, int64_t ticket, int32_t* status, double* latency_us);
@@ -385,7 +409,8 @@ int cyrus_engine_completed(cyrus_engine* eng, int64_t* tickets, double* latency_
 /* Copy a finished request's codebook ([nodes][E] bytes) and release its slot. */
 int cyrus_engine_result(cyrus_engine* eng, int64_t ticket, uint8_t* alloc, size_t bytes);
 
-/* Counters: [0] submitted, [1] completed, [2] steps launched, [3] admissions
+/* Counters: [0] submitted, [1] completed, [2] steps launched (resident worker:
+ * worker launches), [3] admissions
  * deferred for memory, [4] admissions deferred for batch slots,
  * [5] device-pool bytes in use, [6] peak device-pool bytes in use. */
 int cyrus_engine_stats(const cyrus_engine* eng, int64_t* counters, int32_t n);

@@ -272,6 +272,20 @@ hipError_t note_slot_use(cyrus_codebook* cb, int slot, hipStream_t stream)
     return hipSuccess;
 }
 
+hipError_t note_build_use(cyrus_codebook* cb, int slot, hipStream_t stream)
+{
+    if (cb->done_slot >= 0 && (cb->done_stream != stream || cb->done_slot != slot)) {
+        // an event recorded now on the old stream follows every build
+        // enqueued there, the one ev_done marked included
+        const hipError_t e = note_slot_use(cb, cb->done_slot, cb->done_stream);
+        if (e != hipSuccess)
+            return e;
+    }
+    cb->done_stream = stream;
+    cb->done_slot = slot;
+    return hipSuccess;
+}
+
 int codebook_path(const cyrus_codebook* cb) { return cb->path; }
 int codebook_rtt(const cyrus_codebook* cb) { return cb->rtt; }
 const Shape& codebook_shape(const cyrus_codebook* cb) { return cb->s; }
@@ -315,6 +329,8 @@ static int load_weights(cyrus_codebook* cb, const cyrus_weights* w, hipStream_t 
                     "the engine until they finish", cb->engine_refs[target]);
     for (auto& u : cb->slot_use[target])
         HIP_TRY(hipEventSynchronize(u.second));
+    if (cb->done_slot == target)
+        HIP_TRY(hipEventSynchronize(cb->ev_done));
     uint8_t* wb = cb->ws + s.off_w[target];
     float* staging = reinterpret_cast<float*>(cb->ws + s.off_staging);
     cb->pack.assign(s.staging_floats, 0.f);
@@ -349,6 +365,7 @@ static int load_weights(cyrus_codebook* cb, const cyrus_weights* w, hipStream_t 
         cb->inv_in[target][l] = 1.f / a_scale[l];
     }
     cb->active = target;
+    cb->wversion++;
     return CYRUS_OK;
 }
 
@@ -362,12 +379,13 @@ static int enqueue_tree(cyrus_codebook* cb, const DevTree& t, hipStream_t stream
     return CYRUS_OK;
 }
 
+// The kernels of one build; the caller then records ev_done on `stream`.
 static int enqueue_kernels(cyrus_codebook* cb, const int32_t* ue_dev, hipStream_t stream)
 {
     int rc = enqueue_tree(cb, make_devtree(cb, ue_dev), stream);
     if (rc)
         return rc;
-    HIP_TRY(note_slot_use(cb, cb->active, stream));
+    HIP_TRY(note_build_use(cb, cb->active, stream));
     return CYRUS_OK;
 }
 
@@ -474,7 +492,9 @@ static int stage_ue(cyrus_codebook* cb, const cyrus_ue_state* ue)
         if (!std::isfinite(ue->sinr_db[e]))
             return fail(CYRUS_EINVAL, "sinr_db[%d] is not finite", e);
     }
-    if (cb->staged_recorded)
+    if (cb->staged_is_done)
+        HIP_TRY(wait_event(cb->ev_done));
+    else if (cb->staged_recorded)
         HIP_TRY(hipEventSynchronize(cb->ev_staged));
     int32_t* st = reinterpret_cast<int32_t*>(cb->host + cb->s.hoff_ue);
     for (int e = 0; e < E; ++e) {
@@ -504,10 +524,10 @@ int cyrus_codebook_build(cyrus_codebook* cb, const cyrus_ue_state* ue, void* str
         rc = enqueue_tree(cb, t, st);
         if (rc)
             return rc;
-        HIP_TRY(note_slot_use(cb, cb->active, st));
-        HIP_TRY(hipEventRecord(cb->ev_staged, st));
-        cb->staged_recorded = true;
+        // the kernel reads the staged UE state, so ev_done also releases it
+        HIP_TRY(note_build_use(cb, cb->active, st));
         HIP_TRY(hipEventRecord(cb->ev_done, st));
+        cb->staged_is_done = true;
         cb->built = cb->pending = cb->mirror_valid = true;
         return CYRUS_OK;
     }
@@ -515,6 +535,7 @@ int cyrus_codebook_build(cyrus_codebook* cb, const cyrus_ue_state* ue, void* str
     HIP_TRY(hipMemcpyAsync(ue_dev, cb->host + s.hoff_ue, (size_t)3 * s.E * 4, hipMemcpyHostToDevice, st));
     HIP_TRY(hipEventRecord(cb->ev_staged, st));
     cb->staged_recorded = true;
+    cb->staged_is_done = false;
     rc = enqueue_kernels(cb, ue_dev, st);
     if (rc)
         return rc;

@@ -154,7 +154,7 @@ extern "C" int cyrus_codebook_build_batch_device(cyrus_codebook* const* cbs, con
     if (rc)
         return rc;
     for (int i = 0; i < n; ++i) {
-        e = note_slot_use(cbs[i], cbs[i]->active, st);
+        e = note_build_use(cbs[i], cbs[i]->active, st);
         if (e == hipSuccess)
             e = hipEventRecord(cbs[i]->ev_done, st);
         if (e != hipSuccess)
@@ -213,12 +213,13 @@ extern "C" int cyrus_codebook_build_batch(cyrus_codebook* const* cbs, const cyru
             e = hipMemcpyAsync(cb->host + s.hoff_logits, cb->ws + s.off_logits, (size_t)s.nodes * s.E * 4,
                                hipMemcpyDeviceToHost, st);
         if (e == hipSuccess)
-            e = note_slot_use(cb, cb->active, st);
+            e = note_build_use(cb, cb->active, st);
         if (e == hipSuccess)
             e = hipEventRecord(cb->ev_done, st);
         if (e != hipSuccess)
             return hip_fail(e, "codebook copy to the pinned mirror");
         cb->staged_recorded = true;
+        cb->staged_is_done = false;
         cb->built = cb->pending = cb->mirror_valid = true;
     }
     return CYRUS_OK;

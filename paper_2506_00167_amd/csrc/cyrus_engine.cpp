@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cstdio>
 #include <cstring>
@@ -110,6 +111,9 @@ struct Request {
     int wslot = 0;               // the cell's weight buffer, fixed at admission
     size_t dev_off = 0, dev_bytes = 0, host_off = 0, host_bytes = 0;
     bool has_dev = false, has_host = false;
+    int rslot = -1;     // resident worker: slot of the request
+    uint32_t gen = 0;   // resident worker: admission generation (nonzero, 20 bits)
+    bool copying = false;  // resident worker: codebook copy to the host pool enqueued
 };
 
 size_t slot_bytes()
@@ -148,6 +152,30 @@ struct cyrus_engine {
     int next_slot = 0;
     int64_t counters[7] = {};
     std::deque<Request*> newly_done;
+    // resident worker (cyrus_engine_set_resident)
+    bool resident = false;
+    ServeRequest* d_recs = nullptr;   // device record table of the resident worker
+    ServeCtl* d_ctl = nullptr;        // device counters
+    ServeHost* h_shared = nullptr;    // pinned shared block, host address
+    ServeHost* h_shared_dev = nullptr;  // and its device address
+    uint8_t* hpool_dev = nullptr;     // device address of the pinned pool
+    std::vector<int> free_rslots;
+    uint32_t tail = 0;
+    uint32_t next_gen = 0;
+    bool worker_live = false;
+    hipEvent_t worker_ev = nullptr;
+    hipStream_t copy_stream = nullptr;      // codebooks to the host pool, beside the worker
+    hipEvent_t copy_ev[kServeSlots] = {};   // per slot: its request's copy
+    std::vector<cyrus_codebook*> cells;  // every cell seen by submit
+    bool plan_dirty = false, have_plan = false;
+    int plan_rtt = 0, plan_buf = 0;
+    size_t plan_bias = 0, plan_lds = 0;
+    int ncu = 256;
+    uint64_t wall_khz = 100000;  // device wall clock (s_memrealtime) rate
+    // weights each cell had when last admitted; a change (or a first
+    // sight) bumps the epoch, and the workers invalidate their caches once
+    std::unordered_map<cyrus_codebook*, uint64_t> seen_wversion;
+    uint32_t wepoch = 0;
 };
 
 namespace {
@@ -347,6 +375,211 @@ int launch_step(cyrus_engine* e)
     return CYRUS_OK;
 }
 
+// ------------------------------------------------------------ resident worker
+
+constexpr double kWorkerIdleMs = 20.0;    // the worker leaves after this long with nothing in flight
+constexpr double kWorkerStallMs = 2000.0;  // and after this long with requests in flight but no progress
+
+uint32_t host_load(const volatile uint32_t* p)
+{
+    const uint32_t v = *p;
+    std::atomic_thread_fence(std::memory_order_acquire);
+    return v;
+}
+
+// Whether the current LDS plan covers every cell seen so far; if not, the
+// plan that does.
+bool plan_covers(const cyrus_engine* e, const DevTree& t)
+{
+    return e->have_plan && level_buf_bytes(t, e->prec, e->plan_rtt) <= (size_t)e->plan_buf &&
+           level_bias_bytes(t) <= e->plan_bias;
+}
+
+int replan(cyrus_engine* e)
+{
+    std::vector<DevTree> trees;
+    for (cyrus_codebook* c : e->cells)
+        trees.push_back(make_devtree(c, nullptr));
+    int rtt = 0, buf = 0;
+    size_t lds = 0;
+    if (!plan_level_batch(trees.data(), (int)trees.size(), e->prec, &rtt, &buf, &lds))
+        return set_error(CYRUS_EUNSUPPORTED, "the engine's cells do not fit one level-kernel LDS plan");
+    size_t bias = 0;
+    for (const DevTree& t : trees)
+        bias = std::max(bias, level_bias_bytes(t));
+    e->plan_rtt = rtt;
+    e->plan_buf = buf;
+    e->plan_bias = bias;
+    e->plan_lds = level_lds_for_buf((size_t)buf, bias, rtt);
+    e->have_plan = true;
+    e->plan_dirty = false;
+    return CYRUS_OK;
+}
+
+int retire_resident(cyrus_engine* e)
+{
+    for (size_t i = 0; i < e->running.size();) {
+        Request* r = e->running[i];
+        if (!r->copying) {
+            // the worker has finished the tree: its codebook (device pool) goes to
+            // the request's block of the host pool on the copy stream
+            if (host_load(&e->h_shared->finished[r->rslot]) == r->gen) {
+                const Shape& s = codebook_shape(r->cell);
+                hipError_t err = hipMemcpyAsync(e->hpool + r->host_off, e->dpool + r->dev_off, (size_t)s.nodes * s.E,
+                                                hipMemcpyDeviceToHost, e->copy_stream);
+                if (err == hipSuccess)
+                    err = hipEventRecord(e->copy_ev[r->rslot], e->copy_stream);
+                if (err != hipSuccess)
+                    return hip_err(err, "codebook copy");
+                r->copying = true;
+            }
+            ++i;
+            continue;
+        }
+        const hipError_t q = hipEventQuery(e->copy_ev[r->rslot]);
+        if (q == hipErrorNotReady) {
+            ++i;
+            continue;
+        }
+        if (q != hipSuccess)
+            return hip_err(q, "hipEventQuery(codebook copy)");
+        r->status = CYRUS_REQ_DONE;
+        r->t_done = now_us();
+        r->cell->engine_refs[r->wslot]--;
+        release_request_device(e, r);
+        e->free_rslots.push_back(r->rslot);
+        e->newly_done.push_back(r);
+        e->counters[1]++;
+        e->running[i] = e->running.back();
+        e->running.pop_back();
+    }
+    return CYRUS_OK;
+}
+
+bool worker_running(cyrus_engine* e)
+{
+    if (e->worker_live && hipEventQuery(e->worker_ev) == hipSuccess)
+        e->worker_live = false;
+    return e->worker_live;
+}
+
+int admit_resident(cyrus_engine* e)
+{
+    if (e->plan_dirty) {
+        bool covered = e->have_plan;
+        for (cyrus_codebook* c : e->cells)
+            covered = covered && plan_covers(e, make_devtree(c, nullptr));
+        if (covered) {
+            e->plan_dirty = false;
+        } else if (!worker_running(e) && e->running.empty()) {
+            // (requests in flight keep the tiling they were admitted with)
+            const int rc = replan(e);
+            if (rc)
+                return rc;
+        } else {
+            // a wider plan needs a new launch: let the worker drain and leave
+            if (e->running.empty())
+                e->h_shared->stop = 1;
+            return CYRUS_OK;
+        }
+    }
+    while (!e->waiting.empty()) {
+        if ((int)e->running.size() >= e->max_active || e->free_rslots.empty()) {
+            e->counters[4]++;
+            break;
+        }
+        Request* r = e->waiting.front();
+        const Shape& s = codebook_shape(r->cell);
+        const size_t tree = ((size_t)s.nodes * s.E + 255) / 256 * 256;
+        r->dev_bytes = 2 * tree;  // codebook, then node states
+        r->host_bytes = request_host_bytes(s);
+        if (!e->dfree.alloc(r->dev_bytes, &r->dev_off)) {
+            e->counters[3]++;
+            break;
+        }
+        if (!e->hfree.alloc(r->host_bytes, &r->host_off)) {
+            e->dfree.release(r->dev_off, r->dev_bytes);
+            e->counters[3]++;
+            break;
+        }
+        r->has_dev = r->has_host = true;
+        r->rslot = e->free_rslots.back();
+        e->free_rslots.pop_back();
+        r->wslot = r->cell->active;
+        r->cell->engine_refs[r->wslot]++;
+        e->next_gen = e->next_gen % (kServeGenMask - 1) + 1;
+        r->gen = e->next_gen;
+        ServeRequest& q = e->h_shared->ring[e->tail % kServeRing];
+        DevTree t = make_devtree(r->cell, nullptr, r->wslot);  // the device points t.ue at its record
+        t.alloc = e->dpool + r->dev_off;
+        t.state = e->dpool + r->dev_off + tree;
+        t.logits = nullptr;
+        t.seed = r->seed;
+        t.tti = r->tti;
+        int32_t nt[8] = {0};
+        for (int tau = 1; tau <= s.M; ++tau) {
+            const int64_t n_eval = (int64_t)s.K * ipow(s.K + 1, tau - 1);
+            // in [1, kServeMaxTiles]: K, M <= 7 give at most 7 * 8^6 / 16 = 114,688 tiles
+            nt[tau] = (int32_t)((n_eval + 16 * e->plan_rtt - 1) / (16 * e->plan_rtt));
+        }
+        auto seen = e->seen_wversion.find(r->cell);
+        if (seen == e->seen_wversion.end() || seen->second != r->cell->wversion) {
+            ++e->wepoch;  // new or refreshed weights: the workers drop their cached lines once
+            e->seen_wversion[r->cell] = r->cell->wversion;
+        }
+        std::memcpy(&q.t, &t, sizeof t);
+        std::memcpy(q.ntiles, nt, sizeof nt);
+        q.slot = r->rslot;
+        q.gen = r->gen;
+        q.wepoch = e->wepoch;
+        q.pad = 0;
+        std::memset(q.ue, 0, sizeof q.ue);
+        std::memcpy(q.ue, r->ue.data(), r->ue.size() * 4);
+        std::atomic_thread_fence(std::memory_order_release);
+        *reinterpret_cast<volatile uint32_t*>(&e->h_shared->tail) = ++e->tail;
+        r->status = CYRUS_REQ_RUNNING;
+        r->copying = false;
+        e->running.push_back(r);
+        e->waiting.pop_front();
+    }
+    return CYRUS_OK;
+}
+
+int ensure_worker(cyrus_engine* e)
+{
+    if (worker_running(e))
+        return CYRUS_OK;
+    const uint32_t consumed = host_load(&e->h_shared->consumed);
+    if (consumed == e->tail)
+        return CYRUS_OK;  // nothing waits in the ring
+    if (!e->have_plan) {
+        const int rc = replan(e);
+        if (rc)
+            return rc;
+    }
+    e->h_shared->stop = 0;
+    std::atomic_thread_fence(std::memory_order_release);
+    ServeArgs a{};
+    a.recs = e->d_recs;
+    a.ctl = e->d_ctl;
+    a.host = e->h_shared_dev;
+    a.head0 = consumed;
+    a.bufsize = e->plan_buf;
+    a.idle_ticks = (uint64_t)(kWorkerIdleMs * (double)e->wall_khz);
+    a.stall_ticks = (uint64_t)(kWorkerStallMs * (double)e->wall_khz);
+    // quit is the only counter a finished launch leaves set
+    hipError_t err = hipMemsetAsync(&e->d_ctl->quit, 0, sizeof(int32_t), e->stream);
+    if (err == hipSuccess)
+        err = launch_serve(a, e->prec, e->plan_rtt, e->ncu, e->plan_lds, e->stream);
+    if (err == hipSuccess)
+        err = hipEventRecord(e->worker_ev, e->stream);
+    if (err != hipSuccess)
+        return hip_err(err, "resident worker launch");
+    e->worker_live = true;
+    e->counters[2]++;
+    return CYRUS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -405,8 +638,18 @@ int cyrus_engine_submit(cyrus_engine* e, cyrus_codebook* cell, const cyrus_ue_st
         if (ue->rb[i] < 0 || ue->rb[i] > 255)
             return set_error(CYRUS_ERANGE, "rb outside [0, 255]");
     // a request that can never fit the pools would block the FIFO forever
-    if (request_dev_bytes(s) > e->dcap || request_host_bytes(s) > e->hcap)
+    const size_t dev_need = e->resident ? 2 * (((size_t)s.nodes * s.E + 255) / 256 * 256) : request_dev_bytes(s);
+    if (dev_need > e->dcap || request_host_bytes(s) > e->hcap)
         return set_error(CYRUS_EWORKSPACE, "the request's tree does not fit the engine's pools");
+    if (e->resident && std::find(e->cells.begin(), e->cells.end(), cell) == e->cells.end()) {
+        int rtt = 0, buf = 0;
+        size_t lds = 0;
+        const DevTree t = make_devtree(cell, nullptr);
+        if (!plan_level_batch(&t, 1, s.prec, &rtt, &buf, &lds))
+            return set_error(CYRUS_EUNSUPPORTED, "the cell does not fit the level kernel's LDS");
+        e->cells.push_back(cell);
+        e->plan_dirty = true;
+    }
     e->prec = s.prec;
     Request* r = new (std::nothrow) Request();
     if (!r)
@@ -439,17 +682,89 @@ int cyrus_engine_set_levels_per_step(cyrus_engine* e, int32_t levels)
     return CYRUS_OK;
 }
 
+int cyrus_engine_set_resident(cyrus_engine* e, int32_t on)
+{
+    if (!e)
+        return set_error(CYRUS_EINVAL, "NULL engine");
+    if (on != 0 && on != 1)
+        return set_error(CYRUS_EINVAL, "on must be 0 or 1");
+    if (e->next_ticket != 0)
+        return set_error(CYRUS_EINVAL, "the worker mode is chosen before the first submit");
+    if (on == (int)e->resident)
+        return CYRUS_OK;
+    if (!on)
+        return set_error(CYRUS_EINVAL, "the resident worker cannot be switched off once chosen");
+    if (hipSetDevice(e->device) != hipSuccess)
+        return set_error(CYRUS_EDEVICE, "hipSetDevice failed");
+    if (hipHostGetDevicePointer(reinterpret_cast<void**>(&e->hpool_dev), e->hpool, 0) != hipSuccess ||
+        !e->hpool_dev) {
+        (void)hipGetLastError();
+        return set_error(CYRUS_EUNSUPPORTED, "the host pool is not mapped into the device address space");
+    }
+    size_t doff_slots = 0, doff_ctl = 0, hoff = 0;
+    const size_t slots_bytes = sizeof(ServeRequest) * kServeRecords;
+    if (!e->dfree.alloc(slots_bytes, &doff_slots))
+        return set_error(CYRUS_EWORKSPACE, "device pool too small for the worker's record table");
+    if (!e->dfree.alloc(sizeof(ServeCtl), &doff_ctl)) {
+        e->dfree.release(doff_slots, slots_bytes);
+        return set_error(CYRUS_EWORKSPACE, "device pool too small for the worker's counters");
+    }
+    if (!e->hfree.alloc(sizeof(ServeHost), &hoff)) {
+        e->dfree.release(doff_ctl, sizeof(ServeCtl));
+        e->dfree.release(doff_slots, slots_bytes);
+        return set_error(CYRUS_EWORKSPACE, "host pool too small for the worker's ring");
+    }
+    e->d_recs = reinterpret_cast<ServeRequest*>(e->dpool + doff_slots);
+    e->d_ctl = reinterpret_cast<ServeCtl*>(e->dpool + doff_ctl);
+    e->h_shared = reinterpret_cast<ServeHost*>(e->hpool + hoff);
+    e->h_shared_dev = reinterpret_cast<ServeHost*>(e->hpool_dev + hoff);
+    std::memset(e->h_shared, 0, sizeof(ServeHost));
+    hipError_t err = hipMemsetAsync(e->d_ctl, 0, sizeof(ServeCtl), e->stream);
+    if (err == hipSuccess)
+        err = hipStreamSynchronize(e->stream);
+    if (err == hipSuccess && !e->worker_ev)
+        err = hipEventCreateWithFlags(&e->worker_ev, hipEventDisableTiming);
+    if (err == hipSuccess && !e->copy_stream)
+        err = hipStreamCreateWithFlags(&e->copy_stream, hipStreamNonBlocking);
+    for (int i = 0; err == hipSuccess && i < kServeSlots; ++i)
+        if (!e->copy_ev[i])
+            err = hipEventCreateWithFlags(&e->copy_ev[i], hipEventDisableTiming);
+    if (err != hipSuccess)
+        return hip_err(err, "resident worker set-up");
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, e->device) == hipSuccess && n > 1)
+        e->ncu = n;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeWallClockRate, e->device) == hipSuccess && n > 0)
+        e->wall_khz = (uint64_t)n;
+    e->free_rslots.clear();
+    for (int i = kServeSlots - 1; i >= 0; --i)
+        e->free_rslots.push_back(i);
+    e->dcap -= std::min(e->dcap, (slots_bytes + 255) / 256 * 256 + (sizeof(ServeCtl) + 255) / 256 * 256);
+    e->hcap -= std::min(e->hcap, (sizeof(ServeHost) + 63) / 64 * 64);
+    e->resident = true;
+    return CYRUS_OK;
+}
+
 int cyrus_engine_step(cyrus_engine* e, int32_t* running, int32_t* waiting)
 {
     if (!e)
         return set_error(CYRUS_EINVAL, "NULL engine");
     if (hipSetDevice(e->device) != hipSuccess)
         return set_error(CYRUS_EDEVICE, "hipSetDevice failed");
-    int rc = retire(e);
-    if (rc == CYRUS_OK)
-        rc = admit(e);
-    for (int i = 0; rc == CYRUS_OK && i < e->levels_per_step && !e->running.empty(); ++i)
-        rc = launch_step(e);
+    int rc;
+    if (e->resident) {
+        rc = retire_resident(e);
+        if (rc == CYRUS_OK)
+            rc = admit_resident(e);
+        if (rc == CYRUS_OK)
+            rc = ensure_worker(e);
+    } else {
+        rc = retire(e);
+        if (rc == CYRUS_OK)
+            rc = admit(e);
+        for (int i = 0; rc == CYRUS_OK && i < e->levels_per_step && !e->running.empty(); ++i)
+            rc = launch_step(e);
+    }
     if (running)
         *running = (int32_t)e->running.size();
     if (waiting)
@@ -529,7 +844,20 @@ void cyrus_engine_destroy(cyrus_engine* e)
     if (!e)
         return;
     (void)hipSetDevice(e->device);
+    if (e->resident && e->h_shared) {
+        e->h_shared->stop = 1;  // the worker leaves; requests still in flight are abandoned
+        std::atomic_thread_fence(std::memory_order_seq_cst);
+    }
     (void)hipStreamSynchronize(e->stream);
+    if (e->copy_stream) {
+        (void)hipStreamSynchronize(e->copy_stream);
+        (void)hipStreamDestroy(e->copy_stream);
+    }
+    for (hipEvent_t ev : e->copy_ev)
+        if (ev)
+            (void)hipEventDestroy(ev);
+    if (e->worker_ev)
+        (void)hipEventDestroy(e->worker_ev);
     for (Request* r : e->running)
         r->cell->engine_refs[r->wslot]--;
     for (Request* r : e->draining)

@@ -52,6 +52,9 @@ int set_error(int status, const char* msg);
 // Mark weight buffer `slot` of cb as read by the work enqueued so far on
 // `stream` (records that stream's use event for the slot).
 hipError_t note_slot_use(cyrus_codebook* cb, int slot, hipStream_t stream);
+// Before a build of cb that reads weight buffer `slot` records ev_done on
+// `stream`: keeps the use ev_done marked so far if ev_done moves elsewhere.
+hipError_t note_build_use(cyrus_codebook* cb, int slot, hipStream_t stream);
 // Validate one host UE state and copy it into cb's pinned staging area (after
 // the previous copy out of it has finished).
 int stage_ue_host(cyrus_codebook* cb, const cyrus_ue_state* ue);
@@ -81,11 +84,19 @@ struct cyrus_codebook {
     mutable bool mirror_valid = false;  // the pinned mirror holds the last build
     // Last use of each weight buffer: one event per stream that enqueued work
     // reading it. set_weights waits for these before overwriting a buffer.
+    // The builds of the handle itself mark their use with ev_done (the weight
+    // buffer done_slot on stream done_stream), so a build records one event;
+    // an entry in slot_use is recorded only when ev_done moves to another
+    // stream or buffer.
     std::vector<std::pair<hipStream_t, hipEvent_t>> slot_use[2];
+    hipStream_t done_stream = nullptr;
+    int done_slot = -1;  // -1: ev_done marks no build
+    bool staged_is_done = false;  // the last host build's staging is released by ev_done
     // Serving-engine requests admitted with each weight buffer and not yet
     // retired (their next launches are not enqueued yet, so no event covers
     // them); set_weights refuses to overwrite a buffer while this is nonzero.
     int engine_refs[2] = {0, 0};
+    uint64_t wversion = 0;  // incremented by every weight load (create, set_weights)
     int path = 0;  // 0 level, 1 subtree
     int rtt = 1;
     uint64_t rng_seed = 0, rng_tti = 0;  // Gaussian head: Philox key and TTI of the next builds

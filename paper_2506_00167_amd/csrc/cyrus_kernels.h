@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include "cyrus_internal.h"
+#include "cyrus_serve.h"
 
 namespace cyrus {
 
@@ -18,6 +19,13 @@ hipError_t launch_level(const DevTree& t, int prec, int rtt, int tau, hipStream_
 // workgroups [prefix[j], prefix[j+1]) of an nblocks = prefix[n] launch.
 hipError_t launch_level_batch(const DevTree* trees, const int* ent_tree, const int* ent_tau, const int* prefix, int n,
                               int nblocks, int prec, int rtt, int buf, size_t lds, hipStream_t s);
+
+// Resident serving worker over `grid` workgroups (workgroup 0 admits, the
+// others run row tiles), with the LDS plan (rtt, a.bufsize, lds) of a batched
+// level launch covering every request it will be handed.
+hipError_t launch_serve(const ServeArgs& a, int prec, int rtt, int grid, size_t lds, hipStream_t s);
+size_t level_bias_bytes(const DevTree& t);
+size_t level_lds_for_buf(size_t buf, size_t bias_bytes, int rtt);
 
 // Critic pass (kernels_critic.hip). nets: actor, Q1, Q2, Qtarg1, Qtarg2 as
 // FP32 MLP descriptors (E = number of outputs, softmax head = raw outputs).

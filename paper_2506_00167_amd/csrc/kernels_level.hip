@@ -28,7 +28,25 @@ __device__ __forceinline__ int64_t dev_level_offset(int K, int tau)
 // evaluated node writes its allocation and state; the first child (k = 1) of
 // every parent also writes the k = 0 sibling, which punctures nothing and
 // passes the parent state on unchanged.
-template <int G>
+// Stores of the resident worker (COH): node states and codebook bytes with
+// agent-scope relaxed atomic stores, which write through the non-coherent
+// caches, so other workgroups (on any XCD) and the copy engine that later
+// moves the codebook to the host read them without a cache flush.
+template <bool COH>
+__device__ __forceinline__ void put_state(gu8* p, uint8_t v)
+{
+    if constexpr (COH)
+        __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else
+        *p = v;
+}
+template <bool COH>
+__device__ __forceinline__ void put_alloc(gu8* p, uint8_t v)
+{
+    put_state<COH>(p, v);
+}
+
+template <int G, bool COH = false>
 __device__ __forceinline__ void finish_rows_level(const DevTree& t, const float* zl, const int* R, int rsum, int row0,
                                                   int nrows, int64_t off, const uint8_t* pst, int p_lo)
 {
@@ -54,14 +72,14 @@ __device__ __forceinline__ void finish_rows_level(const DevTree& t, const float*
             if (e < E) {
                 const int64_t node = off + (int64_t)p * (K + 1) + k;
                 const uint8_t c = pst[(p - p_lo) * E + e];
-                alloc[node * E + e] = (uint8_t)a;
-                state[node * E + e] = (uint8_t)(c + a);
+                put_alloc<COH>(alloc + node * E + e, (uint8_t)a);
+                put_state<COH>(state + node * E + e, (uint8_t)(c + a));
                 if (with_logits)
                     logits[node * E + e] = z;
                 if (k == 1) {
                     const int64_t sib = off + (int64_t)p * (K + 1);
-                    alloc[sib * E + e] = 0;
-                    state[sib * E + e] = c;
+                    put_alloc<COH>(alloc + sib * E + e, 0);
+                    put_state<COH>(state + sib * E + e, c);
                     if (with_logits)
                         logits[sib * E + e] = 0.f;
                 }
@@ -108,8 +126,11 @@ __device__ __forceinline__ LevelSmem level_smem(uint8_t* smem, int bufsize)
     return m;
 }
 
-// One tile of evaluated rows [row0, row0 + nrows) of level tau.
-template <int P, int RTT>
+// One tile of evaluated rows [row0, row0 + nrows) of level tau. COH (the
+// resident worker): the parent states and the UE state, which other
+// workgroups of the same launch wrote, are read with agent-scope relaxed
+// atomic loads (coherent across XCDs), and the stores are the coherent ones.
+template <int P, int RTT, bool COH = false>
 __device__ __forceinline__ void level_tile(const DevTree& t, int tau, int row0, int nrows, const LevelSmem& m)
 {
     constexpr int es = Traits<P>::kEsize, F = 16 / es;  // features per 16-byte LDS segment
@@ -130,12 +151,21 @@ __device__ __forceinline__ void level_tile(const DevTree& t, int tau, int row0, 
 #pragma unroll
     for (int j = 0; j < kPstIters; ++j) {
         const int i = (int)threadIdx.x + j * kThreads;
-        pv[j] = i < npb ? sp[i] : (uint8_t)0;
+        if constexpr (COH)
+            pv[j] = i < npb ? __hip_atomic_load(t.state + (poff + p_lo) * E + i, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT)
+                            : (uint8_t)0;
+        else
+            pv[j] = i < npb ? sp[i] : (uint8_t)0;
     }
     const int f = threadIdx.x;  // feature index of the template
     int uev = 0;
-    if (f < 3 * E)
-        uev = gptr(t.ue)[f];
+    if (f < 3 * E) {
+        if constexpr (COH)
+            uev = __hip_atomic_load(t.ue + f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        else
+            uev = gptr(t.ue)[f];
+    }
     int nb4 = 0;
     for (int l = 0; l < nl; ++l)
         nb4 += t.out_pad[l] >> 2;
@@ -237,11 +267,11 @@ __device__ __forceinline__ void level_tile(const DevTree& t, int tau, int row0, 
 
     const int rsum = *m.rsum;
     if (E <= 8)
-        finish_rows_level<8>(t, m.zl, m.R, rsum, row0, nrows, off, m.pst, p_lo);
+        finish_rows_level<8, COH>(t, m.zl, m.R, rsum, row0, nrows, off, m.pst, p_lo);
     else if (E <= 16)
-        finish_rows_level<16>(t, m.zl, m.R, rsum, row0, nrows, off, m.pst, p_lo);
+        finish_rows_level<16, COH>(t, m.zl, m.R, rsum, row0, nrows, off, m.pst, p_lo);
     else
-        finish_rows_level<32>(t, m.zl, m.R, rsum, row0, nrows, off, m.pst, p_lo);
+        finish_rows_level<32, COH>(t, m.zl, m.R, rsum, row0, nrows, off, m.pst, p_lo);
 }
 
 template <int P, int RTT>
@@ -297,6 +327,264 @@ __global__ __launch_bounds__(kThreads) void level_kernel_batch(const DevTree* __
         if (nrows > 0)
             level_tile<P, RTT>(t, tau, row0, nrows, m);
         lds_barrier();  // LDS is reused by the next tile
+    }
+}
+
+// ----------------------------------------------------------------- serving
+// Resident serving worker. Workgroup 0 is the control workgroup: it polls the
+// ring in pinned host memory, copies each new request into the device slot
+// table, clears the root state and opens level 1 of the request. Every other
+// workgroup loops: claim one row tile of the oldest admitted request whose
+// current level still has unclaimed tiles (one compare-and-swap on that
+// slot's claim word, which also names the level, so a stale claim of a
+// finished level cannot succeed), run it with the level kernel's tile body,
+// count it done; the workgroup that completes a level's last tile opens the
+// next level, or after level M flags the request finished in pinned memory.
+// No workgroup ever waits for another: a level's work appears only once the
+// previous level is complete.
+//
+// Coherence without cache flushes: every value one workgroup hands to another
+// (slot records, counters, node states, UE state) or to the host (codebook
+// bytes, flags) is written and read with relaxed atomic accesses of agent
+// (device) or system scope, which bypass the non-coherent caches, and each
+// workgroup waits for its stores to complete before the counter update that
+// publishes them. An acquire fence would invalidate the whole L2 of the XCD
+// and evict the actors' weights, which every tile reads through the caches; it
+// is taken only when the host reports a weight refresh (wepoch).
+//
+// Exits: the host's stop flag; the control workgroup leaves after idle_ticks
+// of wall-clock time with no request in flight and none in the ring (it then
+// sets quit), or after stall_ticks with requests in flight and none finishing;
+// the tile workgroups leave when they find no work and quit or stop is set, or
+// after stall_ticks idle.
+
+__device__ __forceinline__ uint32_t sys_load_u32(const uint32_t* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ __forceinline__ void sys_store_u32(uint32_t* p, uint32_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+template <class T>
+__device__ __forceinline__ T dev_load(const T* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T>
+__device__ __forceinline__ void dev_store(T* p, T v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+
+// Control workgroup: admission from the ring.
+__device__ void serve_control(const ServeArgs& a, int* sh)
+{
+    const int tid = threadIdx.x;
+    uint32_t head = a.head0;
+    int last_active = -1;
+    uint64_t since = wall_clock64();  // start of the current idle or stalled stretch
+    for (;;) {
+        if (tid == 0) {
+            sh[0] = (int)sys_load_u32(&a.host->stop);
+            sh[1] = (int)sys_load_u32(&a.host->tail);
+            sh[2] = dev_load(&a.ctl->active);
+        }
+        __syncthreads();
+        const int stop = sh[0], active = sh[2];
+        const uint32_t tail = (uint32_t)sh[1];
+        __syncthreads();
+        if (stop)
+            break;
+        if (head != tail) {
+            // copy the entry word by word with system-scope loads into the
+            // slot record with agent-scope stores
+            const ServeRequest* src = &a.host->ring[head % kServeRing];
+            const uint32_t* sw = reinterpret_cast<const uint32_t*>(src);
+            constexpr int kWords = (int)(sizeof(ServeRequest) / 4);
+            const int rec = (int)(head - a.head0);
+            if (rec >= kServeRecords)
+                break;  // every record of this launch is used: the host relaunches
+            const int slot = (int)sys_load_u32(reinterpret_cast<const uint32_t*>(&src->slot));
+            ServeRequest* dst = &a.recs[rec];
+            uint32_t* dw = reinterpret_cast<uint32_t*>(dst);
+            for (int i = tid; i < kWords; i += kThreads)
+                dev_store(dw + i, sys_load_u32(sw + i));
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+            if (tid == 0)  // the UE state is this record's own copy
+                dev_store(reinterpret_cast<uint64_t*>(&dst->t.ue), (uint64_t)(uintptr_t)dst->ue);
+            // the fields needed here are read from the ring as well
+            const uint32_t gen = sys_load_u32(&src->gen);
+            const uint32_t wepoch = sys_load_u32(&src->wepoch);
+            const int E = (int)sys_load_u32(reinterpret_cast<const uint32_t*>(&src->t.E));
+            const int nt1 = (int)sys_load_u32(reinterpret_cast<const uint32_t*>(&src->ntiles[1]));
+            uint8_t* state = reinterpret_cast<uint8_t*>(__hip_atomic_load(
+                reinterpret_cast<const uint64_t*>(&src->t.state), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM));
+            uint8_t* alloc = reinterpret_cast<uint8_t*>(__hip_atomic_load(
+                reinterpret_cast<const uint64_t*>(&src->t.alloc), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM));
+            ServeSlotCtl& sc = a.ctl->slot[slot];
+            if (tid < E) {  // the root punctures nothing
+                dev_store(state + tid, (uint8_t)0);
+                dev_store(alloc + tid, (uint8_t)0);
+            }
+            if (tid < 8)
+                dev_store(&sc.ntiles[tid], (int32_t)sys_load_u32(reinterpret_cast<const uint32_t*>(&src->ntiles[tid])));
+            if (tid == 0) {
+                dev_store(&sc.M, (int32_t)sys_load_u32(reinterpret_cast<const uint32_t*>(&src->t.M)));
+                dev_store(&sc.rec, rec);
+                dev_store(&sc.done, 0u);
+                if (wepoch != dev_load(&a.ctl->wepoch))
+                    dev_store(&a.ctl->wepoch, wepoch);
+            }
+            __builtin_amdgcn_s_waitcnt(0);  // every store above has completed
+            __syncthreads();
+            if (tid == 0) {
+                __hip_atomic_fetch_add(&a.ctl->active, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_max(&a.ctl->hi, slot + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __builtin_amdgcn_s_waitcnt(0);
+                dev_store(&sc.claim, serve_claim_word(gen, 1, nt1));
+                sys_store_u32(&a.host->consumed, head + 1);
+            }
+            ++head;
+            since = wall_clock64();
+            continue;
+        }
+        const uint64_t now = wall_clock64();
+        if (active != last_active)
+            since = now;  // a request was admitted or finished
+        last_active = active;
+        if (now - since > (active == 0 ? a.idle_ticks : a.stall_ticks))
+            break;
+        __builtin_amdgcn_s_sleep(16);
+    }
+    if (tid == 0)
+        dev_store(&a.ctl->quit, 1);
+}
+
+// Wave 0 of a tile workgroup: claim the next tile. Every lane reads the claim
+// words of two slots; the oldest request (smallest generation) with tiles
+// left gets one fetch-and-add, whose result is authoritative: if it names a
+// live level and a count below that level's tiles, that tile is this
+// workgroup's (whatever level the slot has reached meanwhile), else the
+// increment is spent and the scan repeats. Returns in sh[0] the slot (-1:
+// nothing claimed), sh[1] the level, sh[2] the tile.
+__device__ void serve_claim(const ServeArgs& a, int* sh)
+{
+    const int lane = threadIdx.x & 63;
+    for (int attempt = 0; attempt < 4; ++attempt) {
+        uint64_t best = ~0ull;
+#pragma unroll
+        for (int j = 0; j < kServeSlots / 64; ++j) {
+            const int s = lane + 64 * j;
+            const uint64_t w = dev_load(&a.ctl->slot[s].claim);
+            const int lvl = (int)((w >> 41) & 7u), nt = (int)((w >> 24) & 0x1FFFFu), cnt = (int)(w & 0xFFFFFFu);
+            const uint64_t key = ((w >> 44) << 8) | (uint64_t)s;
+            if (lvl != 0 && cnt < nt && key < best)
+                best = key;
+        }
+        uint64_t m = best;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const uint64_t v = __shfl_xor(m, o);
+            m = v < m ? v : m;
+        }
+        if (m == ~0ull)
+            break;
+        const int slot = (int)(m & 0xFF);
+        int got = 0;
+        if (lane == 0) {
+            const uint64_t w = __hip_atomic_fetch_add(&a.ctl->slot[slot].claim, (uint64_t)1, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+            const int lvl = (int)((w >> 41) & 7u), nt = (int)((w >> 24) & 0x1FFFFu), cnt = (int)(w & 0xFFFFFFu);
+            if (lvl != 0 && cnt < nt) {
+                got = 1;
+                sh[0] = slot;
+                sh[1] = lvl;
+                sh[2] = cnt;
+            }
+        }
+        if (__shfl(got, 0))
+            return;
+    }
+    if (lane == 0)
+        sh[0] = -1;
+}
+
+template <int P, int RTT>
+__global__ __launch_bounds__(kThreads) void serve_kernel(ServeArgs a, const ServeRequest* __restrict__ recs)
+{
+    extern __shared__ __align__(16) uint8_t smem[];
+    const LevelSmem m = level_smem<RTT>(smem, a.bufsize);
+    int* sh = m.tab;  // scheduler words
+    if (blockIdx.x == 0) {
+        serve_control(a, sh);
+        return;
+    }
+    const int tid = threadIdx.x;
+    uint32_t wepoch = 0;  // weight-refresh epoch this workgroup's caches reflect
+    uint64_t since = wall_clock64();
+    for (;;) {
+        if (tid < 64)
+            serve_claim(a, sh);
+        __syncthreads();
+        const int slot = sh[0], tau = sh[1], tile = sh[2];
+        __syncthreads();
+        if (slot < 0) {
+            if (tid == 0)
+                sh[3] = dev_load(&a.ctl->quit) | (int)sys_load_u32(&a.host->stop);
+            __syncthreads();
+            const int leave = sh[3];
+            __syncthreads();
+            if (leave || wall_clock64() - since > a.stall_ticks)
+                break;
+            __builtin_amdgcn_s_sleep(8);
+            continue;
+        }
+        since = wall_clock64();
+        // the request's record, and a cache invalidation if the host
+        // refreshed some cell's weights
+        if (tid == 0) {
+            sh[4] = dev_load(&a.ctl->slot[slot].rec);
+            sh[5] = (int)dev_load(&a.ctl->wepoch);
+        }
+        __syncthreads();
+        const int rec = __builtin_amdgcn_readfirstlane(sh[4]);
+        const uint32_t we = (uint32_t)sh[5];
+        if (we != wepoch) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            wepoch = we;
+        }
+        const DevTree& t = recs[rec].t;
+        const int n_eval = (int)(t.K * (dev_level_offset(t.K, tau) - dev_level_offset(t.K, tau - 1)));
+        const int row0 = tile * 16 * RTT;
+        const int nrows = min(16 * RTT, n_eval - row0);
+        const int M = t.M;
+        if (nrows > 0)
+            level_tile<P, RTT, true>(t, tau, row0, nrows, m);
+        // every store of the tile has completed before it is counted
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (tid == 0) {
+            ServeSlotCtl& sc = a.ctl->slot[slot];
+            const uint32_t nt = (uint32_t)dev_load(&sc.ntiles[tau]);
+            const uint32_t prev = __hip_atomic_fetch_add(&sc.done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (prev + 1 == nt) {
+                const uint32_t gen = (uint32_t)(dev_load(&sc.claim) >> 44);
+                if (tau < M) {
+                    dev_store(&sc.done, 0u);
+                    __builtin_amdgcn_s_waitcnt(0);
+                    dev_store(&sc.claim, serve_claim_word(gen, tau + 1, dev_load(&sc.ntiles[tau + 1])));
+                } else {
+                    dev_store(&sc.claim, serve_claim_word(gen, 0, 0));
+                    __hip_atomic_fetch_add(&a.ctl->active, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __builtin_amdgcn_s_waitcnt(0);
+                    sys_store_u32(&a.host->finished[slot], gen);
+                }
+            }
+        }
+        __syncthreads();  // LDS is reused by the next tile
     }
 }
 
@@ -434,6 +722,34 @@ hipError_t launch_level_batch(const DevTree* trees, const int* ent_tree, const i
     CYRUS_LEVEL_CASE(kBF16, 1) CYRUS_LEVEL_CASE(kBF16, 2) CYRUS_LEVEL_CASE(kBF16, 4) CYRUS_LEVEL_CASE(kBF16, 6)
     CYRUS_LEVEL_CASE(kFP8, 1) CYRUS_LEVEL_CASE(kFP8, 2) CYRUS_LEVEL_CASE(kFP8, 4) CYRUS_LEVEL_CASE(kFP8, 6)
 #undef CYRUS_LEVEL_CASE
+    return hipErrorInvalidValue;
+}
+
+template <int P, int RTT>
+static hipError_t launch_serve_t(const ServeArgs& a, int grid, size_t lds, hipStream_t s)
+{
+    static bool attr = false;
+    if (!attr) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&serve_kernel<P, RTT>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        attr = true;
+    }
+    hipLaunchKernelGGL((serve_kernel<P, RTT>), dim3(grid), dim3(kThreads), lds, s, a,
+                       static_cast<const ServeRequest*>(a.recs));
+    return hipGetLastError();
+}
+
+hipError_t launch_serve(const ServeArgs& a, int prec, int rtt, int grid, size_t lds, hipStream_t s)
+{
+    if (grid < 2 || lds < level_lds_for_buf(0, 0, rtt))
+        return hipErrorInvalidValue;
+#define CYRUS_SERVE_CASE(P, R)                                                                                         \
+    if (prec == P && rtt == R)                                                                                         \
+        return launch_serve_t<P, R>(a, grid, lds, s);
+    CYRUS_SERVE_CASE(kFP32, 1) CYRUS_SERVE_CASE(kFP32, 2) CYRUS_SERVE_CASE(kFP32, 4)
+    CYRUS_SERVE_CASE(kBF16, 1) CYRUS_SERVE_CASE(kBF16, 2) CYRUS_SERVE_CASE(kBF16, 4) CYRUS_SERVE_CASE(kBF16, 6)
+    CYRUS_SERVE_CASE(kFP8, 1) CYRUS_SERVE_CASE(kFP8, 2) CYRUS_SERVE_CASE(kFP8, 4) CYRUS_SERVE_CASE(kFP8, 6)
+#undef CYRUS_SERVE_CASE
     return hipErrorInvalidValue;
 }
 

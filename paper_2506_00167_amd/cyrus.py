@@ -40,6 +40,7 @@ SYMBOLS = (
     "cyrus_critic_workspace_size", "cyrus_critic_create", "cyrus_critic_evaluate", "cyrus_critic_evaluate_noalloc",
     "cyrus_critic_destroy",
     "cyrus_engine_create", "cyrus_engine_submit", "cyrus_engine_step", "cyrus_engine_set_levels_per_step",
+    "cyrus_engine_set_resident",
     "cyrus_engine_poll",
     "cyrus_engine_completed", "cyrus_engine_result", "cyrus_engine_stats", "cyrus_engine_destroy",
 )
@@ -136,6 +137,7 @@ def lib():
                                             vp, vp, vp, vp]
         L.cyrus_critic_evaluate_noalloc.argtypes = [vp, ctypes.POINTER(cyrus_critic_batch), ctypes.c_uint64,
                                                     ctypes.c_uint64, vp, vp, vp, vp]
+        L.cyrus_engine_set_resident.argtypes = [vp, ctypes.c_int32]
         L.cyrus_critic_destroy.argtypes = [vp]
         L.cyrus_critic_destroy.restype = None
         L.cyrus_codebook_destroy.argtypes = [vp]
@@ -349,6 +351,7 @@ class Codebook:
         self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
         self.host = torch.empty(self.host_bytes, dtype=torch.uint8, pin_memory=True)
         self._w = _WeightsView(weights, act_scale)
+        self.weights, self.act_scale = weights, act_scale
         self.stream = stream
         with torch.cuda.device(self.device):
             self.handle = cyrus_codebook_create(self.cconf, self._w.struct, self.ws.data_ptr(), self.ws_bytes,
@@ -368,6 +371,7 @@ class Codebook:
 
     def set_weights(self, weights, act_scale=None):
         self._w = _WeightsView(weights, act_scale)
+        self.weights, self.act_scale = weights, act_scale
         cyrus_codebook_set_weights(self.handle, self._w.struct, self.stream)
 
     def build(self, ue: UEState):
@@ -478,7 +482,7 @@ class Engine:
     and pinned host memory). Cells are Codebook objects (their weights)."""
 
     def __init__(self, device_pool_bytes: int, host_pool_bytes: int, max_active: int = 64, device: str = "cuda",
-                 stream=None):
+                 stream=None, resident: bool = False):
         import torch
         self.dpool = torch.empty(device_pool_bytes, dtype=torch.uint8, device=device)
         self.hpool = torch.empty(host_pool_bytes, dtype=torch.uint8, pin_memory=True)
@@ -486,6 +490,9 @@ class Engine:
         self.handle = cyrus_engine_create(self.dpool.data_ptr(), device_pool_bytes, self.hpool.data_ptr(),
                                           host_pool_bytes, max_active, stream)
         self._cells = {}
+        self.resident = bool(resident)
+        if resident:
+            _check(lib().cyrus_engine_set_resident(self.handle, 1), "cyrus_engine_set_resident")
 
     def submit(self, cell: Codebook, ue: UEState) -> int:
         s, keep = ue_struct(ue)

@@ -41,9 +41,10 @@ def make_requests(cells, n: int, seed: int = 7):
     return out
 
 
-def default_engine(max_active: int = 64, pool_mib: int = 256, stream=None, levels_per_step: int = 1):
-    eng = cyrus.Engine(pool_mib << 20, pool_mib << 20, max_active=max_active, stream=stream)
-    return eng.set_levels_per_step(levels_per_step)
+def default_engine(max_active: int = 64, pool_mib: int = 256, stream=None, levels_per_step: int = 1,
+                   resident: bool = False):
+    eng = cyrus.Engine(pool_mib << 20, pool_mib << 20, max_active=max_active, stream=stream, resident=resident)
+    return eng if resident else eng.set_levels_per_step(levels_per_step)
 
 
 def run_stream(engine, cells, requests, arrivals_s, keep_results: bool = False):
@@ -111,8 +112,9 @@ def main():
     ap.add_argument("--loads", default="0.25,0.5,0.75,0.9")
     ap.add_argument("--max-active", type=int, default=64)
     ap.add_argument("--pool-mib", type=int, default=256)
-    ap.add_argument("--levels-per-step", default="1,7",
-                    help="comma separated: 1 = iteration-level batching, 7 = each step runs its requests to the end")
+    ap.add_argument("--levels-per-step", default="0,1,7",
+                    help="comma separated engine modes: 0 = the resident worker, 1 = host-stepped iteration-level "
+                         "batching, 7 = each host step runs its requests to the end")
     args = ap.parse_args()
     import torch
     cyrus.lib()
@@ -120,7 +122,8 @@ def main():
     cells = make_cells(args.cells, stream=stream)
     torch.cuda.synchronize()
     for lps in [int(x) for x in args.levels_per_step.split(",")]:
-        eng = default_engine(args.max_active, args.pool_mib, stream=stream, levels_per_step=lps)
+        eng = default_engine(args.max_active, args.pool_mib, stream=stream, levels_per_step=max(lps, 1),
+                             resident=lps == 0)
         warm = make_requests(cells, 200, seed=1)
         saturation(eng, cells, warm)
         reqs = make_requests(cells, args.requests, seed=2)

@@ -1,9 +1,16 @@
 """Continuous-batching engine (many cells, Poisson arrivals) and the batched
 stress launch, through the C ABI.
 
-- A request's codebook is bit-identical alone and in a mix of requests of
-  other shapes at other levels, and equal to the same cell's own level-path
-  build (the engine uses the same kernel).
+- Host-stepped engine: a request's codebook, alone and in a mix of requests
+  of other shapes at other levels, is bit-identical to the same request built
+  on its own by one of the two kernels the engine may give it (the
+  single-launch subtree kernel for a fresh request on a subtree-capable cell
+  under light load, else the level kernel); each of those builds is checked
+  against the oracle by the parity tests.
+- Resident worker: every request runs the same tile code, so alone, in the
+  mix and the cell's own level-path build are all bit-identical; a small cell
+  is checked node by node against the BF16 oracle; the worker leaves when
+  idle and is relaunched for the next request.
 - Memory admission: with a pool that holds only a few trees, every request
   still completes, admissions are deferred, and the pool high-water mark stays
   within the pool.
@@ -57,12 +64,87 @@ def test_mixed_equals_alone_and_single_build(cells, levels_per_step):
     print(f"[serving] mix: {json.dumps({k: v for k, v in res.items() if k != 'results'})}", flush=True)
     assert res["engine"]["steps"] > 0
     for i in probe_idx:
-        assert np.array_equal(res["results"][i], alone[i]), f"request {i} differs alone vs in the mix"
         c, ue = reqs[i]
-        cells[c].build(ue)
-        single, _ = cells[c].export()
-        assert np.array_equal(single, alone[i]), f"request {i} differs from the cell's own build"
+        builds = _own_builds(cells[c], ue)
+        for tag, got in (("alone", alone[i]), ("mix", res["results"][i])):
+            assert any(np.array_equal(got, b) for b in builds.values()), (
+                f"request {i} {tag} equals neither of its cell's own builds ({list(builds)})")
         parity.check_invariants(cells[c].cfg, ue, alone[i])
+    eng.close()
+
+
+def _own_builds(cell, ue):
+    """The request built on its own by each kernel the stepped engine may use:
+    the cell's own path, and the level kernel."""
+    out = {}
+    cell.build(ue)
+    out[cell.kernel_path] = cell.export()[0]
+    if cell.kernel_path != "level":
+        lv = cyrus.Codebook(cell.cfg, cell.weights, force_level=True)
+        lv.build(ue)
+        out["level"] = lv.export()[0]
+        lv.close()
+    return out
+
+
+def test_resident_mixed_equals_alone_and_level_build(cells):
+    eng = serving.default_engine(max_active=32, pool_mib=128, resident=True)
+    reqs = serving.make_requests(cells, 40, seed=11)
+    probe_idx = [3, 17, 29]
+    alone = {i: _alone(eng, cells[reqs[i][0]], reqs[i][1]) for i in probe_idx}
+    arrivals = np.linspace(0.0, 0.002, len(reqs))
+    res = serving.run_stream(eng, cells, reqs, arrivals, keep_results=True)
+    print(f"[serving] resident mix: {json.dumps({k: v for k, v in res.items() if k != 'results'})}", flush=True)
+    assert res["engine"]["completed"] == len(reqs) + len(probe_idx)
+    for i in probe_idx:
+        c, ue = reqs[i]
+        lv = cyrus.Codebook(cells[c].cfg, cells[c].weights, force_level=True)
+        lv.build(ue)
+        ref, _ = lv.export()
+        lv.close()
+        assert np.array_equal(alone[i], ref), f"request {i}: resident alone differs from the level-path build"
+        assert np.array_equal(res["results"][i], ref), f"request {i}: resident mix differs from the level-path build"
+        parity.check_invariants(cells[c].cfg, ue, ref)
+    for j, (c, ue) in enumerate(reqs):
+        parity.check_invariants(cells[c].cfg, ue, res["results"][j])
+    eng.close()
+
+
+def test_resident_matches_same_precision_oracle(cells):
+    small = min(range(len(cells)), key=lambda j: cells[j].num_nodes * cells[j].cfg.hidden[0])
+    cell = cells[small]
+    ue = wl.make_ue_state(cell.cfg.num_ue, 78)
+    eng = serving.default_engine(max_active=4, pool_mib=64, resident=True)
+    alloc = _alone(eng, cell, ue)
+    weights = wl.make_weights(cell.cfg, wl.serving_cell_configs(16, 424242)[small][1])
+    ref = cyrus.Codebook(cell.cfg, weights, export_logits=True, force_level=True)
+    ref.build(ue)
+    ref_alloc, ref_logits = ref.export()
+    ref.close()
+    assert np.array_equal(ref_alloc, alloc)
+    nodes = wl.sample_nodes(cell.cfg, 600, seed=4)
+    rep = parity.compare(cell.cfg, weights, ue, ref_alloc, ref_logits, nodes=nodes, precision="bf16", logit_tol=2e-3)
+    rep.check(f"resident {cell.cfg}", exact=False)
+    eng.close()
+
+
+def test_resident_memory_admission_and_relaunch(cells):
+    import time
+    biggest = max(c.num_nodes * c.cfg.num_ue for c in cells)
+    pool = 3 * biggest + (1 << 20)  # the worker's tables plus a few state arrays
+    eng = cyrus.Engine(pool, 3 * biggest + (2 << 20), max_active=16, resident=True)
+    reqs = serving.make_requests(cells, 24, seed=12)
+    res = serving.run_stream(eng, cells, reqs, np.zeros(len(reqs)), keep_results=True)
+    st = res["engine"]
+    print(f"[serving] resident small pool: {st}", flush=True)
+    assert st["completed"] == 24 and st["deferred_memory"] > 0
+    assert st["pool_bytes_peak"] <= pool
+    launches = st["steps"]
+    time.sleep(0.2)  # the worker leaves after about 40 ms idle
+    c, ue = reqs[0]
+    again = _alone(eng, cells[c], ue)
+    assert eng.stats()["steps"] == launches + 1, "the idle worker was not relaunched"
+    assert np.array_equal(again, res["results"][0])
     eng.close()
 
 
@@ -150,3 +232,20 @@ def test_stress_batch_equals_single_and_oracle():
         assert rep.cond_unexplained == 0
     for c in cells_:
         c.close()
+
+
+def test_oversize_request_is_refused(cells):
+    """A request whose tree can never fit the pools is refused at submit, so
+    it cannot block the FIFO; later requests still complete."""
+    from paper_2506_00167_amd import stress
+    cfg, big, _ = stress.make_cells(n=1, precision="bf16")
+    eng = cyrus.Engine(2 << 20, 4 << 20, max_active=8)  # the slots and a few small trees
+    with pytest.raises(cyrus.CyrusError) as ei:
+        eng.submit(big[0], wl.make_ue_state(cfg.num_ue, 1))
+    assert ei.value.status == -3
+    small = min(cells, key=lambda c: c.num_nodes * c.cfg.num_ue)
+    ue = wl.make_ue_state(small.cfg.num_ue, 2)
+    alloc = _alone(eng, small, ue)
+    parity.check_invariants(small.cfg, ue, alloc)
+    eng.close()
+    big[0].close()
