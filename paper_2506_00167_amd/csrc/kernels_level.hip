@@ -503,6 +503,7 @@ __device__ void serve_claim(const ServeArgs& a, int* sh)
                 sh[0] = slot;
                 sh[1] = lvl;
                 sh[2] = cnt;
+                sh[3] = (int)(uint32_t)(w >> 44);  // generation
             }
         }
         if (__shfl(got, 0))
@@ -525,42 +526,57 @@ __global__ __launch_bounds__(kThreads) void serve_kernel(ServeArgs a, const Serv
     const int tid = threadIdx.x;
     uint32_t wepoch = 0;  // weight-refresh epoch this workgroup's caches reflect
     uint64_t since = wall_clock64();
+    int backoff = 1;      // idle sleep in units of about 64 cycles, doubled up to 64
+    int cont = 0;         // the previous tile opened the next level and kept its tile 0
+    int slot = 0, tau = 0, tile = 0, rec = 0, nt = 0, M = 0;
+    uint32_t gen = 0;
     for (;;) {
-        if (tid < 64)
-            serve_claim(a, sh);
-        __syncthreads();
-        const int slot = sh[0], tau = sh[1], tile = sh[2];
-        __syncthreads();
-        if (slot < 0) {
-            if (tid == 0)
-                sh[3] = dev_load(&a.ctl->quit) | (int)sys_load_u32(&a.host->stop);
+        if (!cont) {
+            if (tid < 64)
+                serve_claim(a, sh);
             __syncthreads();
-            const int leave = sh[3];
+            slot = sh[0];
+            tau = sh[1];
+            tile = sh[2];
+            gen = (uint32_t)sh[3];
             __syncthreads();
-            if (leave || wall_clock64() - since > a.stall_ticks)
-                break;
-            __builtin_amdgcn_s_sleep(8);
-            continue;
+            if (slot < 0) {
+                if (tid == 0)
+                    sh[3] = dev_load(&a.ctl->quit) | (int)sys_load_u32(&a.host->stop);
+                __syncthreads();
+                const int leave = sh[3];
+                __syncthreads();
+                if (leave || wall_clock64() - since > a.stall_ticks)
+                    break;
+                for (int i = 0; i < backoff; ++i)
+                    __builtin_amdgcn_s_sleep(1);
+                backoff = backoff < 64 ? 2 * backoff : 64;
+                continue;
+            }
+            backoff = 1;
+            // the request's record and the level's tiles, and a cache
+            // invalidation if the host refreshed some cell's weights
+            if (tid == 0) {
+                const ServeSlotCtl& sc = a.ctl->slot[slot];
+                sh[4] = dev_load(&sc.rec);
+                sh[5] = (int)dev_load(&a.ctl->wepoch);
+                sh[6] = dev_load(&sc.ntiles[tau]);
+            }
+            __syncthreads();
+            rec = __builtin_amdgcn_readfirstlane(sh[4]);
+            nt = __builtin_amdgcn_readfirstlane(sh[6]);
+            const uint32_t we = (uint32_t)sh[5];
+            if (we != wepoch) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                wepoch = we;
+            }
         }
         since = wall_clock64();
-        // the request's record, and a cache invalidation if the host
-        // refreshed some cell's weights
-        if (tid == 0) {
-            sh[4] = dev_load(&a.ctl->slot[slot].rec);
-            sh[5] = (int)dev_load(&a.ctl->wepoch);
-        }
-        __syncthreads();
-        const int rec = __builtin_amdgcn_readfirstlane(sh[4]);
-        const uint32_t we = (uint32_t)sh[5];
-        if (we != wepoch) {
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            wepoch = we;
-        }
         const DevTree& t = recs[rec].t;
+        M = t.M;
         const int n_eval = (int)(t.K * (dev_level_offset(t.K, tau) - dev_level_offset(t.K, tau - 1)));
         const int row0 = tile * 16 * RTT;
         const int nrows = min(16 * RTT, n_eval - row0);
-        const int M = t.M;
         if (nrows > 0)
             level_tile<P, RTT, true>(t, tau, row0, nrows, m);
         // every store of the tile has completed before it is counted
@@ -568,14 +584,18 @@ __global__ __launch_bounds__(kThreads) void serve_kernel(ServeArgs a, const Serv
         __syncthreads();
         if (tid == 0) {
             ServeSlotCtl& sc = a.ctl->slot[slot];
-            const uint32_t nt = (uint32_t)dev_load(&sc.ntiles[tau]);
+            int next = 0;
             const uint32_t prev = __hip_atomic_fetch_add(&sc.done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (prev + 1 == nt) {
-                const uint32_t gen = (uint32_t)(dev_load(&sc.claim) >> 44);
+            if (prev + 1 == (uint32_t)nt) {
                 if (tau < M) {
+                    // open the next level with its tile 0 already claimed by
+                    // this workgroup, which goes on with it at once
+                    const int nt_next = dev_load(&sc.ntiles[tau + 1]);
                     dev_store(&sc.done, 0u);
                     __builtin_amdgcn_s_waitcnt(0);
-                    dev_store(&sc.claim, serve_claim_word(gen, tau + 1, dev_load(&sc.ntiles[tau + 1])));
+                    dev_store(&sc.claim, serve_claim_word(gen, tau + 1, nt_next) + 1);
+                    next = 1;
+                    sh[6] = nt_next;
                 } else {
                     dev_store(&sc.claim, serve_claim_word(gen, 0, 0));
                     __hip_atomic_fetch_add(&a.ctl->active, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -583,8 +603,16 @@ __global__ __launch_bounds__(kThreads) void serve_kernel(ServeArgs a, const Serv
                     sys_store_u32(&a.host->finished[slot], gen);
                 }
             }
+            sh[7] = next;
         }
         __syncthreads();  // LDS is reused by the next tile
+        cont = sh[7];
+        if (cont) {
+            ++tau;
+            tile = 0;
+            nt = __builtin_amdgcn_readfirstlane(sh[6]);
+        }
+        __syncthreads();
     }
 }
 
