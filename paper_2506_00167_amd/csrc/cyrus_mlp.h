@@ -8,7 +8,7 @@
 
 namespace cyrus {
 
-constexpr int kPF = 4;  // output-layer weight chunks loaded per group
+constexpr int kPF = 8;  // output-layer weight chunks per load group (even: chunk pairs)
 
 // One hidden layer, out = ReLU(W in + b), for the T neuron tiles this wave
 // owns (tiles wave, wave + 8, ...). The reduction runs over chunk pairs; the
@@ -128,7 +128,8 @@ template <int P, int RTT>
 __device__ __forceinline__ void run_mlp(const DevTree& t, int nrows, uint8_t* bufA, uint8_t* bufB, float* zl,
                                         const float* bias, int64_t off, int row0)
 {
-    constexpr int kc = Traits<P>::kChunk, es = Traits<P>::kEsize, RT = 16 * RTT;
+    constexpr int kc = Traits<P>::kChunk, es = Traits<P>::kEsize;
+    static_assert(RTT <= kWaves, "the output layer gives each row tile a wave");
     const int lane = threadIdx.x & 63, wave = wave_id(), g = lane >> 4, c16 = lane & 15;
     const int art = (nrows + 15) >> 4;
     uint8_t* in = bufA;
@@ -155,68 +156,74 @@ __device__ __forceinline__ void run_mlp(const DevTree& t, int nrows, uint8_t* bu
         in = out;
         out = tmp;
     }
-    // Output layer: the reduction dimension is split across the waves; each
-    // wave leaves a partial logit tile, summed in wave order below.
+    // Output layer. Wave w owns row tile w (RTT <= waves) and reduces over
+    // the whole input in chunk order, so a row's logits do not depend on the
+    // tile it was computed in. The wave's weight fragments arrive in groups
+    // of kPF chunks, the next group requested before the current one's MFMAs.
+    // Softmax head: the lanes write their logits to zl directly; Gaussian
+    // head: the raw outputs go through LDS, since a log-share needs output e
+    // and output E + e, which other lanes may hold.
     {
         const int l = t.n_layers - 1;
         const int nch = t.in_pad[l] / kc;
         const int sin = t.in_pad[l] * es + 16;
         const int opad = t.out_pad[l];
         const int ntile = opad >> 4;
-        const int cpw = (nch + kWaves - 1) / kWaves;
-        const int c0 = wave * cpw, c1 = min(nch, c0 + cpw);
-        float* part = reinterpret_cast<float*>(out);
-        const guint4* wl = as_global(t.w[l]);
-        for (int nt = 0; nt < ntile; ++nt) {
-            floatx4 acc[RTT];
-#pragma unroll
-            for (int rt = 0; rt < RTT; ++rt)
-                acc[rt] = floatx4{0.f, 0.f, 0.f, 0.f};
-            const guint4* wp = wl + (size_t)nt * nch * 64 + lane;
-            const uint8_t* bp = in + c16 * sin + g * (kc / 4) * es;
-            for (int cb = c0; cb < c1; cb += kPF) {
-                uint4 a[kPF];
-#pragma unroll
-                for (int j = 0; j < kPF; ++j)
-                    a[j] = (cb + j < c1) ? gld(wp + (size_t)(cb + j) * 64) : uint4{0, 0, 0, 0};
-#pragma unroll
-                for (int j = 0; j < kPF; ++j) {
-                    if (cb + j < c1) {
-#pragma unroll
-                        for (int rt = 0; rt < RTT; ++rt) {
-                            if (rt < art) {
-                                const uint4 b =
-                                    *reinterpret_cast<const uint4*>(bp + rt * 16 * sin + (cb + j) * kc * es);
-                                mma_chunk<P>(a[j], b, acc[rt]);
-                            }
-                        }
-                    }
-                }
-            }
-#pragma unroll
-            for (int rt = 0; rt < RTT; ++rt)
-                if (rt < art)
-                    *reinterpret_cast<floatx4*>(part + (size_t)(wave * RT + rt * 16 + c16) * opad + nt * 16 + g * 4) =
-                        acc[rt];
-        }
-        lds_barrier();
         const int E = t.E, K = t.K;
         const float deq = t.deq[l];
         const bool gaussian = t.head == kGaussianHead;
-        for (int idx = threadIdx.x; idx < nrows * E; idx += kThreads) {
-            const int row = idx / E, e = idx - row * E;
-            float s = 0.f;
-            for (int w = 0; w < kWaves; ++w)
-                s += part[(size_t)(w * RT + row) * opad + e];
-            float z = s * deq + bias[e];
-            if (gaussian) {  // outputs E..2E-1 are the log standard deviations
-                float s2 = 0.f;
-                for (int w = 0; w < kWaves; ++w)
-                    s2 += part[(size_t)(w * RT + row) * opad + E + e];
-                const int r = row0 + row, p = r / K, k = r - p * K + 1;
-                z = gaussian_log_share(z, s2 * deq + bias[E + e], t.seed, t.tti, off + (int64_t)p * (K + 1) + k, e);
+        float* raw = reinterpret_cast<float*>(out);  // [RT][opad], Gaussian head
+        const int rt = wave;
+        if (rt < art) {
+            const guint4* wl = as_global(t.w[l]);
+            const int row = rt * 16 + c16;
+            const uint8_t* bp = in + row * sin + g * (kc / 4) * es;
+            for (int nt = 0; nt < ntile; ++nt) {
+                floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+                const guint4* wp = wl + (size_t)nt * nch * 64 + lane;
+                uint4 a[kPF], an[kPF];
+#pragma unroll
+                for (int j = 0; j < kPF; ++j)
+                    a[j] = j < nch ? gld(wp + (size_t)j * 64) : uint4{0, 0, 0, 0};
+                for (int cb = 0; cb < nch; cb += kPF) {
+#pragma unroll
+                    for (int j = 0; j < kPF; ++j)
+                        an[j] = cb + kPF + j < nch ? gld(wp + (size_t)(cb + kPF + j) * 64) : uint4{0, 0, 0, 0};
+#pragma unroll
+                    for (int j = 0; j < kPF; j += 2) {
+                        const int c = cb + j;
+                        if (c + 1 < nch) {
+                            const uint4 b0 = *reinterpret_cast<const uint4*>(bp + c * kc * es);
+                            const uint4 b1 = *reinterpret_cast<const uint4*>(bp + (c + 1) * kc * es);
+                            mma_pair<P>(a[j], a[j + 1], b0, b1, acc);
+                        } else if (c < nch) {
+                            mma_chunk<P>(a[j], *reinterpret_cast<const uint4*>(bp + c * kc * es), acc);
+                        }
+                    }
+#pragma unroll
+                    for (int j = 0; j < kPF; ++j)
+                        a[j] = an[j];
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int e = nt * 16 + g * 4 + i;
+                    const float z = acc[i] * deq + bias[e];
+                    if (gaussian)
+                        raw[row * opad + e] = z;
+                    else if (row < nrows && e < E)
+                        zl[row * kLogitStride + e] = z;
+                }
             }
-            zl[row * kLogitStride + e] = z;
+        }
+        if (gaussian) {
+            lds_barrier();
+            for (int idx = threadIdx.x; idx < nrows * E; idx += kThreads) {
+                const int row = idx / E, e = idx - row * E;
+                const int r = row0 + row, p = r / K, k = r - p * K + 1;
+                // outputs E..2E-1 are the log standard deviations
+                zl[row * kLogitStride + e] = gaussian_log_share(raw[row * opad + e], raw[row * opad + E + e], t.seed,
+                                                                t.tti, off + (int64_t)p * (K + 1) + k, e);
+            }
         }
         lds_barrier();
     }
