@@ -106,7 +106,9 @@ typedef struct {
  *   act_scale  FP8 only: num_hidden+1 positive powers of two, the scale of each
  *              layer's input (input / scale is rounded to E4M3); NULL otherwise.
  * Weight scales for FP8 are derived by the library (smallest power of two that
- * keeps max|w|/scale <= 448). */
+ * keeps max|w|/scale <= 448). Each layer's combined output scale, weight scale
+ * x act_scale[l] / act_scale[l+1] (the last layer: weight scale x
+ * act_scale[l]), must lie in 2^-126..2^127, else CYRUS_ERANGE. */
 typedef struct {
     const float* w[CYRUS_MAX_LAYERS];
     const float* b[CYRUS_MAX_LAYERS];

@@ -315,6 +315,15 @@ static int load_weights(cyrus_codebook* cb, const cyrus_weights* w, hipStream_t 
             a_scale[l] = w->act_scale[l];
             w_scale[l] = e4m3_weight_scale(w->w[l], (size_t)s.dims[l] * s.dims[l + 1]);
         }
+        // the kernels apply each layer's output scale (deq, times the next
+        // layer's inverse input scale for a hidden layer) as an E8M0 block
+        // scale, which holds the powers of two from 2^-126 to 2^127
+        for (int l = 0; l < s.n_layers; ++l) {
+            const float c = w_scale[l] * a_scale[l] / (l + 1 < s.n_layers ? a_scale[l + 1] : 1.f);
+            if (!(c >= 0x1p-126f && c <= 0x1p127f))
+                return fail(CYRUS_ERANGE, "layer %d: weight scale x act_scale[%d] / act_scale[%d] = %g is outside "
+                            "2^-126..2^127", l, l, l + 1, (double)c);
+        }
     }
     for (int l = 0; l < s.n_layers; ++l)
         for (size_t i = 0; i < (size_t)s.dims[l] * s.dims[l + 1]; ++i)

@@ -129,6 +129,26 @@ __device__ __forceinline__ void mma_pair<kFP8>(const uint4& a0, const uint4& a1,
     acc = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b, acc, 0, 0, 0, 127, 0, 127);
 }
 
+// acc += s (A B) for two consecutive chunks, s a power of two given as its
+// E8M0 code (the biased FP32 exponent). FP8 applies s through the block
+// scales of v_mfma_scale_f32_16x16x128_f8f6f4 (exact: a power of two);
+// FP32 and BF16 carry no scales (s = 1), so the code is ignored.
+template <int P>
+__device__ __forceinline__ void mma_pair_scaled(const uint4& a0, const uint4& a1, const uint4& b0, const uint4& b1,
+                                                floatx4& acc, int)
+{
+    mma_pair<P>(a0, a1, b0, b1, acc);
+}
+template <>
+__device__ __forceinline__ void mma_pair_scaled<kFP8>(const uint4& a0, const uint4& a1, const uint4& b0,
+                                                      const uint4& b1, floatx4& acc, int e8m0)
+{
+    const intx8 a = {(int)a0.x, (int)a0.y, (int)a0.z, (int)a0.w, (int)a1.x, (int)a1.y, (int)a1.z, (int)a1.w};
+    const intx8 b = {(int)b0.x, (int)b0.y, (int)b0.z, (int)b0.w, (int)b1.x, (int)b1.y, (int)b1.z, (int)b1.w};
+    acc = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b, acc, 0, 0, 0, e8m0, 0, 127);
+}
+__device__ __forceinline__ int e8m0_of(float pow2) { return (int)((__float_as_uint(pow2) >> 23) & 0xffu); }
+
 // ---------------------------------------------------------------------------
 // Gaussian policy head (Sec. IV-B). Philox4x32-10 (Salmon, Moraes, Dror and
 // Shaw, SC'11), from its definition: ten rounds of two 32x32->64 products of
@@ -272,10 +292,12 @@ __device__ __forceinline__ void store_act4<kBF16>(uint8_t* dst, float v0, float 
 template <>
 __device__ __forceinline__ void store_act4<kFP8>(uint8_t* dst, float v0, float v1, float v2, float v3)
 {
-    v0 = fminf(fmaxf(v0, 0.f), 448.f);
-    v1 = fminf(fmaxf(v1, 0.f), 448.f);
-    v2 = fminf(fmaxf(v2, 0.f), 448.f);
-    v3 = fminf(fmaxf(v3, 0.f), 448.f);
+    // median of (v, 0, 448): ReLU and saturation in one instruction (the
+    // inputs are finite)
+    v0 = __builtin_amdgcn_fmed3f(v0, 0.f, 448.f);
+    v1 = __builtin_amdgcn_fmed3f(v1, 0.f, 448.f);
+    v2 = __builtin_amdgcn_fmed3f(v2, 0.f, 448.f);
+    v3 = __builtin_amdgcn_fmed3f(v3, 0.f, 448.f);
     const int lo = __builtin_amdgcn_cvt_pk_fp8_f32(v0, v1, 0, false);
     *reinterpret_cast<uint32_t*>(dst) = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(v2, v3, lo, true);
 }

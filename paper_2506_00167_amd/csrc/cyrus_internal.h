@@ -8,6 +8,7 @@ namespace cyrus {
 
 constexpr int kWaves = 8;                 // waves per workgroup
 constexpr int kThreads = kWaves * 64;     // threads per workgroup
+constexpr int kXcds = 8;                  // accelerator complex dies, each with its own L2
 constexpr int kMaxLayers = 5;
 constexpr int kMaxUE = 32;
 constexpr int kLogitStride = kMaxUE + 1;  // LDS row stride of the logits (bank-conflict free)

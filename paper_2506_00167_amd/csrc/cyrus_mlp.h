@@ -26,12 +26,20 @@ __device__ __forceinline__ void hidden_layer(const DevTree& t, int l, const uint
     const int sin = t.in_pad[l] * es + 16;
     const int sout = t.out_pad[l] * es + 16;
     const guint4* wl = as_global(t.w[l]);
+    // The accumulators start at the bias, staged in the next layer's input
+    // scale, and the products enter in that scale too: c1 = deq times the
+    // next layer's inverse input scale is a power of two (1 outside FP8),
+    // applied exactly by the FP8 instruction's block scale. The epilogue is
+    // then the activation and the conversion alone.
+    const int sc = e8m0_of(t.deq[l] * t.inv_in_scale[l + 1]);
     floatx4 acc[T][RTT];
 #pragma unroll
-    for (int tt = 0; tt < T; ++tt)
+    for (int tt = 0; tt < T; ++tt) {
+        const floatx4 b4 = *reinterpret_cast<const floatx4*>(bias_l + (wave + kWaves * tt) * 16 + g * 4);
 #pragma unroll
         for (int rt = 0; rt < RTT; ++rt)
-            acc[tt][rt] = floatx4{0.f, 0.f, 0.f, 0.f};
+            acc[tt][rt] = b4;
+    }
     const guint4* wp[T];
 #pragma unroll
     for (int tt = 0; tt < T; ++tt)
@@ -47,8 +55,8 @@ __device__ __forceinline__ void hidden_layer(const DevTree& t, int l, const uint
         const int c_ = min((Q), max(npair - 1, 0)) * 2; /* clamped: past the end reloads the last pair */             \
         _Pragma("unroll") for (int tt = 0; tt < T; ++tt)                                                              \
         {                                                                                                              \
-            D0[tt] = gld(wp[tt] + (size_t)c_ * 64);                                                                          \
-            D1[tt] = gld(wp[tt] + (size_t)(c_ + 1) * 64);                                                                    \
+            D0[tt] = gld(wp[tt] + (size_t)c_ * 64);                                                                    \
+            D1[tt] = gld(wp[tt] + (size_t)(c_ + 1) * 64);                                                              \
         }                                                                                                              \
     }
     // B fragments: row tile rt + 1's pair is read from LDS while row tile
@@ -66,7 +74,7 @@ __device__ __forceinline__ void hidden_layer(const DevTree& t, int l, const uint
                 n1_ = *reinterpret_cast<const uint4*>(bq_ + (rt + 1) * 16 * sin + kc * es);                            \
             }                                                                                                          \
             __builtin_amdgcn_sched_barrier(0);                                                                         \
-            _Pragma("unroll") for (int tt = 0; tt < T; ++tt) mma_pair<P>(S0[tt], S1[tt], b0_, b1_, acc[tt][rt]);      \
+            _Pragma("unroll") for (int tt = 0; tt < T; ++tt) mma_pair_scaled<P>(S0[tt], S1[tt], b0_, b1_, acc[tt][rt], sc); \
             __builtin_amdgcn_sched_barrier(0);                                                                         \
         }                                                                                                              \
     }
@@ -85,7 +93,7 @@ __device__ __forceinline__ void hidden_layer(const DevTree& t, int l, const uint
         CYRUS_MMA_PAIRS(x0, x1, q)
 #undef CYRUS_LOAD_PAIR
 #undef CYRUS_MMA_PAIRS
-    if (nch & 1) {  // odd chunk count (FP32/BF16 first layer): one last chunk
+    if (P != kFP8 && (nch & 1)) {  // odd chunk count (FP32/BF16 first layer; FP8 pads to pairs): one last chunk
         const int c = nch - 1;
         const uint8_t* bq = bp + c * kc * es;
         uint4 a0[T];
@@ -100,20 +108,14 @@ __device__ __forceinline__ void hidden_layer(const DevTree& t, int l, const uint
                 mma_chunk<P>(a0[tt], b0, acc[tt][rt]);
         }
     }
-    // Epilogue in the next layer's input scale: the staged bias is already
-    // multiplied by it, and deq times it is exact (both are powers of two;
-    // 1 outside FP8), so fma(acc, c1, bias) equals the scaled (deq acc + b).
-    const float c1 = t.deq[l] * t.inv_in_scale[l + 1];
 #pragma unroll
     for (int tt = 0; tt < T; ++tt) {
         const int nt = wave + kWaves * tt;
-        const floatx4 bias = *reinterpret_cast<const floatx4*>(bias_l + nt * 16 + g * 4);
 #pragma unroll
         for (int rt = 0; rt < RTT; ++rt) {
             if (rt < art)
-                store_act4<P>(out + (rt * 16 + c16) * sout + (nt * 16 + g * 4) * es,
-                              fmaf(acc[tt][rt][0], c1, bias[0]), fmaf(acc[tt][rt][1], c1, bias[1]),
-                              fmaf(acc[tt][rt][2], c1, bias[2]), fmaf(acc[tt][rt][3], c1, bias[3]));
+                store_act4<P>(out + (rt * 16 + c16) * sout + (nt * 16 + g * 4) * es, acc[tt][rt][0], acc[tt][rt][1],
+                              acc[tt][rt][2], acc[tt][rt][3]);
         }
     }
 }
@@ -135,6 +137,8 @@ __device__ __forceinline__ void run_mlp(const DevTree& t, int nrows, uint8_t* bu
     uint8_t* in = bufA;
     uint8_t* out = bufB;
     for (int l = 0; l + 1 < t.n_layers; ++l) {
+        if (l > 0)
+            lds_barrier();  // the previous layer's outputs are complete and its inputs read
         const int T = (t.out_pad[l] >> 4) / kWaves;  // neuron tiles per wave (hidden widths are multiples of 128)
         switch (T) {
         case 1:
@@ -150,7 +154,6 @@ __device__ __forceinline__ void run_mlp(const DevTree& t, int nrows, uint8_t* bu
             hidden_layer<P, RTT, 4>(t, l, in, out, bias, art);
             break;
         }
-        lds_barrier();
         bias += t.out_pad[l];
         uint8_t* tmp = in;
         in = out;
@@ -159,10 +162,13 @@ __device__ __forceinline__ void run_mlp(const DevTree& t, int nrows, uint8_t* bu
     // Output layer. Wave w owns row tile w (RTT <= waves) and reduces over
     // the whole input in chunk order, so a row's logits do not depend on the
     // tile it was computed in. The wave's weight fragments arrive in groups
-    // of kPF chunks, the next group requested before the current one's MFMAs.
-    // Softmax head: the lanes write their logits to zl directly; Gaussian
-    // head: the raw outputs go through LDS, since a log-share needs output e
-    // and output E + e, which other lanes may hold.
+    // of kPF chunks, the next group requested before the current one's MFMAs;
+    // the first group is requested before the barrier that completes the
+    // last hidden layer. As in the hidden layers, the accumulators start at
+    // the bias and FP8 applies deq through the block scale. Softmax head: the
+    // lanes write their logits to zl directly; Gaussian head: the outputs go
+    // through LDS, since a log-share needs outputs e and E + e, which other
+    // lanes may hold.
     {
         const int l = t.n_layers - 1;
         const int nch = t.in_pad[l] / kc;
@@ -170,21 +176,29 @@ __device__ __forceinline__ void run_mlp(const DevTree& t, int nrows, uint8_t* bu
         const int opad = t.out_pad[l];
         const int ntile = opad >> 4;
         const int E = t.E, K = t.K;
-        const float deq = t.deq[l];
+        const int sc = e8m0_of(t.deq[l]);
         const bool gaussian = t.head == kGaussianHead;
         float* raw = reinterpret_cast<float*>(out);  // [RT][opad], Gaussian head
         const int rt = wave;
+        const guint4* wl = as_global(t.w[l]) + lane;
+        uint4 a[kPF], an[kPF];
         if (rt < art) {
-            const guint4* wl = as_global(t.w[l]);
+#pragma unroll
+            for (int j = 0; j < kPF; ++j)
+                a[j] = j < nch ? gld(wl + (size_t)j * 64) : uint4{0, 0, 0, 0};
+        }
+        lds_barrier();
+        if (rt < art) {
             const int row = rt * 16 + c16;
             const uint8_t* bp = in + row * sin + g * (kc / 4) * es;
             for (int nt = 0; nt < ntile; ++nt) {
-                floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-                const guint4* wp = wl + (size_t)nt * nch * 64 + lane;
-                uint4 a[kPF], an[kPF];
+                const guint4* wp = wl + (size_t)nt * nch * 64;
+                if (nt > 0) {
 #pragma unroll
-                for (int j = 0; j < kPF; ++j)
-                    a[j] = j < nch ? gld(wp + (size_t)j * 64) : uint4{0, 0, 0, 0};
+                    for (int j = 0; j < kPF; ++j)
+                        a[j] = j < nch ? gld(wp + (size_t)j * 64) : uint4{0, 0, 0, 0};
+                }
+                floatx4 acc = *reinterpret_cast<const floatx4*>(bias + nt * 16 + g * 4);
                 for (int cb = 0; cb < nch; cb += kPF) {
 #pragma unroll
                     for (int j = 0; j < kPF; ++j)
@@ -195,8 +209,8 @@ __device__ __forceinline__ void run_mlp(const DevTree& t, int nrows, uint8_t* bu
                         if (c + 1 < nch) {
                             const uint4 b0 = *reinterpret_cast<const uint4*>(bp + c * kc * es);
                             const uint4 b1 = *reinterpret_cast<const uint4*>(bp + (c + 1) * kc * es);
-                            mma_pair<P>(a[j], a[j + 1], b0, b1, acc);
-                        } else if (c < nch) {
+                            mma_pair_scaled<P>(a[j], a[j + 1], b0, b1, acc, sc);
+                        } else if (c < nch) {  // FP32 and BF16 only: FP8 inputs are padded to chunk pairs
                             mma_chunk<P>(a[j], *reinterpret_cast<const uint4*>(bp + c * kc * es), acc);
                         }
                     }
@@ -207,11 +221,10 @@ __device__ __forceinline__ void run_mlp(const DevTree& t, int nrows, uint8_t* bu
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const int e = nt * 16 + g * 4 + i;
-                    const float z = acc[i] * deq + bias[e];
                     if (gaussian)
-                        raw[row * opad + e] = z;
+                        raw[row * opad + e] = acc[i];
                     else if (row < nrows && e < E)
-                        zl[row * kLogitStride + e] = z;
+                        zl[row * kLogitStride + e] = acc[i];
                 }
             }
         }

@@ -309,8 +309,20 @@ __global__ __launch_bounds__(kThreads) void level_kernel_batch(const DevTree* __
         }
     }
     lds_barrier();
+    // XCD-aware tile order. Workgroups are dispatched to the eight XCDs in
+    // turn, so workgroup w runs on XCD w % 8; each XCD takes a contiguous
+    // eighth of the launch's tiles, and since a cell's tiles are contiguous,
+    // its L2 holds the weights of about an eighth of the cells rather than
+    // streaming all of them.
     const int total = s_prefix[n];
-    for (int b = blockIdx.x; b < total; b += gridDim.x) {
+    int b0 = blockIdx.x, bstep = gridDim.x, bend = total;
+    if (gridDim.x % kXcds == 0) {
+        const int x = blockIdx.x % kXcds;
+        b0 = (int)((int64_t)total * x / kXcds) + blockIdx.x / kXcds;
+        bstep = gridDim.x / kXcds;
+        bend = (int)((int64_t)total * (x + 1) / kXcds);
+    }
+    for (int b = b0; b < bend; b += bstep) {
         int lo = 0, hi = n - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
