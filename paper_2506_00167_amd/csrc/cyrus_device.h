@@ -237,10 +237,12 @@ __device__ __forceinline__ uint32_t bf16x2_bits(float v0, float v1)
 // explicit saturation at +-448.
 __device__ __forceinline__ uint32_t e4m3x4(float v0, float v1, float v2, float v3)
 {
-    v0 = fminf(fmaxf(v0, -448.f), 448.f);
-    v1 = fminf(fmaxf(v1, -448.f), 448.f);
-    v2 = fminf(fmaxf(v2, -448.f), 448.f);
-    v3 = fminf(fmaxf(v3, -448.f), 448.f);
+    // saturate to E4M3's finite range (median of three: one instruction; the
+    // inputs are finite)
+    v0 = __builtin_amdgcn_fmed3f(v0, -448.f, 448.f);
+    v1 = __builtin_amdgcn_fmed3f(v1, -448.f, 448.f);
+    v2 = __builtin_amdgcn_fmed3f(v2, -448.f, 448.f);
+    v3 = __builtin_amdgcn_fmed3f(v3, -448.f, 448.f);
     int lo = __builtin_amdgcn_cvt_pk_fp8_f32(v0, v1, 0, false);
     return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(v2, v3, lo, true);
 }
@@ -289,17 +291,21 @@ __device__ __forceinline__ void store_act4<kBF16>(uint8_t* dst, float v0, float 
     store4<kBF16>(dst, fmaxf(v0, 0.f), fmaxf(v1, 0.f), fmaxf(v2, 0.f), fmaxf(v3, 0.f), 1.f);
 }
 
-template <>
-__device__ __forceinline__ void store_act4<kFP8>(uint8_t* dst, float v0, float v1, float v2, float v3)
+// ReLU(v), saturated at 448, as four E4M3 bytes (v0 in the low byte).
+__device__ __forceinline__ uint32_t act4_e4m3(float v0, float v1, float v2, float v3)
 {
-    // median of (v, 0, 448): ReLU and saturation in one instruction (the
-    // inputs are finite)
     v0 = __builtin_amdgcn_fmed3f(v0, 0.f, 448.f);
     v1 = __builtin_amdgcn_fmed3f(v1, 0.f, 448.f);
     v2 = __builtin_amdgcn_fmed3f(v2, 0.f, 448.f);
     v3 = __builtin_amdgcn_fmed3f(v3, 0.f, 448.f);
     const int lo = __builtin_amdgcn_cvt_pk_fp8_f32(v0, v1, 0, false);
-    *reinterpret_cast<uint32_t*>(dst) = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(v2, v3, lo, true);
+    return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(v2, v3, lo, true);
+}
+
+template <>
+__device__ __forceinline__ void store_act4<kFP8>(uint8_t* dst, float v0, float v1, float v2, float v3)
+{
+    *reinterpret_cast<uint32_t*>(dst) = act4_e4m3(v0, v1, v2, v3);
 }
 
 // Store one activation (feature assembly, padding).

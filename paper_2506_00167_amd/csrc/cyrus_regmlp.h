@@ -40,6 +40,10 @@ struct WaveWeights {
     // wave's own last-hidden-layer tiles in the 16x16x16 MFMA layout (lane
     // (g, i): W_o[i][16 nt + 4g .. 16 nt + 4g + 3]), fed from registers
     uint2 wo16[(P == kBF16 && NHH > 0) ? T : 1];
+    // FP8 with a hidden->hidden layer: the same, for 16x16x32 FP8 MFMAs over
+    // pairs of the wave's tiles (lane (g, i): W_o[i][16 nt + 4g .. + 3] of
+    // tile 2p in the low word, of tile 2p + 1 (or zeros) in the high word)
+    uint2 wo8[(P == kFP8 && NHH > 0) ? (T + 1) / 2 : 1];
 };
 
 template <int P, int T, int CH1, int CHH, int NHH>
@@ -83,6 +87,24 @@ __device__ __forceinline__ void load_weights(const DevTree& t, WaveWeights<P, T,
             const int nt = wave + kWaves * tt;
             const int src = i + 16 * (2 * (nt & 1) + (g >> 1));
             W.wo16[tt] = *reinterpret_cast<const uint2*>(gob + ((size_t)(nt >> 1) * 64 + src) * 16 + 8 * (g & 1));
+        }
+    }
+    if constexpr (P == kFP8 && NHH > 0) {
+        // W_o[i][k], k = 16 nt + 4g + j, sits in 64-wide chunk k / 64 at lane
+        // i + 16 ((k % 64) / 16), byte k % 16 = 4g + j: one word per tile
+        const uint8_t* gob = t.w[NHH + 1];
+        const int g = lane >> 4, i = lane & 15;
+#pragma unroll
+        for (int q = 0; q < (T + 1) / 2; ++q) {
+            uint32_t w2[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int tt = 2 * q + h, nt = wave + kWaves * tt;
+                w2[h] = tt < T ? *reinterpret_cast<const uint32_t*>(
+                                     gob + ((size_t)(nt >> 2) * 64 + (nt & 3) * 16 + i) * 16 + 4 * g)
+                               : 0u;
+            }
+            W.wo8[q] = uint2{w2[0], w2[1]};
         }
     }
 }
@@ -152,32 +174,53 @@ __device__ __forceinline__ void layer_acc(const uint4 (&A)[T][NCH], int nch, con
 #pragma unroll
         for (int rt = 0; rt < kRTT; ++rt)
             acc[tt][rt] = floatx4{0.f, 0.f, 0.f, 0.f};
+    static_assert(P != kFP8, "FP8 layers go through layer_acc_fp8");
     const uint8_t* bp = in + c16 * sin + g * (kc / 4) * es;
-    if constexpr (P == kFP8 && NCH % 2 == 0) {
-        // chunk pairs: one 16x16x128 MFMA per pair (nch is even for FP8)
+    layer_acc_dispatch<P, T, NCH, kRTT>(A, nch, bp, sin, art, acc);
+}
+
+// FP8 layer body over NT live row tiles: a layer has at most two chunk
+// pairs, so every B fragment of it is read before the first MFMA; acc holds
+// the starting values, and the products enter scaled by 2^(sc - 127).
+template <int T, int NCH, int NT>
+__device__ __forceinline__ void layer_acc_fp8_tiles(const uint4 (&A)[T][NCH], const uint8_t* bp, int sin, int sc,
+                                                    floatx4 (&acc)[T][Rows<kFP8>::kRTT])
+{
+    constexpr int kc = Traits<kFP8>::kChunk, NP = NCH / 2;
+    static_assert(NCH % 2 == 0, "FP8 inputs are padded to chunk pairs");
+    uint4 b0[NP][NT], b1[NP][NT];
 #pragma unroll
-        for (int c = 0; c < NCH; c += 2) {
-            if (c < nch) {
+    for (int q = 0; q < NP; ++q)
 #pragma unroll
-                for (int rt = 0; rt < kRTT; ++rt) {
-                    if (rt < art) {
-                        const uint8_t* brow = bp + rt * 16 * sin + c * kc * es;
-                        const uint4 b0 = *reinterpret_cast<const uint4*>(brow);
-                        const uint4 b1 = *reinterpret_cast<const uint4*>(brow + kc * es);
-#pragma unroll
-                        for (int tt = 0; tt < T; ++tt)
-                            mma_pair<P>(A[tt][c], A[tt][c + 1], b0, b1, acc[tt][rt]);
-                    }
-                }
-            }
+        for (int rt = 0; rt < NT; ++rt) {
+            b0[q][rt] = *reinterpret_cast<const uint4*>(bp + rt * 16 * sin + 2 * q * kc);
+            b1[q][rt] = *reinterpret_cast<const uint4*>(bp + rt * 16 * sin + (2 * q + 1) * kc);
         }
-    } else {
-        layer_acc_dispatch<P, T, NCH, kRTT>(A, nch, bp, sin, art, acc);
-    }
+#pragma unroll
+    for (int q = 0; q < NP; ++q)
+#pragma unroll
+        for (int rt = 0; rt < NT; ++rt)
+#pragma unroll
+            for (int tt = 0; tt < T; ++tt)
+                mma_pair_scaled<kFP8>(A[tt][2 * q], A[tt][2 * q + 1], b0[q][rt], b1[q][rt], acc[tt][rt], sc);
+}
+
+template <int T, int NCH, int NT>
+__device__ __forceinline__ void layer_acc_fp8(const uint4 (&A)[T][NCH], const uint8_t* bp, int sin, int art, int sc,
+                                              floatx4 (&acc)[T][Rows<kFP8>::kRTT])
+{
+    if (art == NT)
+        layer_acc_fp8_tiles<T, NCH, NT>(A, bp, sin, sc, acc);
+    else if constexpr (NT > 1)
+        layer_acc_fp8<T, NCH, NT - 1>(A, bp, sin, art, sc, acc);
 }
 
 // One layer with register-resident A fragments: out = act(A * in) for the
-// wave's T neuron tiles over `art` row tiles.
+// wave's T neuron tiles over `art` row tiles. FP8: the output in the next
+// layer's input scale is ReLU(deq A in + b) inv_next = ReLU(c1 A in +
+// b inv_next) with c1 = deq inv_next a power of two, so the accumulators
+// start at b inv_next, the products enter through the MFMA block scale c1,
+// and the epilogue is the clamp and the conversion alone.
 template <int P, int T, int NCH>
 __device__ __forceinline__ void layer_regs(const uint4 (&A)[T][NCH], int nch, const uint8_t* in, int sin,
                                            uint8_t* out, int sout, const float* bias, float deq, float inv_next,
@@ -185,18 +228,41 @@ __device__ __forceinline__ void layer_regs(const uint4 (&A)[T][NCH], int nch, co
 {
     constexpr int es = Traits<P>::kEsize, kRTT = Rows<P>::kRTT;
     floatx4 acc[T][kRTT];
-    layer_acc<P, T, NCH>(A, nch, in, sin, art, g, c16, acc);
+    if constexpr (P == kFP8) {
+        const int sc = e8m0_of(deq * inv_next);
 #pragma unroll
-    for (int tt = 0; tt < T; ++tt) {
-        const int nt = wave + kWaves * tt;
-        const float* bb = bias + nt * 16 + g * 4;
-        const float b0 = bb[0], b1 = bb[1], b2 = bb[2], b3 = bb[3];
+        for (int tt = 0; tt < T; ++tt) {
+            const float* bb = bias + (wave + kWaves * tt) * 16 + g * 4;
+            const floatx4 b4 = {bb[0] * inv_next, bb[1] * inv_next, bb[2] * inv_next, bb[3] * inv_next};
 #pragma unroll
-        for (int rt = 0; rt < kRTT; ++rt) {
-            if (rt < art) {
-                store4<P>(out + (rt * 16 + c16) * sout + (nt * 16 + g * 4) * es,
-                          fmaxf(acc[tt][rt][0] * deq + b0, 0.f), fmaxf(acc[tt][rt][1] * deq + b1, 0.f),
-                          fmaxf(acc[tt][rt][2] * deq + b2, 0.f), fmaxf(acc[tt][rt][3] * deq + b3, 0.f), inv_next);
+            for (int rt = 0; rt < kRTT; ++rt)
+                acc[tt][rt] = b4;
+        }
+        layer_acc_fp8<T, NCH, kRTT>(A, in + c16 * sin + g * (Traits<P>::kChunk / 4) * es, sin, art, sc, acc);
+#pragma unroll
+        for (int tt = 0; tt < T; ++tt) {
+            const int nt = wave + kWaves * tt;
+#pragma unroll
+            for (int rt = 0; rt < kRTT; ++rt)
+                if (rt < art)
+                    store_act4<P>(out + (rt * 16 + c16) * sout + (nt * 16 + g * 4) * es, acc[tt][rt][0],
+                                  acc[tt][rt][1], acc[tt][rt][2], acc[tt][rt][3]);
+        }
+    } else {
+        layer_acc<P, T, NCH>(A, nch, in, sin, art, g, c16, acc);
+#pragma unroll
+        for (int tt = 0; tt < T; ++tt) {
+            const int nt = wave + kWaves * tt;
+            const float* bb = bias + nt * 16 + g * 4;
+            const float b0 = bb[0], b1 = bb[1], b2 = bb[2], b3 = bb[3];
+#pragma unroll
+            for (int rt = 0; rt < kRTT; ++rt) {
+                if (rt < art) {
+                    store4<P>(out + (rt * 16 + c16) * sout + (nt * 16 + g * 4) * es,
+                              fmaxf(acc[tt][rt][0] * deq + b0, 0.f), fmaxf(acc[tt][rt][1] * deq + b1, 0.f),
+                              fmaxf(acc[tt][rt][2] * deq + b2, 0.f), fmaxf(acc[tt][rt][3] * deq + b3, 0.f),
+                              inv_next);
+                }
             }
         }
     }
@@ -258,6 +324,53 @@ __device__ __forceinline__ float* mlp_mfma(const DevTree& t, const WaveWeights<P
                 }
         }
         // bufA (the inputs, consumed before the last barrier) takes the partials
+        float* part = reinterpret_cast<float*>(bufA);
+#pragma unroll
+        for (int rt = 0; rt < kRTT; ++rt)
+            if (rt < art)
+                *reinterpret_cast<floatx4*>(part + (size_t)(wave * kRT + rt * 16 + c16) * 16 + g * 4) = acc[rt];
+        lds_barrier();
+        return part;
+    }
+    if constexpr (P == kFP8 && NHH > 0) {
+        // The last hidden layer feeds the output layer from registers, as
+        // above: its accumulators start at b inv_next and take the products
+        // through the block scale, so ReLU and the E4M3 rounding (what an LDS
+        // store would keep) are the whole epilogue; lane (g, c16) then holds
+        // the E4M3 activations of neurons 16 nt + 4g .. + 3 of its row for each
+        // of its tiles, the B fragment of a 16x16x32 FP8 step over a pair of
+        // tiles, with W.wo8 as the matching A fragment.
+        const float inv_next = t.inv_in_scale[2];
+        const int sc = e8m0_of(t.deq[1] * inv_next);
+        floatx4 hacc[T][kRTT];
+#pragma unroll
+        for (int tt = 0; tt < T; ++tt) {
+            const float* bb = bias + bias_off[1] + (wave + kWaves * tt) * 16 + g * 4;
+            const floatx4 b4 = {bb[0] * inv_next, bb[1] * inv_next, bb[2] * inv_next, bb[3] * inv_next};
+#pragma unroll
+            for (int rt = 0; rt < kRTT; ++rt)
+                hacc[tt][rt] = b4;
+        }
+        layer_acc_fp8<T, CHH, kRTT>(W.wh, bufB + c16 * sh + g * (kc / 4) * es, sh, art, sc, hacc);
+        floatx4 acc[kRTT];
+#pragma unroll
+        for (int rt = 0; rt < kRTT; ++rt)
+            acc[rt] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int rt = 0; rt < kRTT; ++rt)
+            if (rt < art) {
+#pragma unroll
+                for (int q = 0; q < (T + 1) / 2; ++q) {
+                    const uint32_t lo = act4_e4m3(hacc[2 * q][rt][0], hacc[2 * q][rt][1], hacc[2 * q][rt][2],
+                                                  hacc[2 * q][rt][3]);
+                    const uint32_t hi = 2 * q + 1 < T ? act4_e4m3(hacc[2 * q + 1][rt][0], hacc[2 * q + 1][rt][1],
+                                                                  hacc[2 * q + 1][rt][2], hacc[2 * q + 1][rt][3])
+                                                      : 0u;
+                    const long a = (long)(((uint64_t)W.wo8[q].y << 32) | W.wo8[q].x);
+                    const long b = (long)(((uint64_t)hi << 32) | lo);
+                    acc[rt] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, acc[rt], 0, 0, 0);
+                }
+            }
         float* part = reinterpret_cast<float*>(bufA);
 #pragma unroll
         for (int rt = 0; rt < kRTT; ++rt)

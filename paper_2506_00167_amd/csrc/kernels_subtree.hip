@@ -255,37 +255,40 @@ struct SubtreeSmem {
 
 // Per-node input rows for `nrows` nodes: [c/64 | tau/8 | k/8], zero padded
 // to in_pad_d, with state c from state_of(row), level tau and arrival
-// arrival_of(row). One thread per input (at most 64 per row).
+// arrival_of(row). One thread per four consecutive inputs of a row (so a
+// single row still spreads over many lanes); groups past the E + 2 values
+// are zeros.
 template <int P, int CH1, class StateOf, class ArrivalOf>
 __device__ __forceinline__ void write_features(const DevTree& t, const SubtreeSmem& sm, int nrows, int tau,
                                                StateOf state_of, ArrivalOf arrival_of)
 {
     constexpr int es = Traits<P>::kEsize, in0 = CH1 * Traits<P>::kChunk, s0 = in0 * es + 16;
-    constexpr int tpr = in0 < 64 ? in0 : 64;  // threads per row
+    constexpr int ngr = in0 / 4;  // groups of four inputs per row
+    static_assert(kThreads % ngr == 0, "whole rows per pass");
     const int E = t.E;
     // MFMA passes read whole 16-row tiles: rows past nrows are zeroed so they
     // stay finite (each output row depends on its own input row only)
     const int nrows_pad = ((nrows + 15) >> 4) << 4;
     const float inv0 = t.inv_in_scale[0], ftau = (float)tau * (1.f / 8.f);
-    const int f0 = threadIdx.x % tpr;
-    for (int row = threadIdx.x / tpr; row < nrows_pad; row += kThreads / tpr) {
-        const bool live = row < nrows;
-        const uint8_t* st = live ? state_of(row) : nullptr;
-        const float fk = live ? (float)arrival_of(row) * (1.f / 8.f) : 0.f;
-        uint8_t* dst = sm.bufA + row * s0;
+    const int grp = threadIdx.x % ngr, fb = grp * 4;
+    for (int row = threadIdx.x / ngr; row < nrows_pad; row += kThreads / ngr) {
+        float v[4] = {0.f, 0.f, 0.f, 0.f};
+        if (row < nrows && fb <= E + 1) {
+            const uint8_t* st = state_of(row);
+            const float fk = (float)arrival_of(row) * (1.f / 8.f);
+            // every state byte is read, and blended in by a multiply, so the
+            // reads are issued together rather than each behind a branch
+            uint32_t sb[4];
 #pragma unroll
-        for (int f = f0; f < in0; f += tpr) {
-            float v = 0.f;
-            if (live) {
-                if (f < E)
-                    v = (float)st[f] * (1.f / 64.f);
-                else if (f == E)
-                    v = ftau;
-                else if (f == E + 1)
-                    v = fk;
+            for (int j = 0; j < 4; ++j)
+                sb[j] = st[min(fb + j, E - 1)];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int f = fb + j;
+                v[j] = (float)sb[j] * (f < E ? 1.f / 64.f : 0.f) + (f == E ? ftau : 0.f) + (f == E + 1 ? fk : 0.f);
             }
-            store1<P>(dst + f * es, v, inv0);
         }
+        store4<P>(sm.bufA + row * s0 + fb * es, v[0], v[1], v[2], v[3], inv0);
     }
 }
 
