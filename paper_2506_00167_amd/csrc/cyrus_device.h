@@ -546,11 +546,14 @@ __device__ __forceinline__ int enforce_group(int E, int e, float z, int R, int r
     bool capped = !live;
     float s = 0.f;
     for (int pass = 0; pass <= G; ++pass) {
-        const float rem = (float)T - group_sum<G>((live && capped) ? (float)R : 0.f);
+        // pass 0 caps only the padding lanes, which add no R: rem is T
+        const float rem = pass == 0 ? (float)T : (float)T - group_sum<G>((live && capped) ? (float)R : 0.f);
         const float psum = group_sum<G>(capped ? 0.f : p);
         s = rem / psum;
         const bool grow = !capped && s * p >= (float)R;
-        if (group_isum<G>(grow ? 1 : 0) == 0)
+        // the loop ends when no lane of the wave grows: a group that has
+        // settled repeats its last pass with the same result
+        if (__ballot(grow) == 0)
             break;
         capped = capped || grow;
     }
@@ -640,11 +643,14 @@ __device__ __forceinline__ int enforce_dpp(int E, int e, float z, int R, int rsu
     bool capped = !live;
     float s = 0.f;
     for (int pass = 0; pass <= G; ++pass) {
-        const float rem = (float)T - dsum<G>((live && capped) ? (float)R : 0.f);
+        // pass 0 caps only the padding lanes, which add no R: rem is T
+        const float rem = pass == 0 ? (float)T : (float)T - dsum<G>((live && capped) ? (float)R : 0.f);
         const float psum = dsum<G>(capped ? 0.f : p);
         s = rem / psum;
         const bool grow = !capped && s * p >= (float)R;
-        if (disum<G>(grow ? 1 : 0) == 0)
+        // the loop ends when no lane of the wave grows: a group that has
+        // settled repeats its last pass with the same result
+        if (__ballot(grow) == 0)
             break;
         capped = capped || grow;
     }
