@@ -558,7 +558,12 @@ def main():
         "serving": serving_res,
     }
     if "bf16" in legs:
+        # back-to-back builds, each with its completion event (what a caller
+        # sees); and the kernels alone, from the rocprofv3 traces of the same
+        # sources (null when they were taken on other sources)
         out["bf16_vs_fp32_speedup"] = legs["bf16"]["nodes_per_s"] / head["nodes_per_s"]
+        pb = legs["bf16"].get("profiled_kernel_us")
+        out["bf16_vs_fp32_speedup_kernel_time"] = prof_us / pb if prof_us and pb else None
     if not args.no_cpu:
         threads = args.cpu_threads or min(16, len(os.sched_getaffinity(0)))
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds, threads, stream)
