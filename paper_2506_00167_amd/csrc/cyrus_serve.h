@@ -67,6 +67,7 @@ struct ServeCtl {
     int32_t quit;     // the control workgroup has exited: workers leave when idle
     int32_t hi;       // 1 + the highest slot index admitted so far
     uint32_t wepoch;  // latest weight-refresh epoch admitted
+    uint32_t opened;  // bumped after each level that others may claim tiles of is opened
 };
 
 // Pinned host memory shared with the worker.

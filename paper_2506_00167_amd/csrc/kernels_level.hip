@@ -364,11 +364,18 @@ __global__ __launch_bounds__(kThreads) void level_kernel_batch(const DevTree* __
 // and evict the actors' weights, which every tile reads through the caches; it
 // is taken only when the host reports a weight refresh (wepoch).
 //
-// Exits: the host's stop flag; the control workgroup leaves after idle_ticks
-// of wall-clock time with no request in flight and none in the ring (it then
-// sets quit), or after stall_ticks with requests in flight and none finishing;
-// the tile workgroups leave when they find no work and quit or stop is set, or
-// after stall_ticks idle.
+// Idle tile workgroups poll one counter (opened), which the control workgroup
+// bumps after admitting a request and a workgroup that opens a level of
+// several tiles bumps after publishing it; they scan the claim words only
+// when it has changed since their last fruitless scan, or right after a tile.
+// (Scanning every slot on every poll, each a load past the per-XCD caches,
+// kept the fabric busy enough to slow the loads of the workgroups at work.)
+//
+// Exits: the host's stop flag, which only the control workgroup reads; it
+// leaves on it, after idle_ticks of wall-clock time with no request in
+// flight and none in the ring, or after stall_ticks with requests in flight
+// and none finishing, and then sets quit; the tile workgroups leave when they
+// find no work and quit is set, or after stall_ticks idle.
 
 __device__ __forceinline__ uint32_t sys_load_u32(const uint32_t* p)
 {
@@ -457,6 +464,8 @@ __device__ void serve_control(const ServeArgs& a, int* sh)
                 __hip_atomic_fetch_max(&a.ctl->hi, slot + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __builtin_amdgcn_s_waitcnt(0);
                 dev_store(&sc.claim, serve_claim_word(gen, 1, nt1));
+                __builtin_amdgcn_s_waitcnt(0);  // the claim word is visible before the bump
+                __hip_atomic_fetch_add(&a.ctl->opened, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 sys_store_u32(&a.host->consumed, head + 1);
             }
             ++head;
@@ -540,25 +549,36 @@ __global__ __launch_bounds__(kThreads) void serve_kernel(ServeArgs a, const Serv
     uint64_t since = wall_clock64();
     int backoff = 1;      // idle sleep in units of about 64 cycles, doubled up to 64
     int cont = 0;         // the previous tile opened the next level and kept its tile 0
+    int worked = 1;       // the last pass ran a tile: scan again whatever opened says
+    uint32_t seen = 0;    // opened as read before the last fruitless scan
     int slot = 0, tau = 0, tile = 0, rec = 0, nt = 0, M = 0;
     uint32_t gen = 0;
     for (;;) {
         if (!cont) {
-            if (tid < 64)
-                serve_claim(a, sh);
+            if (tid == 0) {
+                sh[8] = (int)dev_load(&a.ctl->opened);
+                sh[9] = dev_load(&a.ctl->quit);
+            }
+            __syncthreads();
+            const uint32_t op = (uint32_t)sh[8];
+            const int quit = sh[9];
+            __syncthreads();
+            if (worked || op != seen) {
+                seen = op;  // read before the scan: a level opened after it changes opened
+                if (tid < 64)
+                    serve_claim(a, sh);
+            } else if (tid == 0) {
+                sh[0] = -1;
+            }
             __syncthreads();
             slot = sh[0];
             tau = sh[1];
             tile = sh[2];
             gen = (uint32_t)sh[3];
             __syncthreads();
+            worked = slot >= 0;
             if (slot < 0) {
-                if (tid == 0)
-                    sh[3] = dev_load(&a.ctl->quit) | (int)sys_load_u32(&a.host->stop);
-                __syncthreads();
-                const int leave = sh[3];
-                __syncthreads();
-                if (leave || wall_clock64() - since > a.stall_ticks)
+                if (quit || wall_clock64() - since > a.stall_ticks)
                     break;
                 for (int i = 0; i < backoff; ++i)
                     __builtin_amdgcn_s_sleep(1);
@@ -606,6 +626,10 @@ __global__ __launch_bounds__(kThreads) void serve_kernel(ServeArgs a, const Serv
                     dev_store(&sc.done, 0u);
                     __builtin_amdgcn_s_waitcnt(0);
                     dev_store(&sc.claim, serve_claim_word(gen, tau + 1, nt_next) + 1);
+                    if (nt_next > 1) {  // tiles for others: wake the idle workgroups
+                        __builtin_amdgcn_s_waitcnt(0);
+                        __hip_atomic_fetch_add(&a.ctl->opened, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
                     next = 1;
                     sh[6] = nt_next;
                 } else {
