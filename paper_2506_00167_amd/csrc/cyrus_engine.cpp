@@ -114,6 +114,7 @@ struct Request {
     int rslot = -1;     // resident worker: slot of the request
     uint32_t gen = 0;   // resident worker: admission generation (nonzero, 20 bits)
     bool copying = false;  // resident worker: codebook copy to the host pool enqueued
+    bool device_copy = false;  // resident worker: the worker writes the codebook to the host pool
 };
 
 size_t slot_bytes()
@@ -416,13 +417,33 @@ int replan(cyrus_engine* e)
     return CYRUS_OK;
 }
 
+// Request running[i] has its codebook in its host block: done.
+void finish_resident(cyrus_engine* e, size_t i)
+{
+    Request* r = e->running[i];
+    r->status = CYRUS_REQ_DONE;
+    r->t_done = now_us();
+    r->cell->engine_refs[r->wslot]--;
+    release_request_device(e, r);
+    e->free_rslots.push_back(r->rslot);
+    e->newly_done.push_back(r);
+    e->counters[1]++;
+    e->running[i] = e->running.back();
+    e->running.pop_back();
+}
+
 int retire_resident(cyrus_engine* e)
 {
     for (size_t i = 0; i < e->running.size();) {
         Request* r = e->running[i];
         if (!r->copying) {
             // the worker has finished the tree: its codebook (device pool) goes to
-            // the request's block of the host pool on the copy stream
+            // the request's block of the host pool on the copy stream, unless
+            // the worker has delivered it there itself
+            if (host_load(&e->h_shared->finished[r->rslot]) == r->gen && r->device_copy) {
+                finish_resident(e, i);
+                continue;
+            }
             if (host_load(&e->h_shared->finished[r->rslot]) == r->gen) {
                 const Shape& s = codebook_shape(r->cell);
                 hipError_t err = hipMemcpyAsync(e->hpool + r->host_off, e->dpool + r->dev_off, (size_t)s.nodes * s.E,
@@ -443,15 +464,7 @@ int retire_resident(cyrus_engine* e)
         }
         if (q != hipSuccess)
             return hip_err(q, "hipEventQuery(codebook copy)");
-        r->status = CYRUS_REQ_DONE;
-        r->t_done = now_us();
-        r->cell->engine_refs[r->wslot]--;
-        release_request_device(e, r);
-        e->free_rslots.push_back(r->rslot);
-        e->newly_done.push_back(r);
-        e->counters[1]++;
-        e->running[i] = e->running.back();
-        e->running.pop_back();
+        finish_resident(e, i);
     }
     return CYRUS_OK;
 }
@@ -532,7 +545,11 @@ int admit_resident(cyrus_engine* e)
         q.slot = r->rslot;
         q.gen = r->gen;
         q.wepoch = e->wepoch;
-        q.pad = 0;
+        // a small codebook is delivered by the worker into the request's host block
+        const size_t cb_bytes = (size_t)s.nodes * s.E;
+        r->device_copy = cb_bytes <= kServeDeviceCopyBytes;
+        q.cb_words = r->device_copy ? (uint32_t)((cb_bytes + 3) / 4) : 0u;
+        q.cb_host = r->device_copy ? (uint64_t)(uintptr_t)(e->hpool_dev + r->host_off) : 0u;
         std::memset(q.ue, 0, sizeof q.ue);
         std::memcpy(q.ue, r->ue.data(), r->ue.size() * 4);
         std::atomic_thread_fence(std::memory_order_release);

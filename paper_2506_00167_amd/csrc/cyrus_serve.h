@@ -17,16 +17,19 @@ constexpr int kServeSlots = 128;  // requests in flight (engine slots)
 
 // One request as the host hands it over (pinned ring entry) and as the device
 // keeps it (record table): the tree descriptor (t.ue is set by the device to
-// this record's UE copy, t.alloc points at the pinned codebook mirror,
-// t.state at the request's device state array), the row tiles of each level
-// and the admission generation (nonzero, 20 bits).
+// this record's UE copy; t.alloc and t.state point at the request's codebook
+// and node states in the device pool), the row tiles of each level, the
+// admission generation (nonzero, 20 bits) and, for a small codebook, where
+// the worker itself delivers it in the pinned pool.
+constexpr uint32_t kServeDeviceCopyBytes = 128 * 1024;  // larger codebooks go by copy engine
 struct alignas(64) ServeRequest {
     DevTree t;
     int32_t ntiles[8];  // [tau], tau = 1..M
     int32_t slot;
     uint32_t gen;
     uint32_t wepoch;    // weight-refresh epoch of the host at admission
-    int32_t pad;
+    uint32_t cb_words;  // codebook words the worker copies to cb_host (0: the host copies it)
+    uint64_t cb_host;   // device address of the request's codebook block in the pinned pool
     int32_t ue[3 * kMaxUE];
 };
 

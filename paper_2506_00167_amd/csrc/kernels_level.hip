@@ -616,7 +616,7 @@ __global__ __launch_bounds__(kThreads) void serve_kernel(ServeArgs a, const Serv
         __syncthreads();
         if (tid == 0) {
             ServeSlotCtl& sc = a.ctl->slot[slot];
-            int next = 0;
+            int next = 0, last = 0;
             const uint32_t prev = __hip_atomic_fetch_add(&sc.done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (prev + 1 == (uint32_t)nt) {
                 if (tau < M) {
@@ -633,13 +633,45 @@ __global__ __launch_bounds__(kThreads) void serve_kernel(ServeArgs a, const Serv
                     next = 1;
                     sh[6] = nt_next;
                 } else {
-                    dev_store(&sc.claim, serve_claim_word(gen, 0, 0));
-                    __hip_atomic_fetch_add(&a.ctl->active, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    __builtin_amdgcn_s_waitcnt(0);
-                    sys_store_u32(&a.host->finished[slot], gen);
+                    last = 1;  // the request is complete: finished below
                 }
             }
             sh[7] = next;
+            sh[10] = last;
+        }
+        __syncthreads();
+        if (sh[10]) {
+            // Every tile's stores completed before its count, so the whole
+            // codebook is in device memory. A small one is delivered here,
+            // into the request's block of the pinned pool (coherent word
+            // loads, system-scope stores), before the finished flag.
+            const ServeRequest& q = recs[rec];
+            const uint32_t words = q.cb_words;
+            const uint32_t* src = reinterpret_cast<const uint32_t*>(q.t.alloc);
+            uint32_t* dst = reinterpret_cast<uint32_t*>(q.cb_host);
+            for (uint32_t i0 = 0; i0 < words; i0 += 8 * kThreads) {
+                uint32_t v[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const uint32_t i = i0 + j * kThreads + tid;
+                    v[j] = i < words ? dev_load(src + i) : 0u;
+                }
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const uint32_t i = i0 + j * kThreads + tid;
+                    if (i < words)
+                        sys_store_u32(dst + i, v[j]);
+                }
+            }
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+            if (tid == 0) {
+                ServeSlotCtl& sc = a.ctl->slot[slot];
+                dev_store(&sc.claim, serve_claim_word(gen, 0, 0));
+                __hip_atomic_fetch_add(&a.ctl->active, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __builtin_amdgcn_s_waitcnt(0);
+                sys_store_u32(&a.host->finished[slot], gen);
+            }
         }
         __syncthreads();  // LDS is reused by the next tile
         cont = sh[7];
