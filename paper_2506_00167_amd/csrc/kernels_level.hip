@@ -617,17 +617,23 @@ __global__ __launch_bounds__(kThreads) void serve_kernel(ServeArgs a, const Serv
         if (tid == 0) {
             ServeSlotCtl& sc = a.ctl->slot[slot];
             int next = 0, last = 0;
-            const uint32_t prev = __hip_atomic_fetch_add(&sc.done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (prev + 1 == (uint32_t)nt) {
+            // the only tile of a level needs no count: its workgroup finishes it
+            const bool finisher =
+                nt == 1 ||
+                __hip_atomic_fetch_add(&sc.done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1 == (uint32_t)nt;
+            if (finisher) {
                 if (tau < M) {
                     // open the next level with its tile 0 already claimed by
-                    // this workgroup, which goes on with it at once
-                    const int nt_next = dev_load(&sc.ntiles[tau + 1]);
-                    dev_store(&sc.done, 0u);
-                    __builtin_amdgcn_s_waitcnt(0);
-                    dev_store(&sc.claim, serve_claim_word(gen, tau + 1, nt_next) + 1);
-                    if (nt_next > 1) {  // tiles for others: wake the idle workgroups
+                    // this workgroup, which goes on with it at once. A next
+                    // level of one tile is not published: the claim word keeps
+                    // showing an earlier level with every tile taken (levels
+                    // only grow, so that level had one tile too).
+                    const int nt_next = recs[rec].ntiles[tau + 1];
+                    if (nt_next > 1) {
+                        dev_store(&sc.done, 0u);
                         __builtin_amdgcn_s_waitcnt(0);
+                        dev_store(&sc.claim, serve_claim_word(gen, tau + 1, nt_next) + 1);
+                        __builtin_amdgcn_s_waitcnt(0);  // tiles for others: wake the idle workgroups
                         __hip_atomic_fetch_add(&a.ctl->opened, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     }
                     next = 1;
