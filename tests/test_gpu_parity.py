@@ -6,6 +6,9 @@ reported); free-running disagreements must descend from conditioned ones.
 Logits within 1e-4. BF16: against the oracle run in BF16, every disagreement
 explained by the node's measured logit error (tests/parity.py).
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -434,3 +437,30 @@ def test_hidden_widths_padded(precision):
             rep = parity.compare(cfg, weights, ue, alloc, logits, precision="bf16", logit_tol=2e-3)
             _report(f"bf16 hidden 160/96 level={force_level}", rep, exact=False)
         cb.close()
+
+
+def test_fp8_scale_outside_block_scale_range_is_refused():
+    """Each FP8 layer's combined output scale (weight scale x its input scale
+    / the next layer's input scale) is applied as an E8M0 block scale, which
+    holds 2^-126..2^127: act_scale values that push it outside are refused
+    at creation and at a weight refresh, and the old weights stay usable."""
+    cfg = wl.TREE_E8K3.with_precision("fp8")
+    weights = wl.make_weights(cfg, wl.WEIGHT_SEEDS["tree-e8k3"])
+    bad = [2.0 ** -100, 2.0 ** 100, 1.0]
+    with pytest.raises(cyrus.CyrusError) as ei:
+        cyrus.Codebook(cfg, weights, act_scale=bad)
+    assert ei.value.status == -2
+    good = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "fp8_act_scales.json")))[
+        f"tree-e8k3/{wl.WEIGHT_SEEDS['tree-e8k3']}"]
+    cb = cyrus.Codebook(cfg, weights, act_scale=good)
+    ue = wl.make_ue_state(cfg.num_ue, wl.ue_seed(0))
+    cb.build(ue)
+    cb.wait()
+    first = cb.export()[0]
+    with pytest.raises(cyrus.CyrusError) as ei:
+        cb.set_weights(weights, act_scale=bad)
+    assert ei.value.status == -2
+    cb.build(ue)
+    cb.wait()
+    assert np.array_equal(cb.export()[0], first)
+    cb.close()
