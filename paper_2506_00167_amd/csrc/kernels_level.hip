@@ -105,6 +105,7 @@ struct LevelSmem {
     int* R;         // [kMaxUE]
     int* rsum;      // [4]
     float* tmpl;    // [kMaxIn0] features common to every row (UE radio state, tau), zero elsewhere
+    uint8_t* tmplq; // [kMaxIn0 * 4] the same row in the storage type of the first layer's input
     uint8_t* pst;   // [(RT + 2) * kMaxUE] states of the parents of the tile's rows
     int* tab;       // [3 * (kMaxEntries + 1)] ent_tree, ent_tau, prefix
     float* bias;    // [sum of out_pad] biases of all layers
@@ -120,7 +121,8 @@ __device__ __forceinline__ LevelSmem level_smem(uint8_t* smem, int bufsize)
     m.R = reinterpret_cast<int*>(m.zl + 16 * RTT * kLogitStride);
     m.rsum = m.R + kMaxUE;
     m.tmpl = reinterpret_cast<float*>(m.rsum + 4);
-    m.pst = reinterpret_cast<uint8_t*>(m.tmpl + kMaxIn0);
+    m.tmplq = reinterpret_cast<uint8_t*>(m.tmpl + kMaxIn0);
+    m.pst = m.tmplq + kMaxIn0 * 4;
     m.tab = reinterpret_cast<int*>(m.pst + pst_bytes(RTT));
     m.bias = reinterpret_cast<float*>(reinterpret_cast<uint8_t*>(m.tab) + tab_bytes());
     return m;
@@ -203,6 +205,7 @@ __device__ __forceinline__ void level_tile(const DevTree& t, int tau, int row0, 
         else if (f == 4 * E)
             v = (float)tau * (1.f / 8.f);
         m.tmpl[f] = v;  // parent state and k are filled in per row
+        store1<P>(m.tmplq + f * es, v, t.inv_in_scale[0]);
     }
     if (threadIdx.x < 64) {  // wave 0 holds R (f < E <= 32): sum by shuffles
         int r = f < E ? uev : 0;
@@ -225,41 +228,46 @@ __device__ __forceinline__ void level_tile(const DevTree& t, int tau, int row0, 
     // Features of every row, zero padded to the k-chunk and to whole row
     // tiles, one 16-byte segment (F features) per step: the template, with
     // the parent state (features 3E..4E-1) and k/8 (feature 4E+1) of the row.
+    // Segments without row-dependent features are copied from the template
+    // already in the storage type. Row and parent come from small quotients
+    // taken in float, exact here (numerators below 2^12, distance to the
+    // next integer at least 1/(2 divisor)).
     const int s0 = in0 * es + 16;
     const int nseg = in0 / F;
     const int nrows_pad = ((nrows + 15) >> 4) << 4;
-    const float inv0 = t.inv_in_scale[0];
+    const float inv0 = t.inv_in_scale[0], inv_nseg = 1.f / (float)nseg, invK = 1.f / (float)K;
+    const int rk0 = row0 - p_lo * K;  // row0's position among the children of parent p_lo
+    const int d0 = 3 * E, d1 = 4 * E + 2;  // row-dependent features [d0, d1)
     for (int idx = threadIdx.x; idx < nrows_pad * nseg; idx += kThreads) {
-        const int row = idx / nseg, f0 = (idx - row * nseg) * F;
-        const int r = row0 + row, p = r / K, k = r - p * K + 1;
-        const bool live = row < nrows;
-        const uint8_t* ps = m.pst + (live ? p - p_lo : 0) * E;
-        const float kf = (float)k * (1.f / 8.f);
-        float v[F];
+        const int row = (int)(((float)idx + 0.5f) * inv_nseg), f0 = (idx - row * nseg) * F;
+        uint8_t* dst = m.bufA + row * s0 + f0 * es;
+        if (row >= nrows) {
+            *reinterpret_cast<uint4*>(dst) = uint4{0, 0, 0, 0};
+        } else if (f0 >= d1 || f0 + F <= d0) {
+            *reinterpret_cast<uint4*>(dst) = *reinterpret_cast<const uint4*>(m.tmplq + f0 * es);
+        } else {
+            const int pq = (int)(((float)(rk0 + row) + 0.5f) * invK);  // parent - p_lo
+            const int k = rk0 + row - pq * K + 1;
+            const uint8_t* ps = m.pst + pq * E;
+            const float kf = (float)k * (1.f / 8.f);
+            float v[F];
 #pragma unroll
-        for (int j = 0; j < F; j += 4) {
-            const floatx4 q = *reinterpret_cast<const floatx4*>(m.tmpl + f0 + j);
-            v[j] = q[0];
-            v[j + 1] = q[1];
-            v[j + 2] = q[2];
-            v[j + 3] = q[3];
-        }
-        if (f0 < 4 * E + 2 && f0 + F > 3 * E) {  // segment holds row-dependent features
+            for (int j = 0; j < F; j += 4) {
+                const floatx4 q = *reinterpret_cast<const floatx4*>(m.tmpl + f0 + j);
+                v[j] = q[0];
+                v[j + 1] = q[1];
+                v[j + 2] = q[2];
+                v[j + 3] = q[3];
+            }
 #pragma unroll
             for (int j = 0; j < F; ++j) {
                 const int fj = f0 + j;
-                const int si = min(max(fj - 3 * E, 0), E - 1);
-                const float sv = (float)ps[si] * (1.f / 64.f);
-                v[j] = (fj >= 3 * E && fj < 4 * E) ? sv : (fj == 4 * E + 1 ? kf : v[j]);
+                const float sv = (float)ps[min(max(fj - d0, 0), E - 1)] * (1.f / 64.f);
+                v[j] = (fj >= d0 && fj < 4 * E) ? sv : (fj == 4 * E + 1 ? kf : v[j]);
             }
-        }
-        uint8_t* dst = m.bufA + row * s0 + f0 * es;
 #pragma unroll
-        for (int j = 0; j < F; j += 4) {
-            if (live)
+            for (int j = 0; j < F; j += 4)
                 store4<P>(dst + j * es, v[j], v[j + 1], v[j + 2], v[j + 3], inv0);
-            else
-                store4<P>(dst + j * es, 0.f, 0.f, 0.f, 0.f, inv0);
         }
     }
     lds_barrier();
@@ -729,7 +737,7 @@ size_t level_bias_bytes(const DevTree& t)
 
 size_t level_lds_for_buf(size_t buf, size_t bias_bytes, int rtt)
 {
-    return 2 * buf + (size_t)16 * rtt * kLogitStride * 4 + (kMaxUE + 4) * 4 + kMaxIn0 * 4 + pst_bytes(rtt) +
+    return 2 * buf + (size_t)16 * rtt * kLogitStride * 4 + (kMaxUE + 4) * 4 + 2 * kMaxIn0 * 4 + pst_bytes(rtt) +
            tab_bytes() + bias_bytes;
 }
 
