@@ -370,9 +370,11 @@ class Codebook:
         return self
 
     def set_weights(self, weights, act_scale=None):
-        self._w = _WeightsView(weights, act_scale)
+        view = _WeightsView(weights, act_scale)
+        cyrus_codebook_set_weights(self.handle, view.struct, self.stream)
+        # only a refresh that took effect replaces the weights this handle reports
+        self._w = view
         self.weights, self.act_scale = weights, act_scale
-        cyrus_codebook_set_weights(self.handle, self._w.struct, self.stream)
 
     def build(self, ue: UEState):
         s, keep = ue_struct(ue)

@@ -249,3 +249,54 @@ def test_oversize_request_is_refused(cells):
     parity.check_invariants(small.cfg, ue, alloc)
     eng.close()
     big[0].close()
+
+
+def test_resident_weight_refresh_reuses_buffers(cells):
+    """Weight refreshes while the resident worker stays up: the codebook
+    handle double-buffers its weights, so the second refresh overwrites the
+    buffer the first request read. Every request must see the weights current
+    at its admission (the worker drops its cached lines when the host reports a
+    refresh), a refresh is refused while an admitted request holds the buffer
+    it would overwrite, and results equal fresh level-path builds."""
+    small = min(range(len(cells)), key=lambda j: cells[j].num_nodes * cells[j].cfg.hidden[0])
+    cell = cells[small]
+    cfg = cell.cfg
+    w1 = cell.weights
+    w2 = wl.make_weights(cfg, 9001)
+    w3 = wl.make_weights(cfg, 9002)
+    ue = wl.make_ue_state(cfg.num_ue, 31)
+
+    def fresh(weights):
+        ref = cyrus.Codebook(cfg, weights, force_level=True)
+        ref.build(ue)
+        a, _ = ref.export()
+        ref.close()
+        return a
+
+    refs = [fresh(w) for w in (w1, w2, w3)]
+    assert not np.array_equal(refs[0], refs[1]) and not np.array_equal(refs[1], refs[2])
+    eng = serving.default_engine(max_active=8, pool_mib=64, resident=True)
+    try:
+        got = [_alone(eng, cell, ue)]
+        cell.set_weights(w2)
+        got.append(_alone(eng, cell, ue))
+        cell.set_weights(w3)  # back into the first buffer
+        got.append(_alone(eng, cell, ue))
+        for k in range(3):
+            assert np.array_equal(got[k], refs[k]), f"request after refresh {k}: not the current weights' codebook"
+        # an admitted request keeps its buffer: the refresh that would overwrite it waits
+        t = eng.submit(cell, ue)
+        eng.step()
+        with pytest.raises(cyrus.CyrusError) as ei:
+            cell.set_weights(w1)  # would overwrite w2's buffer, held by no one: allowed
+            cell.set_weights(w2)  # would overwrite w3's buffer, held by the request
+        assert ei.value.status == -5
+        while True:
+            eng.step()
+            done = dict(eng.completed())
+            if t in done:
+                break
+        assert np.array_equal(eng.result(t), refs[2]), "the admitted request did not keep its weights"
+    finally:
+        eng.close()
+        cell.set_weights(w1)
