@@ -382,12 +382,14 @@ int cyrus_engine_set_levels_per_step(cyrus_engine* eng, int32_t levels);
  * the device reads and writes directly); every other workgroup repeatedly
  * claims one row tile of the oldest admitted request whose current level has
  * tiles left, runs it (the batched level kernel's tile), and the workgroup
- * that finishes a level's last tile opens the next level; after level M the
- * request's completion flag is set in pinned memory. Levels of different
- * requests overlap freely and no host step is needed between levels:
- * cyrus_engine_step retires finished requests (it reads the flags and copies
- * each finished codebook from the device pool into the request's block of
- * the host pool on a copy stream of the engine's own), admits waiting ones
+ * that finishes a level's last tile opens the next level; after level M that
+ * workgroup writes a codebook of up to 128 KiB into the request's block of
+ * the host pool itself and sets the request's completion flag in pinned
+ * memory. Levels of different requests overlap freely and no host step is
+ * needed between levels: cyrus_engine_step retires finished requests (it
+ * reads the flags, and copies each larger codebook from the device pool into
+ * the request's block of the host pool on a copy stream of the engine's
+ * own), admits waiting ones
  * into free slots and pool memory, and relaunches the worker when it has
  * exited with requests waiting. The worker leaves after 20 ms with nothing to
  * do, after 2 s without progress, after admitting 2,048 requests (the host then
@@ -396,7 +398,7 @@ int cyrus_engine_set_levels_per_step(cyrus_engine* eng, int32_t levels);
  * to the same request alone (every request runs the same tile code whatever
  * the mix). CYRUS_EINVAL after a submit or for on = 0 once resident;
  * CYRUS_EWORKSPACE if the pools cannot hold the worker's tables (about
- * 1.5 MiB device, 90 KiB host); CYRUS_EUNSUPPORTED if the host pool is not
+ * 1.6 MiB device, 100 KiB host); CYRUS_EUNSUPPORTED if the host pool is not
  * mapped for the device. */
 int cyrus_engine_set_resident(cyrus_engine* eng, int32_t on);
 

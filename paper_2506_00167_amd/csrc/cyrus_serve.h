@@ -22,7 +22,7 @@ constexpr int kServeSlots = 128;  // requests in flight (engine slots)
 // admission generation (nonzero, 20 bits) and, for a small codebook, where
 // the worker itself delivers it in the pinned pool.
 constexpr uint32_t kServeDeviceCopyBytes = 128 * 1024;  // larger codebooks go by copy engine
-struct alignas(64) ServeRequest {
+struct alignas(128) ServeRequest {
     DevTree t;
     int32_t ntiles[8];  // [tau], tau = 1..M
     int32_t slot;
@@ -51,7 +51,8 @@ struct alignas(128) ServeSlotCtl {
 // request it admits into record k, so within a launch every record is written
 // once, before any workgroup reads it, and the tile workgroups can read the
 // tree descriptor through the scalar cache (as a kernel argument). Records
-// are whole 64-byte lines, so reading one never caches part of the next. A
+// are whole 128-byte lines (the L2 line), so reading one never caches part of
+// the next. A
 // launch that has used every record stops admitting and leaves; the host
 // relaunches it for the rest.
 constexpr int kServeRecords = 2048;
