@@ -43,8 +43,9 @@ WORKLOAD = "tree-e8k3"
 # Sources each kernel path is compiled from: HBM traffic measured on them is
 # reported only while they are unchanged.
 KERNEL_SOURCES = {
-    "subtree": ["kernels_subtree.hip", "cyrus_regmlp.h", "cyrus_device.h", "cyrus_internal.h"],
-    "level": ["kernels_level.hip", "cyrus_device.h", "cyrus_internal.h"],
+    "subtree": ["kernels_subtree.hip", "cyrus_subtree.h", "cyrus_regmlp.h", "cyrus_device.h", "cyrus_internal.h"],
+    "level": ["kernels_level.hip", "cyrus_mlp.h", "cyrus_serve.h", "cyrus_subtree.h", "cyrus_regmlp.h",
+              "cyrus_device.h", "cyrus_internal.h"],
 }
 
 
