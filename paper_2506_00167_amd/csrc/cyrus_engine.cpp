@@ -115,6 +115,7 @@ struct Request {
     uint32_t gen = 0;   // resident worker: admission generation (nonzero, 20 bits)
     bool copying = false;  // resident worker: codebook copy to the host pool enqueued
     bool device_copy = false;  // resident worker: the worker writes the codebook to the host pool
+    bool subtree = false;      // resident worker: built as subtree units
 };
 
 size_t slot_bytes()
@@ -535,6 +536,23 @@ int admit_resident(cyrus_engine* e)
             // in [1, kServeMaxTiles]: K, M <= 7 give at most 7 * 8^6 / 16 = 114,688 tiles
             nt[tau] = (int32_t)((n_eval + 16 * e->plan_rtt - 1) / (16 * e->plan_rtt));
         }
+        // A tree the worker's subtree units cover (BF16, two hidden layers of
+        // 256) is built as (K+1)^L units with roots at level L = min(3, M-1):
+        // each unit is a register-resident pass over its ancestors and its
+        // subtree, so the request takes one round of units instead of M
+        // dependent level steps, for about the same work (the ancestors are
+        // recomputed per unit) as the level tiles.
+        int sub_split = 0, sub_buf = 0, sub_st = 0;
+        {
+            const int L = std::min(3, s.M - 1);
+            size_t sub_lds = 0;
+            if (L >= 1 && plan_subtree_units(t, e->prec, L, &sub_buf, &sub_st, &sub_lds) && sub_lds <= e->plan_lds) {
+                sub_split = L;
+                std::memset(nt, 0, sizeof nt);
+                nt[1] = (int32_t)ipow(s.K + 1, L);
+            }
+        }
+        r->subtree = sub_split > 0;
         auto seen = e->seen_wversion.find(r->cell);
         if (seen == e->seen_wversion.end() || seen->second != r->cell->wversion) {
             ++e->wepoch;  // new or refreshed weights: the workers drop their cached lines once
@@ -550,6 +568,10 @@ int admit_resident(cyrus_engine* e)
         r->device_copy = cb_bytes <= kServeDeviceCopyBytes;
         q.cb_words = r->device_copy ? (uint32_t)((cb_bytes + 3) / 4) : 0u;
         q.cb_host = r->device_copy ? (uint64_t)(uintptr_t)(e->hpool_dev + r->host_off) : 0u;
+        q.sub_split = sub_split;
+        q.sub_bufsize = sub_buf;
+        q.sub_stbytes = sub_st;
+        q.sub_pad = 0;
         std::memset(q.ue, 0, sizeof q.ue);
         std::memcpy(q.ue, r->ue.data(), r->ue.size() * 4);
         std::atomic_thread_fence(std::memory_order_release);

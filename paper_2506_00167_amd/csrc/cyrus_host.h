@@ -61,6 +61,9 @@ int stage_ue_host(cyrus_codebook* cb, const cyrus_ue_state* ue);
 
 // Subtree (single-launch latency) path.
 bool subtree_supported(const DevTree& t, int prec);
+// The resident worker's subtree units (roots at level `split`): whether the
+// tree has the shape the worker's instantiation carries, and its LDS plan.
+bool plan_subtree_units(const DevTree& t, int prec, int split, int* bufsize, int* stbytes, size_t* lds);
 hipError_t launch_subtree(const DevTree& t, int prec, hipStream_t s);
 
 }  // namespace cyrus

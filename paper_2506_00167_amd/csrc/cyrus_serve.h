@@ -19,8 +19,8 @@ constexpr int kServeSlots = 128;  // requests in flight (engine slots)
 // keeps it (record table): the tree descriptor (t.ue is set by the device to
 // this record's UE copy; t.alloc and t.state point at the request's codebook
 // and node states in the device pool), the row tiles of each level, the
-// admission generation (nonzero, 20 bits) and, for a small codebook, where
-// the worker itself delivers it in the pinned pool.
+// admission generation (nonzero, 20 bits), for a small codebook where the
+// worker itself delivers it in the pinned pool, and the subtree-unit plan.
 constexpr uint32_t kServeDeviceCopyBytes = 128 * 1024;  // larger codebooks go by copy engine
 struct alignas(128) ServeRequest {
     DevTree t;
@@ -30,6 +30,13 @@ struct alignas(128) ServeRequest {
     uint32_t wepoch;    // weight-refresh epoch of the host at admission
     uint32_t cb_words;  // codebook words the worker copies to cb_host (0: the host copies it)
     uint64_t cb_host;   // device address of the request's codebook block in the pinned pool
+    // subtree units (sub_split > 0): the whole request is (K+1)^sub_split
+    // units, claimed as the tiles of level 1, each the subtree algorithm
+    // for one root of level sub_split (LDS plan: sub_bufsize, sub_stbytes)
+    int32_t sub_split;
+    int32_t sub_bufsize;
+    int32_t sub_stbytes;
+    int32_t sub_pad;
     int32_t ue[3 * kMaxUE];
 };
 

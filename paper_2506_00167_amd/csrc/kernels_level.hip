@@ -13,6 +13,7 @@
 #include "cyrus_device.h"
 #include "cyrus_kernels.h"
 #include "cyrus_mlp.h"
+#include "cyrus_subtree.h"
 
 namespace cyrus {
 
@@ -613,12 +614,26 @@ __global__ __launch_bounds__(kThreads) void serve_kernel(ServeArgs a, const Serv
         }
         since = wall_clock64();
         const DevTree& t = recs[rec].t;
-        M = t.M;
-        const int n_eval = (int)(t.K * (dev_level_offset(t.K, tau) - dev_level_offset(t.K, tau - 1)));
-        const int row0 = tile * 16 * RTT;
-        const int nrows = min(16 * RTT, n_eval - row0);
-        if (nrows > 0)
-            level_tile<P, RTT, true>(t, tau, row0, nrows, m);
+        const int split = recs[rec].sub_split;
+        if (split > 0) {
+            // subtree units: the request is one "level" whose tiles are the
+            // subtree roots; the unit writes its nodes' allocations itself
+            M = 1;
+            if constexpr (P == kBF16) {
+                const int bufsize = recs[rec].sub_bufsize, stbytes = recs[rec].sub_stbytes;
+                if (t.E <= 8)
+                    subtree_body<kBF16, 2, 1, 8, 1, 8, false, true>(t, split, tile, bufsize, stbytes, smem);
+                else
+                    subtree_body<kBF16, 2, 1, 8, 1, 16, false, true>(t, split, tile, bufsize, stbytes, smem);
+            }
+        } else {
+            M = t.M;
+            const int n_eval = (int)(t.K * (dev_level_offset(t.K, tau) - dev_level_offset(t.K, tau - 1)));
+            const int row0 = tile * 16 * RTT;
+            const int nrows = min(16 * RTT, n_eval - row0);
+            if (nrows > 0)
+                level_tile<P, RTT, true>(t, tau, row0, nrows, m);
+        }
         // every store of the tile has completed before it is counted
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();

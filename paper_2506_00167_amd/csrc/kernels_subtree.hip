@@ -49,7 +49,8 @@ int num_cus()
     return g_num_cu;
 }
 
-bool plan_subtree(const DevTree& t, int prec, SubtreePlan& pl)
+// The LDS plan of the subtree algorithm with its roots at level `split`.
+bool plan_subtree_at(const DevTree& t, int prec, int split, SubtreePlan& pl)
 {
     if (t.E > 16 || t.n_layers < 2 || t.n_layers > 3 || t.out_pad[t.n_layers - 1] > 16)
         return false;  // one 16-wide output tile (E logits, or mu and log sigma for E <= 8)
@@ -65,10 +66,8 @@ bool plan_subtree(const DevTree& t, int prec, SubtreePlan& pl)
     if (!t.w1d || t.in_pad_d % kc != 0 || nch1 < 1 || nch1 > (prec == kFP32 ? 2 : (prec == kBF16 ? 1 : 2)) ||
         (prec == kFP8 && nch1 != 2))
         return false;
-    const int ncu = num_cus();
-    int split = 0;
-    while (split + 1 <= t.M - 1 && ipow(t.K + 1, split + 1) <= ncu)
-        ++split;
+    if (split < 0 || split > t.M - 1)
+        return false;
     const int64_t width_max = ipow(t.K + 1, t.M - split);
     const int64_t st = width_max * t.E;
     if (st > 16 * 1024)
@@ -92,6 +91,16 @@ bool plan_subtree(const DevTree& t, int prec, SubtreePlan& pl)
     if (t.head == kGaussianHead)  // the precomputed draws, 16-byte aligned
         pl.lds += 16 + (size_t)eps_slots(t.K, t.M, split) * t.E * 4;
     return pl.lds <= 160 * 1024;
+}
+
+// One launch: the deepest split whose (K+1)^split roots fit one workgroup per CU.
+bool plan_subtree(const DevTree& t, int prec, SubtreePlan& pl)
+{
+    const int ncu = num_cus();
+    int split = 0;
+    while (split + 1 <= t.M - 1 && ipow(t.K + 1, split + 1) <= ncu)
+        ++split;
+    return plan_subtree_at(t, prec, split, pl);
 }
 
 template <int P, int T, int CH1, int CHH, int NHH>
@@ -126,6 +135,22 @@ hipError_t dispatch_width(const DevTree& t, const SubtreePlan& pl, hipStream_t s
 }
 
 }  // namespace
+
+bool plan_subtree_units(const DevTree& t, int prec, int split, int* bufsize, int* stbytes, size_t* lds)
+{
+    // the resident worker carries one instantiation: BF16, two hidden layers
+    // of 256, per-node inputs in one chunk, softmax head, largest remainder
+    if (prec != kBF16 || t.n_layers != 3 || t.out_pad[0] != 256 || t.out_pad[1] != 256 ||
+        t.in_pad_d != prec_chunk(prec) || t.head != kSoftmaxHead || t.rounding != kLargestRemainder)
+        return false;
+    SubtreePlan pl;
+    if (!plan_subtree_at(t, prec, split, pl))
+        return false;
+    *bufsize = pl.bufsize;
+    *stbytes = pl.stbytes;
+    *lds = pl.lds;
+    return true;
+}
 
 bool subtree_supported(const DevTree& t, int prec)
 {

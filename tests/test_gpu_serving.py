@@ -43,6 +43,18 @@ def cells():
         c.close()
 
 
+def _single_build(cell, ue, weights=None):
+    """The one-codebook build the resident worker's result must equal: the
+    subtree path where the cell has the shape of the worker's subtree units
+    (BF16, two hidden layers of 256), else the level path."""
+    cb = cyrus.Codebook(cell.cfg, cell.weights if weights is None else weights)
+    cb.build(ue)
+    a, _ = cb.export()
+    path = cb.kernel_path
+    cb.close()
+    return a, path
+
+
 def _alone(engine, cell, ue):
     t = engine.submit(cell, ue)
     while True:
@@ -87,7 +99,7 @@ def _own_builds(cell, ue):
     return out
 
 
-def test_resident_mixed_equals_alone_and_level_build(cells):
+def test_resident_mixed_equals_alone_and_single_build(cells):
     eng = serving.default_engine(max_active=32, pool_mib=128, resident=True)
     reqs = serving.make_requests(cells, 40, seed=11)
     probe_idx = [3, 17, 29]
@@ -98,15 +110,17 @@ def test_resident_mixed_equals_alone_and_level_build(cells):
     assert res["engine"]["completed"] == len(reqs) + len(probe_idx)
     for i in probe_idx:
         c, ue = reqs[i]
-        lv = cyrus.Codebook(cells[c].cfg, cells[c].weights, force_level=True)
-        lv.build(ue)
-        ref, _ = lv.export()
-        lv.close()
-        assert np.array_equal(alone[i], ref), f"request {i}: resident alone differs from the level-path build"
-        assert np.array_equal(res["results"][i], ref), f"request {i}: resident mix differs from the level-path build"
-        parity.check_invariants(cells[c].cfg, ue, ref)
+        ref, path = _single_build(cells[c], ue)
+        assert np.array_equal(alone[i], ref), f"request {i}: resident alone differs from the {path}-path build"
+    paths = set()
     for j, (c, ue) in enumerate(reqs):
-        parity.check_invariants(cells[c].cfg, ue, res["results"][j])
+        ref, path = _single_build(cells[c], ue)
+        paths.add(path)
+        assert np.array_equal(res["results"][j], ref), f"request {j}: resident mix differs from the {path}-path build"
+        parity.check_invariants(cells[c].cfg, ue, ref)
+    # both ways of building a request in the worker: subtree units (two
+    # hidden layers of 256) and level tiles (512)
+    assert paths == {"subtree", "level"}, paths
     eng.close()
 
 
@@ -117,7 +131,7 @@ def test_resident_matches_same_precision_oracle(cells):
     eng = serving.default_engine(max_active=4, pool_mib=64, resident=True)
     alloc = _alone(eng, cell, ue)
     weights = wl.make_weights(cell.cfg, wl.serving_cell_configs(16, 424242)[small][1])
-    ref = cyrus.Codebook(cell.cfg, weights, export_logits=True, force_level=True)
+    ref = cyrus.Codebook(cell.cfg, weights, export_logits=True)
     ref.build(ue)
     ref_alloc, ref_logits = ref.export()
     ref.close()
@@ -257,7 +271,7 @@ def test_resident_weight_refresh_reuses_buffers(cells):
     buffer the first request read. Every request must see the weights current
     at its admission (the worker drops its cached lines when the host reports a
     refresh), a refresh is refused while an admitted request holds the buffer
-    it would overwrite, and results equal fresh level-path builds."""
+    it would overwrite, and results equal fresh single-codebook builds."""
     small = min(range(len(cells)), key=lambda j: cells[j].num_nodes * cells[j].cfg.hidden[0])
     cell = cells[small]
     cfg = cell.cfg
@@ -267,11 +281,7 @@ def test_resident_weight_refresh_reuses_buffers(cells):
     ue = wl.make_ue_state(cfg.num_ue, 31)
 
     def fresh(weights):
-        ref = cyrus.Codebook(cfg, weights, force_level=True)
-        ref.build(ue)
-        a, _ = ref.export()
-        ref.close()
-        return a
+        return _single_build(cell, ue, weights)[0]
 
     refs = [fresh(w) for w in (w1, w2, w3)]
     assert not np.array_equal(refs[0], refs[1]) and not np.array_equal(refs[1], refs[2])
