@@ -261,9 +261,10 @@ typedef struct {
     int32_t num_minislots;                  /* M in [1, 7]: steps per sample */
     int32_t num_samples;                    /* H >= 1, H*M <= 2^24 */
     int32_t actor_hidden_layers;            /* in [1, 4] */
-    int32_t actor_hidden[CYRUS_MAX_HIDDEN]; /* multiples of 128 in [128, 512] */
+    int32_t actor_hidden[CYRUS_MAX_HIDDEN]; /* multiples of 32 in [32, 512] (zero-padded
+                                               to the next multiple of 128 inside) */
     int32_t critic_hidden_layers;           /* in [1, 4] */
-    int32_t critic_hidden[CYRUS_MAX_HIDDEN];
+    int32_t critic_hidden[CYRUS_MAX_HIDDEN]; /* as actor_hidden */
     float discount;                         /* lambda of Eq. (4) */
     float entropy_coef;                     /* zeta of Eq. (4) */
 } cyrus_critic_config;

@@ -66,9 +66,9 @@ int check_hidden(int n, const int32_t* h, const char* what)
         return fail_msg(CYRUS_ERANGE, buf);
     }
     for (int i = 0; i < n; ++i)
-        if (h[i] < 128 || h[i] > 512 || h[i] % 128) {
+        if (h[i] < 32 || h[i] > 512 || h[i] % 32) {
             char buf[128];
-            snprintf(buf, sizeof buf, "%s_hidden[%d] = %d is not a multiple of 128 in [128, 512]", what, i, h[i]);
+            snprintf(buf, sizeof buf, "%s_hidden[%d] = %d is not a multiple of 32 in [32, 512]", what, i, h[i]);
             return fail_msg(CYRUS_ERANGE, buf);
         }
     return CYRUS_OK;
@@ -90,15 +90,23 @@ int validate(const cyrus_critic_config* c)
     return rc ? rc : check_hidden(c->critic_hidden_layers, c->critic_hidden, "critic");
 }
 
-// The register-resident critic kernel takes two hidden layers of one width H
-// in {128, 256} in all five networks and at most 16 actor outputs (E <= 8);
-// every network's first layer is then padded to the critics' 5E+2 inputs.
+// Hidden layers are computed 128 neurons at a time: a width that is a
+// multiple of 32 is zero-padded to the next multiple of 128 (zero weights and
+// bias, so a padded neuron is ReLU(0) = 0 and its zero outgoing weights add
+// nothing to the next layer).
+int hidden_pad(int h) { return (int)align_up(h, 128); }
+
+// The register-resident critic kernel takes two hidden layers of one padded
+// width H in {128, 256} in all five networks and at most 16 actor outputs
+// (E <= 8); every network's first layer is then padded to the critics' 5E+2
+// inputs.
 bool regs_shape(const cyrus_critic_config* c, int* H)
 {
-    const int h = c->actor_hidden[0];
+    const int h = hidden_pad(c->actor_hidden[0]);
     *H = h;
     return c->actor_hidden_layers == 2 && c->critic_hidden_layers == 2 && (h == 128 || h == 256) &&
-           c->actor_hidden[1] == h && c->critic_hidden[0] == h && c->critic_hidden[1] == h && 2 * c->num_ue <= 16;
+           hidden_pad(c->actor_hidden[1]) == h && hidden_pad(c->critic_hidden[0]) == h &&
+           hidden_pad(c->critic_hidden[1]) == h && 2 * c->num_ue <= 16;
 }
 
 CriticLayout layout(const cyrus_critic_config* c)
@@ -122,8 +130,8 @@ CriticLayout layout(const cyrus_critic_config* c)
             s.dims[i + 1] = hw[i];
         s.dims[nh + 1] = actor ? 2 * E : 1;
         for (int l = 0; l < s.n_layers; ++l) {
-            s.in_pad[l] = (l == 0 && regs) ? in0 : (int)align_up(s.dims[l], 16);
-            s.out_pad[l] = (int)align_up(s.dims[l + 1], 16);
+            s.in_pad[l] = l == 0 ? (regs ? in0 : (int)align_up(s.dims[0], 16)) : hidden_pad(s.dims[l]);
+            s.out_pad[l] = l < nh ? hidden_pad(s.dims[l + 1]) : (int)align_up(s.dims[l + 1], 16);
             s.w_off[l] = off;
             off = align_up(off + (size_t)s.in_pad[l] * s.out_pad[l] * 4, 256);
             s.b_off[l] = off;

@@ -74,6 +74,23 @@ def test_hidden_width_and_state_range(lib):
         cyrus.cyrus_codebook_workspace_size(c)
 
 
+def test_critic_hidden_widths(lib):
+    # multiples of 32 in [32, 512] are accepted (zero-padded to the next
+    # multiple of 128 inside); anything else is refused before a device is used
+    def size(actor, critic):
+        c = cyrus.make_critic_config(wl.CriticConfig(num_ue=4, max_arrival=2, num_minislots=7, num_samples=16,
+                                                     actor_hidden=actor, critic_hidden=critic))
+        d = ctypes.c_size_t()
+        rc = lib.cyrus_critic_workspace_size(ctypes.byref(c), ctypes.byref(d))
+        return rc, d.value
+    ok = {w: size((w, w), (w, w)) for w in (32, 96, 128, 160, 256, 480, 512)}
+    assert all(rc == 0 for rc, _ in ok.values())
+    assert ok[32][1] == ok[96][1] == ok[128][1] < ok[160][1] == ok[256][1] < ok[480][1] == ok[512][1]
+    for bad in (0, 16, 100, 544, 1024):
+        assert size((bad,), (128,))[0] == -2
+        assert size((128,), (128, bad))[0] == -2
+
+
 def test_null_handles_are_safe(lib):
     assert lib.cyrus_codebook_num_nodes(None) == -1
     assert lib.cyrus_codebook_kernel_path(None) == b"none"

@@ -63,6 +63,11 @@ def test_critic_small_ragged():
     dict(num_ue=3, num_minislots=5, num_samples=41, actor_hidden=(128, 128), critic_hidden=(128, 128)),
     # 256-wide layers, 5E+2 = 12 inputs in one chunk, 23 x 7 = 161 rows
     dict(num_ue=2, num_minislots=7, num_samples=23),
+    # widths that are multiples of 32 but not of 128 (zero-padded to 128 and
+    # 256): the register-resident kernel with 96-wide layers, then the
+    # streamed-weight kernel with 160- and 224-wide layers
+    dict(num_ue=3, num_minislots=5, num_samples=29, actor_hidden=(96, 96), critic_hidden=(96, 96)),
+    dict(num_ue=4, num_minislots=7, num_samples=17, actor_hidden=(160,), critic_hidden=(224, 32)),
 ])
 def test_critic_register_shapes(shape):
     _check(wl.CriticConfig(**shape), 67, 68, 11, 3)
