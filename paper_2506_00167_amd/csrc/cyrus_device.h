@@ -677,4 +677,74 @@ __device__ __forceinline__ int enforce_dpp(int E, int e, float z, int R, int rsu
     return f + ((elig && rank < r) ? 1 : 0);
 }
 
+// enforce_dpp for N rows at once per G-lane group (row j: logit z[j],
+// demand[j], ranks through rank_row[j], which is touched only for a live row
+// that needs a split; rows with live_row[j] false give 0).
+// Each row's arithmetic is enforce_dpp's, in the same order, so the
+// allocations are the same; the N independent reduction chains interleave, so
+// one pass over N rows takes little more than a pass over one. The capping
+// loop runs until no row of the wave grows: a settled row repeats its last
+// pass with the same result, as a settled group does in enforce_dpp.
+template <int G, int N>
+__device__ __forceinline__ void enforce_dpp_n(int E, int e, const float (&z)[N], int R, int rsum,
+                                              const int (&demand)[N], const bool (&live_row)[N],
+                                              float* const (&rank_row)[N], int rounding, int (&a)[N])
+{
+    const bool live = e < E;
+    int T[N];
+    bool done[N], capped[N];
+    float p[N], s[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        T[j] = demand[j] < rsum ? demand[j] : rsum;
+        done[j] = !live_row[j] || T[j] >= rsum;  // no split to compute
+        const float zmax = dmax<G>(live ? z[j] : -3.0e38f);
+        p[j] = live ? expf(fmaxf(z[j] - zmax, -80.f)) : 0.f;
+        capped[j] = !live;
+        s[j] = 0.f;
+    }
+    for (int pass = 0; pass <= G; ++pass) {
+        bool grow[N], any = false;
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            const float rem = pass == 0 ? (float)T[j] : (float)T[j] - dsum<G>((live && capped[j]) ? (float)R : 0.f);
+            const float psum = dsum<G>(capped[j] ? 0.f : p[j]);
+            s[j] = rem / psum;
+            grow[j] = !done[j] && !capped[j] && s[j] * p[j] >= (float)R;
+            any = any || grow[j];
+        }
+        if (__ballot(any) == 0)
+            break;
+#pragma unroll
+        for (int j = 0; j < N; ++j)
+            capped[j] = capped[j] || grow[j];
+    }
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        const float x = !live ? 0.f : (capped[j] ? (float)R : s[j] * p[j]);
+        a[j] = (live_row[j] && live) ? R : 0;  // the rows without a split
+        if (done[j])
+            continue;  // uniform over the group (its lanes share the row)
+        if (rounding == kHuntingtonHill) {
+            a[j] = hh_round<G>(e, live, x, R, T[j]);
+        } else {
+            const float fl = floorf(x);
+            const int f = (int)fl;
+            const float frac = x - fl;
+            const int r = T[j] - disum<G>(f);
+            const bool elig = live && f < R;
+            rank_row[j][e] = elig ? frac : -1.f;
+            float fq[G];
+#pragma unroll
+            for (int q = 0; q < G; ++q)
+                fq[q] = rank_row[j][q];
+            int rank = 0;
+#pragma unroll
+            for (int q = 0; q < G; ++q)
+                rank += (fq[q] > frac || (fq[q] == frac && q < e)) ? 1 : 0;
+            a[j] = f + ((elig && rank < r) ? 1 : 0);
+        }
+    }
+}
+
 }  // namespace cyrus

@@ -47,9 +47,13 @@ __device__ __forceinline__ void put_alloc(gu8* p, uint8_t v)
     put_state<COH>(p, v);
 }
 
-template <int G, bool COH = false>
-__device__ __forceinline__ void finish_rows_level(const DevTree& t, const float* zl, const int* R, int rsum, int row0,
-                                                  int nrows, int64_t off, const uint8_t* pst, int p_lo)
+// The enforcer and the stores of rows [0, nrows) of a tile. With G lanes per
+// row, kThreads / G rows make one pass; N passes' rows run together in one
+// call of enforce_dpp_n (G <= 16), so a tile of up to N passes of rows takes
+// one interleaved pass.
+template <int G, int N, bool COH>
+__device__ __forceinline__ void finish_rows_level_n(const DevTree& t, const float* zl, const int* R, int rsum, int row0,
+                                                    int nrows, int64_t off, const uint8_t* pst, int p_lo)
 {
     // Every field of t is read once, before the first store: the output
     // pointers could alias the tree descriptor in global memory, so a field
@@ -59,25 +63,42 @@ __device__ __forceinline__ void finish_rows_level(const DevTree& t, const float*
     gu8* const state = as_global_mut(t.state);
     gf32* const logits = as_global_mut(t.logits);
     const bool with_logits = t.logits != nullptr;
-    for (int base = 0; base < nrows; base += kThreads / G) {
-        const int row = base + (int)threadIdx.x / G, e = (int)threadIdx.x % G;
-        if (row < nrows) {
-            const int r = row0 + row, p = r / K, k = r - p * K + 1;
-            float* zrow = const_cast<float*>(zl) + row * kLogitStride;
-            const float z = e < E ? zrow[e] : 0.f;
-            int a;
-            if constexpr (G <= 16)
-                a = enforce_dpp<G>(E, e, z, e < E ? R[e] : 0, rsum, U * k, zrow, rounding);  // row reused for ranks
-            else
-                a = enforce_group<G>(E, e, z, e < E ? R[e] : 0, rsum, U * k, rounding);
-            if (e < E) {
-                const int64_t node = off + (int64_t)p * (K + 1) + k;
+    constexpr int GR = kThreads / G;  // rows of one pass
+    const int e = (int)threadIdx.x % G;
+    const int Re = e < E ? R[e] : 0;
+    for (int base = 0; base < nrows; base += GR * N) {
+        int row[N], a[N], k[N], pq[N], demand[N];
+        bool live_row[N];
+        float z[N];
+        float* zrow[N];
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            row[j] = base + j * GR + (int)threadIdx.x / G;
+            live_row[j] = row[j] < nrows;
+            const int r = row0 + row[j];
+            pq[j] = r / K;
+            k[j] = r - pq[j] * K + 1;
+            demand[j] = U * k[j];
+            zrow[j] = const_cast<float*>(zl) + (live_row[j] ? row[j] : 0) * kLogitStride;
+            z[j] = (live_row[j] && e < E) ? zrow[j][e] : 0.f;
+        }
+        if constexpr (G <= 16) {
+            enforce_dpp_n<G, N>(E, e, z, Re, rsum, demand, live_row, zrow, rounding, a);  // rows reused for ranks
+        } else {
+            static_assert(N == 1, "groups wider than 16 lanes take one row per call");
+            a[0] = live_row[0] ? enforce_group<G>(E, e, z[0], Re, rsum, demand[0], rounding) : 0;
+        }
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            if (live_row[j] && e < E) {
+                const int p = pq[j];
+                const int64_t node = off + (int64_t)p * (K + 1) + k[j];
                 const uint8_t c = pst[(p - p_lo) * E + e];
-                put_alloc<COH>(alloc + node * E + e, (uint8_t)a);
-                put_state<COH>(state + node * E + e, (uint8_t)(c + a));
+                put_alloc<COH>(alloc + node * E + e, (uint8_t)a[j]);
+                put_state<COH>(state + node * E + e, (uint8_t)(c + a[j]));
                 if (with_logits)
-                    logits[node * E + e] = z;
-                if (k == 1) {
+                    logits[node * E + e] = z[j];
+                if (k[j] == 1) {
                     const int64_t sib = off + (int64_t)p * (K + 1);
                     put_alloc<COH>(alloc + sib * E + e, 0);
                     put_state<COH>(state + sib * E + e, c);
@@ -86,6 +107,27 @@ __device__ __forceinline__ void finish_rows_level(const DevTree& t, const float*
                 }
             }
         }
+    }
+}
+
+template <int G, int RTT, bool COH = false>
+__device__ __forceinline__ void finish_rows_level(const DevTree& t, const float* zl, const int* R, int rsum, int row0,
+                                                  int nrows, int64_t off, const uint8_t* pst, int p_lo)
+{
+    constexpr int GR = kThreads / G;
+    constexpr int kPasses = (16 * RTT + GR - 1) / GR;  // passes of a full tile
+    if constexpr (G > 16 || kPasses == 1) {
+        finish_rows_level_n<G, 1, COH>(t, zl, R, rsum, row0, nrows, off, pst, p_lo);
+    } else {
+        // at most three rows per group; in the serving worker, whose tile
+        // body also holds its claim state, two, and one in 96-row tiles
+        // (registers: the BF16 instantiation would spill)
+        constexpr int kMaxN = COH ? (RTT >= 6 ? 1 : 2) : 3;
+        constexpr int NM = kPasses < kMaxN ? kPasses : kMaxN;
+        if (nrows <= GR)
+            finish_rows_level_n<G, 1, COH>(t, zl, R, rsum, row0, nrows, off, pst, p_lo);
+        else
+            finish_rows_level_n<G, NM, COH>(t, zl, R, rsum, row0, nrows, off, pst, p_lo);
     }
 }
 
@@ -276,11 +318,11 @@ __device__ __forceinline__ void level_tile(const DevTree& t, int tau, int row0, 
 
     const int rsum = *m.rsum;
     if (E <= 8)
-        finish_rows_level<8, COH>(t, m.zl, m.R, rsum, row0, nrows, off, m.pst, p_lo);
+        finish_rows_level<8, RTT, COH>(t, m.zl, m.R, rsum, row0, nrows, off, m.pst, p_lo);
     else if (E <= 16)
-        finish_rows_level<16, COH>(t, m.zl, m.R, rsum, row0, nrows, off, m.pst, p_lo);
+        finish_rows_level<16, RTT, COH>(t, m.zl, m.R, rsum, row0, nrows, off, m.pst, p_lo);
     else
-        finish_rows_level<32, COH>(t, m.zl, m.R, rsum, row0, nrows, off, m.pst, p_lo);
+        finish_rows_level<32, RTT, COH>(t, m.zl, m.R, rsum, row0, nrows, off, m.pst, p_lo);
 }
 
 template <int P, int RTT>
