@@ -414,6 +414,22 @@ int cyrus_engine_completed(cyrus_engine* eng, int64_t* tickets, double* latency_
 /* Copy a finished request's codebook ([nodes][E] bytes) and release its slot. */
 int cyrus_engine_result(cyrus_engine* eng, int64_t ticket, uint8_t* alloc, size_t bytes);
 
+/* A native request loop (Sec. VII's serving timing, without a host
+ * interpreter between steps): request i, for cells[i] with UE state ues[i],
+ * is submitted once arrival_us[i] microseconds have passed since the call
+ * began (non-negative and non-decreasing; all zero submits everything at
+ * once). The loop submits what has arrived, steps the engine, and copies each
+ * finished request's codebook ([nodes][E] bytes) to results[i] and releases
+ * it (results NULL, or results[i] NULL: released without a copy), until all n
+ * are done. latency_us[i] (nullable) receives the time from the request's
+ * arrival to the step that observed its completion, so that a wait before
+ * the submit counts. Requests of earlier submits stay in the engine. Returns
+ * the first error of a submit or step (CYRUS_EINVAL for a NULL array or cell,
+ * CYRUS_ERANGE for arrival times out of order); requests already submitted
+ * then stay in the engine. */
+int cyrus_engine_run(cyrus_engine* eng, int32_t n, cyrus_codebook* const* cells, const cyrus_ue_state* ues,
+                     const double* arrival_us, uint8_t* const* results, double* latency_us);
+
 /* Counters: [0] submitted, [1] completed, [2] steps launched (resident worker:
  * worker launches), [3] admissions
  * deferred for memory, [4] admissions deferred for batch slots,

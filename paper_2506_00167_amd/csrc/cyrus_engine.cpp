@@ -841,10 +841,13 @@ int cyrus_engine_completed(cyrus_engine* e, int64_t* tickets, double* latency_us
     return CYRUS_OK;
 }
 
-int cyrus_engine_result(cyrus_engine* e, int64_t ticket, uint8_t* alloc, size_t bytes)
+}  // extern "C"
+
+namespace {
+
+// Copy a finished request's codebook to alloc (NULL: no copy) and release it.
+int release_result(cyrus_engine* e, int64_t ticket, uint8_t* alloc, size_t bytes)
 {
-    if (!e || !alloc)
-        return set_error(CYRUS_EINVAL, "NULL argument");
     auto it = e->by_ticket.find(ticket);
     if (it == e->by_ticket.end())
         return set_error(CYRUS_ERANGE, "unknown or released ticket");
@@ -853,15 +856,83 @@ int cyrus_engine_result(cyrus_engine* e, int64_t ticket, uint8_t* alloc, size_t 
         return set_error(CYRUS_ENOTREADY, "request not finished");
     const Shape& s = codebook_shape(r->cell);
     const size_t need = (size_t)s.nodes * s.E;
-    if (bytes < need)
+    if (alloc && bytes < need)
         return set_error(CYRUS_ERANGE, "result buffer too small");
-    std::memcpy(alloc, e->hpool + r->host_off, need);
+    if (alloc)
+        std::memcpy(alloc, e->hpool + r->host_off, need);
     e->hfree.release(r->host_off, r->host_bytes);
     e->by_ticket.erase(it);
     auto nd = std::find(e->newly_done.begin(), e->newly_done.end(), r);
     if (nd != e->newly_done.end())
         e->newly_done.erase(nd);
     delete r;
+    return CYRUS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cyrus_engine_result(cyrus_engine* e, int64_t ticket, uint8_t* alloc, size_t bytes)
+{
+    if (!e || !alloc)
+        return set_error(CYRUS_EINVAL, "NULL argument");
+    return release_result(e, ticket, alloc, bytes);
+}
+
+int cyrus_engine_run(cyrus_engine* e, int32_t n, cyrus_codebook* const* cells, const cyrus_ue_state* ues,
+                     const double* arrival_us, uint8_t* const* results, double* latency_us)
+{
+    if (!e || n < 0 || (n > 0 && (!cells || !ues || !arrival_us)))
+        return set_error(CYRUS_EINVAL, "NULL argument");
+    for (int32_t i = 0; i < n; ++i) {
+        if (!cells[i])
+            return set_error(CYRUS_EINVAL, "a cell handle is NULL");
+        if (!(arrival_us[i] >= 0.0) || (i > 0 && arrival_us[i] < arrival_us[i - 1]))
+            return set_error(CYRUS_ERANGE, "arrival_us must be non-negative and non-decreasing");
+    }
+    std::unordered_map<int64_t, int32_t> index;  // ticket -> request
+    index.reserve((size_t)n * 2);
+    const double t0 = now_us();
+    int32_t next = 0, done = 0;
+    while (done < n) {
+        // submit what has arrived
+        const double now = now_us() - t0;
+        while (next < n && arrival_us[next] <= now) {
+            int64_t ticket = 0;
+            const int rc = cyrus_engine_submit(e, cells[next], &ues[next], &ticket);
+            if (rc)
+                return rc;
+            index[ticket] = next++;
+        }
+        int32_t running = 0, waiting = 0;
+        int rc = cyrus_engine_step(e, &running, &waiting);
+        if (rc)
+            return rc;
+        // collect what has finished (requests of earlier submits are left alone)
+        for (auto it = e->newly_done.begin(); it != e->newly_done.end();) {
+            Request* r = *it;
+            auto f = index.find(r->ticket);
+            if (f == index.end()) {
+                ++it;
+                continue;
+            }
+            const int32_t i = f->second;
+            index.erase(f);
+            if (latency_us)
+                latency_us[i] = r->t_done - (t0 + arrival_us[i]);
+            it = e->newly_done.erase(it);
+            const Shape& s = codebook_shape(r->cell);
+            rc = release_result(e, r->ticket, results ? results[i] : nullptr, (size_t)s.nodes * s.E);
+            if (rc)
+                return rc;
+            ++done;
+        }
+        // nothing in flight: wait for the next arrival
+        if (running == 0 && waiting == 0 && done == next && next < n)
+            while (now_us() - t0 < arrival_us[next]) {
+            }
+    }
     return CYRUS_OK;
 }
 

@@ -42,7 +42,8 @@ SYMBOLS = (
     "cyrus_engine_create", "cyrus_engine_submit", "cyrus_engine_step", "cyrus_engine_set_levels_per_step",
     "cyrus_engine_set_resident",
     "cyrus_engine_poll",
-    "cyrus_engine_completed", "cyrus_engine_result", "cyrus_engine_stats", "cyrus_engine_destroy",
+    "cyrus_engine_completed", "cyrus_engine_result", "cyrus_engine_run", "cyrus_engine_stats",
+    "cyrus_engine_destroy",
 )
 REQ_WAITING, REQ_RUNNING, REQ_DONE = 0, 1, 2
 
@@ -155,6 +156,9 @@ def lib():
         L.cyrus_engine_completed.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
                                              ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
         L.cyrus_engine_result.argtypes = [vp, ctypes.c_int64, _u8p, sz]
+        L.cyrus_engine_run.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(vp), ctypes.POINTER(cyrus_ue_state),
+                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(vp),
+                                       ctypes.POINTER(ctypes.c_double)]
         L.cyrus_engine_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]
         L.cyrus_engine_destroy.argtypes = [vp]
         L.cyrus_engine_destroy.restype = None
@@ -467,6 +471,20 @@ def cyrus_engine_result(eng: int, ticket: int, nodes: int, num_ue: int) -> np.nd
     return out
 
 
+def cyrus_engine_run(eng: int, cells: Sequence[int], ues: Sequence[cyrus_ue_state], arrival_us,
+                     results: Optional[Sequence[int]] = None) -> np.ndarray:
+    """Native request loop; returns the latency of each request in us."""
+    n = len(cells)
+    hs = (ctypes.c_void_p * n)(*cells)
+    us = (cyrus_ue_state * n)(*ues)
+    arr = np.ascontiguousarray(arrival_us, dtype=np.float64)
+    lat = np.zeros(n, dtype=np.float64)
+    res = (ctypes.c_void_p * n)(*results) if results is not None else None
+    _check(lib().cyrus_engine_run(eng, n, hs, us, arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), res,
+                                  lat.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), "cyrus_engine_run")
+    return lat
+
+
 def cyrus_engine_stats(eng: int) -> dict:
     c = (ctypes.c_int64 * 7)()
     _check(lib().cyrus_engine_stats(eng, c, 7), "cyrus_engine_stats")
@@ -519,6 +537,15 @@ class Engine:
     def result(self, ticket: int) -> np.ndarray:
         cell = self._cells.pop(ticket)
         return cyrus_engine_result(self.handle, ticket, cell.num_nodes, cell.cfg.num_ue)
+
+    def run(self, cells: Sequence[Codebook], ues: Sequence[UEState], arrival_us, keep_results: bool = False):
+        """cyrus_engine_run: the whole request stream in the library's own
+        loop. Returns (latency_us per request, codebooks or None)."""
+        structs = [ue_struct(u) for u in ues]  # the arrays stay referenced for the call
+        outs = [np.zeros((c.num_nodes, c.cfg.num_ue), dtype=np.uint8) for c in cells] if keep_results else None
+        lat = cyrus_engine_run(self.handle, [c.handle for c in cells], [st for st, _ in structs], arrival_us,
+                               [o.ctypes.data for o in outs] if keep_results else None)
+        return lat, outs
 
     def stats(self) -> dict:
         return cyrus_engine_stats(self.handle)

@@ -47,10 +47,19 @@ def default_engine(max_active: int = 64, pool_mib: int = 256, stream=None, level
     return eng if resident else eng.set_levels_per_step(levels_per_step)
 
 
-def run_stream(engine, cells, requests, arrivals_s, keep_results: bool = False):
+def run_stream(engine, cells, requests, arrivals_s, keep_results: bool = False, native: bool = True):
     """Submit requests at their arrival times while stepping the engine.
-    Returns latency statistics (us), throughput and engine counters."""
+    Returns latency statistics (us), throughput and engine counters.
+    native: the library's own request loop (cyrus_engine_run); else a Python
+    loop over submit / step / completed / result."""
     n = len(requests)
+    if native:
+        arr_us = (np.asarray(arrivals_s, dtype=np.float64) - arrivals_s[0]) * 1e6
+        lat, outs = engine.run([cells[c] for c, _ in requests], [ue for _, ue in requests], arr_us, keep_results)
+        # the span on the loop's own clock: from its start to the last completion
+        span_s = float((arr_us + lat).max()) * 1e-6
+        return _stats(engine, cells, requests, arrivals_s, lat, span_s + arrivals_s[0], "native",
+                      dict(enumerate(outs)) if keep_results else None)
     t0 = time.perf_counter()
     sub_wall = {}
     lat_engine = {}
@@ -79,7 +88,12 @@ def run_stream(engine, cells, requests, arrivals_s, keep_results: bool = False):
     for t, l in lat_engine.items():
         idx, s = sub_wall[t]
         lat.append(l + (s - arrivals_s[idx]) * 1e6)  # count queueing before submit too
-    lat = np.array(lat)
+    return _stats(engine, cells, requests, arrivals_s, np.array(lat), wall, "python",
+                  results if keep_results else None)
+
+
+def _stats(engine, cells, requests, arrivals_s, lat, wall, loop, results):
+    n = len(requests)
     nodes = sum(cells[c].num_nodes for c, _ in requests)
     flops = sum(cells[c].cfg.flops_per_codebook for c, _ in requests)
     span = wall - arrivals_s[0]
@@ -93,16 +107,17 @@ def run_stream(engine, cells, requests, arrivals_s, keep_results: bool = False):
                        "p99.9": float(np.percentile(lat, 99.9)), "max": float(lat.max()),
                        "mean": float(lat.mean())},
         "misses_over_125us": int((lat > SLOT_US).sum()),
+        "request_loop": loop,
         "engine": engine.stats(),
     }
-    if keep_results:
+    if results is not None:
         out["results"] = results
     return out
 
 
-def saturation(engine, cells, requests):
+def saturation(engine, cells, requests, native: bool = True):
     """Everything submitted at t = 0: the engine's sustained throughput."""
-    return run_stream(engine, cells, requests, np.zeros(len(requests)))
+    return run_stream(engine, cells, requests, np.zeros(len(requests)), native=native)
 
 
 def main():
@@ -112,6 +127,8 @@ def main():
     ap.add_argument("--loads", default="0.25,0.5,0.75,0.9")
     ap.add_argument("--max-active", type=int, default=64)
     ap.add_argument("--pool-mib", type=int, default=256)
+    ap.add_argument("--python-loop", action="store_true",
+                    help="drive the engine from a Python loop instead of the library's cyrus_engine_run")
     ap.add_argument("--levels-per-step", default="0,1,7",
                     help="comma separated engine modes: 0 = the resident worker, 1 = host-stepped iteration-level "
                          "batching, 7 = each host step runs its requests to the end")
@@ -124,16 +141,17 @@ def main():
     for lps in [int(x) for x in args.levels_per_step.split(",")]:
         eng = default_engine(args.max_active, args.pool_mib, stream=stream, levels_per_step=max(lps, 1),
                              resident=lps == 0)
+        native = not args.python_loop
         warm = make_requests(cells, 200, seed=1)
-        saturation(eng, cells, warm)
+        saturation(eng, cells, warm, native=native)
         reqs = make_requests(cells, args.requests, seed=2)
-        sat = saturation(eng, cells, reqs)
+        sat = saturation(eng, cells, reqs, native=native)
         print(json.dumps({"mode": "saturation", "levels_per_step": lps, **sat}), flush=True)
         rate_sat = sat["served_req_per_s"]
         for load in [float(x) for x in args.loads.split(",")]:
             arr = wl.poisson_arrivals(load * rate_sat, args.requests, seed=424242)
             arr = arr - arr[0]
-            res = run_stream(eng, cells, make_requests(cells, args.requests, seed=3), arr)
+            res = run_stream(eng, cells, make_requests(cells, args.requests, seed=3), arr, native=native)
             print(json.dumps({"mode": "poisson", "levels_per_step": lps, "load": load, **res}), flush=True)
         # one request per cell per slot (8000 slots/s per cell)
         per_slot = 8000.0 * args.cells

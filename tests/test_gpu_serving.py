@@ -209,15 +209,37 @@ def test_batch_slot_admission(cells):
     eng.close()
 
 
-def test_poisson_stream_short(cells):
-    eng = serving.default_engine(max_active=64, pool_mib=256)
+@pytest.mark.parametrize("resident", [False, True])
+@pytest.mark.parametrize("native", [True, False])
+def test_poisson_stream_short(cells, resident, native):
+    # the library's own request loop (cyrus_engine_run) and the Python loop
+    # over submit / step / completed / result serve the same stream; every
+    # request completes, and with the resident worker both loops return the
+    # same codebooks
+    eng = serving.default_engine(max_active=64, pool_mib=256, resident=resident)
     reqs = serving.make_requests(cells, 300, seed=14)
     arr = wl.poisson_arrivals(20000.0, len(reqs))
     arr = arr - arr[0]
-    res = serving.run_stream(eng, cells, reqs, arr)
-    print(f"[serving] poisson 20k req/s: {json.dumps(res)}", flush=True)
-    assert res["engine"]["completed"] == 300
+    res = serving.run_stream(eng, cells, reqs, arr, keep_results=resident, native=native)
+    print(f"[serving] poisson 20k req/s, resident={resident}, native={native}: "
+          f"{json.dumps({k: v for k, v in res.items() if k != 'results'})}", flush=True)
+    assert res["engine"]["completed"] == 300 and res["engine"]["submitted"] == 300
+    assert res["request_loop"] == ("native" if native else "python")
     assert res["latency_us"]["p50"] > 0
+    if resident:
+        for i in (0, 150, 299):
+            c, ue = reqs[i]
+            assert np.array_equal(res["results"][i], _single_build(cells[c], ue)[0]), f"request {i}"
+    eng.close()
+
+
+def test_native_loop_refuses_bad_arrivals(cells):
+    eng = serving.default_engine(max_active=4, pool_mib=64)
+    reqs = serving.make_requests(cells, 3, seed=15)
+    with pytest.raises(cyrus.CyrusError) as ei:
+        eng.run([cells[c] for c, _ in reqs], [u for _, u in reqs], [0.0, 10.0, 5.0])
+    assert ei.value.status == -2
+    assert eng.stats()["submitted"] == 0  # refused before any submit
     eng.close()
 
 
