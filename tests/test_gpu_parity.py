@@ -308,6 +308,9 @@ def test_huntington_hill_fp32(shape, force_level):
     dict(num_ue=4, max_arrival=2, rb_per_unit=5, hidden=(128,)),
     dict(num_ue=16, max_arrival=4, num_minislots=3, hidden=(256, 256)),   # 2E = 32: two output tiles
     dict(num_ue=8, max_arrival=4, num_minislots=6, rb_per_unit=3, hidden=(128, 128)),  # 100-row levels
+    # the paper's own shape (Sec. VII): depth 1, E = 10, two arrival branches,
+    # one hidden layer of 128; 2E = 20 outputs take the level path
+    dict(num_ue=10, max_arrival=2, num_minislots=1, hidden=(128,)),
 ])
 @pytest.mark.parametrize("rounding", ["lr", "hh"])
 def test_gaussian_head_fp32(shape, rounding):
