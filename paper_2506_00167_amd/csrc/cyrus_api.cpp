@@ -378,20 +378,22 @@ static int load_weights(cyrus_codebook* cb, const cyrus_weights* w, hipStream_t 
     return CYRUS_OK;
 }
 
-static int enqueue_tree(cyrus_codebook* cb, const DevTree& t, hipStream_t stream)
+// The launches of one build. done (nullable) completes with the last launch
+// (it rides on that dispatch rather than following it as a separate marker).
+static int enqueue_tree(cyrus_codebook* cb, const DevTree& t, hipStream_t stream, hipEvent_t done)
 {
     if (cb->path == 1)
-        HIP_TRY(launch_subtree(t, cb->s.prec, stream));
+        HIP_TRY(launch_subtree(t, cb->s.prec, stream, done));
     else
         for (int tau = 1; tau <= cb->s.M; ++tau)
-            HIP_TRY(launch_level(t, cb->s.prec, cb->rtt, tau, stream));
+            HIP_TRY(launch_level(t, cb->s.prec, cb->rtt, tau, stream, tau == cb->s.M ? done : nullptr));
     return CYRUS_OK;
 }
 
-// The kernels of one build; the caller then records ev_done on `stream`.
-static int enqueue_kernels(cyrus_codebook* cb, const int32_t* ue_dev, hipStream_t stream)
+// The kernels of one build, `done` completing with the last of them.
+static int enqueue_kernels(cyrus_codebook* cb, const int32_t* ue_dev, hipStream_t stream, hipEvent_t done)
 {
-    int rc = enqueue_tree(cb, make_devtree(cb, ue_dev), stream);
+    int rc = enqueue_tree(cb, make_devtree(cb, ue_dev), stream, done);
     if (rc)
         return rc;
     HIP_TRY(note_build_use(cb, cb->active, stream));
@@ -530,12 +532,12 @@ int cyrus_codebook_build(cyrus_codebook* cb, const cyrus_ue_state* ue, void* str
         DevTree t = make_devtree(cb, reinterpret_cast<const int32_t*>(cb->host_dev + s.hoff_ue));
         t.alloc = cb->host_dev + s.hoff_alloc;
         t.logits = s.export_logits ? reinterpret_cast<float*>(cb->host_dev + s.hoff_logits) : nullptr;
-        rc = enqueue_tree(cb, t, st);
+        // ev_done completes with the launch; the kernel reads the staged UE
+        // state, so ev_done also releases it
+        rc = enqueue_tree(cb, t, st, cb->ev_done);
         if (rc)
             return rc;
-        // the kernel reads the staged UE state, so ev_done also releases it
         HIP_TRY(note_build_use(cb, cb->active, st));
-        HIP_TRY(hipEventRecord(cb->ev_done, st));
         cb->staged_is_done = true;
         cb->built = cb->pending = cb->mirror_valid = true;
         return CYRUS_OK;
@@ -545,7 +547,7 @@ int cyrus_codebook_build(cyrus_codebook* cb, const cyrus_ue_state* ue, void* str
     HIP_TRY(hipEventRecord(cb->ev_staged, st));
     cb->staged_recorded = true;
     cb->staged_is_done = false;
-    rc = enqueue_kernels(cb, ue_dev, st);
+    rc = enqueue_kernels(cb, ue_dev, st, nullptr);
     if (rc)
         return rc;
     HIP_TRY(hipMemcpyAsync(cb->host + s.hoff_alloc, cb->ws + s.off_alloc, (size_t)s.nodes * s.E,
@@ -566,10 +568,9 @@ int cyrus_codebook_build_device(cyrus_codebook* cb, const void* ue_device, void*
         return fail(CYRUS_EINVAL, "UE state must be 4-byte aligned");
     HIP_TRY(hipSetDevice(cb->device));
     hipStream_t st = static_cast<hipStream_t>(stream);
-    int rc = enqueue_kernels(cb, static_cast<const int32_t*>(ue_device), st);
+    int rc = enqueue_kernels(cb, static_cast<const int32_t*>(ue_device), st, cb->ev_done);  // ev_done rides on the last launch
     if (rc)
         return rc;
-    HIP_TRY(hipEventRecord(cb->ev_done, st));
     cb->built = cb->pending = true;
     cb->mirror_valid = false;
     return CYRUS_OK;

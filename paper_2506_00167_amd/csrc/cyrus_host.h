@@ -64,7 +64,9 @@ bool subtree_supported(const DevTree& t, int prec);
 // The resident worker's subtree units (roots at level `split`): whether the
 // tree has the shape the worker's instantiation carries, and its LDS plan.
 bool plan_subtree_units(const DevTree& t, int prec, int split, int* bufsize, int* stbytes, size_t* lds);
-hipError_t launch_subtree(const DevTree& t, int prec, hipStream_t s);
+// done (nullable): an event that completes with the launch (the kernel's own
+// completion signal, so no separate marker follows it in the stream)
+hipError_t launch_subtree(const DevTree& t, int prec, hipStream_t s, hipEvent_t done = nullptr);
 
 }  // namespace cyrus
 

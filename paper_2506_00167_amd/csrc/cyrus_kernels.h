@@ -14,7 +14,9 @@ size_t level_lds_bytes(const DevTree& t, int prec, int rtt);
 // Row tiles per workgroup (rtt), activation-buffer bytes and LDS bytes of one
 // batched level launch over trees[0..n): the largest rtt whose LDS fits.
 bool plan_level_batch(const DevTree* trees, int n, int prec, int* rtt, int* buf, size_t* lds);
-hipError_t launch_level(const DevTree& t, int prec, int rtt, int tau, hipStream_t s);
+// done (nullable): an event that completes with this launch (the kernel's own
+// completion signal, so no separate marker follows it in the stream)
+hipError_t launch_level(const DevTree& t, int prec, int rtt, int tau, hipStream_t s, hipEvent_t done = nullptr);
 // Batched: entry j is codebook ent_tree[j] at level ent_tau[j], owning
 // workgroups [prefix[j], prefix[j+1]) of an nblocks = prefix[n] launch.
 hipError_t launch_level_batch(const DevTree* trees, const int* ent_tree, const int* ent_tau, const int* prefix, int n,

@@ -10,6 +10,8 @@
 // level's states), so waves meet at LDS-only barriers.
 #include <algorithm>
 
+#include <hip/hip_ext.h>
+
 #include "cyrus_device.h"
 #include "cyrus_kernels.h"
 #include "cyrus_mlp.h"
@@ -826,7 +828,7 @@ bool plan_level_batch(const DevTree* trees, int n, int prec, int* rtt, int* buf,
 }
 
 template <int P, int RTT>
-static hipError_t launch_level_t(const DevTree& t, int tau, hipStream_t s)
+static hipError_t launch_level_t(const DevTree& t, int tau, hipStream_t s, hipEvent_t done)
 {
     const int n_eval = (int)(t.K * ipow(t.K + 1, tau - 1));
     const int grid = (n_eval + 16 * RTT - 1) / (16 * RTT);
@@ -838,7 +840,11 @@ static hipError_t launch_level_t(const DevTree& t, int tau, hipStream_t s)
                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         attr = true;
     }
-    hipLaunchKernelGGL((level_kernel<P, RTT>), dim3(grid), dim3(kThreads), lds, s, t, tau, n_eval, buf);
+    if (done)
+        hipExtLaunchKernelGGL((level_kernel<P, RTT>), dim3(grid), dim3(kThreads), lds, s, nullptr, done, 0, t, tau,
+                              n_eval, buf);
+    else
+        hipLaunchKernelGGL((level_kernel<P, RTT>), dim3(grid), dim3(kThreads), lds, s, t, tau, n_eval, buf);
     return hipGetLastError();
 }
 
@@ -867,11 +873,11 @@ static hipError_t launch_level_batch_t(const DevTree* trees, const int* ent_tree
     return hipGetLastError();
 }
 
-hipError_t launch_level(const DevTree& t, int prec, int rtt, int tau, hipStream_t s)
+hipError_t launch_level(const DevTree& t, int prec, int rtt, int tau, hipStream_t s, hipEvent_t done)
 {
 #define CYRUS_LEVEL_CASE(P, R)                                                                                         \
     if (prec == P && rtt == R)                                                                                         \
-        return launch_level_t<P, R>(t, tau, s);
+        return launch_level_t<P, R>(t, tau, s, done);
     CYRUS_LEVEL_CASE(kFP32, 1) CYRUS_LEVEL_CASE(kFP32, 2) CYRUS_LEVEL_CASE(kFP32, 4)
     CYRUS_LEVEL_CASE(kBF16, 1) CYRUS_LEVEL_CASE(kBF16, 2) CYRUS_LEVEL_CASE(kBF16, 4) CYRUS_LEVEL_CASE(kBF16, 6)
     CYRUS_LEVEL_CASE(kFP8, 1) CYRUS_LEVEL_CASE(kFP8, 2) CYRUS_LEVEL_CASE(kFP8, 4) CYRUS_LEVEL_CASE(kFP8, 6)

@@ -3,6 +3,8 @@
 // hidden layers, E <= 16). The tree is cut at level L: workgroup r (one per
 // CU) runs the subtree algorithm (cyrus_subtree.h) for the subtree below node
 // r of level L.
+#include <hip/hip_ext.h>
+
 #include "cyrus_device.h"
 #include "cyrus_host.h"
 #include "cyrus_subtree.h"
@@ -104,7 +106,7 @@ bool plan_subtree(const DevTree& t, int prec, SubtreePlan& pl)
 }
 
 template <int P, int T, int CH1, int CHH, int NHH>
-hipError_t launch_t(const DevTree& t, const SubtreePlan& pl, hipStream_t s)
+hipError_t launch_t(const DevTree& t, const SubtreePlan& pl, hipStream_t s, hipEvent_t done)
 {
     static bool attr = false;
     if (!attr) {
@@ -114,9 +116,19 @@ hipError_t launch_t(const DevTree& t, const SubtreePlan& pl, hipStream_t s)
                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         attr = true;
     }
-    if (t.head == kGaussianHead || t.rounding == kHuntingtonHill)
+    // with `done`, the event rides on the dispatch itself: an event recorded
+    // after the launch would put a marker into the stream that costs about
+    // 3 us of GPU time per build between back-to-back launches
+    const bool ext = t.head == kGaussianHead || t.rounding == kHuntingtonHill;
+    if (ext && done)
+        hipExtLaunchKernelGGL((subtree_kernel<P, T, CH1, CHH, NHH, true>), dim3(pl.grid), dim3(kThreads), pl.lds, s,
+                              nullptr, done, 0, t, pl.split, pl.bufsize, pl.stbytes);
+    else if (ext)
         hipLaunchKernelGGL((subtree_kernel<P, T, CH1, CHH, NHH, true>), dim3(pl.grid), dim3(kThreads), pl.lds, s, t,
                            pl.split, pl.bufsize, pl.stbytes);
+    else if (done)
+        hipExtLaunchKernelGGL((subtree_kernel<P, T, CH1, CHH, NHH, false>), dim3(pl.grid), dim3(kThreads), pl.lds, s,
+                              nullptr, done, 0, t, pl.split, pl.bufsize, pl.stbytes);
     else
         hipLaunchKernelGGL((subtree_kernel<P, T, CH1, CHH, NHH, false>), dim3(pl.grid), dim3(kThreads), pl.lds, s, t,
                            pl.split, pl.bufsize, pl.stbytes);
@@ -124,14 +136,14 @@ hipError_t launch_t(const DevTree& t, const SubtreePlan& pl, hipStream_t s)
 }
 
 template <int P, int CH1>
-hipError_t dispatch_width(const DevTree& t, const SubtreePlan& pl, hipStream_t s)
+hipError_t dispatch_width(const DevTree& t, const SubtreePlan& pl, hipStream_t s, hipEvent_t done)
 {
     constexpr int kc = Traits<P>::kChunk;
     const int H = t.out_pad[0];
     const bool two = t.n_layers == 3;
     if (H == 256)
-        return two ? launch_t<P, 2, CH1, 256 / kc, 1>(t, pl, s) : launch_t<P, 2, CH1, 256 / kc, 0>(t, pl, s);
-    return two ? launch_t<P, 1, CH1, 128 / kc, 1>(t, pl, s) : launch_t<P, 1, CH1, 128 / kc, 0>(t, pl, s);
+        return two ? launch_t<P, 2, CH1, 256 / kc, 1>(t, pl, s, done) : launch_t<P, 2, CH1, 256 / kc, 0>(t, pl, s, done);
+    return two ? launch_t<P, 1, CH1, 128 / kc, 1>(t, pl, s, done) : launch_t<P, 1, CH1, 128 / kc, 0>(t, pl, s, done);
 }
 
 }  // namespace
@@ -158,7 +170,7 @@ bool subtree_supported(const DevTree& t, int prec)
     return plan_subtree(t, prec, pl);
 }
 
-hipError_t launch_subtree(const DevTree& t, int prec, hipStream_t s)
+hipError_t launch_subtree(const DevTree& t, int prec, hipStream_t s, hipEvent_t done)
 {
     SubtreePlan pl;
     if (!plan_subtree(t, prec, pl))
@@ -166,10 +178,10 @@ hipError_t launch_subtree(const DevTree& t, int prec, hipStream_t s)
     // register arrays are sized by the exact chunk count of the per-node inputs
     const int nch1 = t.in_pad_d / prec_chunk(prec);
     if (prec == kFP32)
-        return nch1 == 1 ? dispatch_width<kFP32, 1>(t, pl, s) : dispatch_width<kFP32, 2>(t, pl, s);
+        return nch1 == 1 ? dispatch_width<kFP32, 1>(t, pl, s, done) : dispatch_width<kFP32, 2>(t, pl, s, done);
     if (prec == kBF16)
-        return dispatch_width<kBF16, 1>(t, pl, s);
-    return dispatch_width<kFP8, 2>(t, pl, s);
+        return dispatch_width<kBF16, 1>(t, pl, s, done);
+    return dispatch_width<kFP8, 2>(t, pl, s, done);
 }
 
 }  // namespace cyrus
