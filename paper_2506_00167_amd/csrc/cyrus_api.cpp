@@ -339,7 +339,7 @@ static int load_weights(cyrus_codebook* cb, const cyrus_weights* w, hipStream_t 
     for (auto& u : cb->slot_use[target])
         HIP_TRY(hipEventSynchronize(u.second));
     if (cb->done_slot == target)
-        HIP_TRY(hipEventSynchronize(cb->ev_done));
+        HIP_TRY(hipEventSynchronize(cb->done_event()));
     uint8_t* wb = cb->ws + s.off_w[target];
     float* staging = reinterpret_cast<float*>(cb->ws + s.off_staging);
     cb->pack.assign(s.staging_floats, 0.f);
@@ -504,7 +504,7 @@ static int stage_ue(cyrus_codebook* cb, const cyrus_ue_state* ue)
             return fail(CYRUS_EINVAL, "sinr_db[%d] is not finite", e);
     }
     if (cb->staged_is_done)
-        HIP_TRY(wait_event(cb->ev_done));
+        HIP_TRY(wait_event(cb->done_event()));
     else if (cb->staged_recorded)
         HIP_TRY(hipEventSynchronize(cb->ev_staged));
     int32_t* st = reinterpret_cast<int32_t*>(cb->host + cb->s.hoff_ue);
@@ -534,6 +534,7 @@ int cyrus_codebook_build(cyrus_codebook* cb, const cyrus_ue_state* ue, void* str
         t.logits = s.export_logits ? reinterpret_cast<float*>(cb->host_dev + s.hoff_logits) : nullptr;
         // ev_done completes with the launch; the kernel reads the staged UE
         // state, so ev_done also releases it
+        cb->batch_done.reset();
         rc = enqueue_tree(cb, t, st, cb->ev_done);
         if (rc)
             return rc;
@@ -547,6 +548,7 @@ int cyrus_codebook_build(cyrus_codebook* cb, const cyrus_ue_state* ue, void* str
     HIP_TRY(hipEventRecord(cb->ev_staged, st));
     cb->staged_recorded = true;
     cb->staged_is_done = false;
+    cb->batch_done.reset();
     rc = enqueue_kernels(cb, ue_dev, st, nullptr);
     if (rc)
         return rc;
@@ -568,6 +570,7 @@ int cyrus_codebook_build_device(cyrus_codebook* cb, const void* ue_device, void*
         return fail(CYRUS_EINVAL, "UE state must be 4-byte aligned");
     HIP_TRY(hipSetDevice(cb->device));
     hipStream_t st = static_cast<hipStream_t>(stream);
+    cb->batch_done.reset();
     int rc = enqueue_kernels(cb, static_cast<const int32_t*>(ue_device), st, cb->ev_done);  // ev_done rides on the last launch
     if (rc)
         return rc;
@@ -581,7 +584,7 @@ int cyrus_codebook_wait(cyrus_codebook* cb)
     if (!cb)
         return fail(CYRUS_EINVAL, "handle is NULL");
     if (cb->pending) {
-        HIP_TRY(wait_event(cb->ev_done));
+        HIP_TRY(wait_event(cb->done_event()));
         cb->pending = false;
     }
     return CYRUS_OK;
@@ -594,7 +597,7 @@ static int sync_mirror(const cyrus_codebook* cb)
     if (!cb->built)
         return fail(CYRUS_ENOTREADY, "no build has been enqueued on this handle");
     if (cb->pending) {
-        HIP_TRY(wait_event(cb->ev_done));
+        HIP_TRY(wait_event(cb->done_event()));
         cb->pending = false;
     }
     if (!cb->mirror_valid) {
@@ -704,7 +707,7 @@ void cyrus_codebook_destroy(cyrus_codebook* cb)
         return;
     (void)hipSetDevice(cb->device);
     if (cb->pending)
-        (void)hipEventSynchronize(cb->ev_done);
+        (void)hipEventSynchronize(cb->done_event());
     if (cb->staged_recorded)
         (void)hipEventSynchronize(cb->ev_staged);
     (void)hipEventDestroy(cb->ev_staged);

@@ -41,7 +41,11 @@ static BatchLayout batch_layout()
     return b;
 }
 
-int build_batch_levels(cyrus_codebook* const* cbs, const DevTree* trees, int n, hipStream_t st)
+// The level launches of a batch. The first handle's staging event (its
+// descriptor tables in pinned memory may be rewritten once the copy out of
+// them is done) completes when the first launch starts; done (nullable)
+// completes with the last launch.
+int build_batch_levels(cyrus_codebook* const* cbs, const DevTree* trees, int n, hipStream_t st, hipEvent_t done)
 {
     cyrus_codebook* host_cb = cbs[0];
     const int prec = host_cb->s.prec;
@@ -88,17 +92,16 @@ int build_batch_levels(cyrus_codebook* const* cbs, const DevTree* trees, int n, 
     hipError_t e = hipMemcpyAsync(dbase, hbase, bytes, hipMemcpyHostToDevice, st);
     if (e != hipSuccess)
         return hip_fail(e, "hipMemcpyAsync(batch descriptors)");
-    e = hipEventRecord(host_cb->ev_staged, st);
-    if (e != hipSuccess)
-        return hip_fail(e, "hipEventRecord");
-    host_cb->staged_recorded = true;
     const DevTree* dtrees = reinterpret_cast<const DevTree*>(dbase + L.trees);
     for (int tau = 1; tau <= max_m; ++tau) {
         const int32_t* slot = reinterpret_cast<const int32_t*>(dbase + L.slot0 + (tau - 1) * L.slot_bytes);
         e = launch_level_batch(dtrees, slot, slot + kMaxBatch, slot + 2 * kMaxBatch, entries[tau], blocks[tau], prec,
-                               rtt, buf, lds, st);
+                               rtt, buf, lds, st, tau == 1 ? host_cb->ev_staged : nullptr,
+                               tau == max_m ? done : nullptr);
         if (e != hipSuccess)
             return hip_fail(e, "level batch launch");
+        if (tau == 1)
+            host_cb->staged_recorded = true;
     }
     return CYRUS_OK;
 }
@@ -150,15 +153,20 @@ extern "C" int cyrus_codebook_build_batch_device(cyrus_codebook* const* cbs, con
     if (e != hipSuccess)
         return hip_fail(e, "hipSetDevice");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    rc = build_batch_levels(cbs, trees, n, st);
+    // one completion event for the whole batch, carried by its last launch
+    hipEvent_t ev = nullptr;
+    e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e != hipSuccess)
+        return hip_fail(e, "hipEventCreateWithFlags");
+    std::shared_ptr<std::remove_pointer_t<hipEvent_t>> done(ev, [](hipEvent_t x) { (void)hipEventDestroy(x); });
+    rc = build_batch_levels(cbs, trees, n, st, ev);
     if (rc)
         return rc;
     for (int i = 0; i < n; ++i) {
         e = note_build_use(cbs[i], cbs[i]->active, st);
-        if (e == hipSuccess)
-            e = hipEventRecord(cbs[i]->ev_done, st);
         if (e != hipSuccess)
-            return hip_fail(e, "hipEventRecord");
+            return hip_fail(e, "weight buffer use");
+        cbs[i]->batch_done = done;
         cbs[i]->built = cbs[i]->pending = true;
         cbs[i]->mirror_valid = false;
     }
@@ -199,11 +207,12 @@ extern "C" int cyrus_codebook_build_batch(cyrus_codebook* const* cbs, const cyru
         if (e != hipSuccess)
             return hip_fail(e, "hipMemcpyAsync(UE state)");
     }
-    rc = build_batch_levels(cbs, trees, n, st);
+    rc = build_batch_levels(cbs, trees, n, st, nullptr);
     if (rc)
         return rc;
     for (int i = 0; i < n; ++i) {
         cyrus_codebook* cb = cbs[i];
+        cb->batch_done.reset();  // ev_done, recorded after this handle's copies, completes the build
         const Shape& s = cb->s;
         e = hipEventRecord(cb->ev_staged, st);  // the UE copy out of the pinned buffer
         if (e == hipSuccess)

@@ -6,6 +6,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <memory>
+#include <type_traits>
 #include <utility>
 #include <vector>
 
@@ -83,19 +85,26 @@ struct cyrus_codebook {
     float inv_in[2][cyrus::kMaxLayers];  // per weight buffer: FP8 1 / input scale, else 1
     hipEvent_t ev_staged = nullptr;
     hipEvent_t ev_done = nullptr;
+    // A device batch completes all its codebooks with one event, carried by
+    // its last launch and shared by the handles it built (recording one
+    // event per codebook after the batch put a marker into the stream for
+    // each, several microseconds of GPU time apiece); a single build clears it.
+    std::shared_ptr<std::remove_pointer_t<hipEvent_t>> batch_done;
+    // The event that completes with the handle's last build.
+    hipEvent_t done_event() const { return batch_done ? batch_done.get() : ev_done; }
     bool staged_recorded = false;
     bool built = false;
     mutable bool pending = false;       // a build may still run (cleared by a wait)
     mutable bool mirror_valid = false;  // the pinned mirror holds the last build
     // Last use of each weight buffer: one event per stream that enqueued work
     // reading it. set_weights waits for these before overwriting a buffer.
-    // The builds of the handle itself mark their use with ev_done (the weight
-    // buffer done_slot on stream done_stream), so a build records one event;
-    // an entry in slot_use is recorded only when ev_done moves to another
-    // stream or buffer.
+    // The builds of the handle itself mark their use with done_event() (the
+    // weight buffer done_slot on stream done_stream), so a build needs no
+    // event of its own for it; an entry in slot_use is recorded only when
+    // builds move to another stream or buffer.
     std::vector<std::pair<hipStream_t, hipEvent_t>> slot_use[2];
     hipStream_t done_stream = nullptr;
-    int done_slot = -1;  // -1: ev_done marks no build
+    int done_slot = -1;  // -1: done_event() marks no build
     bool staged_is_done = false;  // the last host build's staging is released by ev_done
     // Serving-engine requests admitted with each weight buffer and not yet
     // retired (their next launches are not enqueued yet, so no event covers

@@ -270,6 +270,34 @@ def test_stress_batch_equals_single_and_oracle():
         c.close()
 
 
+def test_batch_completion_event_covers_every_codebook():
+    # A device batch completes all its codebooks with one event carried by
+    # its last launch: export (which waits for the handle's last build)
+    # right after the enqueue, with no device synchronization, must see each
+    # whole codebook; a later single build of one handle waits on its own
+    # event again, and a host-state batch after it re-uses the staging area.
+    import torch
+    from paper_2506_00167_amd import stress
+    cfg, cells_, ues = stress.make_cells(n=8)
+    cyrus.build_batch_device(cells_, ues)
+    torch.cuda.synchronize()
+    ref = [c.export()[0] for c in cells_]
+    for rep in range(3):
+        cyrus.build_batch_device(cells_, ues)
+        for j, c in enumerate(cells_):  # no synchronize: export waits for the batch's event
+            assert np.array_equal(c.export()[0], ref[j]), f"repeat {rep}, cell {j}"
+    cells_[3].build_device(ues[3])
+    assert np.array_equal(cells_[3].export()[0], ref[3])
+    host_ues = [wl.make_ue_state(cfg.num_ue, 5_000_000 + j) for j in range(8)]
+    for rep in range(2):
+        cyrus.build_batch(cells_, host_ues)
+        for j, c in enumerate(cells_):
+            c.wait()
+            assert np.array_equal(c.export()[0], ref[j]), f"host batch {rep}, cell {j}"
+    for c in cells_:
+        c.close()
+
+
 def test_oversize_request_is_refused(cells):
     """A request whose tree can never fit the pools is refused at submit, so
     it cannot block the FIFO; later requests still complete."""
