@@ -549,6 +549,21 @@ int cyrus_codebook_build(cyrus_codebook* cb, const cyrus_ue_state* ue, void* str
     cb->staged_recorded = true;
     cb->staged_is_done = false;
     cb->batch_done.reset();
+    if (cb->host_dev) {
+        // level path, no copies back: the UE state goes to the device once
+        // (every tile of every level reads it), and the level kernels write
+        // the codebook (and logits) straight into the pinned mirror, whose
+        // root row is zero from create; ev_done completes with the last level
+        DevTree t = make_devtree(cb, ue_dev);
+        t.alloc = cb->host_dev + s.hoff_alloc;
+        t.logits = s.export_logits ? reinterpret_cast<float*>(cb->host_dev + s.hoff_logits) : nullptr;
+        rc = enqueue_tree(cb, t, st, cb->ev_done);
+        if (rc)
+            return rc;
+        HIP_TRY(note_build_use(cb, cb->active, st));
+        cb->built = cb->pending = cb->mirror_valid = true;
+        return CYRUS_OK;
+    }
     rc = enqueue_kernels(cb, ue_dev, st, nullptr);
     if (rc)
         return rc;
