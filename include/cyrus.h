@@ -152,15 +152,20 @@ int cyrus_codebook_set_weights(cyrus_codebook* cb, const cyrus_weights* w, void*
  * host UE arrays are copied into the pinned buffer before returning; then, on
  * the single-launch path, one kernel reads them from the pinned buffer and
  * writes the codebook (and the logits if exported) straight into the pinned
- * mirror; on the level path, host-to-device copy, kernels and device-to-host
- * copy are enqueued. An event is recorded either way. The device array
- * (cyrus_codebook_device_alloc) is only written by device builds. */
+ * mirror; on the level path, the UE state is copied to the device and the
+ * level kernels write the codebook (and logits) straight into the pinned
+ * mirror too (when the pinned buffer is mapped for the device; else device-to-
+ * host copies follow them). The handle's completion event, which
+ * cyrus_codebook_wait waits for, completes with the last kernel (or copy).
+ * The device array (cyrus_codebook_device_alloc) is only written by device
+ * builds. */
 int cyrus_codebook_build(cyrus_codebook* cb, const cyrus_ue_state* ue, void* stream);
 
 /* Device-resident variant: the UE state is already in device memory as
  * int32 rb[E], int32 mcs[E], float sinr_db[E] (contiguous, 4-byte aligned) and
  * the codebook stays in the device workspace (cyrus_codebook_device_alloc);
- * nothing is copied to the host. Records the same event. */
+ * nothing is copied to the host. The completion event completes with the
+ * last kernel. */
 int cyrus_codebook_build_device(cyrus_codebook* cb, const void* ue_device, void* stream);
 
 /* Build n codebooks in shared launches on one stream (cells batched per
@@ -178,8 +183,10 @@ int cyrus_codebook_build_batch(cyrus_codebook* const* cbs, const cyrus_ue_state*
 
 /* Device-resident batch: ue_device holds n pointers to device UE states laid
  * out as for cyrus_codebook_build_device (4-byte aligned). Results stay in
- * each handle's workspace (cyrus_codebook_device_alloc); each handle's event is
- * recorded after the last launch. Same checks as cyrus_codebook_build_batch. */
+ * each handle's workspace (cyrus_codebook_device_alloc); one event, which
+ * completes with the batch's last launch, serves as every member's completion
+ * event (until the member's next build). Same checks as
+ * cyrus_codebook_build_batch. */
 int cyrus_codebook_build_batch_device(cyrus_codebook* const* cbs, const void* const* ue_device, int32_t n,
                                       void* stream);
 
