@@ -401,8 +401,8 @@ int cyrus_engine_set_levels_per_step(cyrus_engine* eng, int32_t levels);
  * into free slots and pool memory, and relaunches the worker when it has
  * exited with requests waiting. The worker leaves after 20 ms with nothing to
  * do, after 2 s without progress, after admitting 2,048 requests (the host then
- * relaunches it), or when the engine is destroyed (requests still in flight are
- * then abandoned). Up to 128 requests are in flight. Results are bit-identical
+ * relaunches it), or when the engine is destroyed; it first finishes every
+ * request it has admitted (on destroy, their results are dropped). Up to 128 requests are in flight. Results are bit-identical
  * to the same request alone (every request runs the same tile code whatever
  * the mix). CYRUS_EINVAL after a submit or for on = 0 once resident;
  * CYRUS_EWORKSPACE if the pools cannot hold the worker's tables (about

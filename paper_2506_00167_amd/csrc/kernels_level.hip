@@ -424,11 +424,13 @@ __global__ __launch_bounds__(kThreads) void level_kernel_batch(const DevTree* __
 // (Scanning every slot on every poll, each a load past the per-XCD caches,
 // kept the fabric busy enough to slow the loads of the workgroups at work.)
 //
-// Exits: the host's stop flag, which only the control workgroup reads; it
-// leaves on it, after idle_ticks of wall-clock time with no request in
-// flight and none in the ring, or after stall_ticks with requests in flight
-// and none finishing, and then sets quit; the tile workgroups leave when they
-// find no work and quit is set, or after stall_ticks idle.
+// Exits: the control workgroup leaves on the host's stop flag, which only it
+// reads, when every record of the launch is used, after idle_ticks of
+// wall-clock time with no request in flight and none in the ring, or after
+// stall_ticks with requests in flight and none finishing, and then sets quit;
+// the tile workgroups leave once quit is set and every admitted request has
+// finished (they run the later levels of those requests at full width), or
+// after stall_ticks without a tile.
 
 __device__ __forceinline__ uint32_t sys_load_u32(const uint32_t* p)
 {
@@ -611,10 +613,14 @@ __global__ __launch_bounds__(kThreads) void serve_kernel(ServeArgs a, const Serv
             if (tid == 0) {
                 sh[8] = (int)dev_load(&a.ctl->opened);
                 sh[9] = dev_load(&a.ctl->quit);
+                sh[12] = dev_load(&a.ctl->active);
             }
             __syncthreads();
             const uint32_t op = (uint32_t)sh[8];
-            const int quit = sh[9];
+            // the control workgroup has left and no admitted request is
+            // unfinished (leaving while some are would leave their later
+            // levels to the few workgroups still at work)
+            const int quit = sh[9] && sh[12] == 0;
             __syncthreads();
             if (worked || op != seen) {
                 seen = op;  // read before the scan: a level opened after it changes opened

@@ -270,6 +270,25 @@ def test_stress_batch_equals_single_and_oracle():
         c.close()
 
 
+def test_resident_relaunch_after_record_table_keeps_full_width(cells):
+    # A worker launch admits at most 2,048 requests; the next request makes
+    # it stop admitting and leave, and the host relaunches it. Its tile
+    # workgroups must stay until every admitted request has finished: had they
+    # left at once, the later levels of the requests in flight (hundreds of
+    # tiles for the 512-wide K = 4 cells) would fall to the few workgroups
+    # still at work, and the requests queued behind them would wait tens of
+    # milliseconds.
+    eng = serving.default_engine(max_active=128, pool_mib=256, resident=True)
+    reqs = serving.make_requests(cells, 2300, seed=16)
+    arr = wl.poisson_arrivals(12000.0, len(reqs), seed=17)
+    res = serving.run_stream(eng, cells, reqs, arr - arr[0])
+    print(f"[serving] 2300 requests at 12k req/s: {json.dumps(res)}", flush=True)
+    assert res["engine"]["completed"] == 2300
+    assert res["engine"]["steps"] >= 2  # the record table ran out at least once
+    assert res["latency_us"]["max"] < 15000.0, res["latency_us"]
+    eng.close()
+
+
 def test_batch_completion_event_covers_every_codebook():
     # A device batch completes all its codebooks with one event carried by
     # its last launch: export (which waits for the handle's last build)
