@@ -166,12 +166,19 @@ def run_leg(precision: str, steps: int, warmup: int, latency_builds: int, stream
     torch.cuda.synchronize()
     dev_us = np.array([a.elapsed_time(b) * 1e3 for a, b in ev])
 
-    # latency: one build at a time, host clock around enqueue + completion.
+    # latency: one build at a time, host clock around enqueue + completion,
+    # a new UE state for every build (seeded, as the throughput states are).
     # Host-inclusive builds (the paper's definition: s(t) in host memory ->
     # codebook in pinned host memory) get their own warm-up, which touches the
     # pinned mirror and the mapped UE staging first; the Python collector is
     # off while timing so that its pauses do not land in a sample.
-    ue_structs = [cyrus.ue_struct(u) for u in ues]
+    lat_ues = [wl.make_ue_state(cfg.num_ue, wl.ue_seed(64 + i)) for i in range(latency_builds)]
+    ue_structs = [cyrus.ue_struct(u) for u in lat_ues]
+    packed = np.stack([np.concatenate([np.asarray(u.rb, np.int32), np.asarray(u.mcs, np.int32),
+                                       np.asarray(u.sinr_db, np.float32).view(np.int32)]) for u in lat_ues])
+    lat_dev_ues = torch.from_numpy(packed).to("cuda")  # one row per build, the layout of ue_device_tensor
+    torch.cuda.synchronize()
+    row_bytes = lat_dev_ues.shape[1] * 4
     for i in range(max(warmup, 1)):
         cb.build(ues[i % 64])
         cb.wait()
@@ -179,13 +186,14 @@ def run_leg(precision: str, steps: int, warmup: int, latency_builds: int, stream
     gc_was = gc.isenabled()
     gc.disable()
     try:
+        base = lat_dev_ues.data_ptr()
         for i in range(latency_builds):
             t = time.perf_counter()
-            cb.build_device(ue_dev[i % 64])
+            cyrus.cyrus_codebook_build_device(cb.handle, base + i * row_bytes, cb.stream)
             cb.wait()
             lat_dev.append((time.perf_counter() - t) * 1e6)
         for i in range(latency_builds):
-            st = ue_structs[i % 64][0]
+            st = ue_structs[i][0]
             t = time.perf_counter()
             cyrus.cyrus_codebook_build(cb.handle, st, cb.stream)
             cb.wait()
@@ -377,7 +385,7 @@ def stress_leg(iters: int, stream):
 
     cfg, cells, ues = stress.make_cells(stream=stream)
     torch.cuda.synchronize()
-    for _ in range(3):
+    for _ in range(20):
         cyrus.build_batch_device(cells, ues, stream)
     torch.cuda.synchronize()
     start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -467,7 +475,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--latency-builds", type=int, default=2000)
+    ap.add_argument("--latency-builds", type=int, default=10000,
+                    help="one-at-a-time builds per leg for the latency distribution, a new UE state each")
     ap.add_argument("--cpu-seconds", type=float, default=8.0,
                     help="seconds of oracle work per CPU-baseline sample (one thread, then all threads)")
     ap.add_argument("--cpu-threads", type=int, default=0,
@@ -475,7 +484,7 @@ def main():
                          "at most 16)")
     ap.add_argument("--no-stress", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--stress-iters", type=int, default=20)
+    ap.add_argument("--stress-iters", type=int, default=200)
     ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--legs", default="fp32,bf16,fp8")
     ap.add_argument("--context-legs",
