@@ -285,7 +285,9 @@ def test_resident_relaunch_after_record_table_keeps_full_width(cells):
     print(f"[serving] 2300 requests at 12k req/s: {json.dumps(res)}", flush=True)
     assert res["engine"]["completed"] == 2300
     assert res["engine"]["steps"] >= 2  # the record table ran out at least once
-    assert res["latency_us"]["max"] < 15000.0, res["latency_us"]
+    # the stall delayed every request queued behind the narrowed launch (p99
+    # in the tens of milliseconds); a single slow request is another matter
+    assert res["latency_us"]["p99"] < 5000.0, res["latency_us"]
     eng.close()
 
 
