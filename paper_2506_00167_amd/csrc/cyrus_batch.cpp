@@ -43,8 +43,9 @@ static BatchLayout batch_layout()
 
 // The level launches of a batch. The first handle's staging event (its
 // descriptor tables in pinned memory may be rewritten once the copy out of
-// them is done) completes when the first launch starts; done (nullable)
-// completes with the last launch.
+// them is done) follows that copy; done (nullable) completes with the last
+// launch. (A start event carried by the first launch instead of the staging
+// marker measured slower on the latency path.)
 int build_batch_levels(cyrus_codebook* const* cbs, const DevTree* trees, int n, hipStream_t st, hipEvent_t done)
 {
     cyrus_codebook* host_cb = cbs[0];
@@ -92,16 +93,17 @@ int build_batch_levels(cyrus_codebook* const* cbs, const DevTree* trees, int n, 
     hipError_t e = hipMemcpyAsync(dbase, hbase, bytes, hipMemcpyHostToDevice, st);
     if (e != hipSuccess)
         return hip_fail(e, "hipMemcpyAsync(batch descriptors)");
+    e = hipEventRecord(host_cb->ev_staged, st);
+    if (e != hipSuccess)
+        return hip_fail(e, "hipEventRecord");
+    host_cb->staged_recorded = true;
     const DevTree* dtrees = reinterpret_cast<const DevTree*>(dbase + L.trees);
     for (int tau = 1; tau <= max_m; ++tau) {
         const int32_t* slot = reinterpret_cast<const int32_t*>(dbase + L.slot0 + (tau - 1) * L.slot_bytes);
         e = launch_level_batch(dtrees, slot, slot + kMaxBatch, slot + 2 * kMaxBatch, entries[tau], blocks[tau], prec,
-                               rtt, buf, lds, st, tau == 1 ? host_cb->ev_staged : nullptr,
-                               tau == max_m ? done : nullptr);
+                               rtt, buf, lds, st, tau == max_m ? done : nullptr);
         if (e != hipSuccess)
             return hip_fail(e, "level batch launch");
-        if (tau == 1)
-            host_cb->staged_recorded = true;
     }
     return CYRUS_OK;
 }

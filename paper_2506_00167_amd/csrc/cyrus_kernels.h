@@ -19,12 +19,12 @@ bool plan_level_batch(const DevTree* trees, int n, int prec, int* rtt, int* buf,
 hipError_t launch_level(const DevTree& t, int prec, int rtt, int tau, hipStream_t s, hipEvent_t done = nullptr);
 // Batched: entry j is codebook ent_tree[j] at level ent_tau[j], owning
 // workgroups [prefix[j], prefix[j+1]) of an nblocks = prefix[n] launch.
-// started / done (nullable): events that complete when the launch starts /
-// ends (carried by the dispatch itself; recorded in the stream instead if
-// the launch has no workgroups).
+// done (nullable): an event that completes when the launch ends (carried by
+// the dispatch itself; recorded in the stream instead if the launch has no
+// workgroups).
 hipError_t launch_level_batch(const DevTree* trees, const int* ent_tree, const int* ent_tau, const int* prefix, int n,
                               int nblocks, int prec, int rtt, int buf, size_t lds, hipStream_t s,
-                              hipEvent_t started = nullptr, hipEvent_t done = nullptr);
+                              hipEvent_t done = nullptr);
 
 // Resident serving worker over `grid` workgroups (workgroup 0 admits, the
 // others run row tiles), with the LDS plan (rtt, a.bufsize, lds) of a batched

@@ -857,7 +857,7 @@ static hipError_t launch_level_t(const DevTree& t, int tau, hipStream_t s, hipEv
 template <int P, int RTT>
 static hipError_t launch_level_batch_t(const DevTree* trees, const int* ent_tree, const int* ent_tau,
                                        const int* prefix, int n, int nblocks, int buf, size_t lds, hipStream_t s,
-                                       hipEvent_t started, hipEvent_t done)
+                                       hipEvent_t done)
 {
     static bool attr = false;
     if (!attr) {
@@ -873,14 +873,10 @@ static hipError_t launch_level_batch_t(const DevTree* trees, const int* ent_tree
             ncu = 256;
     }
     const int grid = std::min(nblocks, ncu * std::max(1, (int)((160 * 1024) / lds)));
-    if (grid < 1) {
-        hipError_t e = started ? hipEventRecord(started, s) : hipSuccess;
-        if (e == hipSuccess && done)
-            e = hipEventRecord(done, s);
-        return e;
-    }
-    if (started || done)
-        hipExtLaunchKernelGGL((level_kernel_batch<P, RTT>), dim3(grid), dim3(kThreads), lds, s, started, done, 0,
+    if (grid < 1)
+        return done ? hipEventRecord(done, s) : hipSuccess;
+    if (done)
+        hipExtLaunchKernelGGL((level_kernel_batch<P, RTT>), dim3(grid), dim3(kThreads), lds, s, nullptr, done, 0,
                               trees, ent_tree, ent_tau, prefix, n, buf);
     else
         hipLaunchKernelGGL((level_kernel_batch<P, RTT>), dim3(grid), dim3(kThreads), lds, s, trees, ent_tree, ent_tau,
@@ -901,12 +897,11 @@ hipError_t launch_level(const DevTree& t, int prec, int rtt, int tau, hipStream_
 }
 
 hipError_t launch_level_batch(const DevTree* trees, const int* ent_tree, const int* ent_tau, const int* prefix, int n,
-                              int nblocks, int prec, int rtt, int buf, size_t lds, hipStream_t s, hipEvent_t started,
-                              hipEvent_t done)
+                              int nblocks, int prec, int rtt, int buf, size_t lds, hipStream_t s, hipEvent_t done)
 {
 #define CYRUS_LEVEL_CASE(P, R)                                                                                         \
     if (prec == P && rtt == R)                                                                                         \
-        return launch_level_batch_t<P, R>(trees, ent_tree, ent_tau, prefix, n, nblocks, buf, lds, s, started, done);
+        return launch_level_batch_t<P, R>(trees, ent_tree, ent_tau, prefix, n, nblocks, buf, lds, s, done);
     CYRUS_LEVEL_CASE(kFP32, 1) CYRUS_LEVEL_CASE(kFP32, 2) CYRUS_LEVEL_CASE(kFP32, 4)
     CYRUS_LEVEL_CASE(kBF16, 1) CYRUS_LEVEL_CASE(kBF16, 2) CYRUS_LEVEL_CASE(kBF16, 4) CYRUS_LEVEL_CASE(kBF16, 6)
     CYRUS_LEVEL_CASE(kFP8, 1) CYRUS_LEVEL_CASE(kFP8, 2) CYRUS_LEVEL_CASE(kFP8, 4) CYRUS_LEVEL_CASE(kFP8, 6)
