@@ -283,14 +283,24 @@ __device__ __forceinline__ void level_tile(const DevTree& t, int tau, int row0, 
     const float inv0 = t.inv_in_scale[0], inv_nseg = 1.f / (float)nseg, invK = 1.f / (float)K;
     const int rk0 = row0 - p_lo * K;  // row0's position among the children of parent p_lo
     const int d0 = 3 * E, d1 = 4 * E + 2;  // row-dependent features [d0, d1)
+    // segments sg0..sg0+nsg-1 hold row-dependent features; the others are
+    // copied from the template (or zeroed on the padding rows) in a first
+    // pass, the row-dependent ones written in a second, so that neither
+    // pass diverges inside a wave (the two write disjoint segments)
+    const int sg0 = d0 / F, nsg = (d1 - 1) / F - sg0 + 1;
+    const float inv_nsg = 1.f / (float)nsg;
     for (int idx = threadIdx.x; idx < nrows_pad * nseg; idx += kThreads) {
-        const int row = (int)(((float)idx + 0.5f) * inv_nseg), f0 = (idx - row * nseg) * F;
+        const int row = (int)(((float)idx + 0.5f) * inv_nseg), sg = idx - row * nseg, f0 = sg * F;
         uint8_t* dst = m.bufA + row * s0 + f0 * es;
-        if (row >= nrows) {
+        if (row >= nrows)
             *reinterpret_cast<uint4*>(dst) = uint4{0, 0, 0, 0};
-        } else if (f0 >= d1 || f0 + F <= d0) {
+        else if (sg < sg0 || sg >= sg0 + nsg)
             *reinterpret_cast<uint4*>(dst) = *reinterpret_cast<const uint4*>(m.tmplq + f0 * es);
-        } else {
+    }
+    for (int idx = threadIdx.x; idx < nrows * nsg; idx += kThreads) {
+        const int row = (int)(((float)idx + 0.5f) * inv_nsg), f0 = (sg0 + idx - row * nsg) * F;
+        uint8_t* dst = m.bufA + row * s0 + f0 * es;
+        {
             const int pq = (int)(((float)(rk0 + row) + 0.5f) * invK);  // parent - p_lo
             const int k = rk0 + row - pq * K + 1;
             const uint8_t* ps = m.pst + pq * E;
