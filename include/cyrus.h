@@ -410,6 +410,17 @@ int cyrus_engine_set_levels_per_step(cyrus_engine* eng, int32_t levels);
  * mapped for the device. */
 int cyrus_engine_set_resident(cyrus_engine* eng, int32_t on);
 
+/* Resident worker's tile order: its workgroups take tiles of the oldest
+ * request with tiles left, a request built by level tiles (one that the
+ * worker cannot build as register-resident subtree units, such as the 512-wide
+ * cells, which take M dependent steps) ranking as if admitted `lag` requests
+ * later. Requests that can finish within the slot then do not queue behind
+ * the long ones, and a long one is passed over by at most `lag` later
+ * admissions. 0 is first come, first served; default 64. Applies to requests
+ * admitted after the call; results do not depend on it. CYRUS_ERANGE outside
+ * [0, 65536]. */
+int cyrus_engine_set_level_lag(cyrus_engine* eng, int32_t lag);
+
 /* Status of a ticket (CYRUS_REQ_*); *latency_us (nullable) receives, once
  * done, the time from submit to the step that observed completion. */
 int cyrus_engine_poll(cyrus_engine* eng, int64_t ticket, int32_t* status, double* latency_us);

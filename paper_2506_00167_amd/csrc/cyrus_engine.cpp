@@ -141,6 +141,7 @@ struct cyrus_engine {
     size_t dcap = 0, hcap = 0;  // pool bytes left for requests after the descriptor slots
     int max_active = 0;
     int levels_per_step = 1;
+    int level_lag = kServeLevelLag;  // resident worker: lag of requests built by level tiles
     hipStream_t stream = nullptr;
     int device = 0;
     int prec = -1;
@@ -571,7 +572,7 @@ int admit_resident(cyrus_engine* e)
         q.sub_split = sub_split;
         q.sub_bufsize = sub_buf;
         q.sub_stbytes = sub_st;
-        q.sub_pad = 0;
+        q.lag = sub_split > 0 ? 0 : e->level_lag;
         std::memset(q.ue, 0, sizeof q.ue);
         std::memcpy(q.ue, r->ue.data(), r->ue.size() * 4);
         std::atomic_thread_fence(std::memory_order_release);
@@ -718,6 +719,16 @@ int cyrus_engine_set_levels_per_step(cyrus_engine* e, int32_t levels)
     if (levels < 1 || levels > 7)
         return set_error(CYRUS_ERANGE, "levels per step outside [1, 7]");
     e->levels_per_step = levels;
+    return CYRUS_OK;
+}
+
+int cyrus_engine_set_level_lag(cyrus_engine* e, int32_t lag)
+{
+    if (!e)
+        return set_error(CYRUS_EINVAL, "NULL engine");
+    if (lag < 0 || lag > kServeMaxLag)
+        return set_error(CYRUS_ERANGE, "lag outside [0, 65536]");
+    e->level_lag = lag;
     return CYRUS_OK;
 }
 

@@ -36,7 +36,7 @@ struct alignas(128) ServeRequest {
     int32_t sub_split;
     int32_t sub_bufsize;
     int32_t sub_stbytes;
-    int32_t sub_pad;
+    int32_t lag;  // generations added to the request's age when workgroups pick tiles
     int32_t ue[3 * kMaxUE];
 };
 
@@ -52,7 +52,16 @@ struct alignas(128) ServeSlotCtl {
     int32_t M;
     int32_t ntiles[8];  // [tau]
     int32_t rec;        // the request's record in the launch's record table
+    int32_t lag;        // generations added to this request's age when tiles are claimed
 };
+// Default lag of a request built by level tiles (M dependent steps, well over
+// a slot for the 512-wide cells): it ranks, when workgroups pick the oldest
+// request with tiles left, as if it had been admitted this many requests
+// later, so that the requests of subtree units, which can finish within the
+// slot, do not queue behind its level tiles, while it cannot be passed over
+// indefinitely. 0 is first come, first served.
+constexpr int kServeLevelLag = 64;
+constexpr int kServeMaxLag = 1 << 16;
 
 // Request records of one worker launch: the control workgroup copies the k-th
 // request it admits into record k, so within a launch every record is written

@@ -518,6 +518,7 @@ __device__ void serve_control(const ServeArgs& a, int* sh)
             if (tid == 0) {
                 dev_store(&sc.M, (int32_t)sys_load_u32(reinterpret_cast<const uint32_t*>(&src->t.M)));
                 dev_store(&sc.rec, rec);
+                dev_store(&sc.lag, (int32_t)sys_load_u32(reinterpret_cast<const uint32_t*>(&src->lag)));
                 dev_store(&sc.done, 0u);
                 if (wepoch != dev_load(&a.ctl->wepoch))
                     dev_store(&a.ctl->wepoch, wepoch);
@@ -550,8 +551,8 @@ __device__ void serve_control(const ServeArgs& a, int* sh)
 }
 
 // Wave 0 of a tile workgroup: claim the next tile. Every lane reads the claim
-// words of two slots; the oldest request (smallest generation) with tiles
-// left gets one fetch-and-add, whose result is authoritative: if it names a
+// words of two slots; the oldest request (smallest generation plus the
+// slot's lag) with tiles left gets one fetch-and-add, whose result is authoritative: if it names a
 // live level and a count below that level's tiles, that tile is this
 // workgroup's (whatever level the slot has reached meanwhile), else the
 // increment is spent and the scan repeats. Returns in sh[0] the slot (-1:
@@ -565,8 +566,9 @@ __device__ void serve_claim(const ServeArgs& a, int* sh)
         for (int j = 0; j < kServeSlots / 64; ++j) {
             const int s = lane + 64 * j;
             const uint64_t w = dev_load(&a.ctl->slot[s].claim);
+            const int lag = dev_load(&a.ctl->slot[s].lag);
             const int lvl = (int)((w >> 41) & 7u), nt = (int)((w >> 24) & 0x1FFFFu), cnt = (int)(w & 0xFFFFFFu);
-            const uint64_t key = ((w >> 44) << 8) | (uint64_t)s;
+            const uint64_t key = (((w >> 44) + (uint64_t)lag) << 8) | (uint64_t)s;
             if (lvl != 0 && cnt < nt && key < best)
                 best = key;
         }

@@ -40,7 +40,7 @@ SYMBOLS = (
     "cyrus_critic_workspace_size", "cyrus_critic_create", "cyrus_critic_evaluate", "cyrus_critic_evaluate_noalloc",
     "cyrus_critic_destroy",
     "cyrus_engine_create", "cyrus_engine_submit", "cyrus_engine_step", "cyrus_engine_set_levels_per_step",
-    "cyrus_engine_set_resident",
+    "cyrus_engine_set_resident", "cyrus_engine_set_level_lag",
     "cyrus_engine_poll",
     "cyrus_engine_completed", "cyrus_engine_result", "cyrus_engine_run", "cyrus_engine_stats",
     "cyrus_engine_destroy",
@@ -151,6 +151,7 @@ def lib():
         L.cyrus_engine_submit.argtypes = [vp, vp, ctypes.POINTER(cyrus_ue_state), ctypes.POINTER(ctypes.c_int64)]
         L.cyrus_engine_step.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
         L.cyrus_engine_set_levels_per_step.argtypes = [vp, ctypes.c_int32]
+        L.cyrus_engine_set_level_lag.argtypes = [vp, ctypes.c_int32]
         L.cyrus_engine_poll.argtypes = [vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32),
                                         ctypes.POINTER(ctypes.c_double)]
         L.cyrus_engine_completed.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
@@ -522,6 +523,10 @@ class Engine:
 
     def step(self):
         return cyrus_engine_step(self.handle)
+
+    def set_level_lag(self, lag: int):
+        _check(lib().cyrus_engine_set_level_lag(self.handle, int(lag)), "cyrus_engine_set_level_lag")
+        return self
 
     def set_levels_per_step(self, levels: int):
         _check(lib().cyrus_engine_set_levels_per_step(self.handle, int(levels)), "cyrus_engine_set_levels_per_step")

@@ -127,6 +127,9 @@ def main():
     ap.add_argument("--loads", default="0.25,0.5,0.75,0.9")
     ap.add_argument("--max-active", type=int, default=64)
     ap.add_argument("--pool-mib", type=int, default=256)
+    ap.add_argument("--level-lag", type=int, default=None,
+                    help="resident worker: requests built by level tiles rank as if admitted this many requests "
+                         "later (0: first come, first served; default: the library's)")
     ap.add_argument("--python-loop", action="store_true",
                     help="drive the engine from a Python loop instead of the library's cyrus_engine_run")
     ap.add_argument("--levels-per-step", default="0,1,7",
@@ -141,6 +144,8 @@ def main():
     for lps in [int(x) for x in args.levels_per_step.split(",")]:
         eng = default_engine(args.max_active, args.pool_mib, stream=stream, levels_per_step=max(lps, 1),
                              resident=lps == 0)
+        if lps == 0 and args.level_lag is not None:
+            eng.set_level_lag(args.level_lag)
         native = not args.python_loop
         warm = make_requests(cells, 200, seed=1)
         saturation(eng, cells, warm, native=native)

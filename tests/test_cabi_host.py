@@ -98,6 +98,7 @@ def test_null_handles_are_safe(lib):
     assert lib.cyrus_codebook_wait(None) == -1
     assert lib.cyrus_status_string(-3) == b"workspace too small or misplaced"
     assert lib.cyrus_engine_run(None, 0, None, None, None, None, None) == -1
+    assert lib.cyrus_engine_set_level_lag(None, 0) == -1
 
 
 def test_create_rejects_host_memory_as_workspace(lib):

@@ -233,6 +233,24 @@ def test_poisson_stream_short(cells, resident, native):
     eng.close()
 
 
+def test_resident_tile_order_does_not_change_results(cells):
+    # first come, first served (lag 0) and a lag far beyond the stream: the
+    # same codebooks as the single builds, and out-of-range lags are refused
+    for lag in (0, 4096):
+        eng = serving.default_engine(max_active=64, pool_mib=256, resident=True).set_level_lag(lag)
+        reqs = serving.make_requests(cells, 120, seed=18)
+        arr = wl.poisson_arrivals(20000.0, len(reqs), seed=19)
+        res = serving.run_stream(eng, cells, reqs, arr - arr[0], keep_results=True)
+        assert res["engine"]["completed"] == 120
+        for i in (0, 41, 119):
+            c, ue = reqs[i]
+            assert np.array_equal(res["results"][i], _single_build(cells[c], ue)[0]), f"lag {lag}, request {i}"
+        with pytest.raises(cyrus.CyrusError) as ei:
+            eng.set_level_lag(-1)
+        assert ei.value.status == -2
+        eng.close()
+
+
 def test_native_loop_refuses_bad_arrivals(cells):
     eng = serving.default_engine(max_active=4, pool_mib=64)
     reqs = serving.make_requests(cells, 3, seed=15)
